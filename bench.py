@@ -1,0 +1,151 @@
+"""Benchmark: zone-updates/s of the fp64 MHD step on one MI355X.
+
+A step is one full two-stage step of the hot path (ghost fill, both
+finite-volume stages, CFL dt, time update) over the equidistant full domain
+r in [0.1, 2] AU x theta in [30, 150] deg x phi in [0, 360) deg with
+512 x 60 x 180 cells (2,400 blocks of 16 x 12 x 12), seeded wind and cone
+CME, starting from the relaxation initial state.  One zone-update is one leaf
+cell advanced by one full step.
+
+Prints one JSON line.  The roofline entry is for the dominant kernel (the
+fused stage kernel): algorithmic bytes per launch (128 B/cell for stage 1:
+read U^n, write U*; 192 B/cell for stage 2: read U*, U^n, write U^{n+1};
+160 B/cell on average) over its mean launch duration from HIP events on the
+library's stream.  cpu_baseline times the oracle on the host on a bounded
+sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s (fp64 MHD, 1 GPU); AMR+learned flags vs equidistant to arrival"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_CELL_LAUNCH = 160.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "physics.h", "kernels.h", "device.h"):
+        with open(os.path.join(ROOT, "paper_2211_12867_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cells):
+    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "stage_traffic_equidistant_full.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle (plain fp64 C core with OpenMP) on a bounded sample of the
+    workload: the same grid spacing over the inner 64 radial cells."""
+    import numpy as np  # noqa: F401
+    from oracle import solver
+    from synthetic import as_dict, workload
+    w = workload("equidistant_full")
+    g = as_dict(w.grid)
+    dr = (g["x1"][0] - g["x0"][0]) / g["n"][0]
+    nr = 64
+    g["n"] = (nr, g["n"][1], g["n"][2])
+    g["x1"] = (g["x0"][0] + nr * dr, g["x1"][1], g["x1"][2])
+    s = solver.PatchSolver(g, as_dict(w.wind), as_dict(w.cmes[0]))
+    cells = nr * g["n"][1] * g["n"][2]
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        s.step()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or steps >= 50:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells * steps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d steps of the %d x 60 x 180 inner-radius part of the same grid (%.1f s)"
+                      % (steps, nr, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the single-run hot path has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    import paper_2211_12867_amd as ic
+    from synthetic import as_dict, workload
+
+    w = workload("equidistant_full")
+    g = as_dict(w.grid)
+    print("bench: creating %s %s blocks %s" % (w.name, g["n"], g["block"]), file=sys.stderr, flush=True)
+    sim = ic.Sim(g, as_dict(w.wind), [as_dict(w.cmes[0])])
+    cells = g["n"][0] * g["n"][1] * g["n"][2]
+    for _ in range(args.warmup):
+        sim.step()
+    sim.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(args.steps):
+        sim.step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    launches, mean_ms = sim.stage_timing()
+    sim.set_kernel_timing(False)
+    t_s, dt_s = sim.time()
+    sim.close()
+    print("bench: %d steps in %.3f s, stage kernel %d launches, mean %.3f ms, t = %.0f s, dt = %.1f s"
+          % (args.steps, el, launches, mean_ms, t_s, dt_s), file=sys.stderr, flush=True)
+
+    bytes_launch = BYTES_PER_CELL_LAUNCH * cells
+    achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
+    traffic = measured_traffic(cells)
+    out = {
+        "metric": METRIC,
+        "value": cells * args.steps / el,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "equidistant_full: 512x60x180 cells, r 0.1-2 AU, theta 30-150 deg, "
+                               "phi 0-360 deg, 2400 blocks of 16x12x12, seeded wind + cone CME",
+                   "cells": cells, "block": list(g["block"]), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_stage<16,12,12>", "mean_launch_ms": mean_ms,
+                     "bytes_per_launch": bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

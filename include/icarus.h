@@ -1,0 +1,245 @@
+/*
+ * icarus.h -- C ABI of the MI355X library for the Icarus hot path.
+ *
+ * The library advances 3-D ideal MHD in the frame co-rotating with the Sun on
+ * a spherical (r, theta, phi) grid with radial stretching and block-adaptive
+ * refinement (Baratashvili et al., "Improving CME evolution and arrival
+ * predictions with AMR and grid stretching in Icarus", Sect. 2.1-2.2, 3):
+ * a finite-volume TVDLF (Rusanov) scheme with a monotonised-central limiter,
+ * second order in space and time, two ghost layers, inner-boundary driving by
+ * a solar wind plus a cone CME (Eqs. 1-4), refinement by a Loehner-type
+ * density/velocity indicator restricted to compressive cells (div V < 0)
+ * inside the Earth/CME windows of Sect. 3.2.
+ *
+ * Conventions
+ *  - Every pointer argument is a plain host pointer unless it says "device".
+ *    Config structs are copied during ic_create; output buffers belong to the
+ *    caller.  The sim object and all device memory it uses belong to the
+ *    library and are released by ic_destroy.
+ *  - Units at the ABI: AU, degrees, seconds, km/s, cm^-3, K, nT, m^3/s^2.
+ *    State arrays (ic_get_state / ic_set_state / sampled primitives) are in
+ *    the library's code units: length 1 AU, speed 1000 km/s, time
+ *    1 AU / (1000 km/s), density m_p cm^-3, pressure and energy density
+ *    rho0 v0^2, magnetic field sqrt(mu0 rho0 v0^2) (mu0 = 1); ic_units()
+ *    returns these scales.
+ *  - Conserved variables, 8 per cell: rho, m_r, m_theta, m_phi, E, B_r,
+ *    B_theta, B_phi (x, y, z in the cartesian test geometry).
+ *  - Block state layout: [block][variable][k][j][i], i (r) fastest, blocks in
+ *    ascending (level, Morton(i, j, k)) order, as ic_get_blocks lists them.
+ *  - All GPU work is enqueued on the HIP stream given to ic_create (NULL =
+ *    the null stream).  Calls that return host data synchronise that stream.
+ *  - Errors: the return value is IC_OK or a negative ic_status; ic_last_error
+ *    gives a text for the last failing call on the calling thread.  After
+ *    IC_E_UNPHYSICAL, IC_E_DEVICE or IC_E_CAPACITY the sim is poisoned and
+ *    every later call except ic_destroy returns IC_E_STATE.
+ *  - One sim is used from one thread at a time.
+ */
+#ifndef ICARUS_H
+#define ICARUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ic_sim ic_sim;
+
+typedef enum {
+    IC_OK = 0,
+    IC_E_INVALID = -1,     /* bad argument or configuration */
+    IC_E_NOMEM = -2,       /* device or host allocation failed */
+    IC_E_DEVICE = -3,      /* a HIP call failed */
+    IC_E_UNPHYSICAL = -4,  /* rho <= 0, p <= 0 or a non-finite value in a leaf cell */
+    IC_E_OUTSIDE = -5,     /* sample point outside the domain */
+    IC_E_CAPACITY = -6,    /* block pool too small for the requested forest */
+    IC_E_STATE = -7        /* the sim was poisoned by an earlier error */
+} ic_status;
+
+enum { IC_GEOM_SPHERICAL = 0, IC_GEOM_CARTESIAN = 1 };
+enum { IC_BC_OUTFLOW = 0, IC_BC_PERIODIC = 1, IC_BC_INNER = 2 };
+enum { IC_FLAG_COARSEN = -1, IC_FLAG_KEEP = 0, IC_FLAG_REFINE = 1 };
+
+/* Mesh (Sect. 2.2, 3).  Spherical: x = (r [AU], colatitude [deg], longitude
+ * [deg]); cartesian (tests): code units.  Level l has n * 2^(l-1) cells per
+ * direction; blocks hold block[0] x block[1] x block[2] cells and block must
+ * be one of the sizes the library is built for (ic_block_supported).
+ * stretched_r = 1 gives radial faces r_in exp(k ln(r_out/r_in)/N_l) (cells
+ * of equal aspect, Eq. 5); 0 gives equidistant faces.  bc[d][0/1]: lower /
+ * upper boundary of direction d; IC_BC_INNER is the wind + CME inner
+ * boundary (spherical r lower side only); periodic needs both sides periodic.
+ * max_blocks: block-pool capacity per member (0 = a default). */
+typedef struct {
+    int geometry;
+    double x0[3], x1[3];
+    int n[3];
+    int block[3];
+    int stretched_r;
+    int max_level;
+    int bc[3][2];
+    int max_blocks;
+} ic_grid_cfg;
+
+/* Physics: adiabatic index, CFL number (dt = cfl / max sum_d (|v_d|+c_f)/dx_d),
+ * frame rotation rate [rad/s] about the theta = 0 axis, G M_sun [m^3 s^-2],
+ * small-value floors in code units applied to every stage result (a cell with
+ * rho < rho_floor takes rho_floor at unchanged velocity; then a cell with
+ * p < p_floor has its energy raised to give p = p_floor; 0 disables). */
+typedef struct {
+    double gamma;
+    double cfl;
+    double omega;
+    double gm;
+    double rho_floor;
+    double p_floor;
+} ic_phys_cfg;
+
+/* Inner-boundary wind at r_in (Sect. 2.1): v_r = v_min + (v_max - v_min)
+ * (f - f_min)/(f_max - f_min), clamped, f = sum a_lm Y_lm(theta, phi) over
+ * l = 1..3 (orthonormal real harmonics, no Condon-Shortley phase, (l, m)
+ * order); v_r = v_min everywhere if f_max <= f_min.  n = n_ref (v_r/v_ref)^-2,
+ * p = 2 n k_B T, v_phi = -omega r_in sin(theta), B a unipolar Parker field of
+ * magnitude B_nT parallel to v in the co-rotating frame. */
+typedef struct {
+    double alm[15];
+    double f_min, f_max;
+    double v_min_kms, v_max_kms;
+    double n_ref_cm3, v_ref_kms;
+    double T_K;
+    double B_nT;
+} ic_wind_cfg;
+
+/* Cone CME (Eqs. 1-4): inner-boundary points with angular distance d to the
+ * CME centre below the opening angle theta(t) take n, T, v_r = v_kms (B and
+ * v_phi of the wind), for 0 <= t - t_start <= min(duration, 2 r_1/2 / v). */
+typedef struct {
+    double t_start_s, duration_s, v_kms, half_width_deg, colat_deg, lon_deg, n_cm3, T_K;
+    int enabled;
+} ic_cme_cfg;
+
+/* Refinement criterion (Sect. 3.2 windows): a cell is hot at tolerance tol if
+ * it lies in |lon - lon_E| <= dlon_E, |colat - colat_E| <= dclt_E and
+ * |lon - lon_CME| <= dlon_CME (when use_windows), has div V < 0 and
+ * w_rho E(rho) + w_v E(|v|) > tol, E the per-direction Loehner estimator
+ * with parameter eps_lohner.  A block is REFINE below max_level with a hot
+ * cell at tol_refine, COARSEN above level 1 with no hot cell at tol_coarsen,
+ * else KEEP.  buffer_blocks = 1 refines the face neighbours of REFINE blocks
+ * too.  regrid_every is the cadence ic_advance regrids at (0 = never). */
+typedef struct {
+    double eps_lohner, tol_refine, tol_coarsen, w_rho, w_v;
+    double lon_earth_deg, clt_earth_deg, dlon_earth_deg, dclt_earth_deg, dlon_cme_deg;
+    int use_windows;
+    int regrid_every;
+    int buffer_blocks;
+} ic_amr_cfg;
+
+typedef struct {
+    long steps;              /* steps taken by member 0 since ic_create */
+    double t_s;              /* time of member 0 */
+    double dt_s;             /* last step of member 0 */
+    double zone_updates;     /* leaf cells advanced by full steps, all members, since ic_create */
+    int leaves;              /* leaf blocks of member 0 */
+    int leaves_per_level[8];
+} ic_info;
+
+/* Create a sim of n_members independent runs sharing one grid and wind,
+ * member m driven by cmes[m] (cmes may be NULL: no CME).  The state starts
+ * from the relaxation initial condition: rho ~ r^-2, v_r constant along
+ * rays, p ~ r^-2 gamma, B_r ~ r^-2, v_phi = -omega r sin(theta) and B
+ * parallel to v.  amr may be NULL when max_level = 1.  hip_stream is a
+ * hipStream_t (NULL = null stream).  On success *out owns the sim. */
+ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_wind_cfg *wind,
+                    const ic_cme_cfg *cmes, int n_members, const ic_amr_cfg *amr,
+                    void *hip_stream, ic_sim **out);
+
+/* Release the sim and its device memory (NULL is ignored). */
+void ic_destroy(ic_sim *sim);
+
+/* One two-stage step of every member (paper Sect. 2.1: second order in time):
+ * U* = U^n + dt/2 L(U^n) with ghosts at t^n, U^{n+1} = U^n + dt L(U*) with
+ * ghosts at t^n + dt/2.  dt_fixed_s > 0 forces dt; 0 takes the CFL dt of
+ * each member.  out may be NULL.  Returns IC_E_UNPHYSICAL if a leaf cell
+ * went non-physical. */
+ic_status ic_step(ic_sim *sim, double dt_fixed_s, ic_info *out);
+
+/* Advance every member by dt_s (the last step is clipped to land on t + dt_s),
+ * at most max_steps steps, regridding every amr->regrid_every steps when
+ * max_level > 1, and recording the sample point after every step
+ * (ic_timeseries). */
+ic_status ic_advance(ic_sim *sim, double dt_s, long max_steps, ic_info *out);
+
+/* Rebuild every member's forest (Sect. 3): flags NULL evaluates the plain
+ * criterion on the current state; otherwise flags[m * max_blocks + b] gives
+ * member m's flag for its b-th leaf in ic_get_blocks order (IC_FLAG_*).
+ * Then buffer, 2:1 closure over all 26 neighbours, coarsening of complete
+ * sibling octets, and data movement by conservative limited prolongation /
+ * volume-weighted restriction.  Returns IC_E_CAPACITY (sim poisoned) if the
+ * pool cannot hold the new forest. */
+ic_status ic_regrid(ic_sim *sim, const int8_t *flags, ic_info *out);
+
+/* Plain-criterion flags of member's leaves, in ic_get_blocks order; n is the
+ * capacity of flags and must be >= the leaf count. */
+ic_status ic_eval_flags(ic_sim *sim, int member, int8_t *flags, int n);
+
+/* Primitive variables (rho, v_r, v_theta, v_phi, p, B_r, B_theta, B_phi), code
+ * units, at a point: trilinear interpolation between the cell centres of the
+ * level of the finest leaf containing the point (cells of a coarser leaf
+ * count with their covering value, cells under finer leaves with the
+ * volume-weighted mean of their children).  IC_E_OUTSIDE outside the domain. */
+ic_status ic_sample(ic_sim *sim, int member, double r_au, double colat_deg, double lon_deg,
+                    double prim_out[8]);
+
+/* Point recorded after every step by ic_advance (default (1 AU, 90, 0)). */
+ic_status ic_set_sample_point(ic_sim *sim, double r_au, double colat_deg, double lon_deg);
+
+/* Recorded samples of a member: out[s * 9 + 0] = t [s], out[s * 9 + 1..8] =
+ * primitives (code units); *n_inout is the capacity in samples on entry and
+ * the count written on return (the most recent ones if the record is longer).
+ * ic_timeseries_clear drops the record. */
+ic_status ic_timeseries(ic_sim *sim, int member, double *out, int *n_inout);
+ic_status ic_timeseries_clear(ic_sim *sim);
+
+/* Leaf blocks of a member as (level, i, j, k) quadruples, level >= 1, in
+ * ascending (level, Morton) order.  *n_inout: capacity on entry (in blocks),
+ * leaf count on return; IC_E_INVALID if the capacity is too small. */
+ic_status ic_get_blocks(ic_sim *sim, int member, int32_t *lvl_ijk, int *n_inout);
+
+/* Copy a member's conserved state to host_U ([block][8][bk][bj][bi], code
+ * units); n_doubles must be >= leaves * 8 * cells per block. */
+ic_status ic_get_state(ic_sim *sim, int member, double *host_U, size_t n_doubles);
+
+/* Replace a member's forest and state: n_blocks leaves (level, i, j, k) that
+ * tile the domain, with data host_U in the same layout, at time t_s. */
+ic_status ic_set_state(ic_sim *sim, int member, const int32_t *lvl_ijk, int n_blocks,
+                       const double *host_U, double t_s);
+
+/* Time and last dt of a member [s]. */
+ic_status ic_get_time(ic_sim *sim, int member, double *t_s, double *dt_s);
+
+/* Code-unit scales in SI: [0] length m, [1] speed m/s, [2] time s, [3]
+ * density kg/m^3, [4] pressure Pa, [5] field T. */
+void ic_units(double out[6]);
+
+/* Block-pool capacity per member (the stride of the flags array of ic_regrid). */
+int ic_pool_capacity(const ic_sim *sim);
+
+/* 1 if the library has kernels for this block shape, else 0. */
+int ic_block_supported(int bi, int bj, int bk);
+
+/* Kernel timing for measurement: when enabled, ic_step launches its kernels
+ * without graph replay and brackets every launch of the finite-volume stage
+ * kernel with HIP events on the sim's stream; ic_stage_timing returns the
+ * number of timed launches and their mean duration [ms] since the last
+ * reset (it synchronises the stream). */
+ic_status ic_set_kernel_timing(ic_sim *sim, int enable);
+ic_status ic_stage_timing(ic_sim *sim, long *launches, double *mean_ms);
+
+/* Text of the last error on the calling thread. */
+const char *ic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ICARUS_H */

@@ -45,6 +45,35 @@ class UnphysicalState(RuntimeError):
     pass
 
 
+# Small-value floors (code units), applied to every stage result: a cell with
+# rho < RHO_FLOOR takes rho = RHO_FLOOR with its velocity kept; then a cell with
+# p < P_FLOOR has its energy raised so that p = P_FLOOR.  The paper's scheme is
+# not positivity preserving and it does not say how its code treats small
+# values; a fast CME followed by slow wind opens a near-vacuum rarefaction
+# behind the CME, where the exact update undershoots to p < 0.
+RHO_FLOOR = 1.0e-6
+P_FLOOR = 1.0e-9
+
+
+def apply_floors(U, gamma, rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
+    """Floors on a conserved array [8, ...] (in place); returns the cell count changed."""
+    n = 0
+    low = U[0] < rho_floor
+    if np.any(low):
+        fac = np.where(low, rho_floor / np.where(low, U[0], 1.0), 1.0)
+        U[1:4] *= fac
+        U[0] = np.where(low, rho_floor, U[0])
+        n += int(low.sum())
+    kin = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
+    mag = 0.5 * (U[5] ** 2 + U[6] ** 2 + U[7] ** 2)
+    p = (gamma - 1.0) * (U[4] - kin - mag)
+    lowp = p < p_floor
+    if np.any(lowp):
+        U[4] = np.where(lowp, p_floor / (gamma - 1.0) + kin + mag, U[4])
+        n += int(lowp.sum())
+    return n
+
+
 # refinement-criterion readings: Loehner eps, thresholds, weights, the
 # Earth/CME windows of Sect. 3.2, regrid cadence and buffer
 AMR_DEFAULTS = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
@@ -57,7 +86,8 @@ class Solver:
     """Block-forest solver.  State: dict leaf -> U[8, bk, bj, bi] (code units)."""
 
     def __init__(self, grid, wind=None, cme=None, amr=None, omega=None, gm=None, t0_s=0.0,
-                 initial="wind"):
+                 initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
+        self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
         self.grid.setdefault("periodic", (False, False, False))
@@ -371,8 +401,12 @@ class Solver:
         Un = self.U
         L1, _ = self.operator(Un, self.t)
         Us = {b: Un[b] + (0.5 * dt) * L1[b] for b in Un}
+        for u in Us.values():
+            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor)
         L2, _ = self.operator(Us, self.t + 0.5 * dt)
         self.U = {b: Un[b] + dt * L2[b] for b in Un}
+        for u in self.U.values():
+            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor)
         self.t += dt
         self.steps += 1
         return dt
@@ -580,7 +614,9 @@ class PatchSolver:
     """Single-level solver on one global ghosted patch (no blocks).  Used as
     an independent check of the block decomposition and as the CPU baseline."""
 
-    def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind"):
+    def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind",
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
+        self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
         self.grid.setdefault("periodic", (False, False, False))
@@ -655,8 +691,10 @@ class PatchSolver:
         Un = self.U
         L1 = self.operator(Un, self.t)
         Us = Un + (0.5 * dt) * L1
+        self.floored += apply_floors(Us, self.gamma, self.rho_floor, self.p_floor)
         L2 = self.operator(Us, self.t + 0.5 * dt)
         self.U = Un + dt * L2
+        self.floored += apply_floors(self.U, self.gamma, self.rho_floor, self.p_floor)
         self.t += dt
         return dt
 

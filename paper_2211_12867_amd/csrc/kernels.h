@@ -1,0 +1,130 @@
+// kernels.h -- HIP kernels of the Icarus hot path (gfx950).
+//
+// All kernels walk device-resident task lists with a grid-stride loop over
+// work-groups, so a captured graph stays valid when a regrid rewrites the
+// lists.  Block shapes are template parameters (BI x BJ x BK cells).
+#pragma once
+#include "device.h"
+#include "physics.h"
+
+// Ghost-slab face geometry: tangential directions of face direction d, in
+// increasing order.
+__host__ __device__ constexpr int tan1(int d) { return d == 0 ? 1 : 0; }
+__host__ __device__ constexpr int tan2(int d) { return d == 2 ? 1 : 2; }
+
+struct KArgs {
+    double *U;                 // state read by this kernel (stage input)
+    const double *Ubase;       // U^n
+    double *Uout;              // stage output
+    const BlockDesc *desc;
+    double *slabs;
+    double *freg;
+    const LevelGeo *geo;       // [IC_MAX_LEVEL + 2], index = level
+    const MemberConst *mc;
+    const int *items;          // work list (slots)
+    const int *nitems;
+    const double *dt;          // per member
+    const double *t;           // per member
+    double *rate;              // per slot
+    int *bad;                  // per member
+    long slab_stride;          // doubles per slab
+    long reg_stride;           // doubles per flux register
+    double alpha;              // stage weight of dt (1/2 or 1)
+    double tfrac;              // stage time = t + tfrac * dt
+    Gas gas;
+    double omega, gm;
+    double rho_floor, p_floor;
+    int cart;
+    int want_rate;
+};
+
+template <int BI, int BJ, int BK>
+struct Shape {
+    static constexpr int B0 = BI, B1 = BJ, B2 = BK;
+    static constexpr int NC = BI * BJ * BK;
+    __host__ __device__ static constexpr int dim(int d) { return d == 0 ? BI : (d == 1 ? BJ : BK); }
+    __host__ __device__ static constexpr int face_cells(int d) { return dim(tan1(d)) * dim(tan2(d)); }
+    static constexpr int MAXFACE = (BI * BJ > BI * BK ? (BI * BJ > BJ * BK ? BI * BJ : BJ * BK)
+                                                       : (BI * BK > BJ * BK ? BI * BK : BJ * BK));
+};
+
+// Value of variable v of the cell (i, j, k) of block `slot`, where at most one
+// index may lie in the two ghost layers: interior, same-level neighbour,
+// outflow copy of the edge cell, or ghost slab.
+template <class S>
+__device__ inline double ghosted(const double *__restrict__ U, const BlockDesc *__restrict__ desc,
+                                 const double *__restrict__ slabs, long slab_stride, int slot, int v,
+                                 int i, int j, int k)
+{
+    int idx[3] = {i, j, k};
+    int d = -1;
+    if (i < 0 || i >= S::B0) d = 0;
+    else if (j < 0 || j >= S::B1) d = 1;
+    else if (k < 0 || k >= S::B2) d = 2;
+    if (d < 0)
+        return U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k)];
+    const int Bd = S::dim(d);
+    const int side = idx[d] >= Bd ? 1 : 0;
+    const int l = side ? idx[d] - Bd : idx[d] + 2;
+    const int code = desc[slot].nbr[2 * d + side];
+    if (code >= 0) {
+        idx[d] = side ? l : Bd - 2 + l;
+        return U[(size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2])];
+    }
+    if (code == NBR_OUTFLOW) {
+        idx[d] = side ? Bd - 1 : 0;
+        return U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2])];
+    }
+    const int s = nbr_slab(code);
+    const int a = idx[tan1(d)], b = idx[tan2(d)];
+    const int FA = S::dim(tan1(d)), FB = S::dim(tan2(d));
+    return slabs[(size_t)s * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a];
+}
+
+template <class S>
+__device__ inline void ghosted8(const KArgs &a, const double *U, int slot, int i, int j, int k, double u[8])
+{
+#pragma unroll
+    for (int v = 0; v < 8; ++v) u[v] = ghosted<S>(U, a.desc, a.slabs, a.slab_stride, slot, v, i, j, k);
+}
+
+struct IndicatorParams {
+    int max_level;
+    double eps, tol_r, tol_c, w_rho, w_v;
+    int use_windows;
+    double lon_e, clt_e, dlon_e, dclt_e, dlon_c;   // radians
+};
+
+// Launch wrappers per block shape (kernels.hip); the runtime calls these.
+struct Launchers {
+    void (*stage)(dim3, hipStream_t, const KArgs &);
+    void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *);
+    void (*reflux)(dim3, hipStream_t, const KArgs &, const RefluxTask *, const int *, const int *);
+    void (*rate)(dim3, hipStream_t, const KArgs &);
+    void (*indicator)(dim3, hipStream_t, const KArgs &, int8_t *, const IndicatorParams &);
+    void (*move)(dim3, hipStream_t, const KArgs &, double *, const MoveTask *, int);
+    void (*sample)(dim3, hipStream_t, const KArgs &, const SampleDesc *, int, double *, double *, int *, int, int);
+};
+bool get_launchers(int bi, int bj, int bk, Launchers *out);
+void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, int nm, double cfl,
+               double dt_fixed, const double *tend, double *dt_last);
+void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm);
+
+// kernel entry points (defined in kernels.hip)
+template <int BI, int BJ, int BK> __global__ void k_stage(KArgs a);
+template <int BI, int BJ, int BK> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
+template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
+template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);
+template <int BI, int BJ, int BK>
+__global__ void k_indicator(KArgs a, int8_t *flags, int max_level, double eps, double tol_r,
+                            double tol_c, double w_rho, double w_v, int use_windows, double lon_e,
+                            double clt_e, double dlon_e, double dclt_e, double dlon_c);
+template <int BI, int BJ, int BK>
+__global__ void k_move(KArgs a, double *Unew, const MoveTask *tasks, int ntasks);
+template <int BI, int BJ, int BK>
+__global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
+                         int *ring_count, int ring_cap, int record);
+
+__global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, double cfl,
+                     double dt_fixed, const double *tend, double *dt_last);
+__global__ void k_time(double *t, const double *dt, long *nsteps, int nmembers);

@@ -1,0 +1,831 @@
+// kernels.hip -- HIP kernels of the Icarus hot path for gfx950 (CDNA4).
+//
+// k_stage is the fused finite-volume stage (paper Sect. 2.1: TVDLF with a
+// Woodward-type limiter, second order): one work-group per leaf block marches
+// along k (phi) through the block.  For each k-plane the primitives of the
+// plane and of its two-cell i/j halos sit in LDS; every r- and theta-face flux
+// of the plane is computed once by one thread and kept in LDS; the phi-face
+// fluxes are computed once per column in registers (each thread owns one
+// (i, j) column and carries the previous plane's flux, face state and the
+// next two planes' primitives).  The update then adds the flux differences
+// with the finite-volume metric, the hoop, Coriolis, centrifugal and gravity
+// sources, and writes U_out = U_base + alpha dt L(U).  Halo cells come
+// straight from neighbouring blocks (same level), from the block's own edge
+// (outflow) or from ghost slabs (inner boundary, coarse-fine faces).
+#include "kernels.h"
+
+#define NT 256
+
+namespace {
+
+template <class S>
+__device__ inline size_t cidx(int slot, int v, int i, int j, int k)
+{
+    return (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+}
+
+__device__ inline double wave_max(double x)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        double y = __shfl_xor(x, off, 64);
+        x = x > y ? x : y;
+    }
+    return x;
+}
+
+// Block-wide max over NT threads; result valid in all threads.
+__device__ inline double block_max(double x, double *scratch)
+{
+    x = wave_max(x);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) scratch[wid] = x;
+    __syncthreads();
+    double m = scratch[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = m > scratch[w] ? m : scratch[w];
+    __syncthreads();
+    return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// fused stage kernel
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_stage(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    constexpr int PI = BI + 4, PJ = BJ + 4;
+    constexpr int NFI = (BI + 1) * BJ;
+    constexpr int NFJ = BI * (BJ + 1);
+    constexpr int NCOL = BI * BJ;
+    constexpr int NHALO = 4 * (BI + BJ);
+    static_assert(NCOL <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
+
+    __shared__ double sW[8][PJ][PI];
+    __shared__ double sFi[8][BJ][BI + 1];
+    __shared__ double sFj[8][BJ + 1][BI];
+    __shared__ RecR sR[BI + 4];
+    __shared__ RecT sT[BJ + 4];
+    __shared__ double sred[NT / 64];
+
+    const int tid = threadIdx.x;
+    const bool col = tid < NCOL;
+    const int ci = tid % BI, cj = tid / BI;      // column owned by this thread
+    const Gas gs = a.gas;
+    const int nitems = *a.nitems;
+
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int slot = a.items[it];
+        const BlockDesc bd = a.desc[slot];
+        const int mem = bd.member;
+        const double dt = a.dt[mem];
+        if (dt <= 0.0) continue;                 // member finished: state stays in place
+        const LevelGeo lg = a.geo[bd.level];
+        const double adt = a.alpha * dt;
+
+        __syncthreads();
+        for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
+        for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
+        __syncthreads();
+
+        // --- prologue: column primitives for k = -2 .. 1, first phi-face flux
+        double Wk[8], Wk1[8], wLk[8], Fkm[8];
+        double rtc = 0.0, thmc = 0.0, thpc = 0.0, amc = 0.0, apc = 0.0;
+        bool badc = false;
+        if (col) {
+            double u[8], w0[8], w1[8], w2[8], w3[8];
+            ghosted8<S>(a, a.U, slot, ci, cj, -2, u); cons_to_prim(u, w0, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, -1, u); cons_to_prim(u, w1, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, 0, u);  cons_to_prim(u, w2, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, 1, u);  cons_to_prim(u, w3, gs);
+            const RecP pm1 = lg.p[bd.org[2] - 1 + 2], p0 = lg.p[bd.org[2] + 2];
+            double lo[8], hi[8], lo0[8], hi0[8];
+            reconstruct(w0, w1, w2, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
+            reconstruct(w1, w2, w3, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, lo0, hi0);
+            rusanov<2>(hi, lo0, Fkm, gs);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                Wk[v] = w2[v];
+                Wk1[v] = w3[v];
+                wLk[v] = hi0[v];
+            }
+            const RecR rr = sR[ci + 2];
+            const RecT tt = sT[cj + 2];
+            rtc = rr.rt;
+            amc = rr.am;
+            apc = rr.ap;
+            thmc = rr.rt * tt.thm;
+            thpc = rr.rt * tt.thp;
+        }
+        double rmax = 0.0;
+
+        for (int k = 0; k < BK; ++k) {
+            const RecP pk = lg.p[bd.org[2] + k + 2];
+            const RecP pk1 = lg.p[bd.org[2] + k + 3];
+            // (a) plane k into LDS: own column + i/j halos
+            if (col) {
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wk[v];
+            }
+            for (int t = tid; t < NHALO; t += NT) {
+                int i, j;
+                if (t < 4 * BJ) {                 // r-direction halo
+                    const int side = t / (2 * BJ), rem = t % (2 * BJ);
+                    const int l = rem / BJ;
+                    j = rem % BJ;
+                    i = side ? BI + l : l - 2;
+                } else {                          // theta-direction halo
+                    const int q = t - 4 * BJ;
+                    const int side = q / (2 * BI), rem = q % (2 * BI);
+                    const int l = rem / BI;
+                    i = rem % BI;
+                    j = side ? BJ + l : l - 2;
+                }
+                double u[8], w[8];
+                ghosted8<S>(a, a.U, slot, i, j, k, u);
+                cons_to_prim(u, w, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+            }
+            double un[8];
+            if (col) ghosted8<S>(a, a.U, slot, ci, cj, k + 2, un);
+            __syncthreads();
+
+            // (c) r-faces of the plane: face f lies between cells f-1 and f
+            for (int t = tid; t < NFI; t += NT) {
+                const int f = t % (BI + 1), j = t / (BI + 1);
+                double wa[8], wb[8], wc[8], wd[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    wa[v] = sW[v][j + 2][f];
+                    wb[v] = sW[v][j + 2][f + 1];
+                    wc[v] = sW[v][j + 2][f + 2];
+                    wd[v] = sW[v][j + 2][f + 3];
+                }
+                const RecR ra = sR[f + 1], rb = sR[f + 2];
+                double lo[8], hi[8], lo2[8], hi2[8], fx[8];
+                reconstruct(wa, wb, wc, ra.idm, ra.idp, ra.idc, ra.hm, ra.hp, lo, hi);
+                reconstruct(wb, wc, wd, rb.idm, rb.idp, rb.idc, rb.hm, rb.hp, lo2, hi2);
+                rusanov<0>(hi, lo2, fx, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sFi[v][j][f] = fx[v];
+            }
+            // (d) theta-faces of the plane
+            for (int t = tid; t < NFJ; t += NT) {
+                const int i = t % BI, f = t / BI;
+                double wa[8], wb[8], wc[8], wd[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    wa[v] = sW[v][f][i + 2];
+                    wb[v] = sW[v][f + 1][i + 2];
+                    wc[v] = sW[v][f + 2][i + 2];
+                    wd[v] = sW[v][f + 3][i + 2];
+                }
+                const RecT ta = sT[f + 1], tb = sT[f + 2];
+                double lo[8], hi[8], lo2[8], hi2[8], fx[8];
+                reconstruct(wa, wb, wc, ta.idm, ta.idp, ta.idc, ta.hm, ta.hp, lo, hi);
+                reconstruct(wb, wc, wd, tb.idm, tb.idp, tb.idc, tb.hm, tb.hp, lo2, hi2);
+                rusanov<1>(hi, lo2, fx, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sFj[v][f][i] = fx[v];
+            }
+            // (e) phi-face k+1/2 of the column
+            double Fkp[8], lo1[8], hi1[8];
+            if (col) {
+                double wn[8];
+                cons_to_prim(un, wn, gs);
+                reconstruct(Wk, Wk1, wn, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
+                rusanov<2>(wLk, lo1, Fkp, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) un[v] = wn[v];
+            }
+            __syncthreads();
+
+            // (g) update of cell (ci, cj, k)
+            if (col) {
+                badc = badc || unphysical(Wk);
+                double acc[8];
+                const double kf = rtc * sT[cj + 2].phf * pk.iw;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    acc[v] = -(apc * sFi[v][cj][ci + 1] - amc * sFi[v][cj][ci])
+                             - (thpc * sFj[v][cj + 1][ci] - thmc * sFj[v][cj][ci])
+                             - kf * (Fkp[v] - Fkm[v]);
+                }
+                if (!a.cart) {
+                    const RecR rr = sR[ci + 2];
+                    const RecT tt = sT[cj + 2];
+                    add_sources(Wk, rtc, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
+                }
+                const size_t base = cidx<S>(slot, 0, ci, cj, k);
+                double unew[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) unew[v] = a.Ubase[base + (size_t)v * S::NC] + adt * acc[v];
+                // floors now, or after the reflux for cells on a coarse-fine face
+                const int mk = bd.reflux_mask;
+                const bool rf = (ci == 0 && (mk & 1)) || (ci == BI - 1 && (mk & 2)) || (cj == 0 && (mk & 4))
+                             || (cj == BJ - 1 && (mk & 8)) || (k == 0 && (mk & 16)) || (k == BK - 1 && (mk & 32));
+                if (!rf) apply_floors(unew, gs, a.rho_floor, a.p_floor);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
+                if (a.want_rate) {
+                    double w[8];
+                    cons_to_prim(unew, w, gs);
+                    const RecR rr = sR[ci + 2];
+                    const RecT tt = sT[cj + 2];
+                    const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
+                                      + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
+                                      + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pk.iw;
+                    rmax = rate > rmax ? rate : rmax;
+                }
+                // raw fluxes at coarse-fine faces for the reflux
+                if (ci == 0 && bd.freg[0] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[0] * a.reg_stride + ((size_t)v * BK + k) * BJ + cj] = sFi[v][cj][0];
+                if (ci == BI - 1 && bd.freg[1] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[1] * a.reg_stride + ((size_t)v * BK + k) * BJ + cj] = sFi[v][cj][BI];
+                if (cj == 0 && bd.freg[2] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[2] * a.reg_stride + ((size_t)v * BK + k) * BI + ci] = sFj[v][0][ci];
+                if (cj == BJ - 1 && bd.freg[3] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[3] * a.reg_stride + ((size_t)v * BK + k) * BI + ci] = sFj[v][BJ][ci];
+                if (k == 0 && bd.freg[4] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[4] * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fkm[v];
+                if (k == BK - 1 && bd.freg[5] >= 0)
+                    for (int v = 0; v < 8; ++v)
+                        a.freg[(size_t)bd.freg[5] * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fkp[v];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    Fkm[v] = Fkp[v];
+                    Wk[v] = Wk1[v];
+                    Wk1[v] = un[v];
+                    wLk[v] = hi1[v];
+                }
+            }
+        }
+        if (col && badc) a.bad[mem] = 1;
+        if (a.want_rate) {
+            const double m = block_max(col ? rmax : 0.0, sred);
+            if (tid == 0) a.rate[slot] = m;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ghost slabs: inner boundary (wind + cone CME), restriction, prolongation
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, const int *range)
+{
+    using S = Shape<BI, BJ, BK>;
+    const int t0 = range[0], t1 = range[1];
+    const Gas gs = a.gas;
+    for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+        const SlabTask tk = tasks[it];
+        const BlockDesc bd = a.desc[tk.slot];
+        const int d = tk.face >> 1, side = tk.face & 1;
+        const int e1 = tan1(d), e2 = tan2(d);
+        const int FA = S::dim(e1), FB = S::dim(e2);
+        const int Bd = S::dim(d);
+        const int ncell = 2 * FA * FB;
+        const LevelGeo lg = a.geo[bd.level];
+        double *out = a.slabs + (size_t)tk.slab * a.slab_stride;
+        const int mem = bd.member;
+        for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
+            const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
+            int g[3];                               // owner-level global index (unwrapped)
+            g[d] = side ? bd.org[d] + Bd + l : bd.org[d] - 2 + l;
+            g[e1] = bd.org[e1] + ia;
+            g[e2] = bd.org[e2] + ib;
+            double u[8];
+            if (tk.type == SLAB_INNER) {
+                const int jt = g[1], kp = g[2];
+                const int nt = lg.n[1], np = lg.n[2];
+                const size_t o = (size_t)jt * np + kp;
+                const size_t pl = (size_t)nt * np;
+                double w[8];
+                w[0] = lg.wind[0 * pl + o];
+                w[1] = lg.wind[1 * pl + o];
+                w[2] = 0.0;
+                w[3] = lg.wind[2 * pl + o];
+                w[4] = lg.wind[3 * pl + o];
+                w[5] = lg.wind[4 * pl + o];
+                w[6] = 0.0;
+                w[7] = lg.wind[5 * pl + o];
+                const MemberConst mc = a.mc[mem];
+                if (mc.enabled) {
+                    const double ts = a.t[mem] + a.tfrac * a.dt[mem];
+                    const double tau = ts - mc.t0;
+                    if (tau >= 0.0 && tau <= mc.tact) {
+                        const double R = mc.r_in;
+                        const double Rc = tau * mc.v + R - mc.r_half;
+                        double arg = (Rc * Rc + R * R - mc.r_half * mc.r_half) / (2.0 * Rc * R);
+                        arg = arg > 1.0 ? 1.0 : (arg < -1.0 ? -1.0 : arg);
+                        double cd = lg.cosd[(size_t)mem * pl + o];
+                        cd = cd > 1.0 ? 1.0 : (cd < -1.0 ? -1.0 : cd);
+                        if (cd >= arg) {
+                            w[0] = mc.rho;
+                            w[1] = mc.v;
+                            w[4] = mc.p;
+                        }
+                    }
+                }
+                prim_to_cons(w, u, gs);
+            } else if (tk.type == SLAB_RESTRICT) {
+                const LevelGeo fg = a.geo[bd.level + 1];
+                double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
+                int gw[3];
+                for (int e = 0; e < 3; ++e) gw[e] = g[e] + tk.shift[e];
+                for (int o = 0; o < 8; ++o) {
+                    const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+                    int fgi[3], fl[3], q[3];
+                    for (int e = 0; e < 3; ++e) {
+                        fgi[e] = 2 * gw[e] + oo[e];
+                        const int fb = fgi[e] / S::dim(e);
+                        q[e] = fb - tk.fbase[e];
+                        fl[e] = fgi[e] - fb * S::dim(e);
+                    }
+                    const int fslot = tk.src[q[e1] + 2 * q[e2]];
+                    const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
+                    for (int v = 0; v < 8; ++v)
+                        num[v] += wgt * a.U[cidx<S>(fslot, v, fl[0], fl[1], fl[2])];
+                    den += wgt;
+                }
+                for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
+            } else {                                 // SLAB_PROLONG
+                const LevelGeo cg = a.geo[bd.level - 1];
+                const int cs = tk.src[0];
+                int cl[3], cw[3];
+                for (int e = 0; e < 3; ++e) {
+                    const int c2 = g[e] >= 0 ? g[e] / 2 : -((-g[e] + 1) / 2);   // floor(g/2)
+                    cl[e] = c2 + tk.shift[e];
+                    cw[e] = c2 + tk.cwrap[e];
+                }
+                const double poff[3] = {lg.r[g[0] + 2].poff, lg.t[g[1] + 2].poff, lg.p[g[2] + 2].poff};
+                const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
+                const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
+                for (int v = 0; v < 8; ++v) {
+                    const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, cl[0], cl[1], cl[2]);
+                    double val = uc;
+                    for (int e = 0; e < 3; ++e) {
+                        int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
+                        lm[e] -= 1;
+                        lp[e] += 1;
+                        const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lm[0], lm[1], lm[2]);
+                        const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lp[0], lp[1], lp[2]);
+                        const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
+                        const double s = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+                        val += s * poff[e];
+                    }
+                    u[v] = val;
+                }
+            }
+            for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reflux at coarse-fine faces, then the CFL rate of the corrected blocks
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__device__ inline double cell_rate(const double u[8], const RecR &rr, const RecT &tt, const RecP &pp, const Gas &gs)
+{
+    double w[8];
+    cons_to_prim(u, w, gs);
+    return (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
+         + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
+         + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pp.iw;
+}
+
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks)
+{
+    using S = Shape<BI, BJ, BK>;
+    __shared__ double sred[NT / 64];
+    const int nb = *nblocks;
+    for (int it = blockIdx.x; it < nb; it += gridDim.x) {
+        const int t0 = blocks[2 * it], t1 = blocks[2 * it + 1];
+        const int slot = tasks[t0].slot;
+        const BlockDesc bd = a.desc[slot];
+        const double dt = a.dt[bd.member];
+        if (dt <= 0.0) continue;
+        const double adt = a.alpha * dt;
+        const LevelGeo lg = a.geo[bd.level], fg = a.geo[bd.level + 1];
+        for (int q = t0; q < t1; ++q) {
+            const RefluxTask tk = tasks[q];
+            const int d = tk.face >> 1, side = tk.face & 1;
+            const int e1 = tan1(d), e2 = tan2(d);
+            const int FA = S::dim(e1), FB = S::dim(e2);
+            for (int c = threadIdx.x; c < FA * FB; c += blockDim.x) {
+                const int ia = c % FA, ib = c / FA;
+                int loc[3];
+                loc[d] = side ? S::dim(d) - 1 : 0;
+                loc[e1] = ia;
+                loc[e2] = ib;
+                int g[3];
+                for (int e = 0; e < 3; ++e) g[e] = bd.org[e] + loc[e];
+                const RecR rr = lg.r[g[0] + 2];
+                const RecT tt = lg.t[g[1] + 2];
+                const RecP pp = lg.p[g[2] + 2];
+                const double Vc = rr.vw * tt.vw * pp.vw;
+                double ac;
+                if (d == 0) ac = side ? rr.ap : rr.am;
+                else if (d == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
+                else ac = rr.rt * tt.phf * pp.iw;
+                // fine face index along d (global, fine level) and fine tangential cells
+                const int gf = 2 * (bd.org[d] + (side ? S::dim(d) : 0));
+                double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                for (int ob = 0; ob < 2; ++ob) {
+                    for (int oa = 0; oa < 2; ++oa) {
+                        const int fa = 2 * ia + oa, fb = 2 * ib + ob;
+                        const int qa = fa / FA, qb = fb / FB;
+                        const int reg = tk.freg[qa + 2 * qb];
+                        int fgl[3];
+                        fgl[d] = gf;
+                        fgl[e1] = 2 * g[e1] + oa;
+                        fgl[e2] = 2 * g[e2] + ob;
+                        double A;
+                        if (d == 0) A = fg.r[fgl[0] + 2].r2f * fg.t[fgl[1] + 2].vw * fg.p[fgl[2] + 2].vw;
+                        else if (d == 1) A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].sf * fg.p[fgl[2] + 2].vw;
+                        else A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].dth;
+                        const double *F = a.freg + (size_t)reg * a.reg_stride;
+                        const int la = fa - qa * FA, lb = fb - qb * FB;
+                        for (int v = 0; v < 8; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
+                    }
+                }
+                const double *Fc = a.freg + (size_t)tk.creg * a.reg_stride;
+                for (int v = 0; v < 8; ++v) {
+                    const double corr = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
+                    const size_t o = cidx<S>(slot, v, loc[0], loc[1], loc[2]);
+                    a.Uout[o] += side ? adt * corr : -adt * corr;
+                }
+            }
+            __syncthreads();
+        }
+        // floors on the corrected cells (each once, after all its faces)
+        for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
+            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+            const int mk = bd.reflux_mask;
+            const bool rf = (i == 0 && (mk & 1)) || (i == BI - 1 && (mk & 2)) || (j == 0 && (mk & 4))
+                         || (j == BJ - 1 && (mk & 8)) || (k == 0 && (mk & 16)) || (k == BK - 1 && (mk & 32));
+            if (!rf) continue;
+            double u[8];
+            for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
+            apply_floors(u, a.gas, a.rho_floor, a.p_floor);
+            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];
+        }
+        __syncthreads();
+        if (a.want_rate) {
+            double rmax = 0.0;
+            for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
+                const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+                double u[8];
+                for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
+                const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
+                                                       lg.p[bd.org[2] + k + 2], a.gas);
+                rmax = r > rmax ? r : rmax;
+            }
+            const double m = block_max(rmax, sred);
+            if (threadIdx.x == 0) a.rate[slot] = m;
+        }
+    }
+}
+
+// CFL rate of every leaf (after create, set_state, regrid)
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_rate(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    __shared__ double sred[NT / 64];
+    const int n = *a.nitems;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = a.items[it];
+        const BlockDesc bd = a.desc[slot];
+        const LevelGeo lg = a.geo[bd.level];
+        double rmax = 0.0;
+        bool bad = false;
+        for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
+            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+            double u[8], w[8];
+            for (int v = 0; v < 8; ++v) u[v] = a.U[cidx<S>(slot, v, i, j, k)];
+            cons_to_prim(u, w, a.gas);
+            bad = bad || unphysical(w);
+            const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
+                                                   lg.p[bd.org[2] + k + 2], a.gas);
+            rmax = r > rmax ? r : rmax;
+        }
+        if (bad) a.bad[bd.member] = 1;
+        const double m = block_max(rmax, sred);
+        if (threadIdx.x == 0) a.rate[slot] = m;
+    }
+}
+
+// dt per member = cfl / max rate over its leaves (or a fixed dt), clipped to t_end
+__global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, double cfl,
+                     double dt_fixed, const double *tend, double *dt_last)
+{
+    __shared__ double sred[NT / 64];
+    for (int m = blockIdx.x; m < nmembers; m += gridDim.x) {
+        double r = 0.0;
+        for (int q = mbeg[m] + threadIdx.x; q < mend[m]; q += blockDim.x) {
+            const double x = a.rate[a.items[q]];
+            r = x > r ? x : r;
+        }
+        const double mx = block_max(r, sred);
+        if (threadIdx.x == 0) {
+            double dt = dt_fixed > 0.0 ? dt_fixed : (mx > 0.0 ? cfl / mx : 0.0);
+            const double left = tend[m] - a.t[m];
+            if (dt > left) dt = left;
+            if (!(dt > 0.0)) dt = 0.0;
+            ((double *)a.dt)[m] = dt;
+            if (dt > 0.0) dt_last[m] = dt;
+        }
+    }
+}
+
+__global__ void k_time(double *t, const double *dt, long *nsteps, int nmembers)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < nmembers && dt[m] > 0.0) {
+        t[m] += dt[m];
+        nsteps[m] += 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// refinement indicator: Loehner(rho, |v|) with div V < 0 inside the windows
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int max_level, double eps,
+                                                  double tol_r, double tol_c, double w_rho, double w_v,
+                                                  int use_windows, double lon_e, double clt_e,
+                                                  double dlon_e, double dclt_e, double dlon_c)
+{
+    using S = Shape<BI, BJ, BK>;
+    const int n = *a.nitems;
+    const double PI = 3.14159265358979323846;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = a.items[it];
+        const BlockDesc bd = a.desc[slot];
+        const LevelGeo lg = a.geo[bd.level];
+        const double lon_c = a.mc[bd.member].lon_cme;
+        const int cme_on = a.mc[bd.member].enabled;
+        int hot_r = 0, hot_c = 0;
+        for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
+            const int ijk[3] = {c % BI, (c / BI) % BJ, c / (BI * BJ)};
+            const RecR rr = lg.r[bd.org[0] + ijk[0] + 2];
+            const RecT tt = lg.t[bd.org[1] + ijk[1] + 2];
+            const RecP pp = lg.p[bd.org[2] + ijk[2] + 2];
+            bool win = true;
+            if (use_windows && !a.cart) {
+                auto wrap = [&](double x) {
+                    double y = x - 2.0 * PI * floor((x + PI) / (2.0 * PI));
+                    return y == -PI ? PI : y;
+                };
+                win = fabs(wrap(pp.pc - lon_e)) <= dlon_e && fabs(tt.tc - clt_e) <= dclt_e;
+                if (cme_on) win = win && fabs(wrap(pp.pc - lon_c)) <= dlon_c;
+            }
+            double u[8], w0[8];
+            ghosted8<S>(a, a.U, slot, ijk[0], ijk[1], ijk[2], u);
+            cons_to_prim(u, w0, a.gas);
+            const double r0 = w0[0];
+            const double s0 = sqrt(w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]);
+            double num_r = 0, den_r = 0, num_v = 0, den_v = 0, dv = 0;
+            for (int d = 0; d < 3; ++d) {
+                int lo[3] = {ijk[0], ijk[1], ijk[2]}, hi[3] = {ijk[0], ijk[1], ijk[2]};
+                lo[d] -= 1;
+                hi[d] += 1;
+                double wl[8], wh[8];
+                ghosted8<S>(a, a.U, slot, lo[0], lo[1], lo[2], u);
+                cons_to_prim(u, wl, a.gas);
+                ghosted8<S>(a, a.U, slot, hi[0], hi[1], hi[2], u);
+                cons_to_prim(u, wh, a.gas);
+                const double rl = wl[0], rh = wh[0];
+                const double sl = sqrt(wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
+                const double sh = sqrt(wh[1] * wh[1] + wh[2] * wh[2] + wh[3] * wh[3]);
+                double q = rh - 2.0 * r0 + rl;
+                num_r += q * q;
+                q = fabs(rh - r0) + fabs(r0 - rl) + eps * (fabs(rh) + 2.0 * fabs(r0) + fabs(rl));
+                den_r += q * q;
+                q = sh - 2.0 * s0 + sl;
+                num_v += q * q;
+                q = fabs(sh - s0) + fabs(s0 - sl) + eps * (fabs(sh) + 2.0 * fabs(s0) + fabs(sl));
+                den_v += q * q;
+                const double vl = 0.5 * (wl[1 + d] + w0[1 + d]);
+                const double vh = 0.5 * (w0[1 + d] + wh[1 + d]);
+                double am, ap;
+                if (d == 0) { am = rr.am; ap = rr.ap; }
+                else if (d == 1) { am = rr.rt * tt.thm; ap = rr.rt * tt.thp; }
+                else { am = ap = rr.rt * tt.phf * pp.iw; }
+                dv += ap * vh - am * vl;
+            }
+            const double E = w_rho * (den_r > 0.0 ? sqrt(num_r / den_r) : 0.0)
+                           + w_v * (den_v > 0.0 ? sqrt(num_v / den_v) : 0.0);
+            if (win && dv < 0.0) {
+                if (E > tol_r) hot_r = 1;
+                if (E > tol_c) hot_c = 1;
+            }
+        }
+        hot_r = __syncthreads_or(hot_r);
+        hot_c = __syncthreads_or(hot_c);
+        if (threadIdx.x == 0) {
+            int8_t f = 0;
+            if (bd.level < max_level && hot_r) f = 1;
+            else if (bd.level > 1 && !hot_c) f = -1;
+            flags[slot] = f;
+        }
+    }
+}
+#pragma clang fp contract(fast)
+
+// ---------------------------------------------------------------------------
+// regrid data movement: prolong new children, restrict new parents
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTask *tasks, int ntasks)
+{
+    using S = Shape<BI, BJ, BK>;
+    for (int it = blockIdx.x; it < ntasks; it += gridDim.x) {
+        const MoveTask tk = tasks[it];
+        const LevelGeo lg = a.geo[tk.level];
+        for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
+            const int loc[3] = {c % BI, (c / BI) % BJ, c / (BI * BJ)};
+            int g[3];
+            for (int e = 0; e < 3; ++e) g[e] = tk.org[e] + loc[e];
+            if (tk.type == MOVE_PROLONG) {
+                const int ps = tk.src[0];
+                const BlockDesc pd = a.desc[ps];
+                const LevelGeo cg = a.geo[tk.level - 1];
+                int cl[3], cw[3];
+                for (int e = 0; e < 3; ++e) {
+                    cw[e] = g[e] >> 1;
+                    cl[e] = cw[e] - pd.org[e];
+                }
+                const double poff[3] = {lg.r[g[0] + 2].poff, lg.t[g[1] + 2].poff, lg.p[g[2] + 2].poff};
+                const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
+                const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
+                for (int v = 0; v < 8; ++v) {
+                    const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, cl[0], cl[1], cl[2]);
+                    double val = uc;
+                    for (int e = 0; e < 3; ++e) {
+                        int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
+                        lm[e] -= 1;
+                        lp[e] += 1;
+                        const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, lm[0], lm[1], lm[2]);
+                        const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, lp[0], lp[1], lp[2]);
+                        const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
+                        const double s = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+                        val += s * poff[e];
+                    }
+                    Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = val;
+                }
+            } else {
+                const LevelGeo fg = a.geo[tk.level + 1];
+                double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
+                for (int o = 0; o < 8; ++o) {
+                    const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+                    int fl[3], oct = 0, fgi[3];
+                    for (int e = 0; e < 3; ++e) {
+                        const int x = 2 * loc[e] + oo[e];
+                        const int q = x / S::dim(e);
+                        oct |= q << e;
+                        fl[e] = x - q * S::dim(e);
+                        fgi[e] = 2 * g[e] + oo[e];
+                    }
+                    const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
+                    for (int v = 0; v < 8; ++v) num[v] += wgt * a.U[cidx<S>(tk.src[oct], v, fl[0], fl[1], fl[2])];
+                    den += wgt;
+                }
+                for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = num[v] / den;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// point sampling (trilinear between cell centres), one work-group per member
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
+                         int *ring_count, int ring_cap, int record)
+{
+    using S = Shape<BI, BJ, BK>;
+    const int m = blockIdx.x;
+    if (m >= nmembers || threadIdx.x != 0) return;
+    const SampleDesc s = sd[m];
+    if (!s.valid) return;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 8; ++q) {
+        const SampleEntry e = s.e[q];
+        double u[8];
+        if (e.kind == 0) {
+            for (int v = 0; v < 8; ++v) u[v] = a.U[cidx<S>(e.slot, v, e.cell[0], e.cell[1], e.cell[2])];
+        } else {
+            const LevelGeo fg = a.geo[e.level];
+            double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
+            for (int o = 0; o < 8; ++o) {
+                const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+                const double wgt = fg.r[e.g[0] + oo[0] + 2].vw * fg.t[e.g[1] + oo[1] + 2].vw * fg.p[e.g[2] + oo[2] + 2].vw;
+                for (int v = 0; v < 8; ++v)
+                    num[v] += wgt * a.U[cidx<S>(e.slot, v, e.cell[0] + oo[0], e.cell[1] + oo[1], e.cell[2] + oo[2])];
+                den += wgt;
+            }
+            for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
+        }
+        double w[8];
+        cons_to_prim(u, w, a.gas);
+        for (int v = 0; v < 8; ++v) acc[v] += e.w * w[v];
+    }
+    for (int v = 0; v < 8; ++v) out[m * 8 + v] = acc[v];
+    if (record) {
+        const int c = ring_count[m];
+        double *r = ring + ((size_t)m * ring_cap + (c % ring_cap)) * 9;
+        r[0] = a.t[m];
+        for (int v = 0; v < 8; ++v) r[1 + v] = acc[v];
+        ring_count[m] = c + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// instantiations for the supported block shapes
+// ---------------------------------------------------------------------------
+#define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
+    template __global__ void k_stage<BI, BJ, BK>(KArgs);                                           \
+    template __global__ void k_slabs<BI, BJ, BK>(KArgs, const SlabTask *, const int *);            \
+    template __global__ void k_reflux<BI, BJ, BK>(KArgs, const RefluxTask *, const int *, const int *); \
+    template __global__ void k_rate<BI, BJ, BK>(KArgs);                                            \
+    template __global__ void k_indicator<BI, BJ, BK>(KArgs, int8_t *, int, double, double, double, \
+                                                     double, double, int, double, double, double,  \
+                                                     double, double);                              \
+    template __global__ void k_move<BI, BJ, BK>(KArgs, double *, const MoveTask *, int);           \
+    template __global__ void k_sample<BI, BJ, BK>(KArgs, const SampleDesc *, int, double *, double *, \
+                                                  int *, int, int);
+
+#include "shapes.inc"
+#undef IC_INSTANTIATE
+
+// ---------------------------------------------------------------------------
+// launchers (kernels are launched from this translation unit)
+// ---------------------------------------------------------------------------
+namespace {
+template <int BI, int BJ, int BK>
+struct L {
+    static void stage(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_stage<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r)
+    {
+        hipLaunchKernelGGL((k_slabs<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, r);
+    }
+    static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *b, const int *n)
+    {
+        hipLaunchKernelGGL((k_reflux<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, b, n);
+    }
+    static void rate(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_rate<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void indicator(dim3 g, hipStream_t s, const KArgs &a, int8_t *f, const IndicatorParams &p)
+    {
+        hipLaunchKernelGGL((k_indicator<BI, BJ, BK>), g, dim3(NT), 0, s, a, f, p.max_level, p.eps, p.tol_r,
+                           p.tol_c, p.w_rho, p.w_v, p.use_windows, p.lon_e, p.clt_e, p.dlon_e, p.dclt_e,
+                           p.dlon_c);
+    }
+    static void move(dim3 g, hipStream_t s, const KArgs &a, double *Un, const MoveTask *t, int n)
+    {
+        hipLaunchKernelGGL((k_move<BI, BJ, BK>), g, dim3(NT), 0, s, a, Un, t, n);
+    }
+    static void sample(dim3 g, hipStream_t s, const KArgs &a, const SampleDesc *sd, int nm, double *out,
+                       double *ring, int *cnt, int cap, int rec)
+    {
+        hipLaunchKernelGGL((k_sample<BI, BJ, BK>), g, dim3(64), 0, s, a, sd, nm, out, ring, cnt, cap, rec);
+    }
+};
+}  // namespace
+
+bool get_launchers(int bi, int bj, int bk, Launchers *out)
+{
+#define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
+    if (bi == BI && bj == BJ && bk == BK) {                                                        \
+        *out = Launchers{&L<BI, BJ, BK>::stage, &L<BI, BJ, BK>::slabs, &L<BI, BJ, BK>::reflux,     \
+                         &L<BI, BJ, BK>::rate, &L<BI, BJ, BK>::indicator, &L<BI, BJ, BK>::move,    \
+                         &L<BI, BJ, BK>::sample};                                                  \
+        return true;                                                                               \
+    }
+#include "shapes.inc"
+#undef IC_INSTANTIATE
+    return false;
+}
+
+void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, int nm, double cfl,
+               double dt_fixed, const double *tend, double *dt_last)
+{
+    hipLaunchKernelGGL(k_dt, dim3(nm), dim3(NT), 0, s, a, mbeg, mend, nm, cfl, dt_fixed, tend, dt_last);
+}
+
+void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm)
+{
+    hipLaunchKernelGGL(k_time, dim3((nm + 63) / 64), dim3(64), 0, s, t, dt, nsteps, nm);
+}

@@ -1,0 +1,189 @@
+// physics.h -- pointwise ideal-MHD physics for the kernels (fp64).
+//
+// Variables: conserved u = (rho, m0, m1, m2, E, B0, B1, B2), primitive
+// w = (rho, v0, v1, v2, p, B0, B1, B2), mu0 = 1, E = p/(g-1) + rho v^2/2 + B^2/2.
+// Direction 0/1/2 = r/theta/phi (x/y/z in the cartesian test geometry).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define DEV __device__ __forceinline__
+
+struct Gas {
+    double g;       // adiabatic index
+    double gm1;     // g - 1
+    double igm1;    // 1 / (g - 1)
+};
+
+DEV void cons_to_prim(const double u[8], double w[8], const Gas &gs)
+{
+    const double ir = 1.0 / u[0];
+    w[0] = u[0];
+    w[1] = u[1] * ir;
+    w[2] = u[2] * ir;
+    w[3] = u[3] * ir;
+    const double kin = 0.5 * (u[1] * w[1] + u[2] * w[2] + u[3] * w[3]);
+    const double mag = 0.5 * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);
+    w[4] = gs.gm1 * (u[4] - kin - mag);
+    w[5] = u[5];
+    w[6] = u[6];
+    w[7] = u[7];
+}
+
+DEV void prim_to_cons(const double w[8], double u[8], const Gas &gs)
+{
+    const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
+    u[0] = w[0];
+    u[1] = w[0] * w[1];
+    u[2] = w[0] * w[2];
+    u[3] = w[0] * w[3];
+    u[4] = w[4] * gs.igm1 + 0.5 * w[0] * v2 + 0.5 * b2;
+    u[5] = w[5];
+    u[6] = w[6];
+    u[7] = w[7];
+}
+
+// Fast magnetosonic speed along direction D.
+template <int D>
+DEV double fast_speed(const double w[8], const Gas &gs)
+{
+    const double ir = 1.0 / w[0];
+    const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
+    const double gp = gs.g * w[4];
+    const double a = (gp + b2) * ir;
+    const double bn = w[5 + D];
+    double disc = a * a - 4.0 * gp * bn * bn * ir * ir;
+    disc = disc > 0.0 ? disc : 0.0;
+    return sqrt(0.5 * (a + sqrt(disc)));
+}
+
+DEV bool unphysical(const double w[8])
+{
+    // rho <= 0, p <= 0 or NaN (comparisons with NaN are false)
+    bool ok = (w[0] > 0.0) && (w[4] > 0.0);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) ok = ok && (fabs(w[v]) <= 1.7976931348623157e308);
+    return !ok;
+}
+
+// Local Lax-Friedrichs (Rusanov) flux along D between left state wl and right state wr.
+template <int D>
+DEV void rusanov(const double wl[8], const double wr[8], double f[8], const Gas &gs)
+{
+    const double vl2 = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
+    const double vr2 = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
+    const double bl2 = wl[5] * wl[5] + wl[6] * wl[6] + wl[7] * wl[7];
+    const double br2 = wr[5] * wr[5] + wr[6] * wr[6] + wr[7] * wr[7];
+    const double ptl = wl[4] + 0.5 * bl2;
+    const double ptr = wr[4] + 0.5 * br2;
+    const double El = wl[4] * gs.igm1 + 0.5 * wl[0] * vl2 + 0.5 * bl2;
+    const double Er = wr[4] * gs.igm1 + 0.5 * wr[0] * vr2 + 0.5 * br2;
+    const double vnl = wl[1 + D], vnr = wr[1 + D];
+    const double bnl = wl[5 + D], bnr = wr[5 + D];
+    const double vbl = wl[1] * wl[5] + wl[2] * wl[6] + wl[3] * wl[7];
+    const double vbr = wr[1] * wr[5] + wr[2] * wr[6] + wr[3] * wr[7];
+    // fast speeds
+    const double irl = 1.0 / wl[0], irr = 1.0 / wr[0];
+    const double gpl = gs.g * wl[4], gpr = gs.g * wr[4];
+    const double al = (gpl + bl2) * irl, ar = (gpr + br2) * irr;
+    double dl = al * al - 4.0 * gpl * bnl * bnl * irl * irl;
+    double dr = ar * ar - 4.0 * gpr * bnr * bnr * irr * irr;
+    dl = dl > 0.0 ? dl : 0.0;
+    dr = dr > 0.0 ? dr : 0.0;
+    const double cfl = sqrt(0.5 * (al + sqrt(dl)));
+    const double cfr = sqrt(0.5 * (ar + sqrt(dr)));
+    const double sl = fabs(vnl) + cfl, sr = fabs(vnr) + cfr;
+    const double c = sl > sr ? sl : sr;
+    const double hc = 0.5 * c;
+
+    const double ml = wl[0] * vnl, mr = wr[0] * vnr;
+    f[0] = 0.5 * (ml + mr) - hc * (wr[0] - wl[0]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double fl = ml * wl[1 + q] - bnl * wl[5 + q];
+        double fr = mr * wr[1 + q] - bnr * wr[5 + q];
+        if (q == D) {
+            fl += ptl;
+            fr += ptr;
+        }
+        f[1 + q] = 0.5 * (fl + fr) - hc * (wr[0] * wr[1 + q] - wl[0] * wl[1 + q]);
+    }
+    f[4] = 0.5 * ((El + ptl) * vnl - bnl * vbl + (Er + ptr) * vnr - bnr * vbr) - hc * (Er - El);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double fl = vnl * wl[5 + q] - bnl * wl[1 + q];
+        double fr = vnr * wr[5 + q] - bnr * wr[1 + q];
+        if (q == D) {
+            fl = 0.0;
+            fr = 0.0;
+        }
+        f[5 + q] = 0.5 * (fl + fr) - hc * (wr[5 + q] - wl[5 + q]);
+    }
+}
+
+// Monotonised-central slope on a non-uniform coordinate (reciprocal spacings given).
+DEV double mc_slope(double wm, double w0, double wp, double idm, double idp, double idc)
+{
+    const double dm = (w0 - wm) * idm;
+    const double dp = (wp - w0) * idp;
+    const double dc = (wp - wm) * idc;
+    const double a = fmin(fabs(dc), 2.0 * fmin(fabs(dm), fabs(dp)));
+    return (dm * dp <= 0.0) ? 0.0 : copysign(a, dc);
+}
+
+// Face values of a cell from its neighbours along one direction; falls back to
+// zero slope for all variables if a face density or pressure is not positive.
+DEV void reconstruct(const double wm[8], const double w0[8], const double wp[8], double idm,
+                     double idp, double idc, double hm, double hp, double lo[8], double hi[8])
+{
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double s = mc_slope(wm[v], w0[v], wp[v], idm, idp, idc);
+        lo[v] = w0[v] - s * hm;
+        hi[v] = w0[v] + s * hp;
+    }
+    if (!(lo[0] > 0.0 && hi[0] > 0.0 && lo[4] > 0.0 && hi[4] > 0.0)) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            lo[v] = w0[v];
+            hi[v] = w0[v];
+        }
+    }
+}
+
+// Geometric (hoop), frame (Coriolis, centrifugal) and gravity sources of a
+// cell in spherical geometry, added to acc.
+DEV void add_sources(const double w[8], double rt, double ctil, double rc, double sc, double cc,
+                     double om, double gm, double acc[8])
+{
+    const double rho = w[0], vr = w[1], vt = w[2], vp = w[3];
+    const double br = w[5], bt = w[6], bp = w[7];
+    const double ptot = w[4] + 0.5 * (br * br + bt * bt + bp * bp);
+    const double g = -gm / (rc * rc);
+    acc[1] += rt * (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp) + 2.0 * ptot)
+              + rho * (2.0 * om * sc * vp + om * om * rc * sc * sc) + rho * g;
+    acc[2] += rt * (-(rho * vr * vt - br * bt) + ctil * (rho * vp * vp - bp * bp + ptot))
+              + rho * (2.0 * om * cc * vp + om * om * rc * sc * cc);
+    acc[3] += -rt * ((rho * vp * vr - bp * br) + ctil * (rho * vp * vt - bp * bt))
+              - 2.0 * om * rho * (sc * vr + cc * vt);
+    acc[4] += rho * vr * g + rho * om * om * rc * sc * (vr * sc + vt * cc);
+    acc[6] += rt * (vr * bt - vt * br);
+    acc[7] += -rt * ((vp * br - bp * vr) + ctil * (vp * bt - bp * vt));
+}
+
+// Small-value floors on a conserved state: density first (velocity kept),
+// then pressure (energy raised).
+DEV void apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
+{
+    if (u[0] < rho_min) {
+        const double f = rho_min / u[0];
+        u[1] *= f;
+        u[2] *= f;
+        u[3] *= f;
+        u[0] = rho_min;
+    }
+    const double kin = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    const double mag = 0.5 * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);
+    const double p = gs.gm1 * (u[4] - kin - mag);
+    if (p < p_min) u[4] = p_min * gs.igm1 + kin + mag;
+}

@@ -1,0 +1,1707 @@
+// runtime.cpp -- host runtime and C ABI of the Icarus hot-path library.
+//
+// Owns the block forest of every member, the per-level metric tables, the
+// device pools and the task lists the kernels walk; builds neighbour, ghost
+// slab and reflux descriptors after every forest change; runs the two-stage
+// step (eagerly or as a replayed HIP graph) and the regrid.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/icarus.h"
+#include "kernels.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// constants and code units (length 1 AU, speed 1000 km/s)
+// ---------------------------------------------------------------------------
+constexpr double kAU = 1.495978707e11;
+constexpr double kV0 = 1.0e6;
+constexpr double kT0 = kAU / kV0;
+constexpr double kMP = 1.67262192e-27;
+constexpr double kKB = 1.380649e-23;
+constexpr double kRHO0 = kMP * 1.0e6;
+constexpr double kP0 = kRHO0 * kV0 * kV0;
+const double kMU0 = 4.0e-7 * M_PI;
+const double kB0 = std::sqrt(kMU0 * kP0);
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+    ic_status code;
+    Error(ic_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(x)                                                                                \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess)                                                                      \
+            throw Error(IC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+template <class T>
+struct DBuf {  // device buffer with a capacity in elements
+    T *p = nullptr;
+    size_t cap = 0;
+    void alloc(size_t n)
+    {
+        if (n <= cap) return;
+        if (p) HIPCHECK(hipFree(p));
+        p = nullptr;
+        cap = 0;
+        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
+            throw Error(IC_E_NOMEM, "device allocation failed");
+        cap = std::max<size_t>(n, 1);
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// real spherical harmonics l = 1..3, orthonormal, no Condon-Shortley phase
+// ---------------------------------------------------------------------------
+double harmonic_sum(const double *alm, double th, double ph)
+{
+    const double x = std::cos(th), s = std::sin(th);
+    auto P = [&](int l, int m) -> double {
+        if (l == 1) return m == 0 ? x : s;
+        if (l == 2) return m == 0 ? (3.0 * x * x - 1.0) / 2.0 : (m == 1 ? 3.0 * x * s : 3.0 * s * s);
+        switch (m) {
+        case 0: return (5.0 * x * x * x - 3.0 * x) / 2.0;
+        case 1: return 1.5 * (5.0 * x * x - 1.0) * s;
+        case 2: return 15.0 * x * s * s;
+        default: return 15.0 * s * s * s;
+        }
+    };
+    auto fact = [](int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; };
+    double f = 0.0;
+    int q = 0;
+    for (int l = 1; l <= 3; ++l)
+        for (int m = -l; m <= l; ++m, ++q) {
+            const int a = std::abs(m);
+            const double N = std::sqrt((2 * l + 1) / (4.0 * M_PI) * fact(l - a) / fact(l + a));
+            double y;
+            if (m == 0) y = N * P(l, 0);
+            else if (m > 0) y = std::sqrt(2.0) * N * P(l, a) * std::cos(a * ph);
+            else y = std::sqrt(2.0) * N * P(l, a) * std::sin(a * ph);
+            f += alm[q] * y;
+        }
+    return f;
+}
+
+// ---------------------------------------------------------------------------
+// forest keys
+// ---------------------------------------------------------------------------
+struct Key {
+    int l, i, j, k;
+    bool operator<(const Key &o) const
+    {
+        if (l != o.l) return l < o.l;
+        if (k != o.k) return k < o.k;
+        if (j != o.j) return j < o.j;
+        return i < o.i;
+    }
+    bool operator==(const Key &o) const { return l == o.l && i == o.i && j == o.j && k == o.k; }
+};
+
+uint64_t morton(int i, int j, int k)
+{
+    uint64_t key = 0;
+    for (int b = 0; b < 21; ++b) {
+        key |= (uint64_t)((i >> b) & 1) << (3 * b);
+        key |= (uint64_t)((j >> b) & 1) << (3 * b + 1);
+        key |= (uint64_t)((k >> b) & 1) << (3 * b + 2);
+    }
+    return key;
+}
+
+bool abi_order(const Key &a, const Key &b)
+{
+    if (a.l != b.l) return a.l < b.l;
+    return morton(a.i, a.j, a.k) < morton(b.i, b.j, b.k);
+}
+
+struct Member {
+    std::map<Key, int> leaves;     // leaf -> local slot
+    std::vector<int> free_slots;
+    ic_cme_cfg cme{};
+};
+
+struct HostLevel {
+    int n[3];
+    std::vector<RecR> r;
+    std::vector<RecT> t;
+    std::vector<RecP> p;
+    std::vector<double> f[3];      // faces, index m + 2
+    std::vector<double> wind;      // [6][nt][np]
+    std::vector<double> cosd;      // [member][nt][np]
+    DBuf<RecR> dr;
+    DBuf<RecT> dt;
+    DBuf<RecP> dp;
+    DBuf<double> dwind, dcosd;
+};
+
+int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the sim
+// ---------------------------------------------------------------------------
+struct ic_sim {
+    ic_grid_cfg grid{};
+    ic_phys_cfg phys{};
+    ic_wind_cfg wind{};
+    ic_amr_cfg amr{};
+    int nm = 1;
+    int B[3] = {0, 0, 0};
+    int NC = 0;
+    int nb[3] = {0, 0, 0};         // base blocks per direction
+    int max_blocks = 0;
+    int max_level = 1;
+    bool periodic[3] = {false, false, false};
+    bool cart = false;
+    double r_in = 0.1;
+    double omega_code = 0.0, gm_code = 0.0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Launchers L{};
+    bool poisoned = false;
+
+    std::vector<HostLevel> lv;     // index = level, 1..max_level
+    std::vector<Member> mem;
+
+    // device state
+    DBuf<double> U, Us, slabs, freg;
+    DBuf<BlockDesc> desc;
+    DBuf<LevelGeo> geo;
+    DBuf<MemberConst> mc;
+    DBuf<int> items, nitems, mbeg, mend;
+    DBuf<double> dt, t, tend, dt_last, rate;
+    DBuf<int> bad;
+    DBuf<long> nsteps;
+    DBuf<SlabTask> slab_tasks;
+    DBuf<int> slab_ranges;        // [2 * (IC_MAX_LEVEL + 2)]
+    DBuf<RefluxTask> rf_tasks;
+    DBuf<int> rf_blocks, rf_nblocks;
+    DBuf<int8_t> flags;
+    DBuf<MoveTask> moves;
+    DBuf<SampleDesc> sdesc;
+    DBuf<double> sout, ring;
+    DBuf<int> ring_count;
+    int ring_cap = 1 << 16;
+    long slab_stride = 0, reg_stride = 0;
+
+    // host mirrors of the task lists
+    int n_items = 0;
+    int n_slabs = 0, n_regs = 0, n_rf_blocks = 0;
+    int pass_lo[IC_MAX_LEVEL + 2] = {0}, pass_hi[IC_MAX_LEVEL + 2] = {0};
+    bool any_prolong = false, any_reflux = false;
+    std::vector<BlockDesc> hdesc;
+    double zone_updates = 0.0;
+    long host_steps = 0;
+    double sample_point[3] = {1.0, 90.0, 0.0};
+
+    // graph
+    hipGraphExec_t gexec = nullptr;
+    bool graph_dirty = true;
+    double graph_dt_fixed = -1.0;
+    bool use_graph = true;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // pairs
+    long timed = 0;
+
+    int slot_of(int m, int local) const { return m * max_blocks + local; }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// geometry tables (host, fp64)
+// ---------------------------------------------------------------------------
+void build_level(ic_sim *s, int l)
+{
+    HostLevel &L = s->lv[l];
+    const int fac = 1 << (l - 1);
+    for (int d = 0; d < 3; ++d) L.n[d] = s->grid.n[d] * fac;
+    const double deg = M_PI / 180.0;
+    for (int d = 0; d < 3; ++d) {
+        const int n = L.n[d];
+        std::vector<double> &f = L.f[d];
+        f.assign(n + 5, 0.0);
+        double x0 = s->grid.x0[d], x1 = s->grid.x1[d];
+        if (!s->cart && d > 0) {
+            x0 = x0 * deg;
+            x1 = x1 * deg;
+        }
+        if (!s->cart && d == 0 && s->grid.stretched_r) {
+            const double lg = std::log(x1 / x0);
+            for (int m = -2; m <= n + 2; ++m) f[m + 2] = x0 * std::exp(m * (lg / n));
+        } else {
+            const double h = (x1 - x0) / n;
+            for (int m = -2; m <= n + 2; ++m) f[m + 2] = x0 + m * h;
+        }
+        f[2] = x0;
+        f[n + 2] = x1;
+    }
+    auto xc = [&](int d, int m) { return 0.5 * (L.f[d][m + 2] + L.f[d][m + 3]); };
+    auto fc = [&](int d, int m) { return L.f[d][m + 2]; };
+    auto lim = [&](int d, int m, double &idm, double &idp, double &idc, double &hm, double &hp) {
+        const int n = L.n[d];
+        const double x = xc(d, m);
+        idm = m - 1 >= -2 ? 1.0 / (x - xc(d, m - 1)) : 0.0;
+        idp = m + 1 <= n + 1 ? 1.0 / (xc(d, m + 1) - x) : 0.0;
+        idc = (m - 1 >= -2 && m + 1 <= n + 1) ? 1.0 / (xc(d, m + 1) - xc(d, m - 1)) : 0.0;
+        hm = x - fc(d, m);
+        hp = fc(d, m + 1) - x;
+    };
+    auto vw = [&](int d, int m) {
+        const double a = fc(d, m), b = fc(d, m + 1);
+        if (s->cart) return b - a;
+        if (d == 0) return (b * b * b - a * a * a) / 3.0;
+        if (d == 1) return std::cos(a) - std::cos(b);
+        return b - a;
+    };
+    auto poff = [&](int d, int m) {
+        const int c = floordiv(m, 2);
+        const int c0 = 2 * c, c1 = 2 * c + 1;
+        const double w0 = vw(d, c0), w1 = vw(d, c1);
+        const double xbar = (w0 * xc(d, c0) + w1 * xc(d, c1)) / (w0 + w1);
+        return xc(d, m) - xbar;
+    };
+    // radial
+    L.r.assign(L.n[0] + 4, RecR{});
+    for (int m = -2; m < L.n[0] + 2; ++m) {
+        RecR &R = L.r[m + 2];
+        lim(0, m, R.idm, R.idp, R.idc, R.hm, R.hp);
+        const double a = fc(0, m), b = fc(0, m + 1);
+        R.rc = xc(0, m);
+        R.icfl = 1.0 / (b - a);
+        R.vw = vw(0, m);
+        R.poff = poff(0, m);
+        if (s->cart) {
+            R.am = R.ap = 1.0 / (b - a);
+            R.rt = 1.0;
+            R.irc = 1.0;
+            R.r2f = 1.0;
+            R.r2h = b - a;
+        } else {
+            const double dr3 = b * b * b - a * a * a;
+            R.am = 3.0 * a * a / dr3;
+            R.ap = 3.0 * b * b / dr3;
+            R.rt = 1.5 * (b * b - a * a) / dr3;
+            R.irc = 1.0 / R.rc;
+            R.r2f = a * a;
+            R.r2h = 0.5 * (b * b - a * a);
+        }
+    }
+    // colatitude
+    L.t.assign(L.n[1] + 4, RecT{});
+    for (int m = -2; m < L.n[1] + 2; ++m) {
+        RecT &T = L.t[m + 2];
+        lim(1, m, T.idm, T.idp, T.idc, T.hm, T.hp);
+        const double a = fc(1, m), b = fc(1, m + 1);
+        T.tc = xc(1, m);
+        T.icfl = 1.0 / (b - a);
+        T.vw = vw(1, m);
+        T.poff = poff(1, m);
+        if (s->cart) {
+            T.thm = T.thp = 1.0 / (b - a);
+            T.ctil = 0.0;
+            T.sinc = 1.0;
+            T.cosc = 0.0;
+            T.phf = 1.0;
+            T.isinc = 1.0;
+            T.sf = 1.0;
+            T.dth = b - a;
+        } else {
+            const double dmu = std::cos(a) - std::cos(b);
+            T.thm = std::sin(a) / dmu;
+            T.thp = std::sin(b) / dmu;
+            T.ctil = (std::sin(b) - std::sin(a)) / dmu;
+            T.sinc = std::sin(T.tc);
+            T.cosc = std::cos(T.tc);
+            T.phf = (b - a) / dmu;
+            T.isinc = 1.0 / T.sinc;
+            T.sf = std::sin(a);
+            T.dth = b - a;
+        }
+    }
+    // longitude
+    L.p.assign(L.n[2] + 4, RecP{});
+    for (int m = -2; m < L.n[2] + 2; ++m) {
+        RecP &P = L.p[m + 2];
+        lim(2, m, P.idm, P.idp, P.idc, P.hm, P.hp);
+        const double a = fc(2, m), b = fc(2, m + 1);
+        P.iw = 1.0 / (b - a);
+        P.vw = b - a;
+        P.poff = poff(2, m);
+        P.pc = xc(2, m);
+    }
+    // inner-boundary wind at this level's (theta, phi) centres
+    const int nt = L.n[1], np = L.n[2];
+    L.wind.assign((size_t)6 * nt * np, 0.0);
+    L.cosd.assign((size_t)s->nm * nt * np, -2.0);
+    if (!s->cart) {
+        const ic_wind_cfg &w = s->wind;
+        const double Bmag = w.B_nT * 1.0e-9 / kB0;
+        for (int j = 0; j < nt; ++j)
+            for (int k = 0; k < np; ++k) {
+                const double th = L.t[j + 2].tc, ph = L.p[k + 2].pc;
+                double vk;
+                if (w.f_max <= w.f_min) {
+                    vk = w.v_min_kms;
+                } else {
+                    const double f = harmonic_sum(w.alm, th, ph);
+                    vk = w.v_min_kms + (w.v_max_kms - w.v_min_kms) * (f - w.f_min) / (w.f_max - w.f_min);
+                    vk = std::min(std::max(vk, w.v_min_kms), w.v_max_kms);
+                }
+                const double n = w.n_ref_cm3 * std::pow(vk / w.v_ref_kms, -2.0);
+                const double vr = vk * 1.0e3 / kV0;
+                const double vp = -s->omega_code * s->r_in * std::sin(th);
+                const double br = Bmag / std::sqrt(1.0 + (vp / vr) * (vp / vr));
+                const double bp = br * vp / vr;
+                const size_t o = (size_t)j * np + k, pl = (size_t)nt * np;
+                L.wind[0 * pl + o] = n * 1.0e6 * kMP / kRHO0;
+                L.wind[1 * pl + o] = vr;
+                L.wind[2 * pl + o] = vp;
+                L.wind[3 * pl + o] = 2.0 * n * 1.0e6 * kKB * w.T_K / kP0;
+                L.wind[4 * pl + o] = br;
+                L.wind[5 * pl + o] = bp;
+                for (int m = 0; m < s->nm; ++m) {
+                    const ic_cme_cfg &c = s->mem[m].cme;
+                    const double tc = c.colat_deg * deg, pc = c.lon_deg * deg;
+                    L.cosd[(size_t)m * pl + o] =
+                        std::sin(th) * std::sin(tc) * std::cos(ph - pc) + std::cos(th) * std::cos(tc);
+                }
+            }
+    }
+    L.dr.alloc(L.r.size());
+    L.dt.alloc(L.t.size());
+    L.dp.alloc(L.p.size());
+    L.dwind.alloc(L.wind.size());
+    L.dcosd.alloc(L.cosd.size());
+    HIPCHECK(hipMemcpy(L.dr.p, L.r.data(), L.r.size() * sizeof(RecR), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dt.p, L.t.data(), L.t.size() * sizeof(RecT), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dp.p, L.p.data(), L.p.size() * sizeof(RecP), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dwind.p, L.wind.data(), L.wind.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(L.dcosd.p, L.cosd.data(), L.cosd.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// descriptors and task lists after a forest change
+// ---------------------------------------------------------------------------
+int nblocks_at(const ic_sim *s, int l, int d) { return s->nb[d] << (l - 1); }
+
+bool wrap_idx(const ic_sim *s, int l, int idx[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        const int n = nblocks_at(s, l, d);
+        if (idx[d] < 0 || idx[d] >= n) {
+            if (!s->periodic[d]) return false;
+            idx[d] = ((idx[d] % n) + n) % n;
+        }
+    }
+    return true;
+}
+
+void rebuild(ic_sim *s)
+{
+    HIPCHECK(hipStreamSynchronize(s->stream));
+    const int NS = s->nm * s->max_blocks;
+    s->hdesc.assign(NS, BlockDesc{});
+    std::vector<int> items, mbeg(s->nm), mend(s->nm);
+    std::vector<SlabTask> pass1;
+    std::vector<std::vector<SlabTask>> prol(IC_MAX_LEVEL + 2);
+    std::map<std::pair<int, int>, int> regs;     // (slot, face) -> register
+    auto get_reg = [&](int slot, int face) {
+        auto it = regs.find({slot, face});
+        if (it != regs.end()) return it->second;
+        const int r = (int)regs.size();
+        regs[{slot, face}] = r;
+        return r;
+    };
+    std::vector<RefluxTask> rf;
+    int nslab = 0;
+    for (int m = 0; m < s->nm; ++m) {
+        Member &M = s->mem[m];
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        mbeg[m] = (int)items.size();
+        for (const Key &key : keys) {
+            const int slot = s->slot_of(m, M.leaves[key]);
+            items.push_back(slot);
+            BlockDesc &bd = s->hdesc[slot];
+            bd.level = key.l;
+            bd.member = m;
+            const int bi[3] = {key.i, key.j, key.k};
+            for (int d = 0; d < 3; ++d) bd.org[d] = bi[d] * s->B[d];
+            bd.reflux_mask = 0;
+            for (int f = 0; f < 6; ++f) bd.freg[f] = -1;
+            for (int f = 0; f < 6; ++f) {
+                const int d = f >> 1, side = f & 1;
+                int nbi[3] = {bi[0], bi[1], bi[2]};
+                nbi[d] += side ? 1 : -1;
+                int w[3] = {nbi[0], nbi[1], nbi[2]};
+                if (!wrap_idx(s, key.l, w)) {
+                    const int kind = s->grid.bc[d][side];
+                    if (kind == IC_BC_INNER) {
+                        SlabTask tk{};
+                        tk.type = SLAB_INNER;
+                        tk.slab = nslab++;
+                        tk.slot = slot;
+                        tk.face = f;
+                        bd.nbr[f] = slab_code(tk.slab);
+                        pass1.push_back(tk);
+                    } else {
+                        bd.nbr[f] = NBR_OUTFLOW;
+                    }
+                    continue;
+                }
+                auto same = M.leaves.find(Key{key.l, w[0], w[1], w[2]});
+                if (same != M.leaves.end()) {
+                    bd.nbr[f] = s->slot_of(m, same->second);
+                    continue;
+                }
+                auto coarse = key.l > 1 ? M.leaves.find(Key{key.l - 1, w[0] >> 1, w[1] >> 1, w[2] >> 1})
+                                        : M.leaves.end();
+                if (coarse != M.leaves.end()) {
+                    const int cslot = s->slot_of(m, coarse->second);
+                    SlabTask tk{};
+                    tk.type = SLAB_PROLONG;
+                    tk.slab = nslab++;
+                    tk.slot = slot;
+                    tk.face = f;
+                    tk.src[0] = cslot;
+                    const int corg[3] = {coarse->first.i * s->B[0], coarse->first.j * s->B[1],
+                                         coarse->first.k * s->B[2]};
+                    for (int e = 0; e < 3; ++e) {
+                        int cw = 0;
+                        if (e == d && nbi[d] != w[d]) {
+                            const int nc = s->lv[key.l - 1].n[d];
+                            cw = side ? -nc : nc;
+                        }
+                        tk.cwrap[e] = cw;
+                        tk.shift[e] = cw - corg[e];
+                    }
+                    bd.nbr[f] = slab_code(tk.slab);
+                    bd.freg[f] = get_reg(slot, f);
+                    prol[key.l].push_back(tk);
+                    continue;
+                }
+                // finer neighbours: the four children of the neighbour region on this face
+                SlabTask tk{};
+                tk.type = SLAB_RESTRICT;
+                tk.slab = nslab++;
+                tk.slot = slot;
+                tk.face = f;
+                const int e1 = tan1(d), e2 = tan2(d);
+                RefluxTask rt{};
+                rt.slot = slot;
+                rt.face = f;
+                for (int q = 0; q < 4; ++q) {
+                    int c[3];
+                    c[d] = 2 * w[d] + (side ? 0 : 1);
+                    c[e1] = 2 * w[e1] + (q & 1);
+                    c[e2] = 2 * w[e2] + (q >> 1);
+                    auto fl = M.leaves.find(Key{key.l + 1, c[0], c[1], c[2]});
+                    if (fl == M.leaves.end()) throw Error(IC_E_INVALID, "forest violates 2:1 balance");
+                    tk.src[q] = s->slot_of(m, fl->second);
+                    rt.freg[q] = get_reg(tk.src[q], f ^ 1);
+                }
+                for (int e = 0; e < 3; ++e) {
+                    tk.shift[e] = 0;
+                    tk.fbase[e] = 2 * w[e];
+                }
+                tk.fbase[d] = 2 * w[d] + (side ? 0 : 1);
+                if (nbi[d] != w[d]) {
+                    const int n = s->lv[key.l].n[d];
+                    tk.shift[d] = side ? -n : n;
+                }
+                bd.nbr[f] = slab_code(tk.slab);
+                bd.freg[f] = get_reg(slot, f);
+                bd.reflux_mask |= 1 << f;
+                rt.creg = bd.freg[f];
+                rf.push_back(rt);
+                pass1.push_back(tk);
+            }
+        }
+        mend[m] = (int)items.size();
+    }
+    // task lists: pass 1 (inner + restrict), then prolongation by owner level
+    std::vector<SlabTask> all = pass1;
+    s->pass_lo[0] = 0;
+    s->pass_hi[0] = (int)pass1.size();
+    s->any_prolong = false;
+    for (int l = 2; l <= s->max_level; ++l) {
+        s->pass_lo[l] = (int)all.size();
+        all.insert(all.end(), prol[l].begin(), prol[l].end());
+        s->pass_hi[l] = (int)all.size();
+        if (!prol[l].empty()) s->any_prolong = true;
+    }
+    std::sort(rf.begin(), rf.end(), [](const RefluxTask &a, const RefluxTask &b) {
+        return a.slot != b.slot ? a.slot < b.slot : a.face < b.face;
+    });
+    std::vector<int> rfb;
+    for (size_t q = 0; q < rf.size();) {
+        size_t e = q;
+        while (e < rf.size() && rf[e].slot == rf[q].slot) ++e;
+        rfb.push_back((int)q);
+        rfb.push_back((int)e);
+        q = e;
+    }
+    s->n_items = (int)items.size();
+    s->n_slabs = nslab;
+    s->n_regs = (int)regs.size();
+    s->n_rf_blocks = (int)rfb.size() / 2;
+    s->any_reflux = !rf.empty();
+
+    // capacities (growing a buffer invalidates a captured graph)
+    auto grow = [&](auto &buf, size_t need) {
+        if (need > buf.cap) {
+            buf.alloc(std::max(need + need / 2, (size_t)64));
+            s->graph_dirty = true;
+        }
+    };
+    grow(s->slabs, (size_t)std::max(nslab, 1) * s->slab_stride);
+    grow(s->freg, (size_t)std::max(s->n_regs, 1) * s->reg_stride);
+    grow(s->slab_tasks, all.size() + 1);
+    grow(s->rf_tasks, rf.size() + 1);
+    grow(s->rf_blocks, rfb.size() + 2);
+
+    HIPCHECK(hipMemcpy(s->desc.p, s->hdesc.data(), NS * sizeof(BlockDesc), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(s->items.p, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(s->nitems.p, &s->n_items, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(s->mbeg.p, mbeg.data(), s->nm * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(s->mend.p, mend.data(), s->nm * sizeof(int), hipMemcpyHostToDevice));
+    if (!all.empty())
+        HIPCHECK(hipMemcpy(s->slab_tasks.p, all.data(), all.size() * sizeof(SlabTask), hipMemcpyHostToDevice));
+    std::vector<int> ranges(2 * (IC_MAX_LEVEL + 2), 0);
+    for (int l = 0; l <= IC_MAX_LEVEL + 1; ++l) {
+        if (l == 0 || (l >= 2 && l <= s->max_level)) {
+            ranges[2 * l] = s->pass_lo[l];
+            ranges[2 * l + 1] = s->pass_hi[l];
+        }
+    }
+    HIPCHECK(hipMemcpy(s->slab_ranges.p, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!rf.empty()) {
+        HIPCHECK(hipMemcpy(s->rf_tasks.p, rf.data(), rf.size() * sizeof(RefluxTask), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    HIPCHECK(hipMemcpy(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// kernel arguments and the step
+// ---------------------------------------------------------------------------
+KArgs base_args(ic_sim *s)
+{
+    KArgs a{};
+    a.desc = s->desc.p;
+    a.slabs = s->slabs.p;
+    a.freg = s->freg.p;
+    a.geo = s->geo.p;
+    a.mc = s->mc.p;
+    a.items = s->items.p;
+    a.nitems = s->nitems.p;
+    a.dt = s->dt.p;
+    a.t = s->t.p;
+    a.rate = s->rate.p;
+    a.bad = s->bad.p;
+    a.slab_stride = s->slab_stride;
+    a.reg_stride = s->reg_stride;
+    a.gas.g = s->phys.gamma;
+    a.gas.gm1 = s->phys.gamma - 1.0;
+    a.gas.igm1 = 1.0 / (s->phys.gamma - 1.0);
+    a.omega = s->omega_code;
+    a.gm = s->gm_code;
+    a.rho_floor = s->phys.rho_floor;
+    a.p_floor = s->phys.p_floor;
+    a.cart = s->cart ? 1 : 0;
+    return a;
+}
+
+int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
+
+void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
+{
+    KArgs a = base_args(s);
+    a.U = Uin;
+    a.tfrac = tfrac;
+    const int g = grid_for(s->n_slabs + 1, 8192);
+    s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p);
+    for (int l = 2; l <= s->max_level; ++l)
+        s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2 * l);
+}
+
+void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, int want_rate)
+{
+    KArgs a = base_args(s);
+    a.U = Uin;
+    a.Ubase = Ubase;
+    a.Uout = Uout;
+    a.alpha = alpha;
+    a.want_rate = want_rate;
+    const int g = grid_for(s->nm * s->max_blocks, 1 << 17);
+    if (s->timing) {
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, s->stream));
+        s->L.stage(dim3(g), s->stream, a);
+        HIPCHECK(hipEventRecord(e1, s->stream));
+        s->ev.push_back(e0);
+        s->ev.push_back(e1);
+    } else {
+        s->L.stage(dim3(g), s->stream, a);
+    }
+    if (s->any_reflux) {
+        const int gr = grid_for(s->nm * s->max_blocks, 8192);
+        s->L.reflux(dim3(gr), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
+    }
+}
+
+void enqueue_rate(ic_sim *s)
+{
+    KArgs a = base_args(s);
+    a.U = s->U.p;
+    s->L.rate(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a);
+}
+
+void enqueue_sample(ic_sim *s, int record)
+{
+    KArgs a = base_args(s);
+    a.U = s->U.p;
+    s->L.sample(dim3(s->nm), s->stream, a, s->sdesc.p, s->nm, s->sout.p, s->ring.p, s->ring_count.p,
+                s->ring_cap, record);
+}
+
+void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
+{
+    KArgs a = base_args(s);
+    launch_dt(s->stream, a, s->mbeg.p, s->mend.p, s->nm, s->phys.cfl, dt_fixed_code, s->tend.p, s->dt_last.p);
+    fill_ghosts(s, s->U.p, 0.0);
+    stage(s, s->U.p, s->U.p, s->Us.p, 0.5, 0);
+    fill_ghosts(s, s->Us.p, 0.5);
+    stage(s, s->Us.p, s->U.p, s->U.p, 1.0, 1);
+    launch_time(s->stream, s->t.p, s->dt.p, s->nsteps.p, s->nm);
+    if (record) enqueue_sample(s, 1);
+}
+
+void run_step(ic_sim *s, double dt_fixed_code, bool record)
+{
+    if (s->timing || !s->use_graph) {
+        enqueue_step(s, dt_fixed_code, record);
+        return;
+    }
+    if (s->graph_dirty || s->gexec == nullptr || s->graph_dt_fixed != dt_fixed_code) {
+        if (s->gexec) HIPCHECK(hipGraphExecDestroy(s->gexec));
+        s->gexec = nullptr;
+        hipGraph_t g;
+        HIPCHECK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_step(s, dt_fixed_code, true);
+        HIPCHECK(hipStreamEndCapture(s->stream, &g));
+        HIPCHECK(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+        HIPCHECK(hipGraphDestroy(g));
+        s->graph_dirty = false;
+        s->graph_dt_fixed = dt_fixed_code;
+    }
+    (void)record;
+    HIPCHECK(hipGraphLaunch(s->gexec, s->stream));
+}
+
+void check_bad(ic_sim *s)
+{
+    std::vector<int> bad(s->nm);
+    HIPCHECK(hipMemcpyAsync(bad.data(), s->bad.p, s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+    for (int m = 0; m < s->nm; ++m)
+        if (bad[m]) {
+            s->poisoned = true;
+            throw Error(IC_E_UNPHYSICAL, "member " + std::to_string(m) +
+                                             ": a leaf cell has rho <= 0, p <= 0 or a non-finite value");
+        }
+}
+
+void fill_info(ic_sim *s, ic_info *out)
+{
+    if (!out) return;
+    std::memset(out, 0, sizeof(*out));
+    long st = 0;
+    double t = 0, dtl = 0;
+    HIPCHECK(hipMemcpyAsync(&st, s->nsteps.p, sizeof(long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipMemcpyAsync(&t, s->t.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipMemcpyAsync(&dtl, s->dt_last.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+    out->steps = st;
+    out->t_s = t * kT0;
+    out->dt_s = dtl * kT0;
+    out->zone_updates = s->zone_updates;
+    out->leaves = (int)s->mem[0].leaves.size();
+    for (auto &kv : s->mem[0].leaves)
+        if (kv.first.l <= 8) out->leaves_per_level[kv.first.l - 1]++;
+}
+
+long total_cells(const ic_sim *s)
+{
+    long n = 0;
+    for (auto &M : s->mem) n += (long)M.leaves.size() * s->NC;
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// sampling descriptor (host side: which cells, which weights)
+// ---------------------------------------------------------------------------
+const Key *covering_leaf(const Member &M, int l, int bi, int bj, int bk, Key *out)
+{
+    int i = bi, j = bj, k = bk;
+    for (int q = l; q >= 1; --q) {
+        auto it = M.leaves.find(Key{q, i, j, k});
+        if (it != M.leaves.end()) {
+            *out = it->first;
+            return out;
+        }
+        i >>= 1; j >>= 1; k >>= 1;
+    }
+    return nullptr;
+}
+
+bool build_sample(ic_sim *s, int m, double r, double th_deg, double ph_deg, SampleDesc *sd)
+{
+    const Member &M = s->mem[m];
+    double x[3] = {r, th_deg, ph_deg};
+    if (!s->cart) {
+        x[1] = th_deg * (M_PI / 180.0);
+        x[2] = ph_deg * (M_PI / 180.0);
+    }
+    // finest leaf containing the point
+    int lvl = -1;
+    for (int l = s->max_level; l >= 1 && lvl < 0; --l) {
+        const HostLevel &L = s->lv[l];
+        int idx[3];
+        for (int d = 0; d < 3; ++d) {
+            const std::vector<double> &f = L.f[d];
+            const int n = L.n[d];
+            double xx = x[d];
+            if (s->periodic[d]) {
+                const double P = f[n + 2] - f[2];
+                xx = std::fmod(xx - f[2], P);
+                if (xx < 0) xx += P;
+                xx += f[2];
+            }
+            if (xx < f[2] || xx > f[n + 2]) return false;
+            int c = (int)(std::upper_bound(f.begin() + 2, f.begin() + n + 3, xx) - (f.begin() + 2)) - 1;
+            idx[d] = std::min(std::max(c, 0), n - 1);
+        }
+        if (M.leaves.count(Key{l, idx[0] / s->B[0], idx[1] / s->B[1], idx[2] / s->B[2]})) lvl = l;
+    }
+    if (lvl < 0) return false;
+    const HostLevel &L = s->lv[lvl];
+    int lo[3];
+    double wt[3];
+    for (int d = 0; d < 3; ++d) {
+        const int n = L.n[d];
+        std::vector<double> c(n);
+        for (int q = 0; q < n; ++q) c[q] = 0.5 * (L.f[d][q + 2] + L.f[d][q + 3]);
+        if (s->periodic[d]) {
+            const double P = L.f[d][n + 2] - L.f[d][2];
+            double xx = std::fmod(x[d] - c[0], P);
+            if (xx < 0) xx += P;
+            xx += c[0];
+            int q = (int)(std::upper_bound(c.begin(), c.end(), xx) - c.begin()) - 1;
+            lo[d] = q;
+            const double chi = q >= n - 1 ? c[0] + P : c[q + 1];
+            wt[d] = (xx - c[q]) / (chi - c[q]);
+        } else {
+            int q = (int)(std::upper_bound(c.begin(), c.end(), x[d]) - c.begin()) - 1;
+            if (q < 0) { lo[d] = 0; wt[d] = 0.0; }
+            else if (q >= n - 1) { lo[d] = n - 2; wt[d] = 1.0; }
+            else { lo[d] = q; wt[d] = (x[d] - c[q]) / (c[q + 1] - c[q]); }
+        }
+    }
+    for (int o = 0; o < 8; ++o) {
+        const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+        int g[3];
+        double w = 1.0;
+        for (int d = 0; d < 3; ++d) {
+            g[d] = lo[d] + off[d];
+            if (s->periodic[d]) g[d] = ((g[d] % L.n[d]) + L.n[d]) % L.n[d];
+            w *= off[d] ? wt[d] : 1.0 - wt[d];
+        }
+        SampleEntry &e = sd->e[o];
+        e.w = w;
+        Key c;
+        if (covering_leaf(M, lvl, g[0] / s->B[0], g[1] / s->B[1], g[2] / s->B[2], &c)) {
+            const int sh = lvl - c.l;
+            e.kind = 0;
+            e.slot = s->slot_of(m, M.leaves.at(c));
+            e.level = c.l;
+            const int cg[3] = {g[0] >> sh, g[1] >> sh, g[2] >> sh};
+            e.cell[0] = cg[0] - c.i * s->B[0];
+            e.cell[1] = cg[1] - c.j * s->B[1];
+            e.cell[2] = cg[2] - c.k * s->B[2];
+        } else {
+            // covered by finer leaves: mean of the 8 children (one level finer)
+            const int fg[3] = {2 * g[0], 2 * g[1], 2 * g[2]};
+            Key f{lvl + 1, fg[0] / s->B[0], fg[1] / s->B[1], fg[2] / s->B[2]};
+            auto it = M.leaves.find(f);
+            if (it == M.leaves.end()) return false;
+            e.kind = 1;
+            e.slot = s->slot_of(m, it->second);
+            e.level = lvl + 1;
+            for (int d = 0; d < 3; ++d) e.g[d] = fg[d];
+            e.cell[0] = fg[0] - f.i * s->B[0];
+            e.cell[1] = fg[1] - f.j * s->B[1];
+            e.cell[2] = fg[2] - f.k * s->B[2];
+        }
+    }
+    sd->valid = 1;
+    return true;
+}
+
+void update_sample_desc(ic_sim *s)
+{
+    std::vector<SampleDesc> sd(s->nm);
+    for (int m = 0; m < s->nm; ++m) {
+        std::memset(&sd[m], 0, sizeof(SampleDesc));
+        if (!build_sample(s, m, s->sample_point[0], s->sample_point[1], s->sample_point[2], &sd[m]))
+            sd[m].valid = 0;
+    }
+    HIPCHECK(hipMemcpy(s->sdesc.p, sd.data(), s->nm * sizeof(SampleDesc), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// regrid (host forest logic, device data movement)
+// ---------------------------------------------------------------------------
+struct Forest {
+    const ic_sim *s;
+    const std::map<Key, int> &leaves;
+    int maxl;
+    int nblk(int l, int d) const { return s->nb[d] << (l - 1); }
+    bool has(const Key &k) const { return leaves.count(k) != 0; }
+    bool wrap(int l, int idx[3]) const { return wrap_idx(s, l, idx); }
+    // closures of a and b touch (face, edge or corner), through periodic directions
+    bool touch(const Key &a, const Key &b) const
+    {
+        const int L = std::max(std::max(a.l, b.l), maxl);
+        const int sa = 1 << (L - a.l), sb = 1 << (L - b.l);
+        const int ai[3] = {a.i, a.j, a.k}, bi[3] = {b.i, b.j, b.k};
+        for (int d = 0; d < 3; ++d) {
+            const int n = nblk(L, d);
+            const int a0 = ai[d] * sa, a1 = (ai[d] + 1) * sa, b0 = bi[d] * sb, b1 = (bi[d] + 1) * sb;
+            bool ok = false;
+            const int shifts[3] = {-n, 0, n};
+            for (int q = 0; q < 3; ++q) {
+                if (!s->periodic[d] && q != 1) continue;
+                if (a0 <= b1 + shifts[q] && b0 + shifts[q] <= a1) ok = true;
+            }
+            if (!ok) return false;
+        }
+        return true;
+    }
+    // leaves at exactly `level` whose closure touches `leaf`
+    std::vector<Key> touching(const Key &leaf, int level, const std::map<Key, int> *set = nullptr) const
+    {
+        const std::map<Key, int> &S = set ? *set : leaves;
+        std::vector<Key> out;
+        int lo[3], hi[3];
+        const int li[3] = {leaf.i, leaf.j, leaf.k};
+        if (level <= leaf.l) {
+            const int sh = leaf.l - level;
+            for (int d = 0; d < 3; ++d) { lo[d] = (li[d] >> sh) - 1; hi[d] = (li[d] >> sh) + 1; }
+        } else {
+            const int sh = level - leaf.l;
+            for (int d = 0; d < 3; ++d) { lo[d] = (li[d] << sh) - 1; hi[d] = ((li[d] + 1) << sh); }
+        }
+        for (int k = lo[2]; k <= hi[2]; ++k)
+            for (int j = lo[1]; j <= hi[1]; ++j)
+                for (int i = lo[0]; i <= hi[0]; ++i) {
+                    int w[3] = {i, j, k};
+                    if (!wrap(level, w)) continue;
+                    Key c{level, w[0], w[1], w[2]};
+                    if (!S.count(c) || c == leaf) continue;
+                    if (std::find(out.begin(), out.end(), c) != out.end()) continue;
+                    Forest F2{s, S, maxl};
+                    if (F2.touch(leaf, c)) out.push_back(c);
+                }
+        return out;
+    }
+    std::vector<Key> face_neighbours(const Key &leaf, int d, int side) const
+    {
+        int idx[3] = {leaf.i, leaf.j, leaf.k};
+        idx[d] += side ? 1 : -1;
+        if (!wrap(leaf.l, idx)) return {};
+        for (int l = leaf.l, i = idx[0], j = idx[1], k = idx[2]; l >= 1; --l, i >>= 1, j >>= 1, k >>= 1)
+            if (has(Key{l, i, j, k})) return {Key{l, i, j, k}};
+        std::vector<Key> out;
+        std::vector<Key> stack{Key{leaf.l, idx[0], idx[1], idx[2]}};
+        while (!stack.empty()) {
+            Key c = stack.back();
+            stack.pop_back();
+            for (int o = 0; o < 8; ++o) {
+                const int off[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+                if (off[d] != (side ? 0 : 1)) continue;
+                Key ch{c.l + 1, 2 * c.i + off[0], 2 * c.j + off[1], 2 * c.k + off[2]};
+                if (ch.l > maxl + 1) continue;
+                if (has(ch)) out.push_back(ch);
+                else stack.push_back(ch);
+            }
+        }
+        return out;
+    }
+};
+
+void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int buffer_blocks,
+                   std::vector<MoveTask> &moves, std::vector<int> &to_free)
+{
+    Member &M = s->mem[m];
+    Forest F{s, M.leaves, s->max_level};
+    std::map<Key, int> f;
+    for (auto &kv : M.leaves) {
+        auto it = flags_in.find(kv.first);
+        int v = it == flags_in.end() ? 0 : it->second;
+        if (v == 1 && kv.first.l >= s->max_level) v = 0;
+        if (v == -1 && kv.first.l <= 1) v = 0;
+        f[kv.first] = v;
+    }
+    // buffer
+    std::vector<Key> orig;
+    for (auto &kv : f) if (kv.second == 1) orig.push_back(kv.first);
+    for (const Key &b : orig)
+        for (int d = 0; d < 3; ++d)
+            for (int side = 0; side < 2; ++side)
+                for (const Key &n : F.face_neighbours(b, d, side)) {
+                    if (buffer_blocks && n.l < s->max_level && n.l <= b.l) f[n] = 1;
+                    else if (f[n] == -1) f[n] = 0;
+                }
+    // 2:1 closure
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (auto &kv : f) {
+            if (kv.second != 1 || kv.first.l < 2) continue;
+            for (const Key &n : F.touching(kv.first, kv.first.l - 1))
+                if (f[n] != 1) {
+                    f[n] = 1;
+                    changed = true;
+                }
+        }
+    }
+    std::vector<Key> refined;
+    for (auto &kv : f) if (kv.second == 1) refined.push_back(kv.first);
+    std::map<Key, int> post;
+    for (auto &kv : M.leaves) if (f[kv.first] != 1) post[kv.first] = kv.second;
+    for (const Key &b : refined)
+        for (int o = 0; o < 8; ++o)
+            post[Key{b.l + 1, 2 * b.i + (o & 1), 2 * b.j + ((o >> 1) & 1), 2 * b.k + ((o >> 2) & 1)}] = -1;
+    std::map<Key, std::vector<Key>> parents;
+    for (auto &kv : f)
+        if (kv.second == -1) {
+            const Key &b = kv.first;
+            parents[Key{b.l - 1, b.i >> 1, b.j >> 1, b.k >> 1}].push_back(b);
+        }
+    std::vector<Key> coarsened;
+    Forest P{s, post, s->max_level};
+    for (auto &kv : parents) {
+        if (kv.second.size() != 8) continue;
+        bool ok = true;
+        for (int l = kv.first.l + 2; l <= s->max_level && ok; ++l)
+            if (!P.touching(kv.first, l, &post).empty()) ok = false;
+        if (ok) coarsened.push_back(kv.first);
+    }
+    // capacity check
+    long nnew = (long)M.leaves.size() + 7 * (long)refined.size() - 7 * (long)coarsened.size();
+    long transient = (long)M.leaves.size() + 8 * (long)refined.size() + (long)coarsened.size();
+    if (nnew > s->max_blocks || transient > s->max_blocks)
+        throw Error(IC_E_CAPACITY, "member " + std::to_string(m) + ": regrid needs " +
+                                       std::to_string(std::max(nnew, transient)) + " block slots, pool has " +
+                                       std::to_string(s->max_blocks));
+    auto alloc_slot = [&]() {
+        const int q = M.free_slots.back();
+        M.free_slots.pop_back();
+        return q;
+    };
+    std::map<Key, int> newleaves;
+    for (auto &kv : M.leaves) newleaves[kv.first] = kv.second;
+    for (const Key &p : refined) {
+        const int ps = M.leaves.at(p);
+        for (int o = 0; o < 8; ++o) {
+            Key ch{p.l + 1, 2 * p.i + (o & 1), 2 * p.j + ((o >> 1) & 1), 2 * p.k + ((o >> 2) & 1)};
+            const int cs = alloc_slot();
+            newleaves[ch] = cs;
+            MoveTask t{};
+            t.type = MOVE_PROLONG;
+            t.dst = s->slot_of(m, cs);
+            t.src[0] = s->slot_of(m, ps);
+            t.src[1] = o;
+            t.level = ch.l;
+            t.org[0] = ch.i * s->B[0];
+            t.org[1] = ch.j * s->B[1];
+            t.org[2] = ch.k * s->B[2];
+            moves.push_back(t);
+        }
+        newleaves.erase(p);
+        to_free.push_back(s->slot_of(m, ps));
+    }
+    for (const Key &p : coarsened) {
+        const int pslot = alloc_slot();
+        MoveTask t{};
+        t.type = MOVE_RESTRICT;
+        t.dst = s->slot_of(m, pslot);
+        t.level = p.l;
+        t.org[0] = p.i * s->B[0];
+        t.org[1] = p.j * s->B[1];
+        t.org[2] = p.k * s->B[2];
+        for (int o = 0; o < 8; ++o) {
+            Key ch{p.l + 1, 2 * p.i + (o & 1), 2 * p.j + ((o >> 1) & 1), 2 * p.k + ((o >> 2) & 1)};
+            const int cs = M.leaves.at(ch);
+            t.src[o] = s->slot_of(m, cs);
+            newleaves.erase(ch);
+            to_free.push_back(s->slot_of(m, cs));
+        }
+        newleaves[p] = pslot;
+        moves.push_back(t);
+    }
+    M.leaves.swap(newleaves);
+}
+
+void do_regrid(ic_sim *s, const int8_t *user_flags)
+{
+    // ghosts of the current state (prolongation of new children reads them)
+    fill_ghosts(s, s->U.p, 0.0);
+    std::vector<int8_t> fl((size_t)s->nm * s->max_blocks, 0);
+    if (!user_flags) {
+        KArgs a = base_args(s);
+        a.U = s->U.p;
+        IndicatorParams p{};
+        const double deg = M_PI / 180.0;
+        p.max_level = s->max_level;
+        p.eps = s->amr.eps_lohner;
+        p.tol_r = s->amr.tol_refine;
+        p.tol_c = s->amr.tol_coarsen;
+        p.w_rho = s->amr.w_rho;
+        p.w_v = s->amr.w_v;
+        p.use_windows = s->amr.use_windows;
+        p.lon_e = s->amr.lon_earth_deg * deg;
+        p.clt_e = s->amr.clt_earth_deg * deg;
+        p.dlon_e = s->amr.dlon_earth_deg * deg;
+        p.dclt_e = s->amr.dclt_earth_deg * deg;
+        p.dlon_c = s->amr.dlon_cme_deg * deg;
+        s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
+        HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+    }
+    std::vector<MoveTask> moves;
+    std::vector<int> to_free;
+    for (int m = 0; m < s->nm; ++m) {
+        Member &M = s->mem[m];
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        std::map<Key, int8_t> f;
+        for (size_t q = 0; q < keys.size(); ++q) {
+            const int slot = s->slot_of(m, M.leaves[keys[q]]);
+            f[keys[q]] = user_flags ? user_flags[(size_t)m * s->max_blocks + q] : fl[slot];
+        }
+        regrid_member(s, m, f, s->amr.buffer_blocks, moves, to_free);
+    }
+    if (!moves.empty()) {
+        s->moves.alloc(moves.size());
+        HIPCHECK(hipMemcpy(s->moves.p, moves.data(), moves.size() * sizeof(MoveTask), hipMemcpyHostToDevice));
+        KArgs a = base_args(s);
+        a.U = s->U.p;
+        s->L.move(dim3(grid_for((int)moves.size(), 16384)), s->stream, a, s->U.p, s->moves.p, (int)moves.size());
+        HIPCHECK(hipStreamSynchronize(s->stream));
+    }
+    for (int slot : to_free) s->mem[slot / s->max_blocks].free_slots.push_back(slot % s->max_blocks);
+    rebuild(s);
+    update_sample_desc(s);
+    enqueue_rate(s);
+}
+
+void check_sim(ic_sim *s)
+{
+    if (!s) throw Error(IC_E_INVALID, "null sim");
+    if (s->poisoned) throw Error(IC_E_STATE, "sim is poisoned by an earlier error");
+}
+
+template <class F>
+ic_status guard(ic_sim *s, F &&f)
+{
+    try {
+        f();
+        return IC_OK;
+    } catch (const Error &e) {
+        g_err = e.what();
+        if (s && (e.code == IC_E_UNPHYSICAL || e.code == IC_E_DEVICE || e.code == IC_E_CAPACITY))
+            s->poisoned = true;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return IC_E_INVALID;
+    }
+}
+
+void set_initial_state(ic_sim *s)
+{
+    // relaxation start: rho ~ r^-2, v_r const, p ~ r^-2g, B_r ~ r^-2, v_phi = -omega r sin(theta)
+    std::vector<double> h((size_t)s->NC * 8);
+    for (int m = 0; m < s->nm; ++m) {
+        for (auto &kv : s->mem[m].leaves) {
+            const Key &key = kv.first;
+            const HostLevel &L = s->lv[key.l];
+            const HostLevel &L1 = s->lv[1];
+            (void)L1;
+            const int nt = L.n[1], np = L.n[2];
+            const size_t pl = (size_t)nt * np;
+            for (int k = 0; k < s->B[2]; ++k)
+                for (int j = 0; j < s->B[1]; ++j)
+                    for (int i = 0; i < s->B[0]; ++i) {
+                        const int gi = key.i * s->B[0] + i, gj = key.j * s->B[1] + j, gk = key.k * s->B[2] + k;
+                        double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                        if (!s->cart) {
+                            const size_t o = (size_t)gj * np + gk;
+                            const double r = L.r[gi + 2].rc, th = L.t[gj + 2].tc;
+                            const double x = s->r_in / r;
+                            w[0] = L.wind[0 * pl + o] * x * x;
+                            w[1] = L.wind[1 * pl + o];
+                            w[3] = -s->omega_code * r * std::sin(th);
+                            w[4] = L.wind[3 * pl + o] * std::pow(x, 2.0 * s->phys.gamma);
+                            w[5] = L.wind[4 * pl + o] * x * x;
+                            w[7] = w[5] != 0.0 ? w[5] * w[3] / w[1] : 0.0;
+                        } else {
+                            w[0] = 1.0;
+                            w[4] = 1.0;
+                        }
+                        const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+                        const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
+                        double u[8] = {w[0], w[0] * w[1], w[0] * w[2], w[0] * w[3],
+                                       w[4] / (s->phys.gamma - 1.0) + 0.5 * w[0] * v2 + 0.5 * b2, w[5], w[6], w[7]};
+                        for (int v = 0; v < 8; ++v)
+                            h[(size_t)v * s->NC + i + s->B[0] * (j + s->B[1] * k)] = u[v];
+                    }
+            const int slot = s->slot_of(m, kv.second);
+            HIPCHECK(hipMemcpy(s->U.p + (size_t)slot * 8 * s->NC, h.data(), h.size() * sizeof(double),
+                               hipMemcpyHostToDevice));
+        }
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *ic_last_error(void) { return g_err.c_str(); }
+
+void ic_units(double out[6])
+{
+    out[0] = kAU;
+    out[1] = kV0;
+    out[2] = kT0;
+    out[3] = kRHO0;
+    out[4] = kP0;
+    out[5] = kB0;
+}
+
+int ic_pool_capacity(const ic_sim *s) { return s ? s->max_blocks : 0; }
+
+int ic_block_supported(int bi, int bj, int bk)
+{
+    Launchers L;
+    return get_launchers(bi, bj, bk, &L) ? 1 : 0;
+}
+
+ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_wind_cfg *wind,
+                    const ic_cme_cfg *cmes, int n_members, const ic_amr_cfg *amr, void *hip_stream,
+                    ic_sim **out)
+{
+    ic_sim *s = nullptr;
+    ic_status st = guard(nullptr, [&]() {
+        if (!grid || !phys || !out || n_members < 1) throw Error(IC_E_INVALID, "null argument or n_members < 1");
+        if (grid->geometry == IC_GEOM_SPHERICAL && !wind) throw Error(IC_E_INVALID, "spherical geometry needs a wind");
+        if (grid->max_level < 1 || grid->max_level > IC_MAX_LEVEL)
+            throw Error(IC_E_INVALID, "max_level must be in 1.." + std::to_string(IC_MAX_LEVEL));
+        if (grid->max_level > 1 && !amr) throw Error(IC_E_INVALID, "max_level > 1 needs an amr config");
+        if (!(phys->gamma > 1.0) || !(phys->cfl > 0.0)) throw Error(IC_E_INVALID, "gamma must exceed 1 and cfl be positive");
+        s = new ic_sim();
+        s->grid = *grid;
+        s->phys = *phys;
+        if (wind) s->wind = *wind;
+        if (amr) s->amr = *amr;
+        s->nm = n_members;
+        s->cart = grid->geometry == IC_GEOM_CARTESIAN;
+        s->max_level = grid->max_level;
+        s->stream = (hipStream_t)hip_stream;
+        if (!s->stream) {
+            HIPCHECK(hipStreamCreate(&s->stream));   // graph capture needs a stream of its own
+            s->own_stream = true;
+        }
+        for (int d = 0; d < 3; ++d) {
+            s->B[d] = grid->block[d];
+            if (s->B[d] < 4 || s->B[d] % 2) throw Error(IC_E_INVALID, "block dims must be even and >= 4");
+            if (grid->n[d] <= 0 || grid->n[d] % s->B[d]) throw Error(IC_E_INVALID, "cells must be a multiple of the block size");
+            s->nb[d] = grid->n[d] / s->B[d];
+            const bool p0 = grid->bc[d][0] == IC_BC_PERIODIC, p1 = grid->bc[d][1] == IC_BC_PERIODIC;
+            if (p0 != p1) throw Error(IC_E_INVALID, "periodic boundaries must be periodic on both sides");
+            s->periodic[d] = p0;
+            for (int side = 0; side < 2; ++side) {
+                const int b = grid->bc[d][side];
+                if (b != IC_BC_OUTFLOW && b != IC_BC_PERIODIC && b != IC_BC_INNER)
+                    throw Error(IC_E_INVALID, "unknown boundary kind");
+                if (b == IC_BC_INNER && (s->cart || d != 0 || side != 0))
+                    throw Error(IC_E_INVALID, "the inner boundary is the lower r boundary of a spherical grid");
+            }
+            if (!(grid->x1[d] > grid->x0[d])) throw Error(IC_E_INVALID, "empty domain");
+        }
+        if (!s->cart && grid->x0[0] <= 0.0) throw Error(IC_E_INVALID, "r_in must be positive");
+        if (!get_launchers(s->B[0], s->B[1], s->B[2], &s->L))
+            throw Error(IC_E_INVALID, "block shape not built into the library");
+        s->NC = s->B[0] * s->B[1] * s->B[2];
+        s->r_in = s->cart ? 0.0 : grid->x0[0];
+        s->omega_code = s->cart ? 0.0 : phys->omega * kT0;
+        s->gm_code = s->cart ? 0.0 : phys->gm / (kAU * kV0 * kV0);
+        const long nbase = (long)s->nb[0] * s->nb[1] * s->nb[2];
+        long cap = grid->max_blocks > 0 ? grid->max_blocks : nbase;
+        if (grid->max_blocks <= 0)
+            for (int l = 2; l <= s->max_level && cap < 32768; ++l) cap *= 8;
+        if (grid->max_blocks <= 0) cap = std::min(cap, std::max(nbase, 32768L));
+        if (cap < nbase) throw Error(IC_E_CAPACITY, "max_blocks below the base block count");
+        s->max_blocks = (int)cap;
+        s->mem.resize(s->nm);
+        for (int m = 0; m < s->nm; ++m) {
+            if (cmes) s->mem[m].cme = cmes[m];
+            else s->mem[m].cme.enabled = 0;
+        }
+        int dev = 0;
+        HIPCHECK(hipGetDevice(&dev));
+        // levels
+        s->lv.resize(s->max_level + 2);
+        for (int l = 1; l <= s->max_level; ++l) build_level(s, l);
+        std::vector<LevelGeo> lg(IC_MAX_LEVEL + 2);
+        for (int l = 1; l <= s->max_level; ++l) {
+            HostLevel &L = s->lv[l];
+            lg[l].r = L.dr.p;
+            lg[l].t = L.dt.p;
+            lg[l].p = L.dp.p;
+            for (int d = 0; d < 3; ++d) lg[l].n[d] = L.n[d];
+            lg[l].wind = L.dwind.p;
+            lg[l].cosd = L.dcosd.p;
+        }
+        s->geo.alloc(lg.size());
+        HIPCHECK(hipMemcpy(s->geo.p, lg.data(), lg.size() * sizeof(LevelGeo), hipMemcpyHostToDevice));
+        // member constants
+        std::vector<MemberConst> mc(s->nm);
+        for (int m = 0; m < s->nm; ++m) {
+            const ic_cme_cfg &c = s->mem[m].cme;
+            MemberConst &q = mc[m];
+            q.enabled = (cmes && c.enabled && !s->cart) ? 1 : 0;
+            q.r_in = s->r_in;
+            q.lon_cme = c.lon_deg * (M_PI / 180.0);
+            if (q.enabled) {
+                q.t0 = c.t_start_s / kT0;
+                q.v = c.v_kms * 1.0e3 / kV0;
+                q.r_half = s->r_in * std::sin(c.half_width_deg * (M_PI / 180.0));
+                q.tact = std::min(c.duration_s / kT0, 2.0 * q.r_half / q.v);
+                q.rho = c.n_cm3 * 1.0e6 * kMP / kRHO0;
+                q.p = 2.0 * c.n_cm3 * 1.0e6 * kKB * c.T_K / kP0;
+            }
+        }
+        s->mc.alloc(s->nm);
+        HIPCHECK(hipMemcpy(s->mc.p, mc.data(), s->nm * sizeof(MemberConst), hipMemcpyHostToDevice));
+        // pools
+        const size_t NS = (size_t)s->nm * s->max_blocks;
+        s->U.alloc(NS * 8 * s->NC);
+        s->Us.alloc(NS * 8 * s->NC);
+        s->desc.alloc(NS);
+        s->items.alloc(NS);
+        s->nitems.alloc(1);
+        s->mbeg.alloc(s->nm);
+        s->mend.alloc(s->nm);
+        s->dt.alloc(s->nm);
+        s->t.alloc(s->nm);
+        s->tend.alloc(s->nm);
+        s->dt_last.alloc(s->nm);
+        s->rate.alloc(NS);
+        s->bad.alloc(s->nm);
+        s->nsteps.alloc(s->nm);
+        s->slab_ranges.alloc(2 * (IC_MAX_LEVEL + 2));
+        s->rf_nblocks.alloc(1);
+        s->flags.alloc(NS);
+        s->sdesc.alloc(s->nm);
+        s->sout.alloc((size_t)s->nm * 8);
+        s->ring.alloc((size_t)s->nm * s->ring_cap * 9);
+        s->ring_count.alloc(s->nm);
+        int maxface = std::max(s->B[0] * s->B[1], std::max(s->B[0] * s->B[2], s->B[1] * s->B[2]));
+        s->slab_stride = 16L * maxface;
+        s->reg_stride = 8L * maxface;
+        std::vector<double> zeros(s->nm, 0.0), big(s->nm, 1e300);
+        HIPCHECK(hipMemcpy(s->t.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s->dt.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s->dt_last.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemset(s->bad.p, 0, s->nm * sizeof(int)));
+        HIPCHECK(hipMemset(s->nsteps.p, 0, s->nm * sizeof(long)));
+        HIPCHECK(hipMemset(s->ring_count.p, 0, s->nm * sizeof(int)));
+        HIPCHECK(hipMemset(s->rate.p, 0, NS * sizeof(double)));
+        // base forest
+        for (int m = 0; m < s->nm; ++m) {
+            Member &M = s->mem[m];
+            for (int q = s->max_blocks - 1; q >= 0; --q) M.free_slots.push_back(q);
+            for (int k = 0; k < s->nb[2]; ++k)
+                for (int j = 0; j < s->nb[1]; ++j)
+                    for (int i = 0; i < s->nb[0]; ++i) {
+                        const int q = M.free_slots.back();
+                        M.free_slots.pop_back();
+                        M.leaves[Key{1, i, j, k}] = q;
+                    }
+        }
+        rebuild(s);
+        set_initial_state(s);
+        update_sample_desc(s);
+        enqueue_rate(s);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        *out = s;
+    });
+    if (st != IC_OK && s) {
+        ic_destroy(s);
+    }
+    return st;
+}
+
+void ic_destroy(ic_sim *s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    for (auto e : s->ev) (void)hipEventDestroy(e);
+    for (auto &L : s->lv) {
+        L.dr.release(); L.dt.release(); L.dp.release(); L.dwind.release(); L.dcosd.release();
+    }
+    s->U.release(); s->Us.release(); s->slabs.release(); s->freg.release(); s->desc.release();
+    s->geo.release(); s->mc.release(); s->items.release(); s->nitems.release(); s->mbeg.release();
+    s->mend.release(); s->dt.release(); s->t.release(); s->tend.release(); s->dt_last.release();
+    s->rate.release(); s->bad.release(); s->nsteps.release(); s->slab_tasks.release();
+    s->slab_ranges.release(); s->rf_tasks.release(); s->rf_blocks.release(); s->rf_nblocks.release();
+    s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
+    s->ring_count.release();
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}
+
+ic_status ic_step(ic_sim *s, double dt_fixed_s, ic_info *out)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (dt_fixed_s < 0.0) throw Error(IC_E_INVALID, "negative dt");
+        std::vector<double> big(s->nm, 1e300);
+        HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        run_step(s, dt_fixed_s / kT0, true);
+        s->zone_updates += (double)total_cells(s);
+        s->host_steps++;
+        check_bad(s);
+        fill_info(s, out);
+    });
+}
+
+ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (!(dt_s >= 0.0) || max_steps < 0) throw Error(IC_E_INVALID, "negative duration or step limit");
+        std::vector<double> t(s->nm), tend(s->nm);
+        HIPCHECK(hipMemcpyAsync(t.data(), s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        for (int m = 0; m < s->nm; ++m) tend[m] = t[m] + dt_s / kT0;
+        HIPCHECK(hipMemcpyAsync(s->tend.p, tend.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        const int every = (s->max_level > 1 && s->amr.regrid_every > 0) ? s->amr.regrid_every : 0;
+        long done = 0;
+        std::vector<long> ns(s->nm);
+        while (done < max_steps) {
+            const long batch = std::min<long>(max_steps - done, every > 0 ? every : 20);
+            for (long q = 0; q < batch; ++q) {
+                run_step(s, 0.0, true);
+                s->zone_updates += (double)total_cells(s);
+            }
+            done += batch;
+            check_bad(s);
+            HIPCHECK(hipMemcpyAsync(t.data(), s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+            HIPCHECK(hipStreamSynchronize(s->stream));
+            bool all = true;
+            for (int m = 0; m < s->nm; ++m) all = all && t[m] >= tend[m];
+            if (all) break;
+            if (every > 0) do_regrid(s, nullptr);
+        }
+        std::vector<double> big(s->nm, 1e300);
+        HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        fill_info(s, out);
+    });
+}
+
+ic_status ic_regrid(ic_sim *s, const int8_t *flags, ic_info *out)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (s->max_level > 1 || flags) do_regrid(s, flags);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        fill_info(s, out);
+    });
+}
+
+ic_status ic_eval_flags(ic_sim *s, int member, int8_t *flags, int n)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !flags) throw Error(IC_E_INVALID, "bad member or buffer");
+        Member &M = s->mem[member];
+        if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "flag buffer too small");
+        fill_ghosts(s, s->U.p, 0.0);
+        KArgs a = base_args(s);
+        a.U = s->U.p;
+        IndicatorParams p{};
+        const double deg = M_PI / 180.0;
+        p.max_level = s->max_level;
+        p.eps = s->amr.eps_lohner;
+        p.tol_r = s->amr.tol_refine;
+        p.tol_c = s->amr.tol_coarsen;
+        p.w_rho = s->amr.w_rho;
+        p.w_v = s->amr.w_v;
+        p.use_windows = s->amr.use_windows;
+        p.lon_e = s->amr.lon_earth_deg * deg;
+        p.clt_e = s->amr.clt_earth_deg * deg;
+        p.dlon_e = s->amr.dlon_earth_deg * deg;
+        p.dclt_e = s->amr.dclt_earth_deg * deg;
+        p.dlon_c = s->amr.dlon_cme_deg * deg;
+        s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
+        std::vector<int8_t> fl((size_t)s->nm * s->max_blocks);
+        HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        for (size_t q = 0; q < keys.size(); ++q) flags[q] = fl[s->slot_of(member, M.leaves[keys[q]])];
+    });
+}
+
+ic_status ic_sample(ic_sim *s, int member, double r_au, double colat_deg, double lon_deg, double prim_out[8])
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !prim_out) throw Error(IC_E_INVALID, "bad member or buffer");
+        SampleDesc sd{};
+        if (!build_sample(s, member, r_au, colat_deg, lon_deg, &sd)) throw Error(IC_E_OUTSIDE, "point outside the domain");
+        std::vector<SampleDesc> all(s->nm);
+        std::memset(all.data(), 0, all.size() * sizeof(SampleDesc));
+        all[member] = sd;
+        DBuf<SampleDesc> tmp;
+        tmp.alloc(s->nm);
+        HIPCHECK(hipMemcpy(tmp.p, all.data(), s->nm * sizeof(SampleDesc), hipMemcpyHostToDevice));
+        KArgs a = base_args(s);
+        a.U = s->U.p;
+        s->L.sample(dim3(s->nm), s->stream, a, tmp.p, s->nm, s->sout.p, s->ring.p, s->ring_count.p, s->ring_cap, 0);
+        HIPCHECK(hipMemcpyAsync(prim_out, s->sout.p + member * 8, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        tmp.release();
+    });
+}
+
+ic_status ic_set_sample_point(ic_sim *s, double r_au, double colat_deg, double lon_deg)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        s->sample_point[0] = r_au;
+        s->sample_point[1] = colat_deg;
+        s->sample_point[2] = lon_deg;
+        update_sample_desc(s);
+    });
+}
+
+ic_status ic_timeseries(ic_sim *s, int member, double *out, int *n_inout)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !out || !n_inout) throw Error(IC_E_INVALID, "bad argument");
+        int cnt = 0;
+        HIPCHECK(hipMemcpyAsync(&cnt, s->ring_count.p + member, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        const int have = std::min(cnt, s->ring_cap);
+        const int n = std::min(have, *n_inout);
+        std::vector<double> buf((size_t)s->ring_cap * 9);
+        HIPCHECK(hipMemcpy(buf.data(), s->ring.p + (size_t)member * s->ring_cap * 9, buf.size() * sizeof(double),
+                           hipMemcpyDeviceToHost));
+        for (int q = 0; q < n; ++q) {
+            const int idx = (cnt - n + q) % s->ring_cap;
+            std::memcpy(out + (size_t)q * 9, buf.data() + (size_t)idx * 9, 9 * sizeof(double));
+            out[(size_t)q * 9] *= kT0;
+        }
+        *n_inout = n;
+    });
+}
+
+ic_status ic_timeseries_clear(ic_sim *s)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        HIPCHECK(hipMemsetAsync(s->ring_count.p, 0, s->nm * sizeof(int), s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+    });
+}
+
+ic_status ic_get_blocks(ic_sim *s, int member, int32_t *lvl_ijk, int *n_inout)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !n_inout) throw Error(IC_E_INVALID, "bad argument");
+        Member &M = s->mem[member];
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        if (!lvl_ijk || *n_inout < (int)keys.size()) {
+            *n_inout = (int)keys.size();
+            throw Error(IC_E_INVALID, "block buffer too small");
+        }
+        for (size_t q = 0; q < keys.size(); ++q) {
+            lvl_ijk[4 * q + 0] = keys[q].l;
+            lvl_ijk[4 * q + 1] = keys[q].i;
+            lvl_ijk[4 * q + 2] = keys[q].j;
+            lvl_ijk[4 * q + 3] = keys[q].k;
+        }
+        *n_inout = (int)keys.size();
+    });
+}
+
+ic_status ic_get_state(ic_sim *s, int member, double *host_U, size_t n_doubles)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !host_U) throw Error(IC_E_INVALID, "bad argument");
+        Member &M = s->mem[member];
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        const size_t per = (size_t)8 * s->NC;
+        if (n_doubles < keys.size() * per) throw Error(IC_E_INVALID, "state buffer too small");
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        for (size_t q = 0; q < keys.size(); ++q) {
+            const int slot = s->slot_of(member, M.leaves[keys[q]]);
+            HIPCHECK(hipMemcpy(host_U + q * per, s->U.p + (size_t)slot * per, per * sizeof(double), hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+ic_status ic_set_state(ic_sim *s, int member, const int32_t *lvl_ijk, int n_blocks, const double *host_U, double t_s)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !lvl_ijk || !host_U || n_blocks < 1)
+            throw Error(IC_E_INVALID, "bad argument");
+        if (n_blocks > s->max_blocks) throw Error(IC_E_CAPACITY, "more blocks than the pool holds");
+        // validate: levels, ranges, tiling, 2:1
+        std::map<Key, int> leaves;
+        long vol = 0;
+        const int L = s->max_level;
+        for (int q = 0; q < n_blocks; ++q) {
+            Key k{lvl_ijk[4 * q], lvl_ijk[4 * q + 1], lvl_ijk[4 * q + 2], lvl_ijk[4 * q + 3]};
+            if (k.l < 1 || k.l > L) throw Error(IC_E_INVALID, "block level out of range");
+            const int idx[3] = {k.i, k.j, k.k};
+            for (int d = 0; d < 3; ++d)
+                if (idx[d] < 0 || idx[d] >= nblocks_at(s, k.l, d)) throw Error(IC_E_INVALID, "block index out of range");
+            if (leaves.count(k)) throw Error(IC_E_INVALID, "duplicate block");
+            leaves[k] = q;
+            vol += 1L << (3 * (L - k.l));
+        }
+        if (vol != (long)s->nb[0] * s->nb[1] * s->nb[2] << (3 * (L - 1)))
+            throw Error(IC_E_INVALID, "blocks do not tile the domain");
+        Forest F{s, leaves, s->max_level};
+        for (auto &kv : leaves) {
+            int l = kv.first.l - 1, i = kv.first.i >> 1, j = kv.first.j >> 1, k = kv.first.k >> 1;
+            for (; l >= 1; --l, i >>= 1, j >>= 1, k >>= 1)
+                if (leaves.count(Key{l, i, j, k})) throw Error(IC_E_INVALID, "overlapping blocks");
+            for (int lv = kv.first.l + 2; lv <= s->max_level; ++lv)
+                if (!F.touching(kv.first, lv).empty()) throw Error(IC_E_INVALID, "blocks violate 2:1 balance");
+        }
+        Member &M = s->mem[member];
+        M.leaves.clear();
+        M.free_slots.clear();
+        for (int q = s->max_blocks - 1; q >= 0; --q) M.free_slots.push_back(q);
+        const size_t per = (size_t)8 * s->NC;
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        for (int q = 0; q < n_blocks; ++q) {
+            Key k{lvl_ijk[4 * q], lvl_ijk[4 * q + 1], lvl_ijk[4 * q + 2], lvl_ijk[4 * q + 3]};
+            const int ls = M.free_slots.back();
+            M.free_slots.pop_back();
+            M.leaves[k] = ls;
+            HIPCHECK(hipMemcpy(s->U.p + (size_t)s->slot_of(member, ls) * per, host_U + (size_t)q * per,
+                               per * sizeof(double), hipMemcpyHostToDevice));
+        }
+        const double tc = t_s / kT0;
+        HIPCHECK(hipMemcpy(s->t.p + member, &tc, sizeof(double), hipMemcpyHostToDevice));
+        const int zero = 0;
+        HIPCHECK(hipMemcpy(s->bad.p + member, &zero, sizeof(int), hipMemcpyHostToDevice));
+        rebuild(s);
+        update_sample_desc(s);
+        enqueue_rate(s);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+    });
+}
+
+ic_status ic_get_time(ic_sim *s, int member, double *t_s, double *dt_s)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm) throw Error(IC_E_INVALID, "bad member");
+        double t = 0, d = 0;
+        HIPCHECK(hipMemcpyAsync(&t, s->t.p + member, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipMemcpyAsync(&d, s->dt_last.p + member, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        if (t_s) *t_s = t * kT0;
+        if (dt_s) *dt_s = d * kT0;
+    });
+}
+
+ic_status ic_set_kernel_timing(ic_sim *s, int enable)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        for (auto e : s->ev) HIPCHECK(hipEventDestroy(e));
+        s->ev.clear();
+        s->timing = enable != 0;
+    });
+}
+
+ic_status ic_stage_timing(ic_sim *s, long *launches, double *mean_ms)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        double tot = 0.0;
+        const long n = (long)s->ev.size() / 2;
+        for (long q = 0; q < n; ++q) {
+            float ms = 0.f;
+            HIPCHECK(hipEventElapsedTime(&ms, s->ev[2 * q], s->ev[2 * q + 1]));
+            tot += ms;
+        }
+        if (launches) *launches = n;
+        if (mean_ms) *mean_ms = n ? tot / n : 0.0;
+    });
+}
+
+}  // extern "C"

@@ -217,7 +217,7 @@ def workload(name: str) -> Workload:
     if name == "equidistant_full":
         return Workload(
             name, Grid(x0=(0.1, 30.0, 0.0), x1=(2.0, 150.0, 360.0), n=(512, 60, 180),
-                       block=(16, 15, 15), periodic=(False, False, True)),
+                       block=(16, 12, 12), periodic=(False, False, True)),
             Wind(seed=0),
             [Cme(t_start_s=14 * DAY, duration_s=8 * 3600.0, v_kms=1500.0, half_width_deg=45.0,
                  colat_deg=90.0, lon_deg=0.0, n_cm3=1200.0, T_K=0.8e6)],

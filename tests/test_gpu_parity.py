@@ -1,0 +1,280 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle.
+
+Bar (fp64): max relative state error per conserved variable <= 1e-12 after one
+step and <= 1e-9 after 100 steps; refinement flags and block forests
+bit-exact on identical inputs (near-ties in the indicator fail loudly).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_err, tiny_wedge
+from oracle import boundary, forest as fo, solver, units
+from synthetic import as_dict, smooth_modes, Cme
+
+pytestmark = pytest.mark.gpu
+
+
+def _ic():
+    import paper_2211_12867_amd as ic
+    return ic
+
+
+def _smooth_box_state(s_ora, seed=100, amp=0.2):
+    for leaf in s_ora.forest.leaves:
+        g = s_ora.geo[leaf[0]]
+        x = [np.array([g.centre(d, m) for m in range(*s_ora.cell_range(leaf, d))]) for d in range(3)]
+        Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+        W = np.zeros((8,) + X.shape)
+        base = [1.0, 0.0, 0.0, 0.0, 1.0, 0.3, 0.2, -0.1]
+        L = [s_ora.geo[1].f[d][s_ora.geo[1].n[d] + 2] - s_ora.geo[1].f[d][2] for d in range(3)]
+        for v in range(8):
+            ks, amps, ph = smooth_modes(seed + v, 3, amp if v in (0, 4) else 1.5 * amp)
+            f = np.zeros_like(X)
+            for kk, a, p in zip(ks, amps, ph):
+                f += a * np.sin(2 * math.pi * (kk[0] * X / L[0] + kk[1] * Y / L[1] + kk[2] * Z / L[2]) + p)
+            W[v] = base[v] + f
+        s_ora.U[leaf] = boundary.prims_to_cons(W, s_ora.gamma)
+
+
+def _box(levels=1, n=(16, 16, 8), block=(8, 8, 8)):
+    return dict(geometry="cartesian", x0=(0.0, 0.0, 0.0), x1=(1.0, 1.0, 0.5), n=n, block=block,
+                periodic=(True, True, True), max_level=levels, gamma=1.5, cfl=0.4)
+
+
+# --- single level ---------------------------------------------------------------
+
+def test_tiny_wedge_one_step():
+    ic = _ic()
+    g, wind, cme, amr = tiny_wedge()
+    ora = solver.Solver(g, wind, cme, amr)
+    gpu = ic.Sim(g, wind, [cme], amr)
+    bl0, U0 = gpu.state()
+    bo, Uo = ora.state()
+    assert bl0 == bo
+    assert rel_err(U0, Uo) <= 1e-15      # same initial condition up to rounding
+    gpu.set_state(bo, Uo, 0.0)           # identical inputs from here on
+    info = gpu.step()
+    dt = ora.step()
+    assert abs(info["dt_s"] / units.T0 - dt) <= 1e-14 * dt
+    bl, U = gpu.state()
+    e = rel_err(U, ora.state()[1])
+    assert e <= 1e-12, e
+    gpu.close()
+
+
+def test_tiny_wedge_hundred_steps():
+    ic = _ic()
+    g, wind, cme, amr = tiny_wedge()
+    ora = solver.Solver(g, wind, cme, amr)
+    gpu = ic.Sim(g, wind, [cme], amr)
+    bo, Uo = ora.state()
+    gpu.set_state(bo, Uo, 0.0)
+    for n in range(100):
+        gpu.step()
+        ora.step()
+    e = rel_err(gpu.state()[1], ora.state()[1])
+    assert e <= 1e-9, e
+    t_gpu, _ = gpu.time()
+    assert abs(t_gpu / units.T0 - ora.t) <= 1e-12 * ora.t
+    gpu.close()
+
+
+def test_periodic_box_fixed_dt_random_state():
+    ic = _ic()
+    g = _box()
+    ora = solver.Solver(g, initial="zero")
+    _smooth_box_state(ora)
+    gpu = ic.Sim(g)
+    bo, Uo = ora.state()
+    gpu.set_state(bo, Uo, 0.0)
+    dt = 2e-3
+    gpu.step(dt * units.T0)
+    ora.step(dt)
+    e = rel_err(gpu.state()[1], ora.state()[1])
+    assert e <= 1e-12, e
+
+
+def test_block_shapes_agree():
+    """The same problem on 4^3 and 8^3 blocks gives the same result."""
+    ic = _ic()
+    out = []
+    for blk in ((4, 4, 4), (8, 8, 8)):
+        g = _box(block=blk)
+        ora = solver.Solver(g, initial="zero")
+        _smooth_box_state(ora)
+        gpu = ic.Sim(g)
+        gpu.set_state(*ora.state(), 0.0)
+        for _ in range(3):
+            gpu.step(1e-3 * units.T0)
+        bl, U = gpu.state()
+        full = np.zeros((8, 8, 16, 16))
+        for b, u in zip(bl, U):
+            full[:, b[3] * blk[2]:(b[3] + 1) * blk[2], b[2] * blk[1]:(b[2] + 1) * blk[1],
+                 b[1] * blk[0]:(b[1] + 1) * blk[0]] = u
+        out.append(full)
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-13 * np.max(np.abs(out[1]))
+
+
+# --- block AMR -------------------------------------------------------------------
+
+def _refined_box_pair(flags_leaves, levels=2):
+    ic = _ic()
+    g = _box(levels=levels)
+    ora = solver.Solver(g, initial="zero")
+    _smooth_box_state(ora)
+    flags = {b: (fo.REFINE if b in flags_leaves else fo.KEEP) for b in ora.forest.leaves}
+    ora.regrid(flags, buffer_blocks=0)
+    gpu = ic.Sim(g, amr=dict(buffer_blocks=0))
+    gpu.set_state(*ora.state(), 0.0)
+    return ora, gpu
+
+
+def test_two_level_box_steps_with_reflux():
+    ora, gpu = _refined_box_pair({(1, 0, 0, 0), (1, 1, 1, 0)})
+    assert gpu.blocks() == ora.blocks()
+    for _ in range(5):
+        ora.step(1e-3)
+        gpu.step(1e-3 * units.T0)
+    e = rel_err(gpu.state()[1], ora.state()[1])
+    assert e <= 1e-12, e
+
+
+def test_regrid_data_movement():
+    ic = _ic()
+    g = _box(levels=3)
+    ora = solver.Solver(g, initial="zero")
+    _smooth_box_state(ora)
+    gpu = ic.Sim(g, amr=dict(buffer_blocks=0))
+    gpu.set_state(*ora.state(), 0.0)
+    rng = np.random.default_rng(4)
+    for _ in range(3):
+        bl = ora.blocks()
+        f = [int(rng.choice([fo.REFINE, fo.KEEP, fo.COARSEN], p=[0.3, 0.4, 0.3])) for _ in bl]
+        ora.regrid(dict(zip(bl, f)), buffer_blocks=0)
+        gpu.regrid([f])
+        assert gpu.blocks() == ora.blocks()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-13, e
+        ora.step(5e-4)
+        gpu.step(5e-4 * units.T0)
+    e = rel_err(gpu.state()[1], ora.state()[1])
+    assert e <= 1e-12, e
+
+
+def _amr_wedge(max_level=3):
+    grid = dict(geometry="spherical", x0=(0.1, 60.0, 0.0), x1=(1.1, 120.0, 90.0), n=(32, 16, 16),
+                block=(8, 8, 8), stretched_r=True, max_level=max_level, periodic=(False, False, False),
+                gamma=1.5, cfl=0.4)
+    from synthetic import Wind
+    wind = as_dict(Wind(seed=3))
+    cme = as_dict(Cme(t_start_s=0.0, duration_s=6 * 3600.0, v_kms=1400.0, half_width_deg=35.0,
+                      colat_deg=90.0, lon_deg=20.0, n_cm3=1500.0, T_K=0.8e6))
+    amr = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
+               lon_earth_deg=0.0, clt_earth_deg=90.0, dlon_earth_deg=60.0, dclt_earth_deg=30.0,
+               dlon_cme_deg=90.0, use_windows=True, regrid_every=5, buffer_blocks=1)
+    return grid, wind, cme, amr
+
+
+def test_stretched_amr_wedge_flags_forest_and_state():
+    ic = _ic()
+    grid, wind, cme, amr = _amr_wedge()
+    ora = solver.Solver(grid, wind, cme, amr)
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    gpu.set_state(*ora.state(), 0.0)
+    for cycle in range(3):
+        for _ in range(5):
+            ora.step()
+            gpu.step()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-10, (cycle, e)
+        # flags on identical states
+        gpu.set_state(*ora.state(), ora.t * units.T0)
+        ties = []
+        fo_flags = ora.flags(ties)
+        assert not ties, "near-tie in the indicator: %r" % ties[:3]
+        fg = gpu.eval_flags()
+        assert [int(x) for x in fg] == [fo_flags[b] for b in ora.blocks()]
+        ora.regrid(fo_flags)
+        gpu.regrid()
+        assert gpu.blocks() == ora.blocks()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-13, (cycle, e)
+    assert max(b[0] for b in ora.blocks()) >= 2
+
+
+def test_sample_point():
+    ic = _ic()
+    grid, wind, cme, amr = _amr_wedge()
+    ora = solver.Solver(grid, wind, cme, amr)
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    flags = {b: (fo.REFINE if b[1] >= 2 else fo.KEEP) for b in ora.forest.leaves}
+    ora.regrid(flags, buffer_blocks=0)
+    gpu.set_state(*ora.state(), 0.0)
+    for p in [(0.55, 90.0, 20.0), (0.8, 97.3, 44.9), (0.3, 75.0, 3.0), (1.05, 118.0, 88.0)]:
+        a = gpu.sample(*p)
+        b = ora.sample(*p)
+        assert np.allclose(a, b, rtol=1e-13, atol=1e-15 * np.abs(b).max()), (p, a, b)
+    with pytest.raises(ic.ICError) as ex:
+        gpu.sample(1.5, 90.0, 20.0)
+    assert ex.value.status == ic.IC_E_OUTSIDE
+
+
+# --- the equidistant full domain at full size ---------------------------------------
+
+def test_equidistant_full_size_one_step():
+    """All 5.5 M cells, the launch configuration the benchmark times."""
+    ic = _ic()
+    from synthetic import workload
+    w = workload("equidistant_full")
+    g, wind, cme = as_dict(w.grid), as_dict(w.wind), as_dict(w.cmes[0])
+    gpu = ic.Sim(g, wind, [cme])
+    ora = solver.PatchSolver(g, wind, cme)
+    dt = 4e-4
+    gpu.step(dt * units.T0)
+    ora.step(dt)
+    bl, U = gpu.state()
+    bo, Uo = ora.to_blocks(g["block"])
+    assert bl == bo
+    e = rel_err(U, Uo)
+    assert e <= 1e-12, e
+
+
+# --- failure handling ----------------------------------------------------------------
+
+def test_unphysical_state_poisons_the_sim():
+    ic = _ic()
+    g = _box()
+    ora = solver.Solver(g, initial="zero")
+    _smooth_box_state(ora)
+    gpu = ic.Sim(g)
+    bl, U = ora.state()
+    U = U.copy()
+    U[3, 4, 2, 2, 2] = -1.0          # negative total energy -> p < 0
+    gpu.set_state(bl, U, 0.0)
+    with pytest.raises(ic.ICError) as ex:
+        gpu.step(1e-4 * units.T0)
+    assert ex.value.status == ic.IC_E_UNPHYSICAL
+    with pytest.raises(ic.ICError) as ex:
+        gpu.step(1e-4 * units.T0)
+    assert ex.value.status == ic.IC_E_STATE
+
+
+def test_capacity_error():
+    ic = _ic()
+    g = _box(levels=2)
+    gpu = ic.Sim(g, amr=dict(buffer_blocks=0), max_blocks=10)
+    with pytest.raises(ic.ICError) as ex:
+        gpu.regrid([[1] * len(gpu.blocks())])
+    assert ex.value.status == ic.IC_E_CAPACITY
+
+
+def test_invalid_config():
+    ic = _ic()
+    g = _box()
+    g["block"] = (6, 6, 6)
+    g["n"] = (12, 12, 6)
+    with pytest.raises(ic.ICError) as ex:
+        ic.Sim(g)
+    assert ex.value.status == ic.IC_E_INVALID

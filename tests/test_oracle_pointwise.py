@@ -141,3 +141,18 @@ def test_gravity_source():
     S = _clib.sources(w, 0.0, 0.0, 0.5, 1.0, 0.0, 0.0, 1e-3)
     g = -1e-3 / 0.25
     assert S[1] == 2.0 * g and S[4] == 2.0 * 0.5 * g
+
+
+def test_small_value_floors():
+    from oracle.solver import apply_floors
+    g = 1.5
+    U = np.array([[2e-7, 1.0], [4e-7, 0.5], [0.0, 0.1], [0.0, 0.0], [1e-3, 1.0], [0.1, 0.2],
+                  [0.0, 0.0], [0.0, 0.0]])
+    U0 = U.copy()
+    n = apply_floors(U, g, 1e-6, 1e-9)
+    # cell 0: density raised at unchanged velocity, then pressure floored exactly
+    assert U[0, 0] == 1e-6 and abs(U[1, 0] / U[0, 0] - 2.0) < 1e-15
+    W = np.array(_clib.prim(U[:, 0], g))
+    assert abs(W[4] - 1e-9) <= 1e-9 * 1e-6 * (U[4, 0] / 1e-9)
+    # cell 1 is physical and untouched
+    assert np.array_equal(U[:, 1], U0[:, 1]) and n == 2
