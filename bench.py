@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the single-run hot path has no multi-GPU path in this build "
@@ -116,6 +118,16 @@ def main():
     sim.close()
     print("bench: %d steps in %.3f s, stage kernel %d launches, mean %.3f ms, t = %.0f s, dt = %.1f s"
           % (args.steps, el, launches, mean_ms, t_s, dt_s), file=sys.stderr, flush=True)
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: copy calibration, 3 copies of %d bytes" % (n * 8), file=sys.stderr, flush=True)
+        del src, dst
 
     bytes_launch = BYTES_PER_CELL_LAUNCH * cells
     achieved = bytes_launch / (mean_ms * 1e-3) / 1e9

@@ -15,24 +15,33 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = ["hipcc", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+        cmd = ["hipcc", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + \
+              ["-D" + d for d in defines]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+        # the host pass does not know the device-only feature flag; drop that note
+        noise = "is not a recognized feature for this target"
+        text = "\n".join(l for l in res.stdout.splitlines() if noise not in l)
+        if text.strip():
+            print(text, flush=True)
+        if res.returncode != 0:
+            raise subprocess.CalledProcessError(res.returncode, cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
     for o in objs:
         os.remove(o)
-    return LIB
+    return target
 
 
 if __name__ == "__main__":

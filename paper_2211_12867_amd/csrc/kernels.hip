@@ -52,8 +52,44 @@ __device__ inline double block_max(double x, double *scratch)
 // ---------------------------------------------------------------------------
 // fused stage kernel
 // ---------------------------------------------------------------------------
+
+// Left and right states at the face between cells c1 and c2 of an LDS line
+// c0 c1 c2 c3 (cell stride cs, variable stride vs), reconstructed one
+// variable at a time so that only the two face states stay live.  The
+// zero-slope fallback of a cell applies when one of its two face densities or
+// pressures is not positive.
+template <class Rec>
+DEV void face_states(const double *p, int cs, int vs, const Rec &r1, const Rec &r2, double L[8], double R[8])
+{
+    bool ok1 = true, ok2 = true;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double a = p[v * vs], b = p[v * vs + cs], c = p[v * vs + 2 * cs], d = p[v * vs + 3 * cs];
+        const double s1 = mc_slope(a, b, c, r1.idm, r1.idp, r1.idc);
+        const double s2 = mc_slope(b, c, d, r2.idm, r2.idp, r2.idc);
+        L[v] = b + s1 * r1.hp;
+        R[v] = c - s2 * r2.hm;
+        if (v == 0 || v == 4) {
+            ok1 = ok1 && (b - s1 * r1.hm > 0.0) && (L[v] > 0.0);
+            ok2 = ok2 && (R[v] > 0.0) && (c + s2 * r2.hp > 0.0);
+        }
+    }
+    if (!ok1) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) L[v] = p[v * vs + cs];
+    }
+    if (!ok2) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) R[v] = p[v * vs + 2 * cs];
+    }
+}
+
 template <int BI, int BJ, int BK>
-__global__ void __launch_bounds__(NT) k_stage(KArgs a)
+#ifndef IC_STAGE_WAVES
+#define IC_STAGE_WAVES 2
+#endif
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(IC_STAGE_WAVES, IC_STAGE_WAVES)))
+k_stage(KArgs a)
 {
     using S = Shape<BI, BJ, BK>;
     constexpr int PI = BI + 4, PJ = BJ + 4;
@@ -78,56 +114,45 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a)
 
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const int slot = a.items[it];
-        const BlockDesc bd = a.desc[slot];
-        const int mem = bd.member;
+        struct { int org[3]; int reflux_mask; } bd;
+        const int mem = a.desc[slot].member;
+        for (int e = 0; e < 3; ++e) bd.org[e] = a.desc[slot].org[e];
+        bd.reflux_mask = a.desc[slot].reflux_mask;
         const double dt = a.dt[mem];
         if (dt <= 0.0) continue;                 // member finished: state stays in place
-        const LevelGeo lg = a.geo[bd.level];
+        const LevelGeo lg = a.geo[a.desc[slot].level];
         const double adt = a.alpha * dt;
 
         __syncthreads();
         for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
-        __syncthreads();
 
-        // --- prologue: column primitives for k = -2 .. 1, first phi-face flux
-        double Wk[8], Wk1[8], wLk[8], Fkm[8];
-        double rtc = 0.0, thmc = 0.0, thpc = 0.0, amc = 0.0, apc = 0.0;
+        // --- prologue: column primitives of planes 0 and 1, phi-face -1/2
+        // registers carried along k: Wc = W(k), Wn = W(k+1), wL = face state of
+        // cell k at k+1/2, Fm = flux at k-1/2
+        double Wc[8], Wn[8], wL[8], Fm[8];
         bool badc = false;
         if (col) {
-            double u[8], w0[8], w1[8], w2[8], w3[8];
+            double u[8], w0[8], w1[8], lo[8], hi[8], R0[8];
             ghosted8<S>(a, a.U, slot, ci, cj, -2, u); cons_to_prim(u, w0, gs);
             ghosted8<S>(a, a.U, slot, ci, cj, -1, u); cons_to_prim(u, w1, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, 0, u);  cons_to_prim(u, w2, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, 1, u);  cons_to_prim(u, w3, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, 0, u);  cons_to_prim(u, Wc, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, 1, u);  cons_to_prim(u, Wn, gs);
             const RecP pm1 = lg.p[bd.org[2] - 1 + 2], p0 = lg.p[bd.org[2] + 2];
-            double lo[8], hi[8], lo0[8], hi0[8];
-            reconstruct(w0, w1, w2, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
-            reconstruct(w1, w2, w3, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, lo0, hi0);
-            rusanov<2>(hi, lo0, Fkm, gs);
-#pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                Wk[v] = w2[v];
-                Wk1[v] = w3[v];
-                wLk[v] = hi0[v];
-            }
-            const RecR rr = sR[ci + 2];
-            const RecT tt = sT[cj + 2];
-            rtc = rr.rt;
-            amc = rr.am;
-            apc = rr.ap;
-            thmc = rr.rt * tt.thm;
-            thpc = rr.rt * tt.thp;
+            reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
+            reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
+            rusanov<2>(hi, R0, Fm, gs);
+            const int r = a.desc[slot].freg[4];
+            if (r >= 0)
+                for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
         }
         double rmax = 0.0;
 
         for (int k = 0; k < BK; ++k) {
-            const RecP pk = lg.p[bd.org[2] + k + 2];
-            const RecP pk1 = lg.p[bd.org[2] + k + 3];
             // (a) plane k into LDS: own column + i/j halos
             if (col) {
 #pragma unroll
-                for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wk[v];
+                for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
             }
             for (int t = tid; t < NHALO; t += NT) {
                 int i, j;
@@ -149,76 +174,81 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a)
 #pragma unroll
                 for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
             }
-            double un[8];
-            if (col) ghosted8<S>(a, a.U, slot, ci, cj, k + 2, un);
             __syncthreads();
 
             // (c) r-faces of the plane: face f lies between cells f-1 and f
             for (int t = tid; t < NFI; t += NT) {
                 const int f = t % (BI + 1), j = t / (BI + 1);
-                double wa[8], wb[8], wc[8], wd[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    wa[v] = sW[v][j + 2][f];
-                    wb[v] = sW[v][j + 2][f + 1];
-                    wc[v] = sW[v][j + 2][f + 2];
-                    wd[v] = sW[v][j + 2][f + 3];
-                }
-                const RecR ra = sR[f + 1], rb = sR[f + 2];
-                double lo[8], hi[8], lo2[8], hi2[8], fx[8];
-                reconstruct(wa, wb, wc, ra.idm, ra.idp, ra.idc, ra.hm, ra.hp, lo, hi);
-                reconstruct(wb, wc, wd, rb.idm, rb.idp, rb.idc, rb.hm, rb.hp, lo2, hi2);
-                rusanov<0>(hi, lo2, fx, gs);
+                double L[8], R[8], fx[8];
+                face_states(&sW[0][j + 2][f], 1, PJ * PI, sR[f + 1], sR[f + 2], L, R);
+                rusanov<0>(L, R, fx, gs);
 #pragma unroll
                 for (int v = 0; v < 8; ++v) sFi[v][j][f] = fx[v];
+                if (f == 0 || f == BI) {          // raw flux at a coarse-fine face, for the reflux
+                    const int r = a.desc[slot].freg[f == 0 ? 0 : 1];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
+                }
             }
             // (d) theta-faces of the plane
             for (int t = tid; t < NFJ; t += NT) {
                 const int i = t % BI, f = t / BI;
-                double wa[8], wb[8], wc[8], wd[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    wa[v] = sW[v][f][i + 2];
-                    wb[v] = sW[v][f + 1][i + 2];
-                    wc[v] = sW[v][f + 2][i + 2];
-                    wd[v] = sW[v][f + 3][i + 2];
-                }
-                const RecT ta = sT[f + 1], tb = sT[f + 2];
-                double lo[8], hi[8], lo2[8], hi2[8], fx[8];
-                reconstruct(wa, wb, wc, ta.idm, ta.idp, ta.idc, ta.hm, ta.hp, lo, hi);
-                reconstruct(wb, wc, wd, tb.idm, tb.idp, tb.idc, tb.hm, tb.hp, lo2, hi2);
-                rusanov<1>(hi, lo2, fx, gs);
+                double L[8], R[8], fx[8];
+                face_states(&sW[0][f][i + 2], PI, PJ * PI, sT[f + 1], sT[f + 2], L, R);
+                rusanov<1>(L, R, fx, gs);
 #pragma unroll
                 for (int v = 0; v < 8; ++v) sFj[v][f][i] = fx[v];
+                if (f == 0 || f == BJ) {
+                    const int r = a.desc[slot].freg[f == 0 ? 2 : 3];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
+                }
             }
-            // (e) phi-face k+1/2 of the column
-            double Fkp[8], lo1[8], hi1[8];
+            // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
+            double Fp[8];
             if (col) {
-                double wn[8];
-                cons_to_prim(un, wn, gs);
-                reconstruct(Wk, Wk1, wn, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
-                rusanov<2>(wLk, lo1, Fkp, gs);
+                double u[8], W2[8], lo1[8], w0[8];
+                ghosted8<S>(a, a.U, slot, ci, cj, k + 2, u);
+                cons_to_prim(u, W2, gs);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) un[v] = wn[v];
+                for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
+                const RecP pk1 = lg.p[bd.org[2] + k + 3];
+                double hi1[8];
+                reconstruct(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
+                rusanov<2>(wL, lo1, Fp, gs);
+                if (k == BK - 1) {
+                    const int r = a.desc[slot].freg[5];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fp[v];
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    wL[v] = hi1[v];
+                    Wc[v] = Wn[v];
+                    Wn[v] = W2[v];
+                }
             }
             __syncthreads();
 
             // (g) update of cell (ci, cj, k)
             if (col) {
-                badc = badc || unphysical(Wk);
+                const RecP pk = lg.p[bd.org[2] + k + 2];
+                const RecR rr = sR[ci + 2];
+                const RecT tt = sT[cj + 2];
+                double w[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) w[v] = sW[v][cj + 2][ci + 2];
+                badc = badc || unphysical(w);
                 double acc[8];
-                const double kf = rtc * sT[cj + 2].phf * pk.iw;
+                const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
+                const double kf = rr.rt * tt.phf * pk.iw;
 #pragma unroll
                 for (int v = 0; v < 8; ++v) {
-                    acc[v] = -(apc * sFi[v][cj][ci + 1] - amc * sFi[v][cj][ci])
-                             - (thpc * sFj[v][cj + 1][ci] - thmc * sFj[v][cj][ci])
-                             - kf * (Fkp[v] - Fkm[v]);
+                    acc[v] = -(rr.ap * sFi[v][cj][ci + 1] - rr.am * sFi[v][cj][ci])
+                             - (thp * sFj[v][cj + 1][ci] - thm * sFj[v][cj][ci])
+                             - kf * (Fp[v] - Fm[v]);
                 }
-                if (!a.cart) {
-                    const RecR rr = sR[ci + 2];
-                    const RecT tt = sT[cj + 2];
-                    add_sources(Wk, rtc, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
-                }
+                if (!a.cart) add_sources(w, rr.rt, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
                 const size_t base = cidx<S>(slot, 0, ci, cj, k);
                 double unew[8];
 #pragma unroll
@@ -231,41 +261,14 @@ __global__ void __launch_bounds__(NT) k_stage(KArgs a)
 #pragma unroll
                 for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
                 if (a.want_rate) {
-                    double w[8];
                     cons_to_prim(unew, w, gs);
-                    const RecR rr = sR[ci + 2];
-                    const RecT tt = sT[cj + 2];
                     const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
                                       + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
                                       + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pk.iw;
                     rmax = rate > rmax ? rate : rmax;
                 }
-                // raw fluxes at coarse-fine faces for the reflux
-                if (ci == 0 && bd.freg[0] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[0] * a.reg_stride + ((size_t)v * BK + k) * BJ + cj] = sFi[v][cj][0];
-                if (ci == BI - 1 && bd.freg[1] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[1] * a.reg_stride + ((size_t)v * BK + k) * BJ + cj] = sFi[v][cj][BI];
-                if (cj == 0 && bd.freg[2] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[2] * a.reg_stride + ((size_t)v * BK + k) * BI + ci] = sFj[v][0][ci];
-                if (cj == BJ - 1 && bd.freg[3] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[3] * a.reg_stride + ((size_t)v * BK + k) * BI + ci] = sFj[v][BJ][ci];
-                if (k == 0 && bd.freg[4] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[4] * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fkm[v];
-                if (k == BK - 1 && bd.freg[5] >= 0)
-                    for (int v = 0; v < 8; ++v)
-                        a.freg[(size_t)bd.freg[5] * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fkp[v];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    Fkm[v] = Fkp[v];
-                    Wk[v] = Wk1[v];
-                    Wk1[v] = un[v];
-                    wLk[v] = hi1[v];
-                }
+                for (int v = 0; v < 8; ++v) Fm[v] = Fp[v];
             }
         }
         if (col && badc) a.bad[mem] = 1;
