@@ -132,7 +132,12 @@ typedef struct {
     int use_windows;
     int regrid_every;
     int buffer_blocks;
+    int source;             /* IC_SOURCE_*: where ic_regrid(sim, NULL, ...) takes its flags from */
+    int judge_every;        /* learned + judge: evaluate the plain criterion every judge_every-th regrid */
+    double judge_recall;    /* fall back to the plain flags for 10 regrids below this REFINE recall */
 } ic_amr_cfg;
+
+enum { IC_SOURCE_PLAIN = 0, IC_SOURCE_LEARNED = 1, IC_SOURCE_LEARNED_JUDGED = 2 };
 
 typedef struct {
     long steps;              /* steps taken by member 0 since ic_create */
@@ -216,6 +221,55 @@ ic_status ic_set_state(ic_sim *sim, int member, const int32_t *lvl_ijk, int n_bl
 
 /* Time and last dt of a member [s]. */
 ic_status ic_get_time(ic_sim *sim, int member, double *t_s, double *dt_s);
+
+/* ---- learned refinement flags -------------------------------------------
+ * A per-block network predicts whether the plain criterion will ask for
+ * refinement: input 512 values = 8 primitives (log10 rho, v_r, v_theta, v_phi,
+ * log10 p, B_r, B_theta, B_phi; code units) averaged over the cells of each of
+ * the 4 x 4 x 4 sub-cubes of the block, order [primitive][k][j][i], z-scored
+ * per input with training statistics; layers 512 -> 128 -> 128 -> 1, ReLU,
+ * sigmoid; weights, inputs and hidden activations in bf16 with fp32
+ * accumulation; p >= 1/2 means REFINE, otherwise the block may coarsen.
+ * Parameter vector (fp32, IC_MLP_NPARAM values): W1[512][128] (input-major),
+ * b1[128], W2[128][128], b2[128], w3[128], b3. */
+#define IC_MLP_IN 512
+#define IC_MLP_NPARAM 82305
+
+typedef struct {
+    int epochs, batch;
+    float lr, beta1, beta2, eps;
+    unsigned seed;           /* shuffling */
+    float pos_weight;        /* <= 0: N_neg / N_pos of the training set */
+} ic_mlp_hparams;
+
+/* Un-normalised inputs of a member's leaves (ic_get_blocks order) into
+ * raw[n x 512] fp32; block dims must be multiples of 4. */
+ic_status ic_features(ic_sim *sim, int member, float *raw, int n);
+
+/* Install a trained network (params fp32, per-input mean and std). */
+ic_status ic_mlp_set(ic_sim *sim, const float *params, const float *mean, const float *std);
+
+/* Network probability and flag (IC_FLAG_REFINE / IC_FLAG_COARSEN) per leaf. */
+ic_status ic_eval_learned(ic_sim *sim, int member, float *prob, int8_t *flags, int n);
+
+/* Learned-flag bookkeeping since ic_create: regrids that used the network,
+ * regrids judged, judged regrids that fell back, and the last judged REFINE
+ * recall of member 0. */
+ic_status ic_regrid_stats(ic_sim *sim, long *learned, long *judged, long *fallbacks, double *last_recall);
+
+/* Train on n rows (raw inputs as ic_features gives them, labels 0/1) with
+ * weighted binary cross-entropy and Adam on fp32 master weights, fwd/bwd on
+ * the GPU.  params: initial values in, trained values out; mean/std out;
+ * loss_per_epoch (may be NULL) gets the mean loss of each epoch.  Runs on the
+ * null stream of the current device. */
+ic_status ic_mlp_train(const float *raw, const uint8_t *y, long n, const ic_mlp_hparams *hp, float *params,
+                       float *mean, float *std, float *loss_per_epoch);
+
+/* One forward and backward pass on n rows of already normalised inputs
+ * (fp32, rounded to bf16 inside): gradient of the mean weighted BCE in
+ * params layout, and the loss. */
+ic_status ic_mlp_grad(const float *xnorm, const uint8_t *y, int n, float pos_weight, const float *params,
+                      float *grad, float *loss);
 
 /* Code-unit scales in SI: [0] length m, [1] speed m/s, [2] time s, [3]
  * density kg/m^3, [4] pressure Pa, [5] field T. */

@@ -25,6 +25,8 @@ IC_OK, IC_E_INVALID, IC_E_NOMEM, IC_E_DEVICE, IC_E_UNPHYSICAL, IC_E_OUTSIDE, IC_
 IC_GEOM_SPHERICAL, IC_GEOM_CARTESIAN = 0, 1
 IC_BC_OUTFLOW, IC_BC_PERIODIC, IC_BC_INNER = 0, 1, 2
 IC_FLAG_COARSEN, IC_FLAG_KEEP, IC_FLAG_REFINE = -1, 0, 1
+IC_SOURCE_PLAIN, IC_SOURCE_LEARNED, IC_SOURCE_LEARNED_JUDGED = 0, 1, 2
+MLP_IN, MLP_HID, MLP_NPARAM = 512, 128, 82305
 
 OMEGA_SUN = 2.0 * math.pi / (25.38 * 86400.0)     # sidereal, rad/s
 RHO_FLOOR = 1.0e-6                                  # code units
@@ -71,7 +73,14 @@ class AmrCfg(ctypes.Structure):
                 ("lon_earth_deg", ctypes.c_double), ("clt_earth_deg", ctypes.c_double),
                 ("dlon_earth_deg", ctypes.c_double), ("dclt_earth_deg", ctypes.c_double),
                 ("dlon_cme_deg", ctypes.c_double), ("use_windows", ctypes.c_int),
-                ("regrid_every", ctypes.c_int), ("buffer_blocks", ctypes.c_int)]
+                ("regrid_every", ctypes.c_int), ("buffer_blocks", ctypes.c_int), ("source", ctypes.c_int),
+                ("judge_every", ctypes.c_int), ("judge_recall", ctypes.c_double)]
+
+
+class MlpHparams(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint), ("pos_weight", ctypes.c_float)]
 
 
 class Info(ctypes.Structure):
@@ -87,7 +96,8 @@ class Info(ctypes.Structure):
 EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_eval_flags", "ic_sample",
            "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks", "ic_get_state",
            "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
-           "ic_stage_timing", "ic_pool_capacity", "ic_last_error")
+           "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
+           "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_last_error")
 
 
 def _load():
@@ -123,6 +133,13 @@ def _load():
     L.ic_block_supported.restype = ctypes.c_int
     L.ic_set_kernel_timing.argtypes = [vp, ctypes.c_int]
     L.ic_stage_timing.argtypes = [vp, P(ctypes.c_long), P(ctypes.c_double)]
+    fp, u8p, i8p = P(ctypes.c_float), P(ctypes.c_uint8), P(ctypes.c_int8)
+    L.ic_features.argtypes = [vp, ctypes.c_int, fp, ctypes.c_int]
+    L.ic_mlp_set.argtypes = [vp, fp, fp, fp]
+    L.ic_eval_learned.argtypes = [vp, ctypes.c_int, fp, i8p, ctypes.c_int]
+    L.ic_regrid_stats.argtypes = [vp, P(ctypes.c_long), P(ctypes.c_long), P(ctypes.c_long), P(ctypes.c_double)]
+    L.ic_mlp_train.argtypes = [fp, u8p, ctypes.c_long, P(MlpHparams), fp, fp, fp, fp]
+    L.ic_mlp_grad.argtypes = [fp, u8p, ctypes.c_int, ctypes.c_float, fp, fp, fp]
     L.ic_pool_capacity.argtypes = [vp]
     L.ic_pool_capacity.restype = ctypes.c_int
     L.ic_last_error.restype = ctypes.c_char_p
@@ -212,7 +229,8 @@ def amr_cfg(amr):
     a = AmrCfg()
     defaults = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
                     lon_earth_deg=0.0, clt_earth_deg=90.0, dlon_earth_deg=30.0, dclt_earth_deg=10.0,
-                    dlon_cme_deg=90.0, use_windows=True, regrid_every=10, buffer_blocks=1)
+                    dlon_cme_deg=90.0, use_windows=True, regrid_every=10, buffer_blocks=1, source=0,
+                    judge_every=10, judge_recall=0.9)
     for key, dv in defaults.items():
         v = _get(amr, key, dv)
         setattr(a, key, int(v) if isinstance(dv, (bool, int)) and not isinstance(dv, float) else float(v))
@@ -360,3 +378,90 @@ class Sim:
         n, ms = ctypes.c_long(), ctypes.c_double()
         _check(lib.ic_stage_timing(self.h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    # --- learned flags ------------------------------------------------------------
+    def features(self, member=0):
+        n = len(self.blocks(member))
+        out = np.zeros((n, MLP_IN), dtype=np.float32)
+        _check(lib.ic_features(self.h, member, _fptr(out), n))
+        return out
+
+    def mlp_set(self, params, mean, std):
+        self._mlp = [np.ascontiguousarray(params, dtype=np.float32), np.ascontiguousarray(mean, dtype=np.float32),
+                     np.ascontiguousarray(std, dtype=np.float32)]
+        _check(lib.ic_mlp_set(self.h, *[_fptr(a) for a in self._mlp]))
+
+    def eval_learned(self, member=0):
+        n = len(self.blocks(member))
+        prob = np.zeros(n, dtype=np.float32)
+        flags = np.zeros(n, dtype=np.int8)
+        _check(lib.ic_eval_learned(self.h, member, _fptr(prob), flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
+        return prob, flags
+
+    def regrid_stats(self):
+        v = [ctypes.c_long(), ctypes.c_long(), ctypes.c_long(), ctypes.c_double()]
+        _check(lib.ic_regrid_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(learned=v[0].value, judged=v[1].value, fallbacks=v[2].value, last_recall=v[3].value)
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def mlp_train(raw, y, params, epochs=10, batch=4096, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+              pos_weight=0.0):
+    """Train the learned-flag network on the GPU; returns (params, mean, std, loss per epoch)."""
+    raw = np.ascontiguousarray(raw, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    params = np.array(params, dtype=np.float32, copy=True)
+    mean = np.zeros(MLP_IN, dtype=np.float32)
+    std = np.zeros(MLP_IN, dtype=np.float32)
+    loss = np.zeros(max(epochs, 1), dtype=np.float32)
+    hp = MlpHparams(epochs, batch, lr, beta1, beta2, eps, seed, pos_weight)
+    _check(lib.ic_mlp_train(_fptr(raw), y.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(y), ctypes.byref(hp),
+                            _fptr(params), _fptr(mean), _fptr(std), _fptr(loss)))
+    return params, mean, std, loss[:epochs]
+
+
+def mlp_grad(xnorm, y, params, pos_weight=1.0):
+    """Gradient of the mean weighted BCE on the GPU for already normalised inputs."""
+    xnorm = np.ascontiguousarray(xnorm, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    grad = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(lib.ic_mlp_grad(_fptr(xnorm), y.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(y),
+                           float(pos_weight), _fptr(params), _fptr(grad), ctypes.byref(loss)))
+    return grad, loss.value
+
+
+def mlp_init(seed=0):
+    """He-uniform initial parameters (fp32) in the library's parameter layout."""
+    g = np.random.default_rng(seed)
+    p = np.zeros(MLP_NPARAM, dtype=np.float32)
+    o = 0
+    for fan_in, fan_out in ((MLP_IN, MLP_HID), (MLP_HID, MLP_HID), (MLP_HID, 1)):
+        lim = math.sqrt(6.0 / fan_in)
+        p[o:o + fan_in * fan_out] = g.uniform(-lim, lim, fan_in * fan_out)
+        o += fan_in * fan_out + fan_out
+    return p
+
+
+def arrival(t_h, v, t_cme_h, window_h=96.0):
+    """Shock arrival after the CME start [h] and width [h] from a v_r series: v_pre =
+    v_r at the CME start, v_max = max within window_h after it, arrival = first
+    crossing of v_pre + (v_max - v_pre)/2 (linear between samples), width =
+    t(v_max) - arrival.  Returns (nan, nan) without a crossing."""
+    t_h = np.asarray(t_h, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    v_pre = float(np.interp(t_cme_h, t_h, v))
+    idx = np.nonzero((t_h >= t_cme_h) & (t_h <= t_cme_h + window_h))[0]
+    if len(idx) == 0:
+        return float("nan"), float("nan")
+    imax = int(idx[np.argmax(v[idx])])
+    thr = v_pre + 0.5 * (float(v[imax]) - v_pre)
+    for a in idx[1:] if idx[0] == 0 else idx:
+        if v[a - 1] < thr <= v[a]:
+            ta = t_h[a - 1] + (thr - v[a - 1]) * (t_h[a] - t_h[a - 1]) / (v[a] - v[a - 1])
+            return float(ta - t_cme_h), float(t_h[imax] - ta)
+    return float("nan"), float("nan")

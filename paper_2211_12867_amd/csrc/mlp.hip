@@ -1,0 +1,480 @@
+// mlp.hip -- learned refinement flags: per-block features, a 512-128-128-1 MLP
+// on bf16 MFMA (fp32 accumulate), its backward pass and Adam.
+//
+// The network predicts, from a block's primitive variables, whether the plain
+// refinement criterion (Loehner density/velocity estimator with div V < 0 in
+// the Earth/CME windows, paper Sect. 3.2) will ask for refinement of that
+// block; the plain criterion stays the judge and the fallback.
+//
+// Rounding points (the CPU reference follows the same ones): inputs X, the
+// weights W1, W2, w3 and the hidden activations H1 = relu(Z1), H2 = relu(Z2)
+// are bf16 (round to nearest even from fp32); products accumulate in fp32; in
+// the backward pass dZ2 and dZ1 enter the GEMMs as bf16 while the bias
+// gradients sum the fp32 values.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mlp.h"
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline uint16_t f2bf(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// features: 8 primitives x 4^3 patch means, [prim][k][j][i]
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(256) k_features(KArgs a, const int *items, const int *nitems_ptr, float *raw,
+                                                  const float *mean, const float *istd, uint16_t *xb)
+{
+    using S = Shape<BI, BJ, BK>;
+    constexpr int PI = BI / 4, PJ = BJ / 4, PK = BK / 4;
+    const int n = *nitems_ptr;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = items[it];
+        const int t = threadIdx.x;
+        if (t < 64) {
+            const int pi = t & 3, pj = (t >> 2) & 3, pk = t >> 4;
+            double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int k = pk * PK; k < (pk + 1) * PK; ++k)
+                for (int j = pj * PJ; j < (pj + 1) * PJ; ++j)
+                    for (int i = pi * PI; i < (pi + 1) * PI; ++i) {
+                        double u[8], w[8];
+                        for (int v = 0; v < 8; ++v)
+                            u[v] = a.U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + BI * (j + BJ * k)];
+                        cons_to_prim(u, w, a.gas);
+                        for (int v = 0; v < 8; ++v) sum[v] += w[v];
+                    }
+            const double inv = 1.0 / (PI * PJ * PK);
+            for (int v = 0; v < 8; ++v) {
+                double m = sum[v] * inv;
+                if (v == 0 || v == 4) m = log10(m);
+                const float f = (float)m;
+                const int idx = v * 64 + t;
+                if (raw) raw[(size_t)it * IC_MLP_IN + idx] = f;
+                if (xb) xb[(size_t)it * IC_MLP_IN + idx] = f2bf((f - mean[idx]) * istd[idx]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C = A B (+ bias, relu), bf16 operands, fp32 accumulate on
+// v_mfma_f32_16x16x16_bf16.  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
+// Work-group of 4 waves computes a 32x32 tile, one 16x16 sub-tile per wave.
+// MFMA operand layout (wave64): lane l holds row/column (l % 16) of the A/B
+// fragment and k = 4 (l / 16) + 0..3; the accumulator holds column l % 16 and
+// rows 4 (l / 16) + 0..3.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+    const uint16_t *A;
+    long sam, sak;
+    const uint16_t *B;
+    long sbk, sbn;
+    int M, N, K;
+    const float *bias;
+    int relu;
+    float *Cf;
+    uint16_t *Cb;
+    long ldc;
+};
+
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int m0 = blockIdx.y * 32 + (wave & 1) * 16;
+    const int n0 = blockIdx.x * 32 + (wave >> 1) * 16;
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const bool mok = m0 + r < g.M, nok = n0 + r < g.N;
+    for (int k0 = 0; k0 < g.K; k0 += 16) {
+        short4_t av, bv;
+        for (int t = 0; t < 4; ++t) {
+            const int k = k0 + kq + t;
+            av[t] = (mok && k < g.K) ? (short)g.A[(long)(m0 + r) * g.sam + (long)k * g.sak] : (short)0;
+            bv[t] = (nok && k < g.K) ? (short)g.B[(long)k * g.sbk + (long)(n0 + r) * g.sbn] : (short)0;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    for (int t = 0; t < 4; ++t) {
+        const int m = m0 + kq + t, n = n0 + r;
+        if (m < g.M && n < g.N) {
+            float v = acc[t];
+            if (g.bias) v += g.bias[n];
+            if (g.relu) v = v > 0.f ? v : 0.f;
+            if (g.Cf) g.Cf[(long)m * g.ldc + n] = v;
+            if (g.Cb) g.Cb[(long)m * g.ldc + n] = f2bf(v);
+        }
+    }
+}
+
+// logit, probability and (training) the weighted-BCE gradient per row:
+// z = sum_j H2[j] w3[j] + b3 (fp32, j ascending); dl/dz = (s (pw y + 1 - y) - pw y) / n
+__global__ void k_head(const uint16_t *H2, const uint16_t *w3, const float *b3, int n, const uint8_t *y,
+                       float pw, float *z, float *prob, float *dz, float *loss)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    float s = 0.f;
+    for (int j = 0; j < IC_MLP_HID; ++j) s += bf2f(H2[(long)b * IC_MLP_HID + j]) * bf2f(w3[j]);
+    s += b3[0];
+    const float p = 1.f / (1.f + expf(-s));
+    if (z) z[b] = s;
+    if (prob) prob[b] = p;
+    if (y) {
+        const float yy = (float)y[b];
+        dz[b] = (p * (pw * yy + 1.f - yy) - pw * yy) / (float)n;
+        // stable log-sigmoid terms
+        const float lsp = s >= 0.f ? -log1pf(expf(-s)) : s - log1pf(expf(s));     // log p
+        const float lsn = s >= 0.f ? -s - log1pf(expf(-s)) : -log1pf(expf(s));   // log (1 - p)
+        loss[b] = -(pw * yy * lsp + (1.f - yy) * lsn);
+    }
+}
+
+// dZ2 = dz w3 [H2 > 0] (fp32 and bf16 copies)
+__global__ void k_back2(const float *dz, const uint16_t *w3, const uint16_t *H2, int n, float *dZ2, uint16_t *dZ2b)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)n * IC_MLP_HID) return;
+    const int b = (int)(q / IC_MLP_HID), j = (int)(q % IC_MLP_HID);
+    const float v = bf2f(H2[q]) > 0.f ? dz[b] * bf2f(w3[j]) : 0.f;
+    dZ2[q] = v;
+    dZ2b[q] = f2bf(v);
+}
+
+// dZ1 = dH1 [H1 > 0]
+__global__ void k_mask(const float *dH, const uint16_t *H, long count, float *dZ, uint16_t *dZb)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const float v = bf2f(H[q]) > 0.f ? dH[q] : 0.f;
+    dZ[q] = v;
+    dZb[q] = f2bf(v);
+}
+
+// column sums out[j] = sum_b w[b] * M[b][j] (w = NULL: plain sums), fp32, b ascending
+__global__ void k_colsum(const float *Mf, const uint16_t *Mb, const float *w, int n, int ncol, float *out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncol) return;
+    float s = 0.f;
+    for (int b = 0; b < n; ++b) {
+        const float m = Mf ? Mf[(long)b * ncol + j] : bf2f(Mb[(long)b * ncol + j]);
+        s += w ? w[b] * m : m;
+    }
+    out[j] = s;
+}
+
+__global__ void k_adam(float *w, uint16_t *wb, const float *g, float *m1, float *m2, int n, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gg = g[q];
+    m1[q] = b1 * m1[q] + (1.f - b1) * gg;
+    m2[q] = b2 * m2[q] + (1.f - b2) * gg * gg;
+    const float mh = m1[q] / c1, vh = m2[q] / c2;
+    w[q] -= lr * mh / (sqrtf(vh) + eps);
+    if (wb) wb[q] = f2bf(w[q]);
+}
+
+__global__ void k_to_bf16(const float *x, uint16_t *y, long n)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) y[q] = f2bf(x[q]);
+}
+
+// normalised bf16 inputs from raw fp32 features
+__global__ void k_normalise(const float *raw, const float *mean, const float *istd, long n, uint16_t *xb)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n * IC_MLP_IN) return;
+    const int f = (int)(q % IC_MLP_IN);
+    xb[q] = f2bf((raw[q] - mean[f]) * istd[f]);
+}
+
+// minibatch gather: rows order[b0 + q] of the normalised inputs and labels
+__global__ void k_gather(const uint16_t *xall, const uint8_t *yall, const long *order, long b0, int B, uint16_t *xb,
+                         uint8_t *yb)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)B * IC_MLP_IN) return;
+    const int r = (int)(q / IC_MLP_IN), f = (int)(q % IC_MLP_IN);
+    const long row = order[b0 + r];
+    xb[q] = xall[row * IC_MLP_IN + f];
+    if (f == 0) yb[r] = yall[row];
+}
+
+// learned flags: p >= 1/2 -> refine, else coarsen-eligible
+__global__ void k_prob_flags(const float *prob, const int *items, int n, int8_t *flags)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) flags[items[q]] = prob[q] >= 0.5f ? 1 : -1;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+void gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn, int M, int N,
+          int K, const float *bias, int relu, float *Cf, uint16_t *Cb, long ldc)
+{
+    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, bias, relu, Cf, Cb, ldc};
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+}
+
+template <class T>
+struct Buf {
+    T *p = nullptr;
+    size_t n = 0;
+    explicit Buf(size_t count = 0) { alloc(count); }
+    void alloc(size_t count)
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = count;
+        if (count && hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::runtime_error("hipMalloc failed");
+    }
+    ~Buf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    Buf(const Buf &) = delete;
+    Buf &operator=(const Buf &) = delete;
+};
+
+}  // namespace
+
+MlpDevice::MlpDevice() = default;
+
+MlpDevice::~MlpDevice()
+{
+    for (void *q : {(void *)w, (void *)wb, (void *)mean, (void *)istd, (void *)xb, (void *)h1, (void *)h2,
+                    (void *)prob, (void *)flags_tmp})
+        if (q) (void)hipFree(q);
+}
+
+void MlpDevice::set(const float *params, const float *mean_h, const float *std_h)
+{
+    if (!w) {
+        if (hipMalloc(&w, IC_MLP_NPARAM * sizeof(float)) != hipSuccess ||
+            hipMalloc(&wb, IC_MLP_NPARAM * sizeof(uint16_t)) != hipSuccess ||
+            hipMalloc(&mean, IC_MLP_IN * sizeof(float)) != hipSuccess ||
+            hipMalloc(&istd, IC_MLP_IN * sizeof(float)) != hipSuccess)
+            throw std::runtime_error("hipMalloc failed");
+    }
+    std::vector<float> is(IC_MLP_IN);
+    for (int f = 0; f < IC_MLP_IN; ++f) is[f] = 1.0f / std_h[f];
+    if (hipMemcpy(w, params, IC_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(mean, mean_h, IC_MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(istd, is.data(), IC_MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed");
+    hipLaunchKernelGGL(k_to_bf16, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, 0, w, wb, (long)IC_MLP_NPARAM);
+    if (hipDeviceSynchronize() != hipSuccess) throw std::runtime_error("device error");
+    ready = true;
+}
+
+void MlpDevice::reserve(int n)
+{
+    if (n <= cap) return;
+    for (void *q : {(void *)xb, (void *)h1, (void *)h2, (void *)prob})
+        if (q) (void)hipFree(q);
+    cap = n + n / 2 + 64;
+    if (hipMalloc(&xb, (size_t)cap * IC_MLP_IN * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&h1, (size_t)cap * IC_MLP_HID * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&h2, (size_t)cap * IC_MLP_HID * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&prob, (size_t)cap * sizeof(float)) != hipSuccess)
+        throw std::runtime_error("hipMalloc failed");
+}
+
+// forward pass over n rows of xb (already filled) -> prob
+void MlpDevice::forward(hipStream_t s, int n)
+{
+    const uint16_t *W1 = wb + IC_MLP_OFF_W1, *W2 = wb + IC_MLP_OFF_W2, *w3 = wb + IC_MLP_OFF_W3;
+    gemm(s, xb, IC_MLP_IN, 1, W1, IC_MLP_HID, 1, n, IC_MLP_HID, IC_MLP_IN, w + IC_MLP_OFF_B1, 1, nullptr, h1,
+         IC_MLP_HID);
+    gemm(s, h1, IC_MLP_HID, 1, W2, IC_MLP_HID, 1, n, IC_MLP_HID, IC_MLP_HID, w + IC_MLP_OFF_B2, 1, nullptr, h2,
+         IC_MLP_HID);
+    hipLaunchKernelGGL(k_head, dim3((n + 255) / 256), dim3(256), 0, s, h2, w3, w + IC_MLP_OFF_B3, n,
+                       (const uint8_t *)nullptr, 0.f, (float *)nullptr, prob, (float *)nullptr, (float *)nullptr);
+}
+
+void mlp_features(hipStream_t s, const KArgs &a, int bi, int bj, int bk, const int *items,
+                  const int *nitems, int n, float *raw, const float *mean, const float *istd, uint16_t *xb)
+{
+    const dim3 g(std::max(1, std::min(n, 16384)));
+#define IC_INSTANTIATE(BI, BJ, BK)                                                                      \
+    if (bi == BI && bj == BJ && bk == BK) {                                                            \
+        hipLaunchKernelGGL((k_features<BI, BJ, BK>), g, dim3(256), 0, s, a, items, nitems, raw, mean,   \
+                           istd, xb);                                                                   \
+        return;                                                                                        \
+    }
+#include "shapes.inc"
+#undef IC_INSTANTIATE
+}
+
+void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, int8_t *flags)
+{
+    hipLaunchKernelGGL(k_prob_flags, dim3((n + 255) / 256), dim3(256), 0, s, prob, items, n, flags);
+}
+
+// One forward + backward pass on n rows: gradients (fp32, params layout) and mean loss.
+// X: normalised fp32 inputs (converted to bf16 here), params: fp32 master weights.
+static void fwd_bwd(hipStream_t s, int n, const uint16_t *Xb, const uint8_t *y, float pw, const float *w,
+                    const uint16_t *wb, float *grad, float *loss_rows, Buf<uint16_t> &H1, Buf<uint16_t> &H2,
+                    Buf<float> &dz, Buf<float> &dZ2, Buf<uint16_t> &dZ2b, Buf<float> &dH1, Buf<float> &dZ1,
+                    Buf<uint16_t> &dZ1b)
+{
+    const uint16_t *W1 = wb + IC_MLP_OFF_W1, *W2 = wb + IC_MLP_OFF_W2, *w3 = wb + IC_MLP_OFF_W3;
+    gemm(s, Xb, IC_MLP_IN, 1, W1, IC_MLP_HID, 1, n, IC_MLP_HID, IC_MLP_IN, w + IC_MLP_OFF_B1, 1, nullptr, H1.p,
+         IC_MLP_HID);
+    gemm(s, H1.p, IC_MLP_HID, 1, W2, IC_MLP_HID, 1, n, IC_MLP_HID, IC_MLP_HID, w + IC_MLP_OFF_B2, 1, nullptr,
+         H2.p, IC_MLP_HID);
+    hipLaunchKernelGGL(k_head, dim3((n + 255) / 256), dim3(256), 0, s, H2.p, w3, w + IC_MLP_OFF_B3, n, y, pw,
+                       (float *)nullptr, (float *)nullptr, dz.p, loss_rows);
+    // layer 3: dw3 = H2^T dz, db3 = sum dz
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, (const float *)nullptr, H2.p, dz.p, n,
+                       IC_MLP_HID, grad + IC_MLP_OFF_W3);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1), 0, s, dz.p, (const uint16_t *)nullptr, (const float *)nullptr,
+                       n, 1, grad + IC_MLP_OFF_B3);
+    const long nh = (long)n * IC_MLP_HID;
+    hipLaunchKernelGGL(k_back2, dim3((nh + 255) / 256), dim3(256), 0, s, dz.p, w3, H2.p, n, dZ2.p, dZ2b.p);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, dZ2.p, (const uint16_t *)nullptr,
+                       (const float *)nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B2);
+    // dW2 = H1^T dZ2   (M = 128 (k of layer 2), N = 128, K = n)
+    gemm(s, H1.p, 1, IC_MLP_HID, dZ2b.p, IC_MLP_HID, 1, IC_MLP_HID, IC_MLP_HID, n, nullptr, 0, grad + IC_MLP_OFF_W2,
+         nullptr, IC_MLP_HID);
+    // dH1 = dZ2 W2^T   (B(k, j) = W2[j][k])
+    gemm(s, dZ2b.p, IC_MLP_HID, 1, W2, 1, IC_MLP_HID, n, IC_MLP_HID, IC_MLP_HID, nullptr, 0, dH1.p, nullptr,
+         IC_MLP_HID);
+    hipLaunchKernelGGL(k_mask, dim3((nh + 255) / 256), dim3(256), 0, s, dH1.p, H1.p, nh, dZ1.p, dZ1b.p);
+    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, dZ1.p, (const uint16_t *)nullptr,
+                       (const float *)nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B1);
+    // dW1 = X^T dZ1    (M = 512, N = 128, K = n)
+    gemm(s, Xb, 1, IC_MLP_IN, dZ1b.p, IC_MLP_HID, 1, IC_MLP_IN, IC_MLP_HID, n, nullptr, 0, grad + IC_MLP_OFF_W1,
+         nullptr, IC_MLP_HID);
+}
+
+void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float *params, float *grad_out,
+              float *loss_out)
+{
+    hipStream_t s = nullptr;
+    Buf<float> x((size_t)n * IC_MLP_IN), w(IC_MLP_NPARAM), grad(IC_MLP_NPARAM), dz(n), loss(n), dZ2((size_t)n * IC_MLP_HID),
+        dH1((size_t)n * IC_MLP_HID), dZ1((size_t)n * IC_MLP_HID);
+    Buf<uint16_t> xb((size_t)n * IC_MLP_IN), wb(IC_MLP_NPARAM), H1((size_t)n * IC_MLP_HID), H2((size_t)n * IC_MLP_HID),
+        dZ2b((size_t)n * IC_MLP_HID), dZ1b((size_t)n * IC_MLP_HID);
+    Buf<uint8_t> yd(n);
+    if (hipMemcpy(x.p, xnorm, (size_t)n * IC_MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(w.p, params, IC_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(yd.p, y, n, hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed");
+    hipLaunchKernelGGL(k_to_bf16, dim3(((long)n * IC_MLP_IN + 255) / 256), dim3(256), 0, s, x.p, xb.p,
+                       (long)n * IC_MLP_IN);
+    hipLaunchKernelGGL(k_to_bf16, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, w.p, wb.p, (long)IC_MLP_NPARAM);
+    fwd_bwd(s, n, xb.p, yd.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b);
+    std::vector<float> lrow(n);
+    if (hipMemcpy(grad_out, grad.p, IC_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(lrow.data(), loss.p, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed");
+    double l = 0.0;
+    for (int b = 0; b < n; ++b) l += lrow[b];
+    *loss_out = (float)(l / n);
+}
+
+void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp, float *params, float *mean_out,
+               float *std_out, float *loss_epochs)
+{
+    hipStream_t s = nullptr;
+    // per-feature z-score statistics of the training set (fp64 on the host)
+    std::vector<double> mu(IC_MLP_IN, 0.0), var(IC_MLP_IN, 0.0);
+    for (long b = 0; b < n; ++b)
+        for (int f = 0; f < IC_MLP_IN; ++f) mu[f] += raw[b * IC_MLP_IN + f];
+    for (int f = 0; f < IC_MLP_IN; ++f) mu[f] /= (double)n;
+    for (long b = 0; b < n; ++b)
+        for (int f = 0; f < IC_MLP_IN; ++f) {
+            const double d = raw[b * IC_MLP_IN + f] - mu[f];
+            var[f] += d * d;
+        }
+    std::vector<float> mean_h(IC_MLP_IN), std_h(IC_MLP_IN), istd_h(IC_MLP_IN);
+    for (int f = 0; f < IC_MLP_IN; ++f) {
+        mean_h[f] = (float)mu[f];
+        double sd = std::sqrt(var[f] / (double)n);
+        if (!(sd > 1e-6)) sd = 1.0;
+        std_h[f] = (float)sd;
+        istd_h[f] = 1.0f / std_h[f];
+    }
+    long npos = 0;
+    for (long b = 0; b < n; ++b) npos += y[b] ? 1 : 0;
+    const float pw = hp.pos_weight > 0.f ? hp.pos_weight : (npos > 0 ? (float)(n - npos) / (float)npos : 1.f);
+    const int B = hp.batch;
+    Buf<float> rawd((size_t)n * IC_MLP_IN), mean(IC_MLP_IN), istd(IC_MLP_IN), w(IC_MLP_NPARAM), grad(IC_MLP_NPARAM),
+        m1(IC_MLP_NPARAM), m2(IC_MLP_NPARAM), dz(B), loss(B), dZ2((size_t)B * IC_MLP_HID), dH1((size_t)B * IC_MLP_HID),
+        dZ1((size_t)B * IC_MLP_HID);
+    Buf<uint16_t> xall((size_t)n * IC_MLP_IN), xb((size_t)B * IC_MLP_IN), wb(IC_MLP_NPARAM), H1((size_t)B * IC_MLP_HID),
+        H2((size_t)B * IC_MLP_HID), dZ2b((size_t)B * IC_MLP_HID), dZ1b((size_t)B * IC_MLP_HID);
+    Buf<uint8_t> yall(n), yb(B);
+    Buf<long> orderd(n);
+    auto H2D = [](void *d, const void *h, size_t bytes) {
+        if (hipMemcpy(d, h, bytes, hipMemcpyHostToDevice) != hipSuccess) throw std::runtime_error("hipMemcpy failed");
+    };
+    H2D(rawd.p, raw, (size_t)n * IC_MLP_IN * sizeof(float));
+    H2D(mean.p, mean_h.data(), IC_MLP_IN * sizeof(float));
+    H2D(istd.p, istd_h.data(), IC_MLP_IN * sizeof(float));
+    H2D(w.p, params, IC_MLP_NPARAM * sizeof(float));
+    H2D(yall.p, y, n);
+    (void)hipMemset(m1.p, 0, IC_MLP_NPARAM * sizeof(float));
+    (void)hipMemset(m2.p, 0, IC_MLP_NPARAM * sizeof(float));
+    hipLaunchKernelGGL(k_normalise, dim3(((long)n * IC_MLP_IN + 255) / 256), dim3(256), 0, s, rawd.p, mean.p, istd.p,
+                       n, xall.p);
+    hipLaunchKernelGGL(k_to_bf16, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, w.p, wb.p, (long)IC_MLP_NPARAM);
+    // deterministic shuffle per epoch (xorshift on the host), rows gathered by copies
+    std::vector<long> order(n);
+    for (long b = 0; b < n; ++b) order[b] = b;
+    uint64_t st = hp.seed * 2654435761ull + 88172645463325252ull;
+    auto rnd = [&]() {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        return st;
+    };
+    long t = 0;
+    std::vector<float> lrow(B);
+    for (int ep = 0; ep < hp.epochs; ++ep) {
+        for (long b = n - 1; b > 0; --b) std::swap(order[b], order[rnd() % (uint64_t)(b + 1)]);
+        H2D(orderd.p, order.data(), n * sizeof(long));
+        double lsum = 0.0;
+        long lcount = 0;
+        for (long b0 = 0; b0 + B <= n; b0 += B) {
+            hipLaunchKernelGGL(k_gather, dim3(((long)B * IC_MLP_IN + 255) / 256), dim3(256), 0, s, xall.p, yall.p,
+                               orderd.p, b0, B, xb.p, yb.p);
+            fwd_bwd(s, B, xb.p, yb.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b);
+            ++t;
+            const float c1 = 1.f - std::pow(hp.beta1, (float)t), c2 = 1.f - std::pow(hp.beta2, (float)t);
+            hipLaunchKernelGGL(k_adam, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, w.p, wb.p, grad.p, m1.p,
+                               m2.p, IC_MLP_NPARAM, hp.lr, hp.beta1, hp.beta2, hp.eps, c1, c2);
+            if (hipMemcpy(lrow.data(), loss.p, B * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+                throw std::runtime_error("hipMemcpy failed");
+            for (int q = 0; q < B; ++q) lsum += lrow[q];
+            lcount += B;
+        }
+        if (loss_epochs) loss_epochs[ep] = lcount ? (float)(lsum / lcount) : 0.f;
+    }
+    if (hipMemcpy(params, w.p, IC_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed");
+    std::memcpy(mean_out, mean_h.data(), IC_MLP_IN * sizeof(float));
+    std::memcpy(std_out, std_h.data(), IC_MLP_IN * sizeof(float));
+}

@@ -17,6 +17,7 @@
 
 #include "../../include/icarus.h"
 #include "kernels.h"
+#include "mlp.h"
 
 namespace {
 
@@ -219,6 +220,12 @@ struct ic_sim {
     bool graph_dirty = true;
     double graph_dt_fixed = -1.0;
     bool use_graph = true;
+
+    // learned flags
+    MlpDevice mlp;
+    long n_regrids = 0, n_learned = 0, n_judged = 0, n_fallbacks = 0;
+    std::vector<int> fallback_left;
+    double last_recall = -1.0;
 
     // timing
     bool timing = false;
@@ -1080,12 +1087,98 @@ void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int 
     M.leaves.swap(newleaves);
 }
 
+void plain_flags(ic_sim *s, std::vector<int8_t> &fl)
+{
+    KArgs a = base_args(s);
+    a.U = s->U.p;
+    IndicatorParams p{};
+    const double deg = M_PI / 180.0;
+    p.max_level = s->max_level;
+    p.eps = s->amr.eps_lohner;
+    p.tol_r = s->amr.tol_refine;
+    p.tol_c = s->amr.tol_coarsen;
+    p.w_rho = s->amr.w_rho;
+    p.w_v = s->amr.w_v;
+    p.use_windows = s->amr.use_windows;
+    p.lon_e = s->amr.lon_earth_deg * deg;
+    p.clt_e = s->amr.clt_earth_deg * deg;
+    p.dlon_e = s->amr.dlon_earth_deg * deg;
+    p.dclt_e = s->amr.dclt_earth_deg * deg;
+    p.dlon_c = s->amr.dlon_cme_deg * deg;
+    s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
+    HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+}
+
+// network probabilities of every leaf in work-list order into s->mlp.prob
+void learned_prob(ic_sim *s)
+{
+    if (!s->mlp.ready) throw Error(IC_E_INVALID, "no network installed (ic_mlp_set)");
+    for (int d = 0; d < 3; ++d)
+        if (s->B[d] % 4) throw Error(IC_E_INVALID, "learned flags need block dims divisible by 4");
+    s->mlp.reserve(s->n_items);
+    KArgs a = base_args(s);
+    a.U = s->U.p;
+    mlp_features(s->stream, a, s->B[0], s->B[1], s->B[2], s->items.p, s->nitems.p, s->n_items, nullptr,
+                 s->mlp.mean, s->mlp.istd, s->mlp.xb);
+    s->mlp.forward(s->stream, s->n_items);
+}
+
+void learned_flags(ic_sim *s, std::vector<int8_t> &fl)
+{
+    learned_prob(s);
+    mlp_prob_flags(s->stream, s->mlp.prob, s->items.p, s->n_items, s->flags.p);
+    HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+}
+
 void do_regrid(ic_sim *s, const int8_t *user_flags)
 {
     // ghosts of the current state (prolongation of new children reads them)
     fill_ghosts(s, s->U.p, 0.0);
     std::vector<int8_t> fl((size_t)s->nm * s->max_blocks, 0);
-    if (!user_flags) {
+    const int src = s->amr.source;
+    if (!user_flags && src != IC_SOURCE_PLAIN && s->max_level > 1) {
+        // learned flags, judged by the plain criterion every judge_every-th regrid
+        if ((int)s->fallback_left.size() != s->nm) s->fallback_left.assign(s->nm, 0);
+        learned_flags(s, fl);
+        s->n_learned++;
+        const bool judge = src == IC_SOURCE_LEARNED_JUDGED && s->amr.judge_every > 0 &&
+                           s->n_regrids % s->amr.judge_every == 0;
+        bool any_fb = false;
+        for (int m = 0; m < s->nm; ++m) any_fb = any_fb || s->fallback_left[m] > 0;
+        if (judge || any_fb) {
+            std::vector<int8_t> pl(fl.size(), 0);
+            plain_flags(s, pl);
+            if (judge) s->n_judged++;
+            for (int m = 0; m < s->nm; ++m) {
+                bool use_plain = s->fallback_left[m] > 0;
+                if (use_plain) s->fallback_left[m]--;
+                if (judge) {
+                    long hit = 0, tot = 0;
+                    for (auto &kv : s->mem[m].leaves) {
+                        const int slot = s->slot_of(m, kv.second);
+                        if (pl[slot] == 1) {
+                            ++tot;
+                            if (fl[slot] == 1) ++hit;
+                        }
+                    }
+                    const double recall = tot ? (double)hit / tot : 1.0;
+                    if (m == 0) s->last_recall = recall;
+                    if (recall < s->amr.judge_recall) {
+                        s->n_fallbacks++;
+                        s->fallback_left[m] = 10;
+                        use_plain = true;
+                    }
+                }
+                if (use_plain)
+                    for (auto &kv : s->mem[m].leaves) {
+                        const int slot = s->slot_of(m, kv.second);
+                        fl[slot] = pl[slot];
+                    }
+            }
+        }
+    } else if (!user_flags) {
         KArgs a = base_args(s);
         a.U = s->U.p;
         IndicatorParams p{};
@@ -1129,6 +1222,7 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
         HIPCHECK(hipStreamSynchronize(s->stream));
     }
     for (int slot : to_free) s->mem[slot / s->max_blocks].free_slots.push_back(slot % s->max_blocks);
+    s->n_regrids++;
     rebuild(s);
     update_sample_desc(s);
     enqueue_rate(s);
@@ -1673,6 +1767,104 @@ ic_status ic_get_time(ic_sim *s, int member, double *t_s, double *dt_s)
         HIPCHECK(hipStreamSynchronize(s->stream));
         if (t_s) *t_s = t * kT0;
         if (dt_s) *dt_s = d * kT0;
+    });
+}
+
+ic_status ic_features(ic_sim *s, int member, float *raw, int n)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !raw) throw Error(IC_E_INVALID, "bad argument");
+        for (int d = 0; d < 3; ++d)
+            if (s->B[d] % 4) throw Error(IC_E_INVALID, "features need block dims divisible by 4");
+        const int nl = (int)s->mem[member].leaves.size();
+        if (n < nl) throw Error(IC_E_INVALID, "feature buffer too small");
+        std::vector<int> mb(s->nm);
+        HIPCHECK(hipMemcpy(mb.data(), s->mbeg.p, s->nm * sizeof(int), hipMemcpyDeviceToHost));
+        DBuf<float> out;
+        out.alloc((size_t)nl * IC_MLP_IN);
+        DBuf<int> cnt;
+        cnt.alloc(1);
+        HIPCHECK(hipMemcpy(cnt.p, &nl, sizeof(int), hipMemcpyHostToDevice));
+        KArgs a = base_args(s);
+        a.U = s->U.p;
+        mlp_features(s->stream, a, s->B[0], s->B[1], s->B[2], s->items.p + mb[member], cnt.p, nl, out.p, nullptr,
+                     nullptr, nullptr);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        HIPCHECK(hipMemcpy(raw, out.p, (size_t)nl * IC_MLP_IN * sizeof(float), hipMemcpyDeviceToHost));
+        out.release();
+        cnt.release();
+    });
+}
+
+ic_status ic_mlp_set(ic_sim *s, const float *params, const float *mean, const float *std)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (!params || !mean || !std) throw Error(IC_E_INVALID, "null argument");
+        for (int f = 0; f < IC_MLP_IN; ++f)
+            if (!(std[f] > 0.0f)) throw Error(IC_E_INVALID, "std must be positive");
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        s->mlp.set(params, mean, std);
+    });
+}
+
+ic_status ic_eval_learned(ic_sim *s, int member, float *prob, int8_t *flags, int n)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm) throw Error(IC_E_INVALID, "bad member");
+        const int nl = (int)s->mem[member].leaves.size();
+        if (n < nl) throw Error(IC_E_INVALID, "buffer too small");
+        learned_prob(s);
+        std::vector<int> mb(s->nm);
+        HIPCHECK(hipMemcpy(mb.data(), s->mbeg.p, s->nm * sizeof(int), hipMemcpyDeviceToHost));
+        std::vector<float> p(nl);
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        HIPCHECK(hipMemcpy(p.data(), s->mlp.prob + mb[member], nl * sizeof(float), hipMemcpyDeviceToHost));
+        for (int q = 0; q < nl; ++q) {
+            if (prob) prob[q] = p[q];
+            if (flags) flags[q] = p[q] >= 0.5f ? IC_FLAG_REFINE : IC_FLAG_COARSEN;
+        }
+    });
+}
+
+ic_status ic_regrid_stats(ic_sim *s, long *learned, long *judged, long *fallbacks, double *last_recall)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (learned) *learned = s->n_learned;
+        if (judged) *judged = s->n_judged;
+        if (fallbacks) *fallbacks = s->n_fallbacks;
+        if (last_recall) *last_recall = s->last_recall;
+    });
+}
+
+ic_status ic_mlp_train(const float *raw, const uint8_t *y, long n, const ic_mlp_hparams *hp, float *params,
+                       float *mean, float *std, float *loss_per_epoch)
+{
+    return guard(nullptr, [&]() {
+        if (!raw || !y || !hp || !params || !mean || !std || n < 1) throw Error(IC_E_INVALID, "bad argument");
+        if (hp->batch < 1 || hp->batch > n || hp->epochs < 0) throw Error(IC_E_INVALID, "bad hyper-parameters");
+        MlpHparams h{hp->epochs, hp->batch, hp->lr, hp->beta1, hp->beta2, hp->eps, hp->seed, hp->pos_weight};
+        try {
+            mlp_train(raw, y, n, h, params, mean, std, loss_per_epoch);
+        } catch (const std::runtime_error &e) {
+            throw Error(IC_E_DEVICE, e.what());
+        }
+    });
+}
+
+ic_status ic_mlp_grad(const float *xnorm, const uint8_t *y, int n, float pos_weight, const float *params,
+                      float *grad, float *loss)
+{
+    return guard(nullptr, [&]() {
+        if (!xnorm || !y || !params || !grad || !loss || n < 1) throw Error(IC_E_INVALID, "bad argument");
+        try {
+            mlp_grad(xnorm, y, n, pos_weight, params, grad, loss);
+        } catch (const std::runtime_error &e) {
+            throw Error(IC_E_DEVICE, e.what());
+        }
     });
 }
 
