@@ -187,6 +187,13 @@ ic_status ic_regrid(ic_sim *sim, const int8_t *flags, ic_info *out);
  * capacity of flags and must be >= the leaf count. */
 ic_status ic_eval_flags(ic_sim *sim, int member, int8_t *flags, int n);
 
+/* Refinement condition without the level cap (Sect. 3.2 criterion): hot[q] = 1
+ * if some cell of leaf q (ic_get_blocks order) lies in the windows, is
+ * compressive and has an indicator above tol_refine, else 0, whatever the
+ * leaf's level.  Look-ahead labels for the learned flags are built from it.
+ * n is the capacity of hot and must be >= the leaf count. */
+ic_status ic_eval_hot(ic_sim *sim, int member, int8_t *hot, int n);
+
 /* Primitive variables (rho, v_r, v_theta, v_phi, p, B_r, B_theta, B_phi), code
  * units, at a point: trilinear interpolation between the cell centres of the
  * level of the finest leaf containing the point (cells of a coarser leaf

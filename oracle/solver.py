@@ -249,6 +249,7 @@ class Solver:
         K, J, I = np.meshgrid(loc[2], loc[1], loc[0], indexing="ij")
         Uc = Gc[:, K + 2, J + 2, I + 2]
         out = Uc.copy()
+        slopes, sib = [], []
         for d in range(3):
             cg = coarse_glob[d]
             xm = np.array([gc_geo.centre(d, c - 1) for c in cg])
@@ -264,7 +265,20 @@ class Solver:
             b = (Up - Uc) / (xp - x0).reshape(shp)
             s = np.where(a * b > 0.0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
             out = out + s * off[d].reshape(shp)
-        return out
+            slopes.append(s)
+            gf = self._wrap_idx(level_f, d, np.asarray(gidx[d]))
+            sib.append([self._centroid_offsets(level_f, d, 2 * (gf // 2) + o).reshape(shp) for o in (0, 1)])
+        # positivity: a coarse cell whose linear values would give any of its 8
+        # children rho <= 0 or p <= 0 passes its own value to all of them
+        ok = np.ones(Uc.shape[1:], dtype=bool)
+        for o in range(8):
+            c = Uc + slopes[0] * sib[0][o & 1]
+            c = c + slopes[1] * sib[1][(o >> 1) & 1]
+            c = c + slopes[2] * sib[2][(o >> 2) & 1]
+            with np.errstate(divide="ignore", invalid="ignore"):
+                p = c[4] - 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0] - 0.5 * (c[5] ** 2 + c[6] ** 2 + c[7] ** 2)
+            ok &= (c[0] > 0.0) & (p > 0.0)
+        return np.where(ok[None], out, Uc)
 
     def restrict(self, U, level_c, gidx):
         """Values of coarse cells (global indices gidx, level level_c) as the
@@ -472,6 +486,17 @@ class Solver:
                 out[leaf] = fo.COARSEN
             else:
                 out[leaf] = fo.KEEP
+        return out
+
+    def hot(self):
+        """Per leaf: 1 if some cell meets the refinement condition (window,
+        div V < 0, indicator above tol_refine; Sect. 3.2) whatever the leaf's
+        level, else 0."""
+        ind, _ = self.indicator()
+        out = {}
+        for leaf, (E, dv, ds) in ind.items():
+            win = self.window(leaf, self.cme)
+            out[leaf] = int(bool(np.any(win & (dv < 0.0) & (E > self.amr["tol_refine"]))))
         return out
 
     def regrid(self, flags=None, buffer_blocks=None):

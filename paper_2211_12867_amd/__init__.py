@@ -8,7 +8,7 @@ in include/icarus.h (ic_create, ic_step, ...); ``Sim`` wraps one sim object.
 PyTorch is used only to hand the library the current HIP stream.
 
 torch is imported before the library is loaded so that the process holds a
-single HIP runtime (torch's).  The library must have been built (``python -m paper_2211_12867_amd.build`` or
+single HIP runtime (torch's).  The library must have been built (``python paper_2211_12867_amd/build.py`` or
 ``__graft_entry__.build()``); importing fails loudly otherwise.
 """
 import ctypes
@@ -93,9 +93,9 @@ class Info(ctypes.Structure):
                     leaves=self.leaves, leaves_per_level=list(self.leaves_per_level))
 
 
-EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_eval_flags", "ic_sample",
-           "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks", "ic_get_state",
-           "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
+EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_eval_flags", "ic_eval_hot",
+           "ic_sample", "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks",
+           "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_last_error")
 
@@ -107,7 +107,7 @@ def _load():
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError("libicarus.so is not built: run __graft_entry__.build() or "
-                          "python -m paper_2211_12867_amd.build")
+                          "python paper_2211_12867_amd/build.py")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp = ctypes.c_void_p
@@ -118,6 +118,7 @@ def _load():
     L.ic_advance.argtypes = [vp, ctypes.c_double, ctypes.c_long, P(Info)]
     L.ic_regrid.argtypes = [vp, P(ctypes.c_int8), P(Info)]
     L.ic_eval_flags.argtypes = [vp, ctypes.c_int, P(ctypes.c_int8), ctypes.c_int]
+    L.ic_eval_hot.argtypes = [vp, ctypes.c_int, P(ctypes.c_int8), ctypes.c_int]
     L.ic_sample.argtypes = [vp, ctypes.c_int] + [ctypes.c_double] * 3 + [P(ctypes.c_double)]
     L.ic_set_sample_point.argtypes = [vp] + [ctypes.c_double] * 3
     L.ic_timeseries.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_int)]
@@ -319,6 +320,12 @@ class Sim:
         n = len(self.blocks(member))
         out = np.zeros(n, dtype=np.int8)
         _check(lib.ic_eval_flags(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
+        return out
+
+    def eval_hot(self, member=0):
+        n = len(self.blocks(member))
+        out = np.zeros(n, dtype=np.int8)
+        _check(lib.ic_eval_hot(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
         return out
 
     # --- sampling ---------------------------------------------------------------

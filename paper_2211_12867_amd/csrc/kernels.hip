@@ -280,6 +280,72 @@ k_stage(KArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// Limited linear prolongation of the fine cell with (unwrapped) global index g
+// on level geometry lg from its coarse parent: local index cl in the ghosted
+// source block src, wrapped global index cw on level geometry cg.  Slopes are
+// minmod of the one-sided coordinate differences, applied about the volume
+// centroid of the two children along each direction.  A coarse cell whose
+// linear values would give any of its 8 children rho <= 0 or p <= 0 hands its
+// own value to all of them (conservative either way).
+template <int BI, int BJ, int BK>
+__device__ inline void prolong_cell(const KArgs &a, int src, const int cl[3], const int cw[3], const LevelGeo &cg,
+                                    const LevelGeo &lg, const int g[3], double u[8])
+{
+    using S = Shape<BI, BJ, BK>;
+    const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
+    const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
+    double uc[8], sl[3][8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        uc[v] = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, cl[0], cl[1], cl[2]);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
+            lm[e] -= 1;
+            lp[e] += 1;
+            const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, lm[0], lm[1], lm[2]);
+            const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, lp[0], lp[1], lp[2]);
+            const double sa = (uc[v] - um) * idm[e], sb = (up - uc[v]) * idp[e];
+            sl[e][v] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+        }
+    }
+    // centroid offsets of the two children of the parent along each direction
+    double off[3][2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        off[0][o] = lg.r[(g[0] & ~1) + o + 2].poff;
+        off[1][o] = lg.t[(g[1] & ~1) + o + 2].poff;
+        off[2][o] = lg.p[(g[2] & ~1) + o + 2].poff;
+    }
+    bool ok = true;
+    for (int o = 0; o < 8; ++o) {
+        double c[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            double x = uc[v];
+            x += sl[0][v] * off[0][o & 1];
+            x += sl[1][v] * off[1][(o >> 1) & 1];
+            x += sl[2][v] * off[2][(o >> 2) & 1];
+            c[v] = x;
+        }
+        const double kin = 0.5 * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]) / c[0];
+        const double mag = 0.5 * (c[5] * c[5] + c[6] * c[6] + c[7] * c[7]);
+        ok = ok && c[0] > 0.0 && c[4] - kin - mag > 0.0;
+    }
+    const int own[3] = {g[0] & 1, g[1] & 1, g[2] & 1};
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        double x = uc[v];
+        if (ok) {
+            x += sl[0][v] * off[0][own[0]];
+            x += sl[1][v] * off[1][own[1]];
+            x += sl[2][v] * off[2][own[2]];
+        }
+        u[v] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // ghost slabs: inner boundary (wind + cone CME), restriction, prolongation
 // ---------------------------------------------------------------------------
 template <int BI, int BJ, int BK>
@@ -369,24 +435,7 @@ __global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, co
                     cl[e] = c2 + tk.shift[e];
                     cw[e] = c2 + tk.cwrap[e];
                 }
-                const double poff[3] = {lg.r[g[0] + 2].poff, lg.t[g[1] + 2].poff, lg.p[g[2] + 2].poff};
-                const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
-                const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
-                for (int v = 0; v < 8; ++v) {
-                    const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, cl[0], cl[1], cl[2]);
-                    double val = uc;
-                    for (int e = 0; e < 3; ++e) {
-                        int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
-                        lm[e] -= 1;
-                        lp[e] += 1;
-                        const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lm[0], lm[1], lm[2]);
-                        const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lp[0], lp[1], lp[2]);
-                        const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
-                        const double s = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
-                        val += s * poff[e];
-                    }
-                    u[v] = val;
-                }
+                prolong_cell<BI, BJ, BK>(a, cs, cl, cw, cg, lg, g, u);
             }
             for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
         }
@@ -671,24 +720,9 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
                     cw[e] = g[e] >> 1;
                     cl[e] = cw[e] - pd.org[e];
                 }
-                const double poff[3] = {lg.r[g[0] + 2].poff, lg.t[g[1] + 2].poff, lg.p[g[2] + 2].poff};
-                const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
-                const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
-                for (int v = 0; v < 8; ++v) {
-                    const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, cl[0], cl[1], cl[2]);
-                    double val = uc;
-                    for (int e = 0; e < 3; ++e) {
-                        int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
-                        lm[e] -= 1;
-                        lp[e] += 1;
-                        const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, lm[0], lm[1], lm[2]);
-                        const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, ps, v, lp[0], lp[1], lp[2]);
-                        const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
-                        const double s = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
-                        val += s * poff[e];
-                    }
-                    Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = val;
-                }
+                double u[8];
+                prolong_cell<BI, BJ, BK>(a, ps, cl, cw, cg, lg, g, u);
+                for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = u[v];
             } else {
                 const LevelGeo fg = a.geo[tk.level + 1];
                 double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;

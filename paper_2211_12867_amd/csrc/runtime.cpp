@@ -1087,13 +1087,16 @@ void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int 
     M.leaves.swap(newleaves);
 }
 
-void plain_flags(ic_sim *s, std::vector<int8_t> &fl)
+// plain criterion on the current state (ghosts must be filled) into fl, per
+// pool slot; level_cap = s->max_level gives the block flags, a huge cap gives
+// REFINE wherever a cell meets the refinement condition whatever the level
+void run_indicator(ic_sim *s, std::vector<int8_t> &fl, int level_cap)
 {
     KArgs a = base_args(s);
     a.U = s->U.p;
     IndicatorParams p{};
     const double deg = M_PI / 180.0;
-    p.max_level = s->max_level;
+    p.max_level = level_cap;
     p.eps = s->amr.eps_lohner;
     p.tol_r = s->amr.tol_refine;
     p.tol_c = s->amr.tol_coarsen;
@@ -1109,6 +1112,8 @@ void plain_flags(ic_sim *s, std::vector<int8_t> &fl)
     HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
 }
+
+void plain_flags(ic_sim *s, std::vector<int8_t> &fl) { run_indicator(s, fl, s->max_level); }
 
 // network probabilities of every leaf in work-list order into s->mlp.prob
 void learned_prob(ic_sim *s)
@@ -1179,25 +1184,7 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
             }
         }
     } else if (!user_flags) {
-        KArgs a = base_args(s);
-        a.U = s->U.p;
-        IndicatorParams p{};
-        const double deg = M_PI / 180.0;
-        p.max_level = s->max_level;
-        p.eps = s->amr.eps_lohner;
-        p.tol_r = s->amr.tol_refine;
-        p.tol_c = s->amr.tol_coarsen;
-        p.w_rho = s->amr.w_rho;
-        p.w_v = s->amr.w_v;
-        p.use_windows = s->amr.use_windows;
-        p.lon_e = s->amr.lon_earth_deg * deg;
-        p.clt_e = s->amr.clt_earth_deg * deg;
-        p.dlon_e = s->amr.dlon_earth_deg * deg;
-        p.dclt_e = s->amr.dclt_earth_deg * deg;
-        p.dlon_c = s->amr.dlon_cme_deg * deg;
-        s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
-        HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
+        plain_flags(s, fl);
     }
     std::vector<MoveTask> moves;
     std::vector<int> to_free;
@@ -1559,39 +1546,35 @@ ic_status ic_regrid(ic_sim *s, const int8_t *flags, ic_info *out)
     });
 }
 
+namespace {
+// per-leaf indicator output of one member in ic_get_blocks order
+void leaf_indicator(ic_sim *s, int member, int8_t *out, int n, int level_cap, bool hot)
+{
+    check_sim(s);
+    if (member < 0 || member >= s->nm || !out) throw Error(IC_E_INVALID, "bad member or buffer");
+    Member &M = s->mem[member];
+    if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "flag buffer too small");
+    fill_ghosts(s, s->U.p, 0.0);
+    std::vector<int8_t> fl((size_t)s->nm * s->max_blocks);
+    run_indicator(s, fl, level_cap);
+    std::vector<Key> keys;
+    for (auto &kv : M.leaves) keys.push_back(kv.first);
+    std::sort(keys.begin(), keys.end(), abi_order);
+    for (size_t q = 0; q < keys.size(); ++q) {
+        const int8_t f = fl[s->slot_of(member, M.leaves[keys[q]])];
+        out[q] = hot ? (int8_t)(f == IC_FLAG_REFINE) : f;
+    }
+}
+}  // namespace
+
 ic_status ic_eval_flags(ic_sim *s, int member, int8_t *flags, int n)
 {
-    return guard(s, [&]() {
-        check_sim(s);
-        if (member < 0 || member >= s->nm || !flags) throw Error(IC_E_INVALID, "bad member or buffer");
-        Member &M = s->mem[member];
-        if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "flag buffer too small");
-        fill_ghosts(s, s->U.p, 0.0);
-        KArgs a = base_args(s);
-        a.U = s->U.p;
-        IndicatorParams p{};
-        const double deg = M_PI / 180.0;
-        p.max_level = s->max_level;
-        p.eps = s->amr.eps_lohner;
-        p.tol_r = s->amr.tol_refine;
-        p.tol_c = s->amr.tol_coarsen;
-        p.w_rho = s->amr.w_rho;
-        p.w_v = s->amr.w_v;
-        p.use_windows = s->amr.use_windows;
-        p.lon_e = s->amr.lon_earth_deg * deg;
-        p.clt_e = s->amr.clt_earth_deg * deg;
-        p.dlon_e = s->amr.dlon_earth_deg * deg;
-        p.dclt_e = s->amr.dclt_earth_deg * deg;
-        p.dlon_c = s->amr.dlon_cme_deg * deg;
-        s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
-        std::vector<int8_t> fl((size_t)s->nm * s->max_blocks);
-        HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
-        for (size_t q = 0; q < keys.size(); ++q) flags[q] = fl[s->slot_of(member, M.leaves[keys[q]])];
-    });
+    return guard(s, [&]() { leaf_indicator(s, member, flags, n, s->max_level, false); });
+}
+
+ic_status ic_eval_hot(ic_sim *s, int member, int8_t *hot, int n)
+{
+    return guard(s, [&]() { leaf_indicator(s, member, hot, n, 1 << 20, true); });
 }
 
 ic_status ic_sample(ic_sim *s, int member, double r_au, double colat_deg, double lon_deg, double prim_out[8])

@@ -1,0 +1,230 @@
+"""Forecast runs on the library: wind relaxation, the CME phase with the
+sample-point record and the shock arrival there, look-ahead training pairs for
+the learned refinement flags, their training, and the comparison of
+refinement sources.
+
+Everything here drives the C ABI through the binding; every step of the
+method runs in the library's kernels.  Times at this interface are seconds
+unless a name says hours or days.
+
+    python -m paper_2211_12867_amd.forecast train  --out flags.npz ...
+    python -m paper_2211_12867_amd.forecast compare --net flags.npz ...
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_init, mlp_train, units
+
+DAY = 86400.0
+HOUR = 3600.0
+SAMPLE = (1.0, 90.0, 0.0)          # r [AU], colatitude, longitude [deg] in the co-rotating frame
+
+
+def _log(log, msg):
+    if log:
+        log(msg)
+
+
+def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
+    """Advance the relaxation initial state on the base grid (no regrids) to
+    t_end_s.  Returns dict(blocks, U, t_s, steps, wall_s)."""
+    g = dict(grid, max_level=1)
+    sim = Sim(g, wind, [cme], dict(regrid_every=0))
+    t0 = time.perf_counter()
+    steps = 0
+    while sim.time()[0] < t_end_s * (1.0 - 1e-12):
+        info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
+        steps = info["steps"]
+        _log(log, "relax: t = %.2f d, %d steps, %.1f s" % (info["t_s"] / DAY, steps, time.perf_counter() - t0))
+    bl, U = sim.state()
+    out = dict(blocks=bl, U=U, t_s=sim.time()[0], steps=steps, wall_s=time.perf_counter() - t0)
+    sim.close()
+    return out
+
+
+def _series_arrival(ts, t_cme_s):
+    """(t [h], v_r [km/s]) of the record and the shock arrival (R27 reading)."""
+    t_h = ts[:, 0] / HOUR
+    v = ts[:, 2] * units()[1] / 1e3
+    a, w = arrival(t_h, v, t_cme_s / HOUR)
+    return t_h, v, a, w
+
+
+def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4, log=print, max_blocks=0):
+    """From a relaxed state (relax's dict; None starts a plain equidistant run
+    from the initial state and runs it through the relaxation too) advance to
+    t_end_s with regrids at amr's cadence, recording the sample point every
+    step.  network = (params, mean, std) for the learned sources.  Returns
+    dict(arrival_h, width_h, wall_s, steps, leaf_block_steps, max_leaves,
+    regrid_stats, t_h, v_kms)."""
+    sim = Sim(grid, wind, [cme], amr, max_blocks=max_blocks)
+    if start is not None:
+        sim.set_state(start["blocks"], start["U"], start["t_s"])
+    if network is not None:
+        sim.mlp_set(*network)
+    sim.set_sample_point(*SAMPLE)
+    cells = grid["block"][0] * grid["block"][1] * grid["block"][2]
+    zu0 = 0.0
+    max_leaves = len(sim.blocks())
+    ts = []
+    t0 = time.perf_counter()
+    info = None
+    while sim.time()[0] < t_end_s * (1.0 - 1e-12):
+        info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
+        ts.append(sim.timeseries())
+        sim.timeseries_clear()
+        max_leaves = max(max_leaves, info["leaves"])
+        _log(log, "cme: t = %.2f d, %d steps, %d leaves %s, %.1f s"
+             % (info["t_s"] / DAY, info["steps"], info["leaves"], info["leaves_per_level"][:6],
+                time.perf_counter() - t0))
+    wall = time.perf_counter() - t0
+    ts = np.concatenate(ts) if ts else np.zeros((0, 9))
+    t_h, v, a, w = _series_arrival(ts, cme["t_start_s"])
+    out = dict(arrival_h=a, width_h=w, wall_s=wall, steps=info["steps"] if info else 0,
+               leaf_block_steps=((info["zone_updates"] if info else 0.0) - zu0) / cells, max_leaves=max_leaves,
+               regrid_stats=sim.regrid_stats(), t_h=t_h, v_kms=v)
+    sim.close()
+    return out
+
+
+def collect_pairs(grid, wind, cme, amr, start, t_end_s, every, log=print, max_blocks=0):
+    """Training pairs of a plain run (buffer and cadence as in amr): at each
+    regrid time the features of every leaf, labelled 1 if the leaf meets the
+    refinement condition (ic_eval_hot) at that time or after any of the next
+    `every` steps, else 0.  Returns (raw float32 [n, 512], y uint8 [n])."""
+    sim = Sim(grid, wind, [cme], dict(amr, source=IC_SOURCE_PLAIN), max_blocks=max_blocks)
+    sim.set_state(start["blocks"], start["U"], start["t_s"])
+    X, Y = [], []
+    t0 = time.perf_counter()
+    cycle = 0
+    while sim.time()[0] < t_end_s:
+        x = sim.features()
+        lab = sim.eval_hot().astype(bool)
+        for _ in range(every):
+            sim.step()
+            lab |= sim.eval_hot().astype(bool)
+        X.append(x)
+        Y.append(lab.astype(np.uint8))
+        info = sim.regrid()
+        cycle += 1
+        if cycle % 20 == 0:
+            n = sum(len(y) for y in Y)
+            pos = sum(int(y.sum()) for y in Y)
+            _log(log, "collect: t = %.2f d, %d pairs (%.3f positive), %d leaves, %.1f s"
+                 % (sim.time()[0] / DAY, n, pos / max(n, 1), info["leaves"], time.perf_counter() - t0))
+    sim.close()
+    return np.concatenate(X), np.concatenate(Y)
+
+
+def train(raw, y, epochs=10, batch=4096, lr=1e-3, seed=0):
+    """Weighted BCE (pos_weight = N_neg / N_pos) with Adam on the GPU from a
+    He-uniform start.  Returns (params, mean, std, loss per epoch)."""
+    return mlp_train(raw, y, mlp_init(seed), epochs=epochs, batch=batch, lr=lr, seed=seed, pos_weight=0.0)
+
+
+def save_network(path, params, mean, std, meta):
+    np.savez(path, params=np.asarray(params, np.float32), mean=np.asarray(mean, np.float32),
+             std=np.asarray(std, np.float32), meta=np.array(json.dumps(meta)))
+
+
+def load_network(path):
+    d = np.load(path, allow_pickle=False)
+    return (d["params"], d["mean"], d["std"]), json.loads(str(d["meta"]))
+
+
+# --- command line ---------------------------------------------------------------
+
+def _workload_parts(name, wind_seed=None, cme=None, max_level=None):
+    from synthetic import Wind, as_dict, workload
+    w = workload(name)
+    grid = as_dict(w.grid)
+    if max_level is not None:
+        grid["max_level"] = max_level
+    wind = as_dict(w.wind if wind_seed is None else Wind(seed=wind_seed))
+    c = as_dict(w.cmes[0]) if cme is None else cme
+    return grid, wind, c, as_dict(w.amr), w
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_2211_12867_amd.forecast")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train", help="collect look-ahead pairs from seeded plain runs and train the network")
+    t.add_argument("--out", required=True)
+    t.add_argument("--runs", type=int, default=16)
+    t.add_argument("--max-level", type=int, default=5)
+    t.add_argument("--relax-days", type=float, default=14.0)
+    t.add_argument("--cme-days", type=float, default=1.5)
+    t.add_argument("--every", type=int, default=10)
+    t.add_argument("--epochs", type=int, default=10)
+    c = sub.add_parser("compare", help="equidistant vs plain AMR (buffer) vs learned AMR (no buffer) to arrival")
+    c.add_argument("--net", required=True)
+    c.add_argument("--max-level", type=int, default=5)
+    c.add_argument("--relax-days", type=float, default=14.0)
+    c.add_argument("--cme-days", type=float, default=3.0)
+    c.add_argument("--skip-equidistant", action="store_true")
+    c.add_argument("--out")
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    if args.cmd == "train":
+        from synthetic import as_dict, cme_ensemble
+        Xs, Ys = [], []
+        for r in range(args.runs):
+            cme = as_dict(cme_ensemble(1, 2000 + r, t_start_s=args.relax_days * DAY)[0])
+            grid, wind, cme, amr, _ = _workload_parts("learned_flags", wind_seed=1 + r, cme=cme,
+                                                      max_level=args.max_level)
+            log("run %d: wind seed %d, cme %s" % (r, 1 + r, {k: round(v, 1) for k, v in cme.items()
+                                                                if isinstance(v, float)}))
+            st = relax(grid, wind, cme, args.relax_days * DAY, log=log)
+            amr = dict(amr, buffer_blocks=1, regrid_every=args.every)
+            X, y = collect_pairs(grid, wind, cme, amr, st, (args.relax_days + args.cme_days) * DAY, args.every,
+                                 log=log)
+            Xs.append(X)
+            Ys.append(y)
+            log("run %d: %d pairs, %.3f positive" % (r, len(y), y.mean()))
+        X = np.concatenate(Xs)
+        y = np.concatenate(Ys)
+        params, mean, std, loss = train(X, y, epochs=args.epochs)
+        meta = dict(pairs=int(len(y)), positive=float(y.mean()), runs=args.runs, wind_seeds=[1, args.runs],
+                    cme_seeds=[2000, 1999 + args.runs], max_level=args.max_level, every=args.every,
+                    cme_days=args.cme_days, epochs=args.epochs, loss=[float(v) for v in loss])
+        save_network(args.out, params, mean, std, meta)
+        log("trained: %s" % json.dumps(meta))
+        return 0
+
+    net, meta = load_network(args.net)
+    grid, wind, cme, amr, w = _workload_parts("learned_flags", max_level=args.max_level)
+    t_end = (args.relax_days + args.cme_days) * DAY
+    cme = dict(cme, t_start_s=args.relax_days * DAY)
+    res = {}
+    st = relax(grid, wind, cme, args.relax_days * DAY, log=log)
+    runs = (("plain_buffer", dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
+            ("learned", dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0), net),
+            ("plain_no_buffer", dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=0), None))
+    for name, a, n in runs:
+        log("== %s" % name)
+        r = cme_run(grid, wind, cme, a, st, t_end, network=n, log=log)
+        r["relax_wall_s"] = st["wall_s"]
+        res[name] = r
+    if not args.skip_equidistant:
+        g1, w1, c1, _, _ = _workload_parts("equidistant_full")
+        c1 = dict(c1, t_start_s=args.relax_days * DAY)
+        log("== equidistant")
+        res["equidistant"] = cme_run(g1, w1, c1, dict(regrid_every=0), None, t_end, log=log, chunk_s=DAY)
+    summary = {k: {q: v[q] for q in ("arrival_h", "width_h", "wall_s", "steps", "leaf_block_steps", "max_leaves",
+                                     "regrid_stats")} for k, v in res.items()}
+    log(json.dumps(summary))
+    if args.out:
+        np.savez(args.out, **{"%s_%s" % (k, q): res[k][q] for k in res for q in ("t_h", "v_kms")},
+                 summary=np.array(json.dumps(summary)))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -210,3 +210,23 @@ def test_learned_flags_need_a_network():
         gpu.eval_learned()
     assert e.value.status == ic.IC_E_INVALID
     gpu.close()
+
+
+def test_hot_labels_match_oracle():
+    """ic_eval_hot (the refinement condition without the level cap, the
+    source of the look-ahead labels) equals the oracle's, bit for bit."""
+    ic = _ic()
+    ora, grid, wind, cme, amr = _oracle_after(8, max_level=2)
+    ora.regrid()
+    for _ in range(3):
+        ora.step()
+    ties = []
+    ora.flags(ties)
+    assert not ties, ties[:3]
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    gpu.set_state(*ora.state(), ora.t * units.T0)
+    hot = ora.hot()
+    got = gpu.eval_hot()
+    assert [int(h) for h in got] == [hot[b] for b in ora.blocks()]
+    assert any(b[0] == 2 and hot[b] for b in ora.blocks()), "no hot leaf at the finest level"
+    gpu.close()

@@ -278,3 +278,43 @@ def test_invalid_config():
     with pytest.raises(ic.ICError) as ex:
         ic.Sim(g)
     assert ex.value.status == ic.IC_E_INVALID
+
+
+def test_full_longitude_amr_across_the_periodic_seam():
+    """360-degree grid, CME and refinement windows centred on longitude 0:
+    leaves of three levels meet across the periodic phi boundary (ghost
+    slabs, prolongation, restriction and reflux through the seam)."""
+    ic = _ic()
+    grid = dict(geometry="spherical", x0=(0.1, 60.0, 0.0), x1=(1.1, 120.0, 360.0), n=(16, 8, 32),
+                block=(8, 8, 8), stretched_r=True, max_level=3, periodic=(False, False, True), gamma=1.5, cfl=0.4)
+    _, wind, _, amr = _amr_wedge()
+    cme = as_dict(Cme(t_start_s=0.0, duration_s=6 * 3600.0, v_kms=1500.0, half_width_deg=45.0,
+                      colat_deg=90.0, lon_deg=0.0, n_cm3=1200.0, T_K=0.8e6))
+    ora = solver.Solver(grid, wind, cme, amr)
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    gpu.set_state(*ora.state(), 0.0)
+    seam = False
+    for cycle in range(4):
+        for _ in range(5):
+            ora.step()
+            gpu.step()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-10, (cycle, e)
+        gpu.set_state(*ora.state(), ora.t * units.T0)
+        ties = []
+        f = ora.flags(ties)
+        assert not ties, ties[:3]
+        assert [int(x) for x in gpu.eval_flags()] == [f[b] for b in ora.blocks()]
+        ora.regrid(f)
+        gpu.regrid()
+        assert gpu.blocks() == ora.blocks()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-13, (cycle, e)
+        nphi = [grid["n"][2] // grid["block"][2] * 2 ** (b[0] - 1) for b in ora.blocks()]
+        levels_at = {}
+        for b, n in zip(ora.blocks(), nphi):
+            if b[3] in (0, n - 1):
+                levels_at.setdefault(b[3] == 0, set()).add(b[0])
+        seam = seam or (len(levels_at.get(True, ())) > 1 or len(levels_at.get(False, ())) > 1)
+    assert max(b[0] for b in ora.blocks()) == 3
+    assert seam, "no level change along the seam"

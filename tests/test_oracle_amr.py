@@ -2,7 +2,9 @@
 
 - restriction of a prolongation is the identity, and a linear field is
   prolonged exactly where the limiter is inactive (conservative, centroid
-  based prolongation);
+  based prolongation); where linear values would make a child's pressure
+  negative (a cold linear velocity ramp, closed form below) the children
+  take the parent's value;
 - one-level forests give the same state, bit for bit, as the single-patch
   solver (the block decomposition and ghost exchange change nothing);
 - a two-level periodic box with reflux conserves sum(V U) to round-off, and a
@@ -71,7 +73,8 @@ def test_linear_field_prolonged_exactly():
     for leaf in s.forest.leaves:
         x = [np.array([g1.centre(d, m) for m in range(*s.cell_range(leaf, d))]) for d in range(3)]
         Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
-        s.U[leaf] = np.stack([1.0 + 0.5 * X + 0.3 * Y + 0.2 * Z + v for v in range(8)])
+        # physical everywhere (energy offset large), so no positivity fallback
+        s.U[leaf] = np.stack([1.0 + 0.5 * X + 0.3 * Y + 0.2 * Z + (40.0 if v == 4 else 0.1 * v) for v in range(8)])
     G = s.ghosted(s.U, 0.0)
     ch = (2, 2, 2, 2)   # its parent cells and their neighbours are away from the boundary
     gidx = [np.arange(ch[1 + d] * np.array(grid["block"])[d], (ch[1 + d] + 1) * grid["block"][d]) for d in range(3)]
@@ -104,6 +107,47 @@ def test_prolongation_is_conservative():
         s.U[leaf] = 1.0 + rng.uniform(0, 1, s.U[leaf].shape)
     tot0 = s.total()
     _refine(s, {(1, 0, 1, 1), (1, 1, 0, 0)})
+    assert np.allclose(s.total(), tot0, rtol=1e-14)
+
+
+@pytest.mark.parametrize("P", [0.05, 0.5])
+def test_prolongation_positivity_fallback(P):
+    """rho = 1, v_x = k x, B = 0, p/(gamma-1) = P on a uniform Cartesian grid
+    of spacing h.  m_x is linear and prolonged exactly; E = k^2 x^2 / 2 + P has
+    the one-sided slopes k^2 (x -+ h/2), minmod takes the smaller one, and the
+    children of cell x > 0 get p/(gamma-1) = P + 3 k^2 h^2 / 32 at x - h/4 and
+    P - 5 k^2 h^2 / 32 at x + h/4.  With k h = 1 the latter is negative for
+    P = 0.05, so every child takes its parent's value; for P = 0.5 both are
+    positive and the linear values stay."""
+    g = _box(levels=2, n=(16, 4, 4), block=(4, 4, 4), periodic=(False, True, True))
+    g["x1"] = (16.0, 4.0, 4.0)             # h = 1
+    s = solver.Solver(g, initial="zero")
+    k = 1.0
+    for leaf in s.forest.leaves:
+        x = np.array([s.geo[1].centre(0, m) for m in range(*s.cell_range(leaf, 0))])
+        U = np.zeros((8, 4, 4, 4))
+        U[0] = 1.0
+        U[1] = k * x[None, None, :]
+        U[4] = 0.5 * (k * x[None, None, :]) ** 2 + P
+        s.U[leaf] = U
+    parent = (1, 2, 0, 0)                  # cells x = 8.5 .. 11.5, interior
+    U0 = s.U[parent].copy()
+    tot0 = s.total()
+    _refine(s, {parent})
+    kids = [b for b in s.forest.leaves if b[0] == 2]
+    assert len(kids) == 8
+    for ch in kids:
+        Uf = s.U[ch]
+        for i in range(4):
+            gi = ch[1] * 4 + i                 # fine global index, fine spacing h / 2
+            pc = gi // 2 - 8                   # parent-local cell
+            if P == 0.05:
+                assert np.array_equal(Uf[:, :, :, i], np.broadcast_to(U0[:, :, :, pc], Uf[:, :, :, i].shape))
+            else:
+                assert np.allclose(Uf[1, :, :, i], k * (gi + 0.5) * 0.5, rtol=1e-14)
+                eint = Uf[4, :, :, i] - 0.5 * Uf[1, :, :, i] ** 2 / Uf[0, :, :, i]
+                expect = P + (3.0 if gi % 2 == 0 else -5.0) * k ** 2 / 32.0
+                assert np.allclose(eint, expect, rtol=1e-12)
     assert np.allclose(s.total(), tot0, rtol=1e-14)
 
 

@@ -106,3 +106,24 @@ def test_arrival_triangle_width():
     a, width, vpre, vmax = analysis.arrival(t, v, 5.0)
     assert abs(a + 5.0 - 43.0) < 1e-12 and abs(width - 3.0) < 1e-12
     assert vpre == 400.0 and vmax == 800.0
+
+
+def test_hot_is_the_uncapped_refine_condition():
+    """hot() marks the leaves the plain criterion refines when the level cap
+    does not bind, and is independent of the cap."""
+    from synthetic import as_dict, workload
+    w = workload("tiny_wedge")
+    amr = dict(as_dict(w.amr), lon_earth_deg=45.0, dlon_earth_deg=60.0, dclt_earth_deg=30.0)
+    g1 = dict(as_dict(w.grid), max_level=1)
+    g2 = dict(as_dict(w.grid), max_level=2)
+    s1 = solver.Solver(g1, as_dict(w.wind), as_dict(w.cmes[0]), amr)
+    for _ in range(12):
+        s1.step()
+    s2 = solver.Solver(g2, as_dict(w.wind), as_dict(w.cmes[0]), amr)
+    s2.set_state(*s1.state(), s1.t)
+    h1, h2 = s1.hot(), s2.hot()
+    assert h1 == h2
+    f1, f2 = s1.flags(), s2.flags()
+    assert all(f == 0 for f in f1.values())                     # level 1 = max level: never REFINE
+    assert {b: int(f == 1) for b, f in f2.items()} == h2
+    assert 0 < sum(h2.values()) < len(h2)
