@@ -194,6 +194,11 @@ ic_status ic_eval_flags(ic_sim *sim, int member, int8_t *flags, int n);
  * n is the capacity of hot and must be >= the leaf count. */
 ic_status ic_eval_hot(ic_sim *sim, int member, int8_t *hot, int n);
 
+/* Refinement windows per leaf (ic_get_blocks order): in[q] = 1 if some cell
+ * centre of leaf q lies in the Sect. 3.2 windows of the member (always 1 with
+ * use_windows = 0).  Learned flags ask for refinement only on such leaves. */
+ic_status ic_eval_window(ic_sim *sim, int member, int8_t *in, int n);
+
 /* Primitive variables (rho, v_r, v_theta, v_phi, p, B_r, B_theta, B_phi), code
  * units, at a point: trilinear interpolation between the cell centres of the
  * level of the finest leaf containing the point (cells of a coarser leaf
@@ -256,7 +261,8 @@ ic_status ic_features(ic_sim *sim, int member, float *raw, int n);
 /* Install a trained network (params fp32, per-input mean and std). */
 ic_status ic_mlp_set(ic_sim *sim, const float *params, const float *mean, const float *std);
 
-/* Network probability and flag (IC_FLAG_REFINE / IC_FLAG_COARSEN) per leaf. */
+/* Network probability and flag per leaf: IC_FLAG_REFINE if p >= 1/2 and the
+ * leaf touches the refinement windows (ic_eval_window), else IC_FLAG_COARSEN. */
 ic_status ic_eval_learned(ic_sim *sim, int member, float *prob, int8_t *flags, int n);
 
 /* Learned-flag bookkeeping since ic_create: regrids that used the network,
@@ -271,6 +277,12 @@ ic_status ic_regrid_stats(ic_sim *sim, long *learned, long *judged, long *fallba
  * null stream of the current device. */
 ic_status ic_mlp_train(const float *raw, const uint8_t *y, long n, const ic_mlp_hparams *hp, float *params,
                        float *mean, float *std, float *loss_per_epoch);
+
+/* Network probabilities of n rows of raw inputs (as ic_features gives them):
+ * z-scored with mean/std, then the bf16 MFMA forward pass.  Runs on the null
+ * stream of the current device. */
+ic_status ic_mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std,
+                       float *prob);
 
 /* One forward and backward pass on n rows of already normalised inputs
  * (fp32, rounded to bf16 inside): gradient of the mean weighted BCE in

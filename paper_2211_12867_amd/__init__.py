@@ -94,10 +94,10 @@ class Info(ctypes.Structure):
 
 
 EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_eval_flags", "ic_eval_hot",
-           "ic_sample", "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks",
+           "ic_eval_window", "ic_sample", "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks",
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
-           "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_last_error")
+           "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_last_error")
 
 
 def _load():
@@ -119,6 +119,7 @@ def _load():
     L.ic_regrid.argtypes = [vp, P(ctypes.c_int8), P(Info)]
     L.ic_eval_flags.argtypes = [vp, ctypes.c_int, P(ctypes.c_int8), ctypes.c_int]
     L.ic_eval_hot.argtypes = [vp, ctypes.c_int, P(ctypes.c_int8), ctypes.c_int]
+    L.ic_eval_window.argtypes = [vp, ctypes.c_int, P(ctypes.c_int8), ctypes.c_int]
     L.ic_sample.argtypes = [vp, ctypes.c_int] + [ctypes.c_double] * 3 + [P(ctypes.c_double)]
     L.ic_set_sample_point.argtypes = [vp] + [ctypes.c_double] * 3
     L.ic_timeseries.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_int)]
@@ -141,6 +142,7 @@ def _load():
     L.ic_regrid_stats.argtypes = [vp, P(ctypes.c_long), P(ctypes.c_long), P(ctypes.c_long), P(ctypes.c_double)]
     L.ic_mlp_train.argtypes = [fp, u8p, ctypes.c_long, P(MlpHparams), fp, fp, fp, fp]
     L.ic_mlp_grad.argtypes = [fp, u8p, ctypes.c_int, ctypes.c_float, fp, fp, fp]
+    L.ic_mlp_infer.argtypes = [fp, ctypes.c_long, fp, fp, fp, fp]
     L.ic_pool_capacity.argtypes = [vp]
     L.ic_pool_capacity.restype = ctypes.c_int
     L.ic_last_error.restype = ctypes.c_char_p
@@ -316,16 +318,29 @@ class Sim:
     def _max_blocks(self):
         return int(lib.ic_pool_capacity(self.h))
 
+    def n_leaves(self, member=0):
+        n = ctypes.c_int(0)
+        st = lib.ic_get_blocks(self.h, member, None, ctypes.byref(n))
+        if st not in (IC_OK, IC_E_INVALID):
+            _check(st)
+        return n.value
+
     def eval_flags(self, member=0):
-        n = len(self.blocks(member))
+        n = self.n_leaves(member)
         out = np.zeros(n, dtype=np.int8)
         _check(lib.ic_eval_flags(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
         return out
 
     def eval_hot(self, member=0):
-        n = len(self.blocks(member))
+        n = self.n_leaves(member)
         out = np.zeros(n, dtype=np.int8)
         _check(lib.ic_eval_hot(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
+        return out
+
+    def eval_window(self, member=0):
+        n = self.n_leaves(member)
+        out = np.zeros(n, dtype=np.int8)
+        _check(lib.ic_eval_window(self.h, member, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
         return out
 
     # --- sampling ---------------------------------------------------------------
@@ -388,7 +403,7 @@ class Sim:
 
     # --- learned flags ------------------------------------------------------------
     def features(self, member=0):
-        n = len(self.blocks(member))
+        n = self.n_leaves(member)
         out = np.zeros((n, MLP_IN), dtype=np.float32)
         _check(lib.ic_features(self.h, member, _fptr(out), n))
         return out
@@ -399,7 +414,7 @@ class Sim:
         _check(lib.ic_mlp_set(self.h, *[_fptr(a) for a in self._mlp]))
 
     def eval_learned(self, member=0):
-        n = len(self.blocks(member))
+        n = self.n_leaves(member)
         prob = np.zeros(n, dtype=np.float32)
         flags = np.zeros(n, dtype=np.int8)
         _check(lib.ic_eval_learned(self.h, member, _fptr(prob), flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), n))
@@ -440,6 +455,15 @@ def mlp_grad(xnorm, y, params, pos_weight=1.0):
     _check(lib.ic_mlp_grad(_fptr(xnorm), y.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), len(y),
                            float(pos_weight), _fptr(params), _fptr(grad), ctypes.byref(loss)))
     return grad, loss.value
+
+
+def mlp_infer(raw, params, mean, std):
+    """Network probabilities of rows of raw inputs on the GPU."""
+    raw = np.ascontiguousarray(raw, dtype=np.float32)
+    prob = np.zeros(len(raw), dtype=np.float32)
+    ps = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, mean, std)]
+    _check(lib.ic_mlp_infer(_fptr(raw), len(raw), *[_fptr(a) for a in ps], _fptr(prob)))
+    return prob
 
 
 def mlp_init(seed=0):

@@ -54,3 +54,4 @@ void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float
               float *loss_out);
 void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp, float *params, float *mean_out,
                float *std_out, float *loss_epochs);
+void mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std, float *prob);

@@ -478,3 +478,23 @@ void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp,
     std::memcpy(mean_out, mean_h.data(), IC_MLP_IN * sizeof(float));
     std::memcpy(std_out, std_h.data(), IC_MLP_IN * sizeof(float));
 }
+
+void mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std, float *prob)
+{
+    MlpDevice d;
+    d.set(params, mean, std);
+    const long chunk = 65536;
+    d.reserve((int)std::min(n, chunk));
+    Buf<float> rawd((size_t)std::min(n, chunk) * IC_MLP_IN);
+    for (long b0 = 0; b0 < n; b0 += chunk) {
+        const long m = std::min(chunk, n - b0);
+        if (hipMemcpy(rawd.p, raw + b0 * IC_MLP_IN, (size_t)m * IC_MLP_IN * sizeof(float), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            throw std::runtime_error("hipMemcpy failed");
+        hipLaunchKernelGGL(k_normalise, dim3((m * IC_MLP_IN + 255) / 256), dim3(256), 0, 0, rawd.p, d.mean, d.istd, m,
+                           d.xb);
+        d.forward(0, (int)m);
+        if (hipMemcpy(prob + b0, d.prob, m * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+            throw std::runtime_error("hipMemcpy failed");
+    }
+}

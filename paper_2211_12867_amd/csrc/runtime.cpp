@@ -1129,12 +1129,46 @@ void learned_prob(ic_sim *s)
     s->mlp.forward(s->stream, s->n_items);
 }
 
+// 1 if some cell centre of the leaf lies in the refinement windows of member m
+// (the cell test of the indicator: |lon - lon_E| <= dlon_E, |colat - colat_E|
+// <= dclt_E and, with a CME, |lon - lon_CME| <= dlon_CME); always 1 without
+// windows.  The windows separate in colatitude and longitude.
+bool leaf_in_windows(const ic_sim *s, int m, const Key &key)
+{
+    if (!s->amr.use_windows || s->cart) return true;
+    const double deg = M_PI / 180.0, PI = 3.14159265358979323846;
+    const HostLevel &L = s->lv[key.l];
+    auto wrap = [&](double x) {
+        const double y = x - 2.0 * PI * std::floor((x + PI) / (2.0 * PI));
+        return y == -PI ? PI : y;
+    };
+    bool th = false;
+    for (int j = 0; j < s->B[1] && !th; ++j)
+        th = std::fabs(L.t[key.j * s->B[1] + j + 2].tc - s->amr.clt_earth_deg * deg) <= s->amr.dclt_earth_deg * deg;
+    if (!th) return false;
+    const bool cme_on = s->mem[m].cme.enabled != 0;
+    for (int k = 0; k < s->B[2]; ++k) {
+        const double pc = L.p[key.k * s->B[2] + k + 2].pc;
+        if (std::fabs(wrap(pc - s->amr.lon_earth_deg * deg)) <= s->amr.dlon_earth_deg * deg &&
+            (!cme_on || std::fabs(wrap(pc - s->mem[m].cme.lon_deg * deg)) <= s->amr.dlon_cme_deg * deg))
+            return true;
+    }
+    return false;
+}
+
+// learned flags per pool slot: REFINE where the network gives p >= 1/2 and
+// the leaf touches the windows, else COARSEN
 void learned_flags(ic_sim *s, std::vector<int8_t> &fl)
 {
     learned_prob(s);
     mlp_prob_flags(s->stream, s->mlp.prob, s->items.p, s->n_items, s->flags.p);
     HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
+    for (int m = 0; m < s->nm; ++m)
+        for (auto &kv : s->mem[m].leaves) {
+            const int slot = s->slot_of(m, kv.second);
+            if (fl[slot] == IC_FLAG_REFINE && !leaf_in_windows(s, m, kv.first)) fl[slot] = IC_FLAG_COARSEN;
+        }
 }
 
 void do_regrid(ic_sim *s, const int8_t *user_flags)
@@ -1577,6 +1611,20 @@ ic_status ic_eval_hot(ic_sim *s, int member, int8_t *hot, int n)
     return guard(s, [&]() { leaf_indicator(s, member, hot, n, 1 << 20, true); });
 }
 
+ic_status ic_eval_window(ic_sim *s, int member, int8_t *in, int n)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm || !in) throw Error(IC_E_INVALID, "bad member or buffer");
+        Member &M = s->mem[member];
+        if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "buffer too small");
+        std::vector<Key> keys;
+        for (auto &kv : M.leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
+        for (size_t q = 0; q < keys.size(); ++q) in[q] = leaf_in_windows(s, member, keys[q]) ? 1 : 0;
+    });
+}
+
 ic_status ic_sample(ic_sim *s, int member, double r_au, double colat_deg, double lon_deg, double prim_out[8])
 {
     return guard(s, [&]() {
@@ -1805,9 +1853,13 @@ ic_status ic_eval_learned(ic_sim *s, int member, float *prob, int8_t *flags, int
         std::vector<float> p(nl);
         HIPCHECK(hipStreamSynchronize(s->stream));
         HIPCHECK(hipMemcpy(p.data(), s->mlp.prob + mb[member], nl * sizeof(float), hipMemcpyDeviceToHost));
+        std::vector<Key> keys;
+        for (auto &kv : s->mem[member].leaves) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end(), abi_order);
         for (int q = 0; q < nl; ++q) {
             if (prob) prob[q] = p[q];
-            if (flags) flags[q] = p[q] >= 0.5f ? IC_FLAG_REFINE : IC_FLAG_COARSEN;
+            if (flags)
+                flags[q] = p[q] >= 0.5f && leaf_in_windows(s, member, keys[q]) ? IC_FLAG_REFINE : IC_FLAG_COARSEN;
         }
     });
 }
@@ -1845,6 +1897,20 @@ ic_status ic_mlp_grad(const float *xnorm, const uint8_t *y, int n, float pos_wei
         if (!xnorm || !y || !params || !grad || !loss || n < 1) throw Error(IC_E_INVALID, "bad argument");
         try {
             mlp_grad(xnorm, y, n, pos_weight, params, grad, loss);
+        } catch (const std::runtime_error &e) {
+            throw Error(IC_E_DEVICE, e.what());
+        }
+    });
+}
+
+ic_status ic_mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std, float *prob)
+{
+    return guard(nullptr, [&]() {
+        if (!raw || !params || !mean || !std || !prob || n < 1) throw Error(IC_E_INVALID, "bad argument");
+        for (int f = 0; f < IC_MLP_IN; ++f)
+            if (!(std[f] > 0.0f)) throw Error(IC_E_INVALID, "std must be positive");
+        try {
+            mlp_infer(raw, n, params, mean, std, prob);
         } catch (const std::runtime_error &e) {
             throw Error(IC_E_DEVICE, e.what());
         }

@@ -17,7 +17,7 @@ import time
 
 import numpy as np
 
-from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_init, mlp_train, units
+from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_infer, mlp_init, mlp_train, units
 
 DAY = 86400.0
 HOUR = 3600.0
@@ -46,11 +46,20 @@ def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
     return out
 
 
-def _series_arrival(ts, t_cme_s):
-    """(t [h], v_r [km/s]) of the record and the shock arrival (R27 reading)."""
+MIN_JUMP_KMS = 100.0   # a rise of v_r smaller than this within the window is no shock arrival
+
+
+def _series_arrival(ts, t_cme_s, window_h=96.0):
+    """(t [h], v_r [km/s]) of the record and the shock arrival and width [h]
+    (half-rise crossing after the CME start; NaN without a rise of at least
+    MIN_JUMP_KMS)."""
     t_h = ts[:, 0] / HOUR
-    v = ts[:, 2] * units()[1] / 1e3
-    a, w = arrival(t_h, v, t_cme_s / HOUR)
+    v = ts[:, 2] * units()["speed_m_s"] / 1e3
+    t0 = t_cme_s / HOUR
+    win = (t_h >= t0) & (t_h <= t0 + window_h)
+    if not win.any() or v[win].max() - np.interp(t0, t_h, v) < MIN_JUMP_KMS:
+        return t_h, v, float("nan"), float("nan")
+    a, w = arrival(t_h, v, t0, window_h)
     return t_h, v, a, w
 
 
@@ -91,24 +100,31 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
     return out
 
 
-def collect_pairs(grid, wind, cme, amr, start, t_end_s, every, log=print, max_blocks=0):
+def collect_pairs(grid, wind, cme, amr, start, t_end_s, every, log=print, max_blocks=0, keep_every=1):
     """Training pairs of a plain run (buffer and cadence as in amr): at each
-    regrid time the features of every leaf, labelled 1 if the leaf meets the
-    refinement condition (ic_eval_hot) at that time or after any of the next
-    `every` steps, else 0.  Returns (raw float32 [n, 512], y uint8 [n])."""
+    regrid time the features of every leaf that touches the refinement
+    windows (the others never refine, whatever the network says), labelled
+    1 if the leaf meets the refinement condition (ic_eval_hot) at that time or
+    after any of the next `every` steps, else 0; pairs are kept from every
+    keep_every-th regrid cycle.  Returns (raw float32 [n, 512], y uint8 [n])."""
     sim = Sim(grid, wind, [cme], dict(amr, source=IC_SOURCE_PLAIN), max_blocks=max_blocks)
     sim.set_state(start["blocks"], start["U"], start["t_s"])
     X, Y = [], []
     t0 = time.perf_counter()
     cycle = 0
     while sim.time()[0] < t_end_s:
-        x = sim.features()
-        lab = sim.eval_hot().astype(bool)
+        keep = cycle % keep_every == 0
+        if keep:
+            win = sim.eval_window().astype(bool)
+            x = sim.features()[win]
+            lab = sim.eval_hot().astype(bool)
         for _ in range(every):
             sim.step()
-            lab |= sim.eval_hot().astype(bool)
-        X.append(x)
-        Y.append(lab.astype(np.uint8))
+            if keep:
+                lab |= sim.eval_hot().astype(bool)
+        if keep:
+            X.append(x)
+            Y.append(lab[win].astype(np.uint8))
         info = sim.regrid()
         cycle += 1
         if cycle % 20 == 0:
@@ -124,6 +140,16 @@ def train(raw, y, epochs=10, batch=4096, lr=1e-3, seed=0):
     """Weighted BCE (pos_weight = N_neg / N_pos) with Adam on the GPU from a
     He-uniform start.  Returns (params, mean, std, loss per epoch)."""
     return mlp_train(raw, y, mlp_init(seed), epochs=epochs, batch=batch, lr=lr, seed=seed, pos_weight=0.0)
+
+
+def evaluate(raw, y, network):
+    """REFINE recall and precision, accuracy and positive rate of the
+    network's p >= 1/2 decision on labelled rows."""
+    p = mlp_infer(raw, *network) >= 0.5
+    y = np.asarray(y).astype(bool)
+    tp = int(np.sum(p & y))
+    return dict(rows=int(len(y)), positive=float(y.mean()), recall=tp / max(int(y.sum()), 1),
+                precision=tp / max(int(p.sum()), 1), accuracy=float(np.mean(p == y)))
 
 
 def save_network(path, params, mean, std, meta):
@@ -160,6 +186,9 @@ def main(argv=None):
     t.add_argument("--cme-days", type=float, default=1.5)
     t.add_argument("--every", type=int, default=10)
     t.add_argument("--epochs", type=int, default=10)
+    t.add_argument("--keep-every", type=int, default=4)
+    t.add_argument("--time-budget", type=float, default=900.0,
+                   help="seconds after which no further run is started (training uses what was collected)")
     c = sub.add_parser("compare", help="equidistant vs plain AMR (buffer) vs learned AMR (no buffer) to arrival")
     c.add_argument("--net", required=True)
     c.add_argument("--max-level", type=int, default=5)
@@ -167,6 +196,7 @@ def main(argv=None):
     c.add_argument("--cme-days", type=float, default=3.0)
     c.add_argument("--skip-equidistant", action="store_true")
     c.add_argument("--out")
+    c.add_argument("--only", help="comma-separated subset of the AMR runs")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -175,7 +205,12 @@ def main(argv=None):
     if args.cmd == "train":
         from synthetic import as_dict, cme_ensemble
         Xs, Ys = [], []
+        t_start = time.perf_counter()
+        done = 0
         for r in range(args.runs):
+            if time.perf_counter() - t_start > args.time_budget:
+                log("time budget reached after %d runs" % r)
+                break
             cme = as_dict(cme_ensemble(1, 2000 + r, t_start_s=args.relax_days * DAY)[0])
             grid, wind, cme, amr, _ = _workload_parts("learned_flags", wind_seed=1 + r, cme=cme,
                                                       max_level=args.max_level)
@@ -184,15 +219,28 @@ def main(argv=None):
             st = relax(grid, wind, cme, args.relax_days * DAY, log=log)
             amr = dict(amr, buffer_blocks=1, regrid_every=args.every)
             X, y = collect_pairs(grid, wind, cme, amr, st, (args.relax_days + args.cme_days) * DAY, args.every,
-                                 log=log)
+                                 log=log, keep_every=args.keep_every)
             Xs.append(X)
             Ys.append(y)
-            log("run %d: %d pairs, %.3f positive" % (r, len(y), y.mean()))
+            done += 1
+            log("run %d: %d pairs, %.3f positive, %.0f s" % (r, len(y), y.mean(), time.perf_counter() - t_start))
         X = np.concatenate(Xs)
         y = np.concatenate(Ys)
+        del Xs, Ys
+        npairs, ppos = len(y), y.mean()
         params, mean, std, loss = train(X, y, epochs=args.epochs)
-        meta = dict(pairs=int(len(y)), positive=float(y.mean()), runs=args.runs, wind_seeds=[1, args.runs],
-                    cme_seeds=[2000, 1999 + args.runs], max_level=args.max_level, every=args.every,
+        del X, y
+        # held out: wind seed 0 with the evaluation CME
+        grid, wind, cme, amr, _ = _workload_parts("learned_flags", max_level=args.max_level)
+        cme = dict(cme, t_start_s=args.relax_days * DAY)
+        st = relax(grid, wind, cme, args.relax_days * DAY, log=log)
+        Xh, yh = collect_pairs(grid, wind, cme, dict(amr, buffer_blocks=1, regrid_every=args.every), st,
+                               (args.relax_days + args.cme_days) * DAY, args.every, log=log,
+                               keep_every=args.keep_every)
+        held = evaluate(Xh, yh, (params, mean, std))
+        log("held-out: %s" % json.dumps(held))
+        meta = dict(pairs=int(npairs), positive=float(ppos), runs=done, held_out=held, wind_seeds=[1, done],
+                    cme_seeds=[2000, 1999 + done], max_level=args.max_level, every=args.every,
                     cme_days=args.cme_days, epochs=args.epochs, loss=[float(v) for v in loss])
         save_network(args.out, params, mean, std, meta)
         log("trained: %s" % json.dumps(meta))
@@ -204,12 +252,16 @@ def main(argv=None):
     cme = dict(cme, t_start_s=args.relax_days * DAY)
     res = {}
     st = relax(grid, wind, cme, args.relax_days * DAY, log=log)
-    runs = (("plain_buffer", dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
-            ("learned", dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0), net),
-            ("plain_no_buffer", dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=0), None))
-    for name, a, n in runs:
+    lv = args.max_level
+    runs = {"plain_buffer_L%d" % (lv - 1): (lv - 1, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
+            "plain_buffer_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
+            "learned_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0), net),
+            "plain_no_buffer_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=0), None)}
+    for name, (level, a, n) in runs.items():
+        if args.only and name not in args.only.split(","):
+            continue
         log("== %s" % name)
-        r = cme_run(grid, wind, cme, a, st, t_end, network=n, log=log)
+        r = cme_run(dict(grid, max_level=level), wind, cme, a, st, t_end, network=n, log=log)
         r["relax_wall_s"] = st["wall_s"]
         res[name] = r
     if not args.skip_equidistant:

@@ -11,8 +11,10 @@
   oracle's Adam step on the oracle's gradient: every parameter whose
   gradient is not near zero moves by the same amount;
 - training reduces the loss of a learnable synthetic task and classifies it;
-- a regrid from learned flags gives the oracle's forest and state when the
-  oracle regrids with the flags of its own network (no near-ties);
+- a regrid from learned flags (REFINE where p >= 1/2 on leaves that touch
+  the refinement windows) gives the oracle's forest and state when the
+  oracle regrids with the flags of its own network (no near-ties); the
+  window mask per leaf and ic_mlp_infer match the oracle too;
 - the judge: with a recall bar that cannot be met, the regrid falls back to
   the plain criterion and equals the oracle's plain regrid.
 """
@@ -155,8 +157,10 @@ def _network_for(ora, seed):
     p[mlp.OFF_B3] -= np.float32(thr)
     z2, _, _ = mlp.forward(x, p.astype(np.float64))
     assert np.min(np.abs(z2)) > 5e-3
-    flags = {b: (fo.REFINE if zz >= 0.0 else fo.COARSEN) for b, zz in zip(bl, z2)}
-    return p, mean, std, flags, z2
+    win = {b: bool(ora.window(b, ora.cme).any()) for b in bl}
+    flags = {b: (fo.REFINE if zz >= 0.0 and win[b] else fo.COARSEN) for b, zz in zip(bl, z2)}
+    vetoed = sum(zz >= 0.0 and not win[b] for b, zz in zip(bl, z2))
+    return p, mean, std, flags, z2, vetoed
 
 
 def test_learned_regrid_matches_oracle():
@@ -168,7 +172,8 @@ def test_learned_regrid_matches_oracle():
         ora.step()
     gpu = ic.Sim(grid, wind, [cme], dict(amr, source=ic.IC_SOURCE_LEARNED))
     gpu.set_state(*ora.state(), ora.t * units.T0)
-    p, mean, std, flags, z = _network_for(ora, 21)
+    p, mean, std, flags, z, vetoed = _network_for(ora, 21)
+    assert vetoed > 0, "no refinement vetoed by the windows"
     gpu.mlp_set(p, mean, std)
     prob, fl = gpu.eval_learned()
     assert [int(f) for f in fl] == [flags[b] for b in ora.blocks()]
@@ -188,7 +193,7 @@ def test_judge_falls_back_to_plain_criterion():
     gpu = ic.Sim(grid, wind, [cme], dict(amr, source=ic.IC_SOURCE_LEARNED_JUDGED, judge_every=1,
                                           judge_recall=1.5))
     gpu.set_state(*ora.state(), ora.t * units.T0)
-    p, mean, std, _, _ = _network_for(ora, 22)
+    p, mean, std, _, _, _ = _network_for(ora, 22)
     gpu.mlp_set(p, mean, std)
     ties = []
     plain = ora.flags(ties)
@@ -229,4 +234,24 @@ def test_hot_labels_match_oracle():
     got = gpu.eval_hot()
     assert [int(h) for h in got] == [hot[b] for b in ora.blocks()]
     assert any(b[0] == 2 and hot[b] for b in ora.blocks()), "no hot leaf at the finest level"
+    gpu.close()
+
+
+def test_window_mask_and_inference_match_oracle():
+    ic = _ic()
+    ora, grid, wind, cme, amr = _oracle_after(8, max_level=2)
+    ora.regrid()
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    gpu.set_state(*ora.state(), ora.t * units.T0)
+    win = [int(ora.window(b, ora.cme).any()) for b in ora.blocks()]
+    assert [int(x) for x in gpu.eval_window()] == win
+    assert 0 < sum(win) < len(win)
+    bl, U = ora.state()
+    raw = np.stack([mlp.features(U[b], ora.gamma) for b in range(len(bl))])
+    mean = raw.astype(np.float64).mean(axis=0).astype(np.float32)
+    std = np.maximum(raw.astype(np.float64).std(axis=0), 1e-3).astype(np.float32)
+    p = _params(31)
+    prob = ic.mlp_infer(raw, p, mean, std)
+    _, ref, _ = mlp.forward(mlp.normalise(raw, mean, std).astype(np.float64), p.astype(np.float64))
+    np.testing.assert_allclose(prob, ref, atol=2e-3)
     gpu.close()
