@@ -84,7 +84,7 @@ typedef struct {
 /* Physics: adiabatic index, CFL number (dt = cfl / max sum_d (|v_d|+c_f)/dx_d),
  * frame rotation rate [rad/s] about the theta = 0 axis, G M_sun [m^3 s^-2],
  * small-value floors in code units applied to every stage result (a cell with
- * rho < rho_floor takes rho_floor at unchanged velocity; then a cell with
+ * rho < rho_floor takes rho_floor at zero velocity; then a cell with
  * p < p_floor has its energy raised to give p = p_floor; 0 disables). */
 typedef struct {
     double gamma;

@@ -46,8 +46,9 @@ class UnphysicalState(RuntimeError):
 
 
 # Small-value floors (code units), applied to every stage result: a cell with
-# rho < RHO_FLOOR takes rho = RHO_FLOOR with its velocity kept; then a cell with
-# p < P_FLOOR has its energy raised so that p = P_FLOOR.  The paper's scheme is
+# rho < RHO_FLOOR takes rho = RHO_FLOOR at zero velocity (m / rho of a
+# collapsing density is meaningless, and keeping it plants runaway speeds);
+# then a cell with p < P_FLOOR has its energy raised so that p = P_FLOOR.  The paper's scheme is
 # not positivity preserving and it does not say how its code treats small
 # values; a fast CME followed by slow wind opens a near-vacuum rarefaction
 # behind the CME, where the exact update undershoots to p < 0.
@@ -60,8 +61,7 @@ def apply_floors(U, gamma, rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
     n = 0
     low = U[0] < rho_floor
     if np.any(low):
-        fac = np.where(low, rho_floor / np.where(low, U[0], 1.0), 1.0)
-        U[1:4] *= fac
+        U[1:4] = np.where(low, 0.0, U[1:4])
         U[0] = np.where(low, rho_floor, U[0])
         n += int(low.sum())
     kin = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]

@@ -131,7 +131,7 @@ k_stage(KArgs a)
         // registers carried along k: Wc = W(k), Wn = W(k+1), wL = face state of
         // cell k at k+1/2, Fm = flux at k-1/2
         double Wc[8], Wn[8], wL[8], Fm[8];
-        bool badc = false;
+        int badc = -1;                           // first non-physical input cell of this column
         if (col) {
             double u[8], w0[8], w1[8], lo[8], hi[8], R0[8];
             ghosted8<S>(a, a.U, slot, ci, cj, -2, u); cons_to_prim(u, w0, gs);
@@ -238,7 +238,7 @@ k_stage(KArgs a)
                 double w[8];
 #pragma unroll
                 for (int v = 0; v < 8; ++v) w[v] = sW[v][cj + 2][ci + 2];
-                badc = badc || unphysical(w);
+                if (badc < 0 && unphysical(w)) badc = ci + BI * (cj + BJ * k);
                 double acc[8];
                 const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
                 const double kf = rr.rt * tt.phf * pk.iw;
@@ -271,7 +271,7 @@ k_stage(KArgs a)
                 for (int v = 0; v < 8; ++v) Fm[v] = Fp[v];
             }
         }
-        if (col && badc) a.bad[mem] = 1;
+        if (col && badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
         if (a.want_rate) {
             const double m = block_max(col ? rmax : 0.0, sred);
             if (tid == 0) a.rate[slot] = m;
@@ -561,18 +561,18 @@ __global__ void __launch_bounds__(NT) k_rate(KArgs a)
         const BlockDesc bd = a.desc[slot];
         const LevelGeo lg = a.geo[bd.level];
         double rmax = 0.0;
-        bool bad = false;
+        int bad = -1;
         for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
             const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
             double u[8], w[8];
             for (int v = 0; v < 8; ++v) u[v] = a.U[cidx<S>(slot, v, i, j, k)];
             cons_to_prim(u, w, a.gas);
-            bad = bad || unphysical(w);
+            if (bad < 0 && unphysical(w)) bad = c;
             const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
                                                    lg.p[bd.org[2] + k + 2], a.gas);
             rmax = r > rmax ? r : rmax;
         }
-        if (bad) a.bad[bd.member] = 1;
+        if (bad >= 0 && atomicCAS(&a.bad[2 * bd.member], 0, slot + 1) == 0) a.bad[2 * bd.member + 1] = bad;
         const double m = block_max(rmax, sred);
         if (threadIdx.x == 0) a.rate[slot] = m;
     }

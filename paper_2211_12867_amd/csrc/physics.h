@@ -171,16 +171,15 @@ DEV void add_sources(const double w[8], double rt, double ctil, double rc, doubl
     acc[7] += -rt * ((vp * br - bp * vr) + ctil * (vp * bt - bp * vt));
 }
 
-// Small-value floors on a conserved state: density first (velocity kept),
-// then pressure (energy raised).
+// Small-value floors on a conserved state: density first (a cell below the
+// density floor takes it at zero velocity), then pressure (energy raised).
 DEV void apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
 {
     if (u[0] < rho_min) {
-        const double f = rho_min / u[0];
-        u[1] *= f;
-        u[2] *= f;
-        u[3] *= f;
         u[0] = rho_min;
+        u[1] = 0.0;
+        u[2] = 0.0;
+        u[3] = 0.0;
     }
     const double kin = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
     const double mag = 0.5 * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);

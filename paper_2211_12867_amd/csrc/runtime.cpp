@@ -732,16 +732,19 @@ void run_step(ic_sim *s, double dt_fixed_code, bool record)
     HIPCHECK(hipGraphLaunch(s->gexec, s->stream));
 }
 
+std::string describe_bad(ic_sim *s, int m, int slot, int cell);
+
 void check_bad(ic_sim *s)
 {
-    std::vector<int> bad(s->nm);
-    HIPCHECK(hipMemcpyAsync(bad.data(), s->bad.p, s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    std::vector<int> bad(2 * s->nm);
+    HIPCHECK(hipMemcpyAsync(bad.data(), s->bad.p, 2 * s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
     for (int m = 0; m < s->nm; ++m)
-        if (bad[m]) {
+        if (bad[2 * m]) {
             s->poisoned = true;
             throw Error(IC_E_UNPHYSICAL, "member " + std::to_string(m) +
-                                             ": a leaf cell has rho <= 0, p <= 0 or a non-finite value");
+                                             ": a leaf cell has rho <= 0, p <= 0 or a non-finite value" +
+                                             describe_bad(s, m, bad[2 * m] - 1, bad[2 * m + 1]));
         }
 }
 
@@ -972,6 +975,43 @@ struct Forest {
         return out;
     }
 };
+
+// where the first non-physical cell of member m sits: leaf, cell, its current
+// conserved values and the levels of the leaf's face neighbours
+std::string describe_bad(ic_sim *s, int m, int slot, int cell)
+{
+    std::string out;
+    const Member &M = s->mem[m];
+    const Key *key = nullptr;
+    for (auto &kv : M.leaves)
+        if (s->slot_of(m, kv.second) == slot) key = &kv.first;
+    char buf[512];
+    if (!key) return " (slot " + std::to_string(slot) + " is no current leaf)";
+    const int ci = cell % s->B[0], cj = (cell / s->B[0]) % s->B[1], ck = cell / (s->B[0] * s->B[1]);
+    std::snprintf(buf, sizeof buf, " at leaf (level %d, %d, %d, %d) cell (%d, %d, %d)", key->l, key->i, key->j, key->k,
+                  ci, cj, ck);
+    out += buf;
+    const size_t nc = (size_t)s->B[0] * s->B[1] * s->B[2];
+    double u[8];
+    for (int v = 0; v < 8; ++v)
+        if (hipMemcpy(&u[v], s->U.p + (size_t)slot * 8 * nc + v * nc + cell, sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return out;
+    std::snprintf(buf, sizeof buf, "; U = (%.4g, %.4g, %.4g, %.4g, %.4g, %.4g, %.4g, %.4g)", u[0], u[1], u[2], u[3],
+                  u[4], u[5], u[6], u[7]);
+    out += buf;
+    Forest F{s, M.leaves, s->max_level};
+    out += "; face-neighbour levels";
+    for (int d = 0; d < 3; ++d)
+        for (int side = 0; side < 2; ++side) {
+            out += d == 0 && side == 0 ? " " : "/";
+            std::string lv;
+            for (const Key &n : F.face_neighbours(*key, d, side)) lv += (lv.empty() ? "" : ",") + std::to_string(n.l);
+            out += lv.empty() ? "-" : lv;
+        }
+    return out;
+}
+
 
 void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int buffer_blocks,
                    std::vector<MoveTask> &moves, std::vector<int> &to_free)
@@ -1455,7 +1495,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         s->tend.alloc(s->nm);
         s->dt_last.alloc(s->nm);
         s->rate.alloc(NS);
-        s->bad.alloc(s->nm);
+        s->bad.alloc(2 * s->nm);
         s->nsteps.alloc(s->nm);
         s->slab_ranges.alloc(2 * (IC_MAX_LEVEL + 2));
         s->rf_nblocks.alloc(1);
@@ -1472,7 +1512,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         HIPCHECK(hipMemcpy(s->dt.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(s->dt_last.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
-        HIPCHECK(hipMemset(s->bad.p, 0, s->nm * sizeof(int)));
+        HIPCHECK(hipMemset(s->bad.p, 0, 2 * s->nm * sizeof(int)));
         HIPCHECK(hipMemset(s->nsteps.p, 0, s->nm * sizeof(long)));
         HIPCHECK(hipMemset(s->ring_count.p, 0, s->nm * sizeof(int)));
         HIPCHECK(hipMemset(s->rate.p, 0, NS * sizeof(double)));
@@ -1778,8 +1818,8 @@ ic_status ic_set_state(ic_sim *s, int member, const int32_t *lvl_ijk, int n_bloc
         }
         const double tc = t_s / kT0;
         HIPCHECK(hipMemcpy(s->t.p + member, &tc, sizeof(double), hipMemcpyHostToDevice));
-        const int zero = 0;
-        HIPCHECK(hipMemcpy(s->bad.p + member, &zero, sizeof(int), hipMemcpyHostToDevice));
+        const int zero[2] = {0, 0};
+        HIPCHECK(hipMemcpy(s->bad.p + 2 * member, zero, 2 * sizeof(int), hipMemcpyHostToDevice));
         rebuild(s);
         update_sample_desc(s);
         enqueue_rate(s);

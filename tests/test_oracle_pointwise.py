@@ -150,8 +150,8 @@ def test_small_value_floors():
                   [0.0, 0.0], [0.0, 0.0]])
     U0 = U.copy()
     n = apply_floors(U, g, 1e-6, 1e-9)
-    # cell 0: density raised at unchanged velocity, then pressure floored exactly
-    assert U[0, 0] == 1e-6 and abs(U[1, 0] / U[0, 0] - 2.0) < 1e-15
+    # cell 0: density raised at zero velocity, then pressure floored exactly
+    assert U[0, 0] == 1e-6 and U[1, 0] == 0.0 and U[2, 0] == 0.0 and U[3, 0] == 0.0
     W = np.array(_clib.prim(U[:, 0], g))
     assert abs(W[4] - 1e-9) <= 1e-9 * 1e-6 * (U[4, 0] / 1e-9)
     # cell 1 is physical and untouched
