@@ -105,6 +105,8 @@ def main():
     cells = g["n"][0] * g["n"][1] * g["n"][2]
     for _ in range(args.warmup):
         sim.step()
+    tune = sim.autotune(None, reps=3)
+    print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
     sim.set_kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -147,7 +149,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "equidistant_full: 512x60x180 cells, r 0.1-2 AU, theta 30-150 deg, "
                                "phi 0-360 deg, 2400 blocks of 16x12x12, seeded wind + cone CME",
-                   "cells": cells, "block": list(g["block"]), "parallelism": "single GPU"},
+                   "cells": cells, "block": list(g["block"]), "parallelism": "single GPU",
+                   "schedule": {k: tune[k] for k in ("waves_per_simd", "grid", "xcd_order")}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_stage<16,12,12>", "mean_launch_ms": mean_ms,

@@ -290,6 +290,34 @@ ic_status ic_mlp_infer(const float *raw, long n, const float *params, const floa
 ic_status ic_mlp_grad(const float *xnorm, const uint8_t *y, int n, float pos_weight, const float *params,
                       float *grad, float *loss);
 
+/* Stage-kernel schedule.  None of these choices changes any result bit:
+ * waves_per_simd (1 or 2) is the occupancy the kernel's register allocation
+ * targets, grid the launch size (0 = one work-group per leaf block, else a
+ * persistent grid striding over the work list), xcd_order = 1 lays the work
+ * list out as 8 contiguous runs, one per XCD, so that neighbouring blocks
+ * share an L2.  stage_ms / default_ms: measured mean stage time of the choice
+ * and of (2, 0, 0); from_cache: taken from the cache file; candidates: the
+ * schedules timed. */
+typedef struct {
+    int waves_per_simd;
+    int grid;
+    int xcd_order;
+    double stage_ms, default_ms;
+    int from_cache;
+    int candidates;
+} ic_tune_info;
+
+/* Pick the stage-kernel schedule for this sim: look the key (device, CU count,
+ * block shape, variable count, work-item count to a power of two) up in
+ * cache_path (a text file, one result per line; NULL = no cache), else time
+ * every candidate on the current state (reps launches each; the state is not
+ * changed) and append the winner to the cache.  The choice applies to later
+ * steps; out may be NULL. */
+ic_status ic_autotune(ic_sim *sim, const char *cache_path, int reps, ic_tune_info *out);
+
+/* Force a schedule (waves_per_simd, grid, xcd_order of *tune). */
+ic_status ic_set_tuning(ic_sim *sim, const ic_tune_info *tune);
+
 /* Code-unit scales in SI: [0] length m, [1] speed m/s, [2] time s, [3]
  * density kg/m^3, [4] pressure Pa, [5] field T. */
 void ic_units(double out[6]);

@@ -83,6 +83,15 @@ class MlpHparams(ctypes.Structure):
                 ("seed", ctypes.c_uint), ("pos_weight", ctypes.c_float)]
 
 
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("waves_per_simd", ctypes.c_int), ("grid", ctypes.c_int), ("xcd_order", ctypes.c_int),
+                ("stage_ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("from_cache", ctypes.c_int),
+                ("candidates", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Info(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_long), ("t_s", ctypes.c_double), ("dt_s", ctypes.c_double),
                 ("zone_updates", ctypes.c_double), ("leaves", ctypes.c_int),
@@ -97,7 +106,8 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_eval_window", "ic_sample", "ic_set_sample_point", "ic_timeseries", "ic_timeseries_clear", "ic_get_blocks",
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
-           "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_last_error")
+           "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
+           "ic_last_error")
 
 
 def _load():
@@ -143,6 +153,8 @@ def _load():
     L.ic_mlp_train.argtypes = [fp, u8p, ctypes.c_long, P(MlpHparams), fp, fp, fp, fp]
     L.ic_mlp_grad.argtypes = [fp, u8p, ctypes.c_int, ctypes.c_float, fp, fp, fp]
     L.ic_mlp_infer.argtypes = [fp, ctypes.c_long, fp, fp, fp, fp]
+    L.ic_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int, P(TuneInfo)]
+    L.ic_set_tuning.argtypes = [vp, P(TuneInfo)]
     L.ic_pool_capacity.argtypes = [vp]
     L.ic_pool_capacity.restype = ctypes.c_int
     L.ic_last_error.restype = ctypes.c_char_p
@@ -400,6 +412,17 @@ class Sim:
         n, ms = ctypes.c_long(), ctypes.c_double()
         _check(lib.ic_stage_timing(self.h, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    # --- schedule ------------------------------------------------------------------
+    def autotune(self, cache_path=None, reps=5):
+        """Pick the stage-kernel schedule (cached by device and block shape)."""
+        t = TuneInfo()
+        _check(lib.ic_autotune(self.h, cache_path.encode() if cache_path else None, int(reps), ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, waves_per_simd=2, grid=0, xcd_order=0):
+        t = TuneInfo(waves_per_simd, grid, xcd_order, 0.0, 0.0, 0, 0)
+        _check(lib.ic_set_tuning(self.h, ctypes.byref(t)))
 
     # --- learned flags ------------------------------------------------------------
     def features(self, member=0):

@@ -12,14 +12,18 @@ ARCH = os.environ.get("ICARUS_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from emitting packed fp32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         # fuse a*b+c only within an expression: FMA placement is then fixed by the
+         # source, not by register pressure, so every schedule variant of a kernel
+         # gives the same bits
+         "-ffp-contract=on"]
 
 
-def build(verbose=False, out=None, defines=()):
+def build(verbose=False, out=None, defines=(), extra=()):
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = ["hipcc", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + \
+        cmd = ["hipcc", "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + list(extra) + \
               ["-D" + d for d in defines]
         if verbose:
             print(" ".join(cmd), flush=True)

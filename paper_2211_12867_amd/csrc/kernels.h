@@ -36,6 +36,7 @@ struct KArgs {
     double rho_floor, p_floor;
     int cart;
     int want_rate;
+    int xcd_order;             // stage kernel: XCD-contiguous runs of the work list
 };
 
 template <int BI, int BJ, int BK>
@@ -97,7 +98,7 @@ struct IndicatorParams {
 
 // Launch wrappers per block shape (kernels.hip); the runtime calls these.
 struct Launchers {
-    void (*stage)(dim3, hipStream_t, const KArgs &);
+    void (*stage)(dim3, hipStream_t, const KArgs &, int waves);
     void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *);
     void (*reflux)(dim3, hipStream_t, const KArgs &, const RefluxTask *, const int *, const int *);
     void (*rate)(dim3, hipStream_t, const KArgs &);
@@ -111,7 +112,7 @@ void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, 
 void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm);
 
 // kernel entry points (defined in kernels.hip)
-template <int BI, int BJ, int BK> __global__ void k_stage(KArgs a);
+template <int BI, int BJ, int BK, int W> __global__ void k_stage(KArgs a);
 template <int BI, int BJ, int BK> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
 template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);

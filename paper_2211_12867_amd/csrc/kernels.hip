@@ -84,11 +84,20 @@ DEV void face_states(const double *p, int cs, int vs, const Rec &r1, const Rec &
     }
 }
 
-template <int BI, int BJ, int BK>
-#ifndef IC_STAGE_WAVES
-#define IC_STAGE_WAVES 2
-#endif
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(IC_STAGE_WAVES, IC_STAGE_WAVES)))
+// Work item of linear work index w when a.xcd_order is set: the work-groups
+// of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
+// into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
+// neighbouring blocks -- which read each other's halos -- share an L2.
+__device__ inline int xcd_item(int w, int n)
+{
+    const int q = n >> 3, rem = n & 7;
+    const int x = w & 7, pos = w >> 3;
+    return x * q + (x < rem ? x : rem) + pos;
+}
+
+// W: waves per SIMD the register allocation targets (a tuning choice).
+template <int BI, int BJ, int BK, int W>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W, W)))
 k_stage(KArgs a)
 {
     using S = Shape<BI, BJ, BK>;
@@ -112,7 +121,8 @@ k_stage(KArgs a)
     const Gas gs = a.gas;
     const int nitems = *a.nitems;
 
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (int wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
+        const int it = a.xcd_order ? xcd_item(wi, nitems) : wi;
         const int slot = a.items[it];
         struct { int org[3]; int reflux_mask; } bd;
         const int mem = a.desc[slot].member;
@@ -794,7 +804,8 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
 // instantiations for the supported block shapes
 // ---------------------------------------------------------------------------
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
-    template __global__ void k_stage<BI, BJ, BK>(KArgs);                                           \
+    template __global__ void k_stage<BI, BJ, BK, 1>(KArgs);                                        \
+    template __global__ void k_stage<BI, BJ, BK, 2>(KArgs);                                        \
     template __global__ void k_slabs<BI, BJ, BK>(KArgs, const SlabTask *, const int *);            \
     template __global__ void k_reflux<BI, BJ, BK>(KArgs, const RefluxTask *, const int *, const int *); \
     template __global__ void k_rate<BI, BJ, BK>(KArgs);                                            \
@@ -814,7 +825,11 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
 namespace {
 template <int BI, int BJ, int BK>
 struct L {
-    static void stage(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_stage<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void stage(dim3 g, hipStream_t s, const KArgs &a, int waves)
+    {
+        if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 1>), g, dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2>), g, dim3(NT), 0, s, a);
+    }
     static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r)
     {
         hipLaunchKernelGGL((k_slabs<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, r);

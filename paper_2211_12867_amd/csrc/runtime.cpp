@@ -229,6 +229,10 @@ struct ic_sim {
 
     // timing
     bool timing = false;
+    // stage-kernel schedule (ic_autotune / ic_set_tuning): waves per SIMD of
+    // the register allocation, launch grid (0 = one work-group per work item),
+    // XCD-contiguous work order
+    int tune_waves = 2, tune_grid = 0, tune_xcd = 0;
     std::vector<hipEvent_t> ev;   // pairs
     long timed = 0;
 
@@ -640,10 +644,19 @@ KArgs base_args(ic_sim *s)
     a.rho_floor = s->phys.rho_floor;
     a.p_floor = s->phys.p_floor;
     a.cart = s->cart ? 1 : 0;
+    a.xcd_order = s->tune_xcd;
     return a;
 }
 
 int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
+
+// stage launch: one work-group per work item, or a persistent grid of
+// tune_grid work-groups striding over the work list
+int stage_grid(const ic_sim *s)
+{
+    const int n = std::max(1, s->n_items);
+    return s->tune_grid > 0 ? std::min(n, s->tune_grid) : n;
+}
 
 void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
 {
@@ -664,18 +677,18 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
     a.Uout = Uout;
     a.alpha = alpha;
     a.want_rate = want_rate;
-    const int g = grid_for(s->nm * s->max_blocks, 1 << 17);
+    const int g = stage_grid(s);
     if (s->timing) {
         hipEvent_t e0, e1;
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, s->stream));
-        s->L.stage(dim3(g), s->stream, a);
+        s->L.stage(dim3(g), s->stream, a, s->tune_waves);
         HIPCHECK(hipEventRecord(e1, s->stream));
         s->ev.push_back(e0);
         s->ev.push_back(e1);
     } else {
-        s->L.stage(dim3(g), s->stream, a);
+        s->L.stage(dim3(g), s->stream, a, s->tune_waves);
     }
     if (s->any_reflux) {
         const int gr = grid_for(s->nm * s->max_blocks, 8192);
@@ -1362,6 +1375,58 @@ void set_initial_state(ic_sim *s)
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+std::string tune_key(const ic_sim *s)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        throw Error(IC_E_DEVICE, "hipGetDeviceProperties failed");
+    int bucket = 0;                     // work items, log2 bucket
+    while ((1 << (bucket + 1)) <= std::max(1, s->n_items)) ++bucket;
+    std::string arch = prop.gcnArchName;
+    for (auto &c : arch)
+        if (c == ' ') c = '_';
+    return arch + "/cu" + std::to_string(prop.multiProcessorCount) + "/b" + std::to_string(s->B[0]) + "x" +
+           std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar8/items2^" + std::to_string(bucket);
+}
+
+void apply_tuning(ic_sim *s, int waves, int grid, int xcd)
+{
+    if ((waves != 1 && waves != 2) || grid < 0 || (xcd != 0 && xcd != 1))
+        throw Error(IC_E_INVALID, "tuning: waves_per_simd 1 or 2, grid >= 0, xcd_order 0 or 1");
+    s->tune_waves = waves;
+    s->tune_grid = grid;
+    s->tune_xcd = xcd;
+    s->graph_dirty = true;
+}
+
+// mean stage-1 kernel time [ms] of the current schedule on the current state
+double time_stage(ic_sim *s, int reps)
+{
+    KArgs a = base_args(s);
+    a.U = s->U.p;
+    a.Ubase = s->U.p;
+    a.Uout = s->Us.p;
+    a.alpha = 0.5;
+    a.want_rate = 0;
+    const int g = stage_grid(s);
+    s->L.stage(dim3(g), s->stream, a, s->tune_waves);      // warm-up
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    HIPCHECK(hipEventRecord(e0, s->stream));
+    for (int r = 0; r < reps; ++r) s->L.stage(dim3(g), s->stream, a, s->tune_waves);
+    HIPCHECK(hipEventRecord(e1, s->stream));
+    HIPCHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+}  // namespace
+
 extern "C" {
 
 const char *ic_last_error(void) { return g_err.c_str(); }
@@ -1954,6 +2019,83 @@ ic_status ic_mlp_infer(const float *raw, long n, const float *params, const floa
         } catch (const std::runtime_error &e) {
             throw Error(IC_E_DEVICE, e.what());
         }
+    });
+}
+
+
+ic_status ic_set_tuning(ic_sim *s, const ic_tune_info *t)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (!t) throw Error(IC_E_INVALID, "null tuning");
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        apply_tuning(s, t->waves_per_simd, t->grid, t->xcd_order);
+    });
+}
+
+ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info *out)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (reps < 1) throw Error(IC_E_INVALID, "reps must be >= 1");
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        const std::string key = tune_key(s);
+        ic_tune_info res{};
+        // cache: one line per result, "key waves grid xcd ms default_ms"; the last match wins
+        if (cache_path) {
+            std::FILE *f = std::fopen(cache_path, "r");
+            if (f) {
+                char k[512];
+                int w, g, x;
+                double ms, dms;
+                while (std::fscanf(f, "%511s %d %d %d %lf %lf", k, &w, &g, &x, &ms, &dms) == 6)
+                    if (key == k) {
+                        res.waves_per_simd = w;
+                        res.grid = g;
+                        res.xcd_order = x;
+                        res.stage_ms = ms;
+                        res.default_ms = dms;
+                        res.from_cache = 1;
+                    }
+                std::fclose(f);
+            }
+        }
+        if (!res.from_cache) {
+            // stage 1 reads U, writes the scratch stage state: the sim's state is untouched
+            KArgs a = base_args(s);
+            launch_dt(s->stream, a, s->mbeg.p, s->mend.p, s->nm, s->phys.cfl, 0.0, s->tend.p, s->dt_last.p);
+            fill_ghosts(s, s->U.p, 0.0);
+            const int n = std::max(1, s->n_items);
+            std::vector<int> grids{0};
+            for (int g : {1024, 2048})
+                if (g < n) grids.push_back(g);
+            double best = 1e300;
+            for (int w : {2, 1})
+                for (int g : grids)
+                    for (int x : {0, 1}) {
+                        apply_tuning(s, w, g, x);
+                        const double ms = time_stage(s, reps);
+                        res.candidates++;
+                        if (w == 2 && g == 0 && x == 0) res.default_ms = ms;
+                        if (ms < best) {
+                            best = ms;
+                            res.waves_per_simd = w;
+                            res.grid = g;
+                            res.xcd_order = x;
+                            res.stage_ms = ms;
+                        }
+                    }
+            if (cache_path) {
+                std::FILE *f = std::fopen(cache_path, "a");
+                if (f) {
+                    std::fprintf(f, "%s %d %d %d %.6f %.6f\n", key.c_str(), res.waves_per_simd, res.grid,
+                                 res.xcd_order, res.stage_ms, res.default_ms);
+                    std::fclose(f);
+                }
+            }
+        }
+        apply_tuning(s, res.waves_per_simd, res.grid, res.xcd_order);
+        if (out) *out = res;
     });
 }
 
