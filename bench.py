@@ -11,8 +11,9 @@ Prints one JSON line.  The roofline entry is for the dominant kernel (the
 fused stage kernel): algorithmic bytes per launch (128 B/cell for stage 1:
 read U^n, write U*; 192 B/cell for stage 2: read U*, U^n, write U^{n+1};
 160 B/cell on average) over its mean launch duration from HIP events on the
-library's stream.  cpu_baseline times the oracle on the host on a bounded
-sample of the same workload.
+library's stream, in a pass after the timed region (the timed region replays
+the captured step graph without events).  cpu_baseline times the oracle on
+the host on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -107,13 +108,19 @@ def main():
         sim.step()
     tune = sim.autotune(None, reps=3)
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
-    sim.set_kernel_timing(True)
+    sim.step()                                  # captures the step graph for the tuned schedule
+    # timed region: the captured step graph replayed, no per-launch events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for q in range(args.steps):
         sim.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # kernel time of the dominant kernel: HIP events around every stage launch on
+    # the library's stream, over a separate pass of the same steps
+    sim.set_kernel_timing(True)
+    for q in range(max(2, min(args.steps, 10))):
+        sim.step()
     launches, mean_ms = sim.stage_timing()
     sim.set_kernel_timing(False)
     t_s, dt_s = sim.time()

@@ -138,12 +138,12 @@ k_stage(KArgs a)
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
 
         // --- prologue: column primitives of planes 0 and 1, phi-face -1/2
-        // registers carried along k: Wc = W(k), Wn = W(k+1), wL = face state of
-        // cell k at k+1/2, Fm = flux at k-1/2
-        double Wc[8], Wn[8], wL[8], Fm[8];
+        // registers carried along k: Wn = W(k+1), wL = face state of cell k at
+        // k+1/2, Fm = flux at k-1/2; W(k) of the own column sits in LDS
+        double Wn[8], wL[8], Fm[8];
         int badc = -1;                           // first non-physical input cell of this column
         if (col) {
-            double u[8], w0[8], w1[8], lo[8], hi[8], R0[8];
+            double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
             ghosted8<S>(a, a.U, slot, ci, cj, -2, u); cons_to_prim(u, w0, gs);
             ghosted8<S>(a, a.U, slot, ci, cj, -1, u); cons_to_prim(u, w1, gs);
             ghosted8<S>(a, a.U, slot, ci, cj, 0, u);  cons_to_prim(u, Wc, gs);
@@ -155,15 +155,13 @@ k_stage(KArgs a)
             const int r = a.desc[slot].freg[4];
             if (r >= 0)
                 for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
         }
         double rmax = 0.0;
 
         for (int k = 0; k < BK; ++k) {
-            // (a) plane k into LDS: own column + i/j halos
-            if (col) {
-#pragma unroll
-                for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
-            }
+            // (a) i/j halos of plane k into LDS (the own column's W(k) is there)
             for (int t = tid; t < NHALO; t += NT) {
                 int i, j;
                 if (t < 4 * BJ) {                 // r-direction halo
@@ -215,7 +213,7 @@ k_stage(KArgs a)
                 }
             }
             // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
-            double Fp[8];
+            double Fp[8], Wnext[8];
             if (col) {
                 double u[8], W2[8], lo1[8], w0[8];
                 ghosted8<S>(a, a.U, slot, ci, cj, k + 2, u);
@@ -234,7 +232,7 @@ k_stage(KArgs a)
 #pragma unroll
                 for (int v = 0; v < 8; ++v) {
                     wL[v] = hi1[v];
-                    Wc[v] = Wn[v];
+                    Wnext[v] = Wn[v];
                     Wn[v] = W2[v];
                 }
             }
@@ -278,7 +276,10 @@ k_stage(KArgs a)
                     rmax = rate > rmax ? rate : rmax;
                 }
 #pragma unroll
-                for (int v = 0; v < 8; ++v) Fm[v] = Fp[v];
+                for (int v = 0; v < 8; ++v) {
+                    Fm[v] = Fp[v];
+                    sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
+                }
             }
         }
         if (col && badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
@@ -656,7 +657,7 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
             }
             double u[8], w0[8];
             ghosted8<S>(a, a.U, slot, ijk[0], ijk[1], ijk[2], u);
-            cons_to_prim(u, w0, a.gas);
+            cons_to_prim<true>(u, w0, a.gas);
             const double r0 = w0[0];
             const double s0 = sqrt(w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]);
             double num_r = 0, den_r = 0, num_v = 0, den_v = 0, dv = 0;
@@ -666,9 +667,9 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
                 hi[d] += 1;
                 double wl[8], wh[8];
                 ghosted8<S>(a, a.U, slot, lo[0], lo[1], lo[2], u);
-                cons_to_prim(u, wl, a.gas);
+                cons_to_prim<true>(u, wl, a.gas);
                 ghosted8<S>(a, a.U, slot, hi[0], hi[1], hi[2], u);
-                cons_to_prim(u, wh, a.gas);
+                cons_to_prim<true>(u, wh, a.gas);
                 const double rl = wl[0], rh = wh[0];
                 const double sl = sqrt(wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
                 const double sh = sqrt(wh[1] * wh[1] + wh[2] * wh[2] + wh[3] * wh[3]);

@@ -8,15 +8,54 @@
 
 #define DEV __device__ __forceinline__
 
+// Reciprocal of a > 0 (normal): the hardware estimate refined by two
+// Newton-Raphson steps x <- x + x (1 - a x); at most one ulp from 1/a.
+DEV double rcp_pos(double a)
+{
+    double x = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-a, x, 1.0);
+    return fma(x, e, x);
+}
+
+// Square root of x >= 0 (normal or zero): the hardware reciprocal-square-root
+// estimate y, then one coupled Goldschmidt iteration on g = x y, h = y / 2 and
+// a final Newton correction of g; at most one ulp from sqrt(x).
+DEV double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
+// Reciprocals and square roots of the finite-volume update use rcp_pos /
+// sqrt_pos (<= 1 ulp); IC_EXACT_MATH selects the IEEE-rounded operations.
+#ifdef IC_EXACT_MATH
+#define IC_RCP(x) (1.0 / (x))
+#define IC_SQRT(x) sqrt(x)
+#else
+#define IC_RCP(x) rcp_pos(x)
+#define IC_SQRT(x) sqrt_pos(x)
+#endif
+
 struct Gas {
     double g;       // adiabatic index
     double gm1;     // g - 1
     double igm1;    // 1 / (g - 1)
 };
 
+// EXACT: IEEE division (the refinement indicator and the network features,
+// whose decisions match the oracle's bit for bit)
+template <bool EXACT = false>
 DEV void cons_to_prim(const double u[8], double w[8], const Gas &gs)
 {
-    const double ir = 1.0 / u[0];
+    const double ir = EXACT ? 1.0 / u[0] : IC_RCP(u[0]);
     w[0] = u[0];
     w[1] = u[1] * ir;
     w[2] = u[2] * ir;
@@ -47,14 +86,14 @@ DEV void prim_to_cons(const double w[8], double u[8], const Gas &gs)
 template <int D>
 DEV double fast_speed(const double w[8], const Gas &gs)
 {
-    const double ir = 1.0 / w[0];
+    const double ir = IC_RCP(w[0]);
     const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
     const double gp = gs.g * w[4];
     const double a = (gp + b2) * ir;
     const double bn = w[5 + D];
     double disc = a * a - 4.0 * gp * bn * bn * ir * ir;
     disc = disc > 0.0 ? disc : 0.0;
-    return sqrt(0.5 * (a + sqrt(disc)));
+    return IC_SQRT(0.5 * (a + IC_SQRT(disc)));
 }
 
 DEV bool unphysical(const double w[8])
@@ -83,15 +122,15 @@ DEV void rusanov(const double wl[8], const double wr[8], double f[8], const Gas 
     const double vbl = wl[1] * wl[5] + wl[2] * wl[6] + wl[3] * wl[7];
     const double vbr = wr[1] * wr[5] + wr[2] * wr[6] + wr[3] * wr[7];
     // fast speeds
-    const double irl = 1.0 / wl[0], irr = 1.0 / wr[0];
+    const double irl = IC_RCP(wl[0]), irr = IC_RCP(wr[0]);
     const double gpl = gs.g * wl[4], gpr = gs.g * wr[4];
     const double al = (gpl + bl2) * irl, ar = (gpr + br2) * irr;
     double dl = al * al - 4.0 * gpl * bnl * bnl * irl * irl;
     double dr = ar * ar - 4.0 * gpr * bnr * bnr * irr * irr;
     dl = dl > 0.0 ? dl : 0.0;
     dr = dr > 0.0 ? dr : 0.0;
-    const double cfl = sqrt(0.5 * (al + sqrt(dl)));
-    const double cfr = sqrt(0.5 * (ar + sqrt(dr)));
+    const double cfl = IC_SQRT(0.5 * (al + IC_SQRT(dl)));
+    const double cfr = IC_SQRT(0.5 * (ar + IC_SQRT(dr)));
     const double sl = fabs(vnl) + cfl, sr = fabs(vnr) + cfr;
     const double c = sl > sr ? sl : sr;
     const double hc = 0.5 * c;
@@ -159,7 +198,7 @@ DEV void add_sources(const double w[8], double rt, double ctil, double rc, doubl
     const double rho = w[0], vr = w[1], vt = w[2], vp = w[3];
     const double br = w[5], bt = w[6], bp = w[7];
     const double ptot = w[4] + 0.5 * (br * br + bt * bt + bp * bp);
-    const double g = -gm / (rc * rc);
+    const double g = -gm * IC_RCP(rc * rc);
     acc[1] += rt * (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp) + 2.0 * ptot)
               + rho * (2.0 * om * sc * vp + om * om * rc * sc * sc) + rho * g;
     acc[2] += rt * (-(rho * vr * vt - br * bt) + ctil * (rho * vp * vp - bp * bp + ptot))
@@ -181,7 +220,7 @@ DEV void apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
         u[2] = 0.0;
         u[3] = 0.0;
     }
-    const double kin = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    const double kin = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * IC_RCP(u[0]);
     const double mag = 0.5 * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);
     const double p = gs.gm1 * (u[4] - kin - mag);
     if (p < p_min) u[4] = p_min * gs.igm1 + kin + mag;
