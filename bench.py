@@ -32,23 +32,44 @@ BYTES_PER_CELL_LAUNCH = 160.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "physics.h", "kernels.h", "device.h"):
-        with open(os.path.join(ROOT, "paper_2211_12867_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/kernels.hip", "csrc/physics.h", "csrc/kernels.h", "csrc/device.h", "build.py"):
+        with open(os.path.join(ROOT, "paper_2211_12867_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(cells):
-    """HBM bytes per stage launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "stage_traffic_equidistant_full.json")
+def measured_traffic():
+    """HBM bytes per stage launch (FETCH_SIZE + WRITE_SIZE, each scaled by a
+    plain 1 GiB copy) from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source and build flags; else None."""
+    path = os.path.join(ROOT, "profiles", "stage_traffic_equidistant_full.md")
     if not os.path.exists(path):
         return None
+    vals = {}
     with open(path) as fh:
-        d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash():
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("kernel_source_hash", "bytes_per_launch_hbm"):
+                k, v = line.split(":", 1)
+                vals[k] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash() or "bytes_per_launch_hbm" not in vals:
         return None
-    return d.get("bytes_per_launch")
+    return float(vals["bytes_per_launch_hbm"])
+
+
+def measured_valu():
+    """VALU issue fraction and executed fp64 rate of the stage kernel from the
+    committed rocprofv3 counter summary (same kernel source only); else None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "stage_valu_equidistant_full.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_hash: (\w+)", text)
+    q = re.search(r": ([0-9.]+)% of one wave64 VALU instruction.*executed fp64 rate ([0-9.]+) TFLOP/s", text)
+    if not m or m.group(1) != kernel_source_hash() or not q:
+        return None
+    return {"issue_frac": float(q.group(1)) / 100.0, "fp64_tflops_executed": float(q.group(2)), "fp64_peak": 78.6,
+            "source": "profiles/stage_valu_equidistant_full.md"}
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -85,6 +106,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default stage schedule (profiling runs: no tuning launches in the trace)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -106,7 +129,10 @@ def main():
     cells = g["n"][0] * g["n"][1] * g["n"][2]
     for _ in range(args.warmup):
         sim.step()
-    tune = sim.autotune(None, reps=3)
+    if args.no_autotune:
+        tune = dict(waves_per_simd=2, grid=0, xcd_order=0)
+    else:
+        tune = sim.autotune(None, reps=3)
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
     sim.step()                                  # captures the step graph for the tuned schedule
     # timed region: the captured step graph replayed, no per-launch events
@@ -140,7 +166,7 @@ def main():
 
     bytes_launch = BYTES_PER_CELL_LAUNCH * cells
     achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
-    traffic = measured_traffic(cells)
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": cells * args.steps / el,
@@ -161,7 +187,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "kernel": "k_stage<16,12,12>", "mean_launch_ms": mean_ms,
-                     "bytes_per_launch": bytes_launch},
+                     "bytes_per_launch": bytes_launch, "valu": measured_valu()},
     }
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
