@@ -86,7 +86,7 @@ class MlpHparams(ctypes.Structure):
 class TuneInfo(ctypes.Structure):
     _fields_ = [("waves_per_simd", ctypes.c_int), ("grid", ctypes.c_int), ("xcd_order", ctypes.c_int),
                 ("stage_ms", ctypes.c_double), ("default_ms", ctypes.c_double), ("from_cache", ctypes.c_int),
-                ("candidates", ctypes.c_int)]
+                ("candidates", ctypes.c_int), ("ksplit", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -420,8 +420,8 @@ class Sim:
         _check(lib.ic_autotune(self.h, cache_path.encode() if cache_path else None, int(reps), ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, waves_per_simd=2, grid=0, xcd_order=0):
-        t = TuneInfo(waves_per_simd, grid, xcd_order, 0.0, 0.0, 0, 0)
+    def set_tuning(self, waves_per_simd=2, grid=0, xcd_order=0, ksplit=1):
+        t = TuneInfo(waves_per_simd, grid, xcd_order, 0.0, 0.0, 0, 0, ksplit)
         _check(lib.ic_set_tuning(self.h, ctypes.byref(t)))
 
     # --- learned flags ------------------------------------------------------------

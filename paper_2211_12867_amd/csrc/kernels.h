@@ -37,7 +37,11 @@ struct KArgs {
     int cart;
     int want_rate;
     int xcd_order;             // stage kernel: XCD-contiguous runs of the work list
+    int ksplit;                // stage kernel: work-groups per block, each marching over BK / ksplit planes
 };
+
+// CFL maxima are kept per block and k-part: rate[slot * KSPLIT_MAX + part]
+#define KSPLIT_MAX 4
 
 template <int BI, int BJ, int BK>
 struct Shape {

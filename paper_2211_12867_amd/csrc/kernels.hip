@@ -84,6 +84,25 @@ DEV void face_states(const double *p, int cs, int vs, const Rec &r1, const Rec &
     }
 }
 
+// Cell t of the 4 (BI + BJ) r/theta halo cells of plane k (two layers on each
+// side, r-halo first): its (i, j).
+template <int BI, int BJ>
+DEV void halo_cell(int t, int &i, int &j)
+{
+    if (t < 4 * BJ) {                 // r-direction halo
+        const int side = t / (2 * BJ), rem = t % (2 * BJ);
+        const int l = rem / BJ;
+        j = rem % BJ;
+        i = side ? BI + l : l - 2;
+    } else {                          // theta-direction halo
+        const int q = t - 4 * BJ;
+        const int side = q / (2 * BI), rem = q % (2 * BI);
+        const int l = rem / BI;
+        i = rem % BI;
+        j = side ? BJ + l : l - 2;
+    }
+}
+
 // Work item of linear work index w when a.xcd_order is set: the work-groups
 // of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
 // into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
@@ -106,7 +125,8 @@ k_stage(KArgs a)
     constexpr int NFJ = BI * (BJ + 1);
     constexpr int NCOL = BI * BJ;
     constexpr int NHALO = 4 * (BI + BJ);
-    static_assert(NCOL <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
+    static_assert(NCOL + 32 <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
+    constexpr int NIDLE = NT - NCOL;             // threads without a column: they prefetch
 
     __shared__ double sW[8][PJ][PI];
     __shared__ double sFi[8][BJ][BI + 1];
@@ -121,8 +141,12 @@ k_stage(KArgs a)
     const Gas gs = a.gas;
     const int nitems = *a.nitems;
 
-    for (int wi = blockIdx.x; wi < nitems; wi += gridDim.x) {
-        const int it = a.xcd_order ? xcd_item(wi, nitems) : wi;
+    const int ks = a.ksplit;                     // parts of the march along k per block
+    const int nwork = nitems * ks;
+    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        const int ww = a.xcd_order ? xcd_item(wi, nwork) : wi;
+        const int it = ww / ks, part = ww % ks;
+        const int k0 = part * BK / ks, k1 = (part + 1) * BK / ks;
         const int slot = a.items[it];
         struct { int org[3]; int reflux_mask; } bd;
         const int mem = a.desc[slot].member;
@@ -137,52 +161,42 @@ k_stage(KArgs a)
         for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
 
-        // --- prologue: column primitives of planes 0 and 1, phi-face -1/2
+        // --- prologue: column primitives of planes k0 and k0+1, phi-face k0-1/2
         // registers carried along k: Wn = W(k+1), wL = face state of cell k at
         // k+1/2, Fm = flux at k-1/2; W(k) of the own column sits in LDS
         double Wn[8], wL[8], Fm[8];
         int badc = -1;                           // first non-physical input cell of this column
         if (col) {
             double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
-            ghosted8<S>(a, a.U, slot, ci, cj, -2, u); cons_to_prim(u, w0, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, -1, u); cons_to_prim(u, w1, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, 0, u);  cons_to_prim(u, Wc, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, 1, u);  cons_to_prim(u, Wn, gs);
-            const RecP pm1 = lg.p[bd.org[2] - 1 + 2], p0 = lg.p[bd.org[2] + 2];
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
+            const RecP pm1 = lg.p[bd.org[2] + k0 - 1 + 2], p0 = lg.p[bd.org[2] + k0 + 2];
             reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
             reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
             rusanov<2>(hi, R0, Fm, gs);
-            const int r = a.desc[slot].freg[4];
+            const int r = k0 == 0 ? a.desc[slot].freg[4] : -1;
             if (r >= 0)
                 for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
 #pragma unroll
             for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
         }
-        double rmax = 0.0;
-
-        for (int k = 0; k < BK; ++k) {
-            // (a) i/j halos of plane k into LDS (the own column's W(k) is there)
-            for (int t = tid; t < NHALO; t += NT) {
-                int i, j;
-                if (t < 4 * BJ) {                 // r-direction halo
-                    const int side = t / (2 * BJ), rem = t % (2 * BJ);
-                    const int l = rem / BJ;
-                    j = rem % BJ;
-                    i = side ? BI + l : l - 2;
-                } else {                          // theta-direction halo
-                    const int q = t - 4 * BJ;
-                    const int side = q / (2 * BI), rem = q % (2 * BI);
-                    const int l = rem / BI;
-                    i = rem % BI;
-                    j = side ? BJ + l : l - 2;
-                }
-                double u[8], w[8];
-                ghosted8<S>(a, a.U, slot, i, j, k, u);
-                cons_to_prim(u, w, gs);
+        // halos of plane k0, by all threads
+        for (int t = tid; t < NHALO; t += NT) {
+            int i, j;
+            halo_cell<BI, BJ>(t, i, j);
+            double u[8], w[8];
+            ghosted8<S>(a, a.U, slot, i, j, k0, u);
+            cons_to_prim(u, w, gs);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
-            }
-            __syncthreads();
+            for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+        }
+        double rmax = 0.0;
+        __syncthreads();
+
+        for (int k = k0; k < k1; ++k) {
+            // plane k with its i/j halos is in LDS
 
             // (c) r-faces of the plane: face f lies between cells f-1 and f
             for (int t = tid; t < NFI; t += NT) {
@@ -280,12 +294,27 @@ k_stage(KArgs a)
                     Fm[v] = Fp[v];
                     sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
                 }
+            } else if (k + 1 < k1) {
+                // (p) meanwhile the threads without a column load the halos of
+                // plane k+1 (the update reads no halo cell)
+                for (int t = tid - NCOL; t < NHALO; t += NIDLE) {
+                    int i, j;
+                    halo_cell<BI, BJ>(t, i, j);
+                    double u[8], w[8];
+                    ghosted8<S>(a, a.U, slot, i, j, k + 1, u);
+                    cons_to_prim(u, w, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+                }
             }
+            __syncthreads();
         }
         if (col && badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
         if (a.want_rate) {
+            // this part's CFL maximum; the last part clears the unused entries
             const double m = block_max(col ? rmax : 0.0, sred);
-            if (tid == 0) a.rate[slot] = m;
+            if (tid == 0) a.rate[(size_t)slot * KSPLIT_MAX + part] = m;
+            if (part == ks - 1 && tid > part && tid < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + tid] = 0.0;
         }
     }
 }
@@ -555,7 +584,7 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
                 rmax = r > rmax ? r : rmax;
             }
             const double m = block_max(rmax, sred);
-            if (threadIdx.x == 0) a.rate[slot] = m;
+            if (threadIdx.x < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + threadIdx.x] = threadIdx.x == 0 ? m : 0.0;
         }
     }
 }
@@ -585,7 +614,7 @@ __global__ void __launch_bounds__(NT) k_rate(KArgs a)
         }
         if (bad >= 0 && atomicCAS(&a.bad[2 * bd.member], 0, slot + 1) == 0) a.bad[2 * bd.member + 1] = bad;
         const double m = block_max(rmax, sred);
-        if (threadIdx.x == 0) a.rate[slot] = m;
+        if (threadIdx.x < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + threadIdx.x] = threadIdx.x == 0 ? m : 0.0;
     }
 }
 
@@ -597,8 +626,11 @@ __global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, do
     for (int m = blockIdx.x; m < nmembers; m += gridDim.x) {
         double r = 0.0;
         for (int q = mbeg[m] + threadIdx.x; q < mend[m]; q += blockDim.x) {
-            const double x = a.rate[a.items[q]];
-            r = x > r ? x : r;
+#pragma unroll
+            for (int p = 0; p < KSPLIT_MAX; ++p) {
+                const double x = a.rate[(size_t)a.items[q] * KSPLIT_MAX + p];
+                r = x > r ? x : r;
+            }
         }
         const double mx = block_max(r, sred);
         if (threadIdx.x == 0) {

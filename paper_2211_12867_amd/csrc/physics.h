@@ -51,7 +51,7 @@ struct Gas {
 };
 
 // EXACT: IEEE division (the refinement indicator and the network features,
-// whose decisions match the oracle's bit for bit)
+// whose threshold decisions are kept on the correctly rounded quotient)
 template <bool EXACT = false>
 DEV void cons_to_prim(const double u[8], double w[8], const Gas &gs)
 {

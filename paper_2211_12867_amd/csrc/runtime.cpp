@@ -232,7 +232,7 @@ struct ic_sim {
     // stage-kernel schedule (ic_autotune / ic_set_tuning): waves per SIMD of
     // the register allocation, launch grid (0 = one work-group per work item),
     // XCD-contiguous work order
-    int tune_waves = 2, tune_grid = 0, tune_xcd = 0;
+    int tune_waves = 2, tune_grid = 0, tune_xcd = 0, tune_ksplit = 1;
     std::vector<hipEvent_t> ev;   // pairs
     long timed = 0;
 
@@ -645,6 +645,7 @@ KArgs base_args(ic_sim *s)
     a.p_floor = s->phys.p_floor;
     a.cart = s->cart ? 1 : 0;
     a.xcd_order = s->tune_xcd;
+    a.ksplit = s->tune_ksplit;
     return a;
 }
 
@@ -654,7 +655,7 @@ int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
 // tune_grid work-groups striding over the work list
 int stage_grid(const ic_sim *s)
 {
-    const int n = std::max(1, s->n_items);
+    const int n = std::max(1, s->n_items * s->tune_ksplit);
     return s->tune_grid > 0 ? std::min(n, s->tune_grid) : n;
 }
 
@@ -1391,13 +1392,16 @@ std::string tune_key(const ic_sim *s)
            std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar8/items2^" + std::to_string(bucket);
 }
 
-void apply_tuning(ic_sim *s, int waves, int grid, int xcd)
+void apply_tuning(ic_sim *s, int waves, int grid, int xcd, int ksplit)
 {
-    if ((waves != 1 && waves != 2) || grid < 0 || (xcd != 0 && xcd != 1))
-        throw Error(IC_E_INVALID, "tuning: waves_per_simd 1 or 2, grid >= 0, xcd_order 0 or 1");
+    if ((waves != 1 && waves != 2) || grid < 0 || (xcd != 0 && xcd != 1) ||
+        (ksplit != 1 && ksplit != 2 && ksplit != 4) || ksplit > s->B[2])
+        throw Error(IC_E_INVALID, "tuning: waves_per_simd 1 or 2, grid >= 0, xcd_order 0 or 1, "
+                                  "ksplit 1, 2 or 4 (at most the block's phi size)");
     s->tune_waves = waves;
     s->tune_grid = grid;
     s->tune_xcd = xcd;
+    s->tune_ksplit = ksplit;
     s->graph_dirty = true;
 }
 
@@ -1559,7 +1563,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         s->t.alloc(s->nm);
         s->tend.alloc(s->nm);
         s->dt_last.alloc(s->nm);
-        s->rate.alloc(NS);
+        s->rate.alloc(NS * KSPLIT_MAX);
         s->bad.alloc(2 * s->nm);
         s->nsteps.alloc(s->nm);
         s->slab_ranges.alloc(2 * (IC_MAX_LEVEL + 2));
@@ -1580,7 +1584,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         HIPCHECK(hipMemset(s->bad.p, 0, 2 * s->nm * sizeof(int)));
         HIPCHECK(hipMemset(s->nsteps.p, 0, s->nm * sizeof(long)));
         HIPCHECK(hipMemset(s->ring_count.p, 0, s->nm * sizeof(int)));
-        HIPCHECK(hipMemset(s->rate.p, 0, NS * sizeof(double)));
+        HIPCHECK(hipMemset(s->rate.p, 0, NS * KSPLIT_MAX * sizeof(double)));
         // base forest
         for (int m = 0; m < s->nm; ++m) {
             Member &M = s->mem[m];
@@ -2029,7 +2033,7 @@ ic_status ic_set_tuning(ic_sim *s, const ic_tune_info *t)
         check_sim(s);
         if (!t) throw Error(IC_E_INVALID, "null tuning");
         HIPCHECK(hipStreamSynchronize(s->stream));
-        apply_tuning(s, t->waves_per_simd, t->grid, t->xcd_order);
+        apply_tuning(s, t->waves_per_simd, t->grid, t->xcd_order, t->ksplit);
     });
 }
 
@@ -2041,18 +2045,19 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
         HIPCHECK(hipStreamSynchronize(s->stream));
         const std::string key = tune_key(s);
         ic_tune_info res{};
-        // cache: one line per result, "key waves grid xcd ms default_ms"; the last match wins
+        // cache: one line per result, "key waves grid xcd ksplit ms default_ms"; the last match wins
         if (cache_path) {
             std::FILE *f = std::fopen(cache_path, "r");
             if (f) {
                 char k[512];
-                int w, g, x;
+                int w, g, x, ks;
                 double ms, dms;
-                while (std::fscanf(f, "%511s %d %d %d %lf %lf", k, &w, &g, &x, &ms, &dms) == 6)
+                while (std::fscanf(f, "%511s %d %d %d %d %lf %lf", k, &w, &g, &x, &ks, &ms, &dms) == 7)
                     if (key == k) {
                         res.waves_per_simd = w;
                         res.grid = g;
                         res.xcd_order = x;
+                        res.ksplit = ks;
                         res.stage_ms = ms;
                         res.default_ms = dms;
                         res.from_cache = 1;
@@ -2065,36 +2070,40 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
             KArgs a = base_args(s);
             launch_dt(s->stream, a, s->mbeg.p, s->mend.p, s->nm, s->phys.cfl, 0.0, s->tend.p, s->dt_last.p);
             fill_ghosts(s, s->U.p, 0.0);
-            const int n = std::max(1, s->n_items);
-            std::vector<int> grids{0};
-            for (int g : {1024, 2048})
-                if (g < n) grids.push_back(g);
             double best = 1e300;
-            for (int w : {2, 1})
-                for (int g : grids)
-                    for (int x : {0, 1}) {
-                        apply_tuning(s, w, g, x);
-                        const double ms = time_stage(s, reps);
-                        res.candidates++;
-                        if (w == 2 && g == 0 && x == 0) res.default_ms = ms;
-                        if (ms < best) {
-                            best = ms;
-                            res.waves_per_simd = w;
-                            res.grid = g;
-                            res.xcd_order = x;
-                            res.stage_ms = ms;
+            for (int ks : {1, 2, 4}) {
+                if (ks > s->B[2]) continue;
+                const int n = std::max(1, s->n_items * ks);
+                std::vector<int> grids{0};
+                for (int g : {1024, 2048})
+                    if (g < n) grids.push_back(g);
+                for (int w : {2, 1})
+                    for (int g : grids)
+                        for (int x : {0, 1}) {
+                            apply_tuning(s, w, g, x, ks);
+                            const double ms = time_stage(s, reps);
+                            res.candidates++;
+                            if (w == 2 && g == 0 && x == 0 && ks == 1) res.default_ms = ms;
+                            if (ms < best) {
+                                best = ms;
+                                res.waves_per_simd = w;
+                                res.grid = g;
+                                res.xcd_order = x;
+                                res.ksplit = ks;
+                                res.stage_ms = ms;
+                            }
                         }
-                    }
+            }
             if (cache_path) {
                 std::FILE *f = std::fopen(cache_path, "a");
                 if (f) {
-                    std::fprintf(f, "%s %d %d %d %.6f %.6f\n", key.c_str(), res.waves_per_simd, res.grid,
-                                 res.xcd_order, res.stage_ms, res.default_ms);
+                    std::fprintf(f, "%s %d %d %d %d %.6f %.6f\n", key.c_str(), res.waves_per_simd, res.grid,
+                                 res.xcd_order, res.ksplit, res.stage_ms, res.default_ms);
                     std::fclose(f);
                 }
             }
         }
-        apply_tuning(s, res.waves_per_simd, res.grid, res.xcd_order);
+        apply_tuning(s, res.waves_per_simd, res.grid, res.xcd_order, res.ksplit);
         if (out) *out = res;
     });
 }

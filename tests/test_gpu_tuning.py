@@ -1,8 +1,12 @@
 """The stage-kernel schedule and its autotuner, through the C ABI.
 
 - every schedule (waves per SIMD 1 or 2, one work-group per leaf or a
-  persistent grid, plain or XCD-contiguous work order) gives the same state
-  bit for bit on the equidistant 512 x 60 x 180 domain (2,400 blocks);
+  persistent grid, plain or XCD-contiguous work order, 1, 2 or 4 work-groups
+  per block along phi) gives the same state bit for bit on the equidistant
+  512 x 60 x 180 domain (2,400 blocks);
+- with 4 work-groups per block, a refined wedge with regrids (reflux and flux
+  registers at coarse-fine faces, split boundaries inside blocks) matches
+  the oracle;
 - ic_autotune leaves the state and time untouched, picks a schedule no
   slower than the default on its own measurement, and returns the same
   choice from its cache on the second call;
@@ -26,24 +30,26 @@ def _sim(ic):
     return ic.Sim(as_dict(w.grid), as_dict(w.wind), [as_dict(w.cmes[0])])
 
 
+SCHEDULES = [(2, 0, 0, 1), (1, 0, 0, 1), (2, 1024, 0, 1), (2, 0, 1, 1), (1, 1024, 1, 1), (2, 0, 0, 2),
+             (2, 0, 1, 4), (2, 1024, 1, 2)]
+
+
 def test_schedules_are_bit_identical():
     ic = _ic()
     ref = None
-    for waves in (2, 1):
-        for grid in (0, 1024):
-            for xcd in (0, 1):
-                sim = _sim(ic)
-                sim.set_tuning(waves, grid, xcd)
-                for _ in range(2):
-                    sim.step()
-                U = sim.state()[1]
-                t = sim.time()
-                sim.close()
-                if ref is None:
-                    ref = (U, t)
-                else:
-                    assert t == ref[1], (waves, grid, xcd)
-                    assert np.array_equal(U, ref[0]), (waves, grid, xcd)
+    for waves, grid, xcd, ks in SCHEDULES:
+        sim = _sim(ic)
+        sim.set_tuning(waves, grid, xcd, ks)
+        for _ in range(2):
+            sim.step()
+        U = sim.state()[1]
+        t = sim.time()
+        sim.close()
+        if ref is None:
+            ref = (U, t)
+        else:
+            assert t == ref[1], (waves, grid, xcd, ks)
+            assert np.array_equal(U, ref[0]), (waves, grid, xcd, ks)
 
 
 def test_autotune_keeps_state_and_caches(tmp_path):
@@ -66,7 +72,32 @@ def test_autotune_keeps_state_and_caches(tmp_path):
 def test_invalid_schedule_rejected():
     ic = _ic()
     sim = _sim(ic)
-    with pytest.raises(ic.ICError) as e:
-        sim.set_tuning(3, 0, 0)
-    assert e.value.status == ic.IC_E_INVALID
+    for bad in ((3, 0, 0, 1), (2, 0, 0, 3), (2, -1, 0, 1)):
+        with pytest.raises(ic.ICError) as e:
+            sim.set_tuning(*bad)
+        assert e.value.status == ic.IC_E_INVALID
     sim.close()
+
+
+def test_ksplit_amr_wedge_matches_oracle():
+    ic = _ic()
+    from gpu_helpers import rel_err
+    from oracle import solver, units
+    from test_gpu_parity import _amr_wedge
+    grid, wind, cme, amr = _amr_wedge()
+    ora = solver.Solver(grid, wind, cme, amr)
+    gpu = ic.Sim(grid, wind, [cme], amr)
+    gpu.set_state(*ora.state(), 0.0)
+    gpu.set_tuning(2, 0, 1, 4)
+    for cycle in range(3):
+        for _ in range(5):
+            ora.step()
+            gpu.step()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-10, (cycle, e)
+        gpu.set_state(*ora.state(), ora.t * units.T0)
+        ora.regrid()
+        gpu.regrid()
+        assert gpu.blocks() == ora.blocks()
+    assert max(b[0] for b in ora.blocks()) >= 2
+    gpu.close()
