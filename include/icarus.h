@@ -135,6 +135,7 @@ typedef struct {
     int source;             /* IC_SOURCE_*: where ic_regrid(sim, NULL, ...) takes its flags from */
     int judge_every;        /* learned + judge: evaluate the plain criterion every judge_every-th regrid */
     double judge_recall;    /* fall back to the plain flags for 10 regrids below this REFINE recall */
+    double learned_threshold; /* learned REFINE where the network's p >= this (<= 0: 1/2) */
 } ic_amr_cfg;
 
 enum { IC_SOURCE_PLAIN = 0, IC_SOURCE_LEARNED = 1, IC_SOURCE_LEARNED_JUDGED = 2 };
@@ -261,7 +262,8 @@ ic_status ic_features(ic_sim *sim, int member, float *raw, int n);
 /* Install a trained network (params fp32, per-input mean and std). */
 ic_status ic_mlp_set(ic_sim *sim, const float *params, const float *mean, const float *std);
 
-/* Network probability and flag per leaf: IC_FLAG_REFINE if p >= 1/2 and the
+/* Network probability and flag per leaf: IC_FLAG_REFINE if p >= the threshold
+ * (ic_amr_cfg.learned_threshold, default 1/2) and the
  * leaf touches the refinement windows (ic_eval_window), else IC_FLAG_COARSEN. */
 ic_status ic_eval_learned(ic_sim *sim, int member, float *prob, int8_t *flags, int n);
 

@@ -74,7 +74,8 @@ class AmrCfg(ctypes.Structure):
                 ("dlon_earth_deg", ctypes.c_double), ("dclt_earth_deg", ctypes.c_double),
                 ("dlon_cme_deg", ctypes.c_double), ("use_windows", ctypes.c_int),
                 ("regrid_every", ctypes.c_int), ("buffer_blocks", ctypes.c_int), ("source", ctypes.c_int),
-                ("judge_every", ctypes.c_int), ("judge_recall", ctypes.c_double)]
+                ("judge_every", ctypes.c_int), ("judge_recall", ctypes.c_double),
+                ("learned_threshold", ctypes.c_double)]
 
 
 class MlpHparams(ctypes.Structure):
@@ -245,7 +246,7 @@ def amr_cfg(amr):
     defaults = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
                     lon_earth_deg=0.0, clt_earth_deg=90.0, dlon_earth_deg=30.0, dclt_earth_deg=10.0,
                     dlon_cme_deg=90.0, use_windows=True, regrid_every=10, buffer_blocks=1, source=0,
-                    judge_every=10, judge_recall=0.9)
+                    judge_every=10, judge_recall=0.9, learned_threshold=0.5)
     for key, dv in defaults.items():
         v = _get(amr, key, dv)
         setattr(a, key, int(v) if isinstance(dv, (bool, int)) and not isinstance(dv, float) else float(v))

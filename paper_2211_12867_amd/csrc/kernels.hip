@@ -320,24 +320,38 @@ k_stage(KArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Limited linear prolongation of the fine cell with (unwrapped) global index g
-// on level geometry lg from its coarse parent: local index cl in the ghosted
-// source block src, wrapped global index cw on level geometry cg.  Slopes are
-// minmod of the one-sided coordinate differences, applied about the volume
-// centroid of the two children along each direction.  A coarse cell whose
-// linear values would give any of its 8 children rho <= 0 or p <= 0 hands its
-// own value to all of them (conservative either way).
+// Limited linear prolongation from one coarse cell to its 8 children: local
+// index cl in the ghosted source block src, wrapped global index cw on level
+// geometry cg; the children sit on level geometry lg from the (even,
+// unwrapped) global fine index g0 on.  Slopes are minmod of the one-sided
+// coordinate differences, applied about the volume centroid of the two
+// children along each direction.  A coarse cell whose linear values would
+// give any child rho <= 0 or p <= 0 hands its own value to all of them
+// (conservative either way).  value(o, v): child o = ox + 2 oy + 4 oz.
+struct Prolong {
+    double uc[8], sl[3][8], off[3][2];
+    bool ok;
+    DEV double linear(int o, int v) const
+    {
+        double x = uc[v];
+        x += sl[0][v] * off[0][o & 1];
+        x += sl[1][v] * off[1][(o >> 1) & 1];
+        x += sl[2][v] * off[2][(o >> 2) & 1];
+        return x;
+    }
+    DEV double value(int o, int v) const { return ok ? linear(o, v) : uc[v]; }
+};
+
 template <int BI, int BJ, int BK>
-__device__ inline void prolong_cell(const KArgs &a, int src, const int cl[3], const int cw[3], const LevelGeo &cg,
-                                    const LevelGeo &lg, const int g[3], double u[8])
+DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3], const LevelGeo &cg,
+                       const LevelGeo &lg, const int g0[3], Prolong &P)
 {
     using S = Shape<BI, BJ, BK>;
     const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
     const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
-    double uc[8], sl[3][8];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-        uc[v] = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, cl[0], cl[1], cl[2]);
+        P.uc[v] = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, cl[0], cl[1], cl[2]);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
@@ -345,44 +359,26 @@ __device__ inline void prolong_cell(const KArgs &a, int src, const int cl[3], co
             lp[e] += 1;
             const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, lm[0], lm[1], lm[2]);
             const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, lp[0], lp[1], lp[2]);
-            const double sa = (uc[v] - um) * idm[e], sb = (up - uc[v]) * idp[e];
-            sl[e][v] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+            const double sa = (P.uc[v] - um) * idm[e], sb = (up - P.uc[v]) * idp[e];
+            P.sl[e][v] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
         }
     }
-    // centroid offsets of the two children of the parent along each direction
-    double off[3][2];
 #pragma unroll
     for (int o = 0; o < 2; ++o) {
-        off[0][o] = lg.r[(g[0] & ~1) + o + 2].poff;
-        off[1][o] = lg.t[(g[1] & ~1) + o + 2].poff;
-        off[2][o] = lg.p[(g[2] & ~1) + o + 2].poff;
+        P.off[0][o] = lg.r[g0[0] + o + 2].poff;
+        P.off[1][o] = lg.t[g0[1] + o + 2].poff;
+        P.off[2][o] = lg.p[g0[2] + o + 2].poff;
     }
     bool ok = true;
     for (int o = 0; o < 8; ++o) {
         double c[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            double x = uc[v];
-            x += sl[0][v] * off[0][o & 1];
-            x += sl[1][v] * off[1][(o >> 1) & 1];
-            x += sl[2][v] * off[2][(o >> 2) & 1];
-            c[v] = x;
-        }
+        for (int v = 0; v < 8; ++v) c[v] = P.linear(o, v);
         const double kin = 0.5 * (c[1] * c[1] + c[2] * c[2] + c[3] * c[3]) / c[0];
         const double mag = 0.5 * (c[5] * c[5] + c[6] * c[6] + c[7] * c[7]);
         ok = ok && c[0] > 0.0 && c[4] - kin - mag > 0.0;
     }
-    const int own[3] = {g[0] & 1, g[1] & 1, g[2] & 1};
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        double x = uc[v];
-        if (ok) {
-            x += sl[0][v] * off[0][own[0]];
-            x += sl[1][v] * off[1][own[1]];
-            x += sl[2][v] * off[2][own[2]];
-        }
-        u[v] = x;
-    }
+    P.ok = ok;
 }
 
 // ---------------------------------------------------------------------------
@@ -405,6 +401,38 @@ __global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, co
         const LevelGeo lg = a.geo[bd.level];
         double *out = a.slabs + (size_t)tk.slab * a.slab_stride;
         const int mem = bd.member;
+        if (tk.type == SLAB_PROLONG) {
+            // one thread per coarse parent: its 8 children are the 2 layers x 2 x 2 fine cells
+            const LevelGeo cg = a.geo[bd.level - 1];
+            const int cs = tk.src[0];
+            const int HA = FA / 2, HB = FB / 2;
+            for (int c = threadIdx.x; c < HA * HB; c += blockDim.x) {
+                const int ca = c % HA, cb = c / HA;
+                int g0[3];                          // child (0, 0, 0), owner-level global index (unwrapped)
+                g0[d] = side ? bd.org[d] + Bd : bd.org[d] - 2;
+                g0[e1] = bd.org[e1] + 2 * ca;
+                g0[e2] = bd.org[e2] + 2 * cb;
+                int cl[3], cw[3];
+                for (int e = 0; e < 3; ++e) {
+                    const int c2 = g0[e] >= 0 ? g0[e] / 2 : -((-g0[e] + 1) / 2);   // floor(g/2)
+                    cl[e] = c2 + tk.shift[e];
+                    cw[e] = c2 + tk.cwrap[e];
+                }
+                Prolong P;
+                prolong_setup<BI, BJ, BK>(a, cs, cl, cw, cg, lg, g0, P);
+                for (int q = 0; q < 8; ++q) {
+                    const int l = q & 1, oa = (q >> 1) & 1, ob = (q >> 2) & 1;
+                    int bits[3];
+                    bits[d] = l;
+                    bits[e1] = oa;
+                    bits[e2] = ob;
+                    const int o = bits[0] | (bits[1] << 1) | (bits[2] << 2);
+                    const int ia = 2 * ca + oa, ib = 2 * cb + ob;
+                    for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = P.value(o, v);
+                }
+            }
+            continue;
+        }
         for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
             const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
             int g[3];                               // owner-level global index (unwrapped)
@@ -466,16 +494,6 @@ __global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, co
                     den += wgt;
                 }
                 for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
-            } else {                                 // SLAB_PROLONG
-                const LevelGeo cg = a.geo[bd.level - 1];
-                const int cs = tk.src[0];
-                int cl[3], cw[3];
-                for (int e = 0; e < 3; ++e) {
-                    const int c2 = g[e] >= 0 ? g[e] / 2 : -((-g[e] + 1) / 2);   // floor(g/2)
-                    cl[e] = c2 + tk.shift[e];
-                    cw[e] = c2 + tk.cwrap[e];
-                }
-                prolong_cell<BI, BJ, BK>(a, cs, cl, cw, cg, lg, g, u);
             }
             for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
         }
@@ -750,23 +768,34 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
     for (int it = blockIdx.x; it < ntasks; it += gridDim.x) {
         const MoveTask tk = tasks[it];
         const LevelGeo lg = a.geo[tk.level];
+        if (tk.type == MOVE_PROLONG) {
+            // one thread per coarse cell of the parent under this child block: 8 fine cells each
+            const int ps = tk.src[0];
+            const BlockDesc pd = a.desc[ps];
+            const LevelGeo cg = a.geo[tk.level - 1];
+            constexpr int HI = BI / 2, HJ = BJ / 2, HK = BK / 2;
+            for (int c = threadIdx.x; c < HI * HJ * HK; c += blockDim.x) {
+                const int h[3] = {c % HI, (c / HI) % HJ, c / (HI * HJ)};
+                int g0[3], cl[3], cw[3];
+                for (int e = 0; e < 3; ++e) {
+                    g0[e] = tk.org[e] + 2 * h[e];
+                    cw[e] = g0[e] >> 1;
+                    cl[e] = cw[e] - pd.org[e];
+                }
+                Prolong P;
+                prolong_setup<BI, BJ, BK>(a, ps, cl, cw, cg, lg, g0, P);
+                for (int o = 0; o < 8; ++o) {
+                    const int li = 2 * h[0] + (o & 1), lj = 2 * h[1] + ((o >> 1) & 1), lk = 2 * h[2] + ((o >> 2) & 1);
+                    for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, li, lj, lk)] = P.value(o, v);
+                }
+            }
+            continue;
+        }
         for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
             const int loc[3] = {c % BI, (c / BI) % BJ, c / (BI * BJ)};
             int g[3];
             for (int e = 0; e < 3; ++e) g[e] = tk.org[e] + loc[e];
-            if (tk.type == MOVE_PROLONG) {
-                const int ps = tk.src[0];
-                const BlockDesc pd = a.desc[ps];
-                const LevelGeo cg = a.geo[tk.level - 1];
-                int cl[3], cw[3];
-                for (int e = 0; e < 3; ++e) {
-                    cw[e] = g[e] >> 1;
-                    cl[e] = cw[e] - pd.org[e];
-                }
-                double u[8];
-                prolong_cell<BI, BJ, BK>(a, ps, cl, cw, cg, lg, g, u);
-                for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = u[v];
-            } else {
+            {
                 const LevelGeo fg = a.geo[tk.level + 1];
                 double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
                 for (int o = 0; o < 8; ++o) {

@@ -49,7 +49,7 @@ struct MlpDevice {
 
 void mlp_features(hipStream_t s, const KArgs &a, int bi, int bj, int bk, const int *items, const int *nitems, int n,
                   float *raw, const float *mean, const float *istd, uint16_t *xb);
-void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, int8_t *flags);
+void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, float threshold, int8_t *flags);
 void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float *params, float *grad_out,
               float *loss_out);
 void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp, float *params, float *mean_out,

@@ -217,11 +217,11 @@ __global__ void k_gather(const uint16_t *xall, const uint8_t *yall, const long *
     if (f == 0) yb[r] = yall[row];
 }
 
-// learned flags: p >= 1/2 -> refine, else coarsen-eligible
-__global__ void k_prob_flags(const float *prob, const int *items, int n, int8_t *flags)
+// learned flags: p >= threshold -> refine, else coarsen-eligible
+__global__ void k_prob_flags(const float *prob, const int *items, int n, float threshold, int8_t *flags)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < n) flags[items[q]] = prob[q] >= 0.5f ? 1 : -1;
+    if (q < n) flags[items[q]] = prob[q] >= threshold ? 1 : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,9 +327,9 @@ void mlp_features(hipStream_t s, const KArgs &a, int bi, int bj, int bk, const i
 #undef IC_INSTANTIATE
 }
 
-void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, int8_t *flags)
+void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, float threshold, int8_t *flags)
 {
-    hipLaunchKernelGGL(k_prob_flags, dim3((n + 255) / 256), dim3(256), 0, s, prob, items, n, flags);
+    hipLaunchKernelGGL(k_prob_flags, dim3((n + 255) / 256), dim3(256), 0, s, prob, items, n, threshold, flags);
 }
 
 // One forward + backward pass on n rows: gradients (fp32, params layout) and mean loss.

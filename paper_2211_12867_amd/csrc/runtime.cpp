@@ -218,6 +218,7 @@ struct ic_sim {
     // graph
     hipGraphExec_t gexec = nullptr;
     bool graph_dirty = true;
+    int graph_stage_grid = 0;       // stage launch size the captured graph was made with
     double graph_dt_fixed = -1.0;
     bool use_graph = true;
 
@@ -609,6 +610,14 @@ void rebuild(ic_sim *s)
             ranges[2 * l + 1] = s->pass_hi[l];
         }
     }
+    // entry 1 (no level 1 prolongation exists): every prolongation task of every
+    // level in one pass.  A prolongation stencil reads its coarse parent and
+    // the parent's axis neighbours: interior cells, restriction or inner
+    // slabs (pass 1), never another prolongation slab -- that would need a
+    // level-(l-2) block touching a level-l block along an edge, which the
+    // 2:1 balance over all 26 neighbours rules out.
+    ranges[2] = s->pass_lo[2];
+    ranges[3] = s->pass_hi[s->max_level];
     HIPCHECK(hipMemcpy(s->slab_ranges.p, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!rf.empty()) {
         HIPCHECK(hipMemcpy(s->rf_tasks.p, rf.data(), rf.size() * sizeof(RefluxTask), hipMemcpyHostToDevice));
@@ -666,8 +675,7 @@ void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
     a.tfrac = tfrac;
     const int g = grid_for(s->n_slabs + 1, 8192);
     s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p);
-    for (int l = 2; l <= s->max_level; ++l)
-        s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2 * l);
+    if (s->max_level > 1) s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2);
 }
 
 void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, int want_rate)
@@ -730,7 +738,8 @@ void run_step(ic_sim *s, double dt_fixed_code, bool record)
         enqueue_step(s, dt_fixed_code, record);
         return;
     }
-    if (s->graph_dirty || s->gexec == nullptr || s->graph_dt_fixed != dt_fixed_code) {
+    if (s->graph_dirty || s->gexec == nullptr || s->graph_dt_fixed != dt_fixed_code ||
+        s->graph_stage_grid != stage_grid(s)) {
         if (s->gexec) HIPCHECK(hipGraphExecDestroy(s->gexec));
         s->gexec = nullptr;
         hipGraph_t g;
@@ -741,6 +750,7 @@ void run_step(ic_sim *s, double dt_fixed_code, bool record)
         HIPCHECK(hipGraphDestroy(g));
         s->graph_dirty = false;
         s->graph_dt_fixed = dt_fixed_code;
+        s->graph_stage_grid = stage_grid(s);
     }
     (void)record;
     HIPCHECK(hipGraphLaunch(s->gexec, s->stream));
@@ -1210,12 +1220,17 @@ bool leaf_in_windows(const ic_sim *s, int m, const Key &key)
     return false;
 }
 
-// learned flags per pool slot: REFINE where the network gives p >= 1/2 and
+float learned_threshold(const ic_sim *s)
+{
+    return s->amr.learned_threshold > 0.0 ? (float)s->amr.learned_threshold : 0.5f;
+}
+
+// learned flags per pool slot: REFINE where the network gives p >= threshold and
 // the leaf touches the windows, else COARSEN
 void learned_flags(ic_sim *s, std::vector<int8_t> &fl)
 {
     learned_prob(s);
-    mlp_prob_flags(s->stream, s->mlp.prob, s->items.p, s->n_items, s->flags.p);
+    mlp_prob_flags(s->stream, s->mlp.prob, s->items.p, s->n_items, learned_threshold(s), s->flags.p);
     HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
     for (int m = 0; m < s->nm; ++m)
@@ -1968,7 +1983,8 @@ ic_status ic_eval_learned(ic_sim *s, int member, float *prob, int8_t *flags, int
         for (int q = 0; q < nl; ++q) {
             if (prob) prob[q] = p[q];
             if (flags)
-                flags[q] = p[q] >= 0.5f && leaf_in_windows(s, member, keys[q]) ? IC_FLAG_REFINE : IC_FLAG_COARSEN;
+                flags[q] = p[q] >= learned_threshold(s) && leaf_in_windows(s, member, keys[q]) ? IC_FLAG_REFINE
+                                                                                              : IC_FLAG_COARSEN;
         }
     });
 }

@@ -22,6 +22,7 @@ from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_infer
 DAY = 86400.0
 HOUR = 3600.0
 SAMPLE = (1.0, 90.0, 0.0)          # r [AU], colatitude, longitude [deg] in the co-rotating frame
+TUNE_CACHE = None                  # schedule cache file of ic_autotune (None: time the candidates each call)
 
 
 def _log(log, msg):
@@ -35,6 +36,7 @@ def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
     g = dict(grid, max_level=1)
     sim = Sim(g, wind, [cme], dict(regrid_every=0))
     t0 = time.perf_counter()
+    sim.autotune(TUNE_CACHE)
     steps = 0
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
@@ -83,6 +85,7 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
     t0 = time.perf_counter()
     info = None
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
+        sim.autotune(TUNE_CACHE)                 # the work list changes with the forest
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
         ts.append(sim.timeseries())
         sim.timeseries_clear()
@@ -255,7 +258,8 @@ def main(argv=None):
     lv = args.max_level
     runs = {"plain_buffer_L%d" % (lv - 1): (lv - 1, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
             "plain_buffer_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=1), None),
-            "learned_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0), net),
+            "learned_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0,
+                                          learned_threshold=meta.get("threshold", 0.5)), net),
             "plain_no_buffer_L%d" % lv: (lv, dict(amr, source=IC_SOURCE_PLAIN, buffer_blocks=0), None)}
     for name, (level, a, n) in runs.items():
         if args.only and name not in args.only.split(","):
