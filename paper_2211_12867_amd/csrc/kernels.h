@@ -53,37 +53,45 @@ struct Shape {
                                                        : (BI * BK > BJ * BK ? BI * BK : BJ * BK));
 };
 
-// Value of variable v of the cell (i, j, k) of block `slot`, where at most one
-// index may lie in the two ghost layers: interior, same-level neighbour,
-// outflow copy of the edge cell, or ghost slab.
+// Address of variable v of the cell (i, j, k) of block `slot`, where at most
+// one index may lie in the two ghost layers: interior, same-level neighbour,
+// outflow copy of the edge cell, or ghost slab.  Within a block or a slab the
+// cells of one (i, j) plane are contiguous in i, then j.
 template <class S>
-__device__ inline double ghosted(const double *__restrict__ U, const BlockDesc *__restrict__ desc,
-                                 const double *__restrict__ slabs, long slab_stride, int slot, int v,
-                                 int i, int j, int k)
+__device__ inline const double *ghosted_addr(const double *__restrict__ U, const BlockDesc *__restrict__ desc,
+                                             const double *__restrict__ slabs, long slab_stride, int slot, int v,
+                                             int i, int j, int k)
 {
     int idx[3] = {i, j, k};
     int d = -1;
     if (i < 0 || i >= S::B0) d = 0;
     else if (j < 0 || j >= S::B1) d = 1;
     else if (k < 0 || k >= S::B2) d = 2;
-    if (d < 0)
-        return U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k)];
+    if (d < 0) return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
     const int Bd = S::dim(d);
     const int side = idx[d] >= Bd ? 1 : 0;
     const int l = side ? idx[d] - Bd : idx[d] + 2;
     const int code = desc[slot].nbr[2 * d + side];
     if (code >= 0) {
         idx[d] = side ? l : Bd - 2 + l;
-        return U[(size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2])];
+        return U + (size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     if (code == NBR_OUTFLOW) {
         idx[d] = side ? Bd - 1 : 0;
-        return U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2])];
+        return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     const int s = nbr_slab(code);
     const int a = idx[tan1(d)], b = idx[tan2(d)];
     const int FA = S::dim(tan1(d)), FB = S::dim(tan2(d));
-    return slabs[(size_t)s * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a];
+    return slabs + (size_t)s * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a;
+}
+
+template <class S>
+__device__ inline double ghosted(const double *__restrict__ U, const BlockDesc *__restrict__ desc,
+                                 const double *__restrict__ slabs, long slab_stride, int slot, int v,
+                                 int i, int j, int k)
+{
+    return *ghosted_addr<S>(U, desc, slabs, slab_stride, slot, v, i, j, k);
 }
 
 template <class S>

@@ -125,10 +125,20 @@ k_stage(KArgs a)
     constexpr int NFJ = BI * (BJ + 1);
     constexpr int NCOL = BI * BJ;
     constexpr int NHALO = 4 * (BI + BJ);
-    static_assert(NCOL + 32 <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
+    static_assert(NCOL + 64 <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
     constexpr int NIDLE = NT - NCOL;             // threads without a column: they prefetch
+    // the last wave (it owns no column) copies the next planes asynchronously into LDS
+    constexpr int CWAVE = NT / 64 - 1;
+    constexpr int NHP = NHALO * 8 * 2;           // halo: one 4-byte piece per lane, two per double
+    constexpr int NCP = NCOL / 2 * 8;            // column plane: one 16-byte piece (two cells) per lane
+    static_assert(NCOL % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
 
     __shared__ double sW[8][PJ][PI];
+    __shared__ __attribute__((aligned(16))) double sCol[8][NCOL];     // conserved column plane k+2
+    __shared__ __attribute__((aligned(16))) double sHal[8][NHALO];    // conserved halo of plane k+1
+    // per halo cell: address of variable 0 in plane 0 and the strides (doubles) per variable and plane
+    __shared__ const double *sHB[NHALO];
+    __shared__ int sHV[NHALO], sHK[NHALO];
     __shared__ double sFi[8][BJ][BI + 1];
     __shared__ double sFj[8][BJ + 1][BI];
     __shared__ RecR sR[BI + 4];
@@ -182,15 +192,27 @@ k_stage(KArgs a)
 #pragma unroll
             for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
         }
-        // halos of plane k0, by all threads
+        // halos of plane k0, by all threads; the halo address table
         for (int t = tid; t < NHALO; t += NT) {
             int i, j;
             halo_cell<BI, BJ>(t, i, j);
+            {
+                const double *p0 = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 0);
+                sHB[t] = p0;
+                sHV[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 1, i, j, 0) - p0);
+                sHK[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 1) - p0);
+            }
             double u[8], w[8];
             ghosted8<S>(a, a.U, slot, i, j, k0, u);
             cons_to_prim(u, w, gs);
 #pragma unroll
             for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+        }
+        for (int c = tid; c < NCOL; c += NT) {
+            double u[8];
+            ghosted8<S>(a, a.U, slot, c % BI, c / BI, k0 + 2, u);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sCol[v][c] = u[v];
         }
         double rmax = 0.0;
         __syncthreads();
@@ -230,7 +252,8 @@ k_stage(KArgs a)
             double Fp[8], Wnext[8];
             if (col) {
                 double u[8], W2[8], lo1[8], w0[8];
-                ghosted8<S>(a, a.U, slot, ci, cj, k + 2, u);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) u[v] = sCol[v][tid];
                 cons_to_prim(u, W2, gs);
 #pragma unroll
                 for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
@@ -294,17 +317,45 @@ k_stage(KArgs a)
                     Fm[v] = Fp[v];
                     sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
                 }
-            } else if (k + 1 < k1) {
-                // (p) meanwhile the threads without a column load the halos of
-                // plane k+1 (the update reads no halo cell)
-                for (int t = tid - NCOL; t < NHALO; t += NIDLE) {
+            } else if (k + 1 < k1 && (tid >> 6) == CWAVE) {
+                // (p) meanwhile the last wave (no column) copies the conserved halo of
+                // plane k+1 (the update reads no halo cell) and the column plane k+3
+                // (read in (e) of the next plane; this plane's copy was read before
+                // the last barrier) from HBM into LDS without staging in registers,
+                // wait once, and convert the halo to primitives
+                const int lane = tid & 63;
+                typedef __attribute__((address_space(3))) char lds_t;
+#pragma unroll 2
+                for (int q = 0; q * 64 < NHP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NHP) {
+                        const int v = g / (2 * NHALO), cell = (g >> 1) % NHALO, half = g & 1;
+                        const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHal[0][0] + q * 256), 4, 0, 0);
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NCP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NCP) {
+                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
+                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
+                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
+                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);           // this wave's copies have landed
+#pragma unroll 1
+                for (int t = lane; t < NHALO; t += 64) {
                     int i, j;
                     halo_cell<BI, BJ>(t, i, j);
-                    double u[8], w[8];
-                    ghosted8<S>(a, a.U, slot, i, j, k + 1, u);
-                    cons_to_prim(u, w, gs);
+                    double u[8], w8[8];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+                    for (int v = 0; v < 8; ++v) u[v] = sHal[v][t];
+                    cons_to_prim(u, w8, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
                 }
             }
             __syncthreads();
