@@ -129,13 +129,16 @@ k_stage(KArgs a)
     constexpr int NIDLE = NT - NCOL;             // threads without a column: they prefetch
     // the last wave (it owns no column) copies the next planes asynchronously into LDS
     constexpr int CWAVE = NT / 64 - 1;
-    constexpr int NHP = NHALO * 8 * 2;           // halo: one 4-byte piece per lane, two per double
+    constexpr int NHR = 4 * BJ, NHT = 4 * BI;    // r-halo cells (first), theta-halo cells
+    constexpr int NHP = NHR * 8 * 2;             // r-halo: one 4-byte piece per lane, two per double
+    constexpr int NTP = NHT / 2 * 8;             // theta-halo rows: one 16-byte piece (two cells) per lane
     constexpr int NCP = NCOL / 2 * 8;            // column plane: one 16-byte piece (two cells) per lane
-    static_assert(NCOL % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
+    static_assert(NCOL % 2 == 0 && BI % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
 
     __shared__ double sW[8][PJ][PI];
     __shared__ __attribute__((aligned(16))) double sCol[8][NCOL];     // conserved column plane k+2
-    __shared__ __attribute__((aligned(16))) double sHal[8][NHALO];    // conserved halo of plane k+1
+    __shared__ __attribute__((aligned(16))) double sHalR[8][NHR];     // conserved r-halo of plane k+1
+    __shared__ __attribute__((aligned(16))) double sHalT[8][NHT];     // conserved theta-halo of plane k+1
     // per halo cell: address of variable 0 in plane 0 and the strides (doubles) per variable and plane
     __shared__ const double *sHB[NHALO];
     __shared__ int sHV[NHALO], sHK[NHALO];
@@ -329,10 +332,21 @@ k_stage(KArgs a)
                 for (int q = 0; q * 64 < NHP; ++q) {
                     const int g = q * 64 + lane;
                     if (g < NHP) {
-                        const int v = g / (2 * NHALO), cell = (g >> 1) % NHALO, half = g & 1;
+                        const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
                         const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
                         __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (lds_t *)((lds_t *)&sHal[0][0] + q * 256), 4, 0, 0);
+                                                         (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NTP; ++q) {
+                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
+                    const int g = q * 64 + lane;
+                    if (g < NTP) {
+                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
+                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
                     }
                 }
 #pragma unroll 2
@@ -352,7 +366,7 @@ k_stage(KArgs a)
                     halo_cell<BI, BJ>(t, i, j);
                     double u[8], w8[8];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) u[v] = sHal[v][t];
+                    for (int v = 0; v < 8; ++v) u[v] = t < NHR ? sHalR[v][t] : sHalT[v][t - NHR];
                     cons_to_prim(u, w8, gs);
 #pragma unroll
                     for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
