@@ -1672,17 +1672,23 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
         HIPCHECK(hipMemcpyAsync(s->tend.p, tend.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
         const int every = (s->max_level > 1 && s->amr.regrid_every > 0) ? s->amr.regrid_every : 0;
         long done = 0;
-        std::vector<long> ns(s->nm);
+        // zone updates: per member, the steps it took (a member past its end time
+        // takes dt = 0 and does no work) times its leaf cells (fixed within a batch)
+        std::vector<long> ns(s->nm), ns1(s->nm);
+        HIPCHECK(hipMemcpyAsync(ns.data(), s->nsteps.p, s->nm * sizeof(long), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
         while (done < max_steps) {
             const long batch = std::min<long>(max_steps - done, every > 0 ? every : 20);
-            for (long q = 0; q < batch; ++q) {
-                run_step(s, 0.0, true);
-                s->zone_updates += (double)total_cells(s);
-            }
+            for (long q = 0; q < batch; ++q) run_step(s, 0.0, true);
             done += batch;
             check_bad(s);
             HIPCHECK(hipMemcpyAsync(t.data(), s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+            HIPCHECK(hipMemcpyAsync(ns1.data(), s->nsteps.p, s->nm * sizeof(long), hipMemcpyDeviceToHost, s->stream));
             HIPCHECK(hipStreamSynchronize(s->stream));
+            for (int m = 0; m < s->nm; ++m) {
+                s->zone_updates += (double)(ns1[m] - ns[m]) * (double)s->mem[m].leaves.size() * s->NC;
+                ns[m] = ns1[m];
+            }
             bool all = true;
             for (int m = 0; m < s->nm; ++m) all = all && t[m] >= tend[m];
             if (all) break;

@@ -165,6 +165,42 @@ def load_network(path):
     return (d["params"], d["mean"], d["std"]), json.loads(str(d["meta"]))
 
 
+def ensemble_run(grid, wind, cmes, amr, start, t_end_s, chunk_s=DAY / 4, log=print):
+    """All members in one sim from one relaxed state: every leaf of every member
+    in the same launches, per-member dt and regrids.  Returns dict(arrival_h
+    and width_h per member, wall_s, steps per member, zone_updates, max_leaves)."""
+    sim = Sim(grid, wind, cmes, amr)
+    for m in range(len(cmes)):
+        sim.set_state(start["blocks"], start["U"], start["t_s"], member=m)
+    sim.set_sample_point(*SAMPLE)
+    series = [[] for _ in cmes]
+    t0 = time.perf_counter()
+    info = None
+    max_leaves = 0
+    while min(sim.time(m)[0] for m in range(len(cmes))) < t_end_s * (1.0 - 1e-12):
+        sim.autotune(TUNE_CACHE)
+        info = sim.advance(min(chunk_s, t_end_s - sim.time(0)[0]))
+        for m in range(len(cmes)):
+            series[m].append(sim.timeseries(m))
+        sim.timeseries_clear()
+        nl = sum(len(sim.blocks(m)) for m in range(len(cmes)))
+        max_leaves = max(max_leaves, nl)
+        _log(log, "ensemble: t = %.2f d, %d leaves over %d members, %.1f s"
+             % (sim.time(0)[0] / DAY, nl, len(cmes), time.perf_counter() - t0))
+    wall = time.perf_counter() - t0
+    arr, wid, steps = [], [], []
+    for m, c in enumerate(cmes):
+        ts = np.concatenate(series[m])
+        _, _, a, w = _series_arrival(ts, c["t_start_s"])
+        arr.append(a)
+        wid.append(w)
+        steps.append(len(ts))
+    out = dict(arrival_h=arr, width_h=wid, wall_s=wall, steps=steps,
+               zone_updates=info["zone_updates"] if info else 0.0, max_leaves=max_leaves)
+    sim.close()
+    return out
+
+
 # --- command line ---------------------------------------------------------------
 
 def _workload_parts(name, wind_seed=None, cme=None, max_level=None):
@@ -200,6 +236,11 @@ def main(argv=None):
     c.add_argument("--skip-equidistant", action="store_true")
     c.add_argument("--out")
     c.add_argument("--only", help="comma-separated subset of the AMR runs")
+    e = sub.add_parser("ensemble", help="the 32-member cone-CME ensemble on the stretched 3-level grid")
+    e.add_argument("--members", type=int, default=32)
+    e.add_argument("--relax-days", type=float, default=14.0)
+    e.add_argument("--cme-days", type=float, default=3.0)
+    e.add_argument("--out")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -247,6 +288,28 @@ def main(argv=None):
                     cme_days=args.cme_days, epochs=args.epochs, loss=[float(v) for v in loss])
         save_network(args.out, params, mean, std, meta)
         log("trained: %s" % json.dumps(meta))
+        return 0
+
+    if args.cmd == "ensemble":
+        from synthetic import as_dict, workload
+        w = workload("ensemble")
+        grid, wind, amr = as_dict(w.grid), as_dict(w.wind), as_dict(w.amr)
+        cmes = [dict(as_dict(c), t_start_s=args.relax_days * DAY) for c in w.cmes[:args.members]]
+        st = relax(grid, wind, cmes[0], args.relax_days * DAY, log=log)
+        r = ensemble_run(grid, wind, cmes, dict(amr, buffer_blocks=1), st, (args.relax_days + args.cme_days) * DAY,
+                         log=log)
+        cells = grid["block"][0] * grid["block"][1] * grid["block"][2]
+        summary = dict(members=len(cmes), wall_s=r["wall_s"], relax_wall_s=st["wall_s"],
+                       zone_updates=r["zone_updates"], zone_updates_per_s=r["zone_updates"] / r["wall_s"],
+                       max_leaves=r["max_leaves"], leaf_cells_peak=r["max_leaves"] * cells,
+                       arrival_h=[round(x, 3) for x in r["arrival_h"]], width_h=[round(x, 3) for x in r["width_h"]],
+                       steps=r["steps"],
+                       cmes=[{k: round(c[k], 1) for k in ("v_kms", "half_width_deg", "colat_deg", "lon_deg", "n_cm3")}
+                             for c in cmes])
+        log(json.dumps(summary))
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(summary, fh, indent=1)
         return 0
 
     net, meta = load_network(args.net)
