@@ -1,17 +1,20 @@
 // kernels.hip -- HIP kernels of the Icarus hot path for gfx950 (CDNA4).
 //
 // k_stage is the fused finite-volume stage (paper Sect. 2.1: TVDLF with a
-// Woodward-type limiter, second order): one work-group per leaf block marches
-// along k (phi) through the block.  For each k-plane the primitives of the
-// plane and of its two-cell i/j halos sit in LDS; every r- and theta-face flux
-// of the plane is computed once by one thread and kept in LDS; the phi-face
-// fluxes are computed once per column in registers (each thread owns one
-// (i, j) column and carries the previous plane's flux, face state and the
-// next two planes' primitives).  The update then adds the flux differences
-// with the finite-volume metric, the hoop, Coriolis, centrifugal and gravity
-// sources, and writes U_out = U_base + alpha dt L(U).  Halo cells come
-// straight from neighbouring blocks (same level), from the block's own edge
-// (outflow) or from ghost slabs (inner boundary, coarse-fine faces).
+// Woodward-type limiter, second order): a work-group marches along k (phi)
+// through a leaf block (or through 1/2 or 1/4 of it, for short work lists).
+// For each k-plane the primitives of the plane and of its two-cell i/j halos
+// sit in LDS; every r- and theta-face flux of the plane is computed once by
+// one thread and kept in LDS; the phi-face fluxes are computed once per column
+// in registers (each of the first 192 or fewer threads owns one (i, j) column
+// and carries the previous plane's flux, face state and the next plane's
+// primitives).  The update adds the flux differences with the finite-volume
+// metric, the hoop, Coriolis, centrifugal and gravity sources, applies the
+// floors and writes U_out = U_base + alpha dt L(U).  Meanwhile the last wave,
+// which owns no column, copies the next plane's halo and the column plane two
+// ahead from HBM into LDS asynchronously.  Halo cells come from neighbouring
+// blocks (same level), the block's own edge (outflow) or ghost slabs (inner
+// boundary, coarse-fine faces).
 #include "kernels.h"
 
 #define NT 256
@@ -126,7 +129,6 @@ k_stage(KArgs a)
     constexpr int NCOL = BI * BJ;
     constexpr int NHALO = 4 * (BI + BJ);
     static_assert(NCOL + 64 <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
-    constexpr int NIDLE = NT - NCOL;             // threads without a column: they prefetch
     // the last wave (it owns no column) copies the next planes asynchronously into LDS
     constexpr int CWAVE = NT / 64 - 1;
     constexpr int NHR = 4 * BJ, NHT = 4 * BI;    // r-halo cells (first), theta-halo cells
