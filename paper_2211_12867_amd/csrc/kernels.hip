@@ -310,7 +310,7 @@ k_stage(KArgs a)
                 if (!rf) apply_floors(unew, gs, a.rho_floor, a.p_floor);
 #pragma unroll
                 for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
-                if (a.want_rate) {
+                if (a.want_rate && !rf) {            // refluxed cells: after the reflux
                     cons_to_prim(unew, w, gs);
                     const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
                                       + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
@@ -451,124 +451,200 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // ---------------------------------------------------------------------------
 // ghost slabs: inner boundary (wind + cone CME), restriction, prolongation
 // ---------------------------------------------------------------------------
+// One slab task whose face is normal to direction D (a template parameter, so
+// that every per-direction index below is a register, not private memory).
+// Slab layout: element ((v * 2 + l) * FB + b) * FA + a, layer l = 0 nearest
+// the low side.  sP, sOk: LDS for the prolongation's per-parent values.
+template <int BI, int BJ, int BK, int D>
+DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
+{
+    using S = Shape<BI, BJ, BK>;
+    constexpr int E1 = tan1(D), E2 = tan2(D);
+    constexpr int FA = S::dim(E1), FB = S::dim(E2), Bd = S::dim(D);
+    constexpr int NCELL = 2 * FA * FB;
+    const int type = tkp->type, side = tkp->face & 1;
+    const BlockDesc bd = a.desc[tkp->slot];
+    const LevelGeo lg = a.geo[bd.level];
+    double *out = a.slabs + (size_t)tkp->slab * a.slab_stride;
+    const int g0d = side ? bd.org[D] + Bd : bd.org[D] - 2;     // owner-level index of layer 0 along D
+    if (type == SLAB_PROLONG) {
+        // children = 2 layers x 2 x 2 fine cells per coarse parent
+        constexpr int HA = FA / 2, HB = FB / 2, NP = HA * HB;
+        const LevelGeo cg = a.geo[bd.level - 1];
+        const int cs = tkp->src[0];
+        const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
+        const int cwrap[3] = {tkp->cwrap[0], tkp->cwrap[1], tkp->cwrap[2]};
+        // (1) per parent and variable: coarse value and minmod slopes along r, theta, phi
+        for (int t = threadIdx.x; t < NP * 8; t += blockDim.x) {
+            const int c = t % NP, v = t / NP;
+            int g0[3];
+            g0[D] = g0d;
+            g0[E1] = bd.org[E1] + 2 * (c % HA);
+            g0[E2] = bd.org[E2] + 2 * (c / HA);
+            int cl[3], cw[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int c2 = g0[e] >= 0 ? g0[e] / 2 : -((-g0[e] + 1) / 2);   // floor(g/2)
+                cl[e] = c2 + shift[e];
+                cw[e] = c2 + cwrap[e];
+            }
+            const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
+            const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
+            const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, cl[0], cl[1], cl[2]);
+            double *P = sP + (c * 8 + v) * 4;
+            P[0] = uc;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
+                lm[e] -= 1;
+                lp[e] += 1;
+                const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lm[0], lm[1], lm[2]);
+                const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lp[0], lp[1], lp[2]);
+                const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
+                P[1 + e] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+            }
+        }
+        __syncthreads();
+        // (2) per parent: do the linear values give all 8 children rho > 0 and p > 0?
+        for (int c = threadIdx.x; c < NP; c += blockDim.x) {
+            int g0[3];
+            g0[D] = g0d;
+            g0[E1] = bd.org[E1] + 2 * (c % HA);
+            g0[E2] = bd.org[E2] + 2 * (c / HA);
+            const double off[3][2] = {{lg.r[g0[0] + 2].poff, lg.r[g0[0] + 3].poff},
+                                      {lg.t[g0[1] + 2].poff, lg.t[g0[1] + 3].poff},
+                                      {lg.p[g0[2] + 2].poff, lg.p[g0[2] + 3].poff}};
+            const double *P = sP + c * 32;
+            bool ok = true;
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                double q[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    double x = P[v * 4];
+                    x += P[v * 4 + 1] * off[0][o & 1];
+                    x += P[v * 4 + 2] * off[1][(o >> 1) & 1];
+                    x += P[v * 4 + 3] * off[2][(o >> 2) & 1];
+                    q[v] = x;
+                }
+                const double kin = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+                const double mag = 0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+                ok = ok && q[0] > 0.0 && q[4] - kin - mag > 0.0;
+            }
+            sOk[c] = ok;
+        }
+        __syncthreads();
+        // (3) the slab element by element (coalesced); a failing parent hands
+        // its own value to its children
+        for (int e = threadIdx.x; e < 8 * NCELL; e += blockDim.x) {
+            const int ia = e % FA, ib = (e / FA) % FB, l = (e / (FA * FB)) & 1, v = e / NCELL;
+            const int c = (ia >> 1) + HA * (ib >> 1);
+            const double *P = sP + (c * 8 + v) * 4;
+            double x = P[0];
+            if (sOk[c]) {
+                int g[3];
+                g[D] = g0d + l;
+                g[E1] = bd.org[E1] + ia;
+                g[E2] = bd.org[E2] + ib;
+                x += P[1] * lg.r[g[0] + 2].poff;
+                x += P[2] * lg.t[g[1] + 2].poff;
+                x += P[3] * lg.p[g[2] + 2].poff;
+            }
+            out[e] = x;
+        }
+        __syncthreads();                            // sP and sOk are reused by the next task
+        return;
+    }
+    const Gas gs = a.gas;
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
+        int g[3];                                   // owner-level global index (unwrapped)
+        g[D] = g0d + l;
+        g[E1] = bd.org[E1] + ia;
+        g[E2] = bd.org[E2] + ib;
+        double u[8];
+        if (type == SLAB_INNER) {
+            const int jt = g[1], kp = g[2];
+            const int nt = lg.n[1], np = lg.n[2];
+            const size_t o = (size_t)jt * np + kp;
+            const size_t pl = (size_t)nt * np;
+            double w[8];
+            w[0] = lg.wind[0 * pl + o];
+            w[1] = lg.wind[1 * pl + o];
+            w[2] = 0.0;
+            w[3] = lg.wind[2 * pl + o];
+            w[4] = lg.wind[3 * pl + o];
+            w[5] = lg.wind[4 * pl + o];
+            w[6] = 0.0;
+            w[7] = lg.wind[5 * pl + o];
+            const int mem = bd.member;
+            const MemberConst mc = a.mc[mem];
+            if (mc.enabled) {
+                const double ts = a.t[mem] + a.tfrac * a.dt[mem];
+                const double tau = ts - mc.t0;
+                if (tau >= 0.0 && tau <= mc.tact) {
+                    const double R = mc.r_in;
+                    const double Rc = tau * mc.v + R - mc.r_half;
+                    double arg = (Rc * Rc + R * R - mc.r_half * mc.r_half) / (2.0 * Rc * R);
+                    arg = arg > 1.0 ? 1.0 : (arg < -1.0 ? -1.0 : arg);
+                    double cd = lg.cosd[(size_t)mem * pl + o];
+                    cd = cd > 1.0 ? 1.0 : (cd < -1.0 ? -1.0 : cd);
+                    if (cd >= arg) {
+                        w[0] = mc.rho;
+                        w[1] = mc.v;
+                        w[4] = mc.p;
+                    }
+                }
+            }
+            prim_to_cons(w, u, gs);
+        } else {                                    // SLAB_RESTRICT
+            const LevelGeo fg = a.geo[bd.level + 1];
+            double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
+            int gw[3];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) gw[e] = g[e] + tkp->shift[e];
+            const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                int fgi[3], fl[3], q[3];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    fgi[e] = 2 * gw[e] + ((o >> e) & 1);
+                    const int fb = fgi[e] / S::dim(e);
+                    q[e] = fb - fbase[e];
+                    fl[e] = fgi[e] - fb * S::dim(e);
+                }
+                const int fslot = tkp->src[q[E1] + 2 * q[E2]];
+                const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) num[v] += wgt * a.U[cidx<S>(fslot, v, fl[0], fl[1], fl[2])];
+                den += wgt;
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
+    }
+}
+
 template <int BI, int BJ, int BK>
 __global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, const int *range)
 {
     using S = Shape<BI, BJ, BK>;
+    __shared__ double sP[S::MAXFACE / 4 * 32];
+    __shared__ int sOk[S::MAXFACE / 4];
     const int t0 = range[0], t1 = range[1];
-    const Gas gs = a.gas;
     for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
-        const SlabTask tk = tasks[it];
-        const BlockDesc bd = a.desc[tk.slot];
-        const int d = tk.face >> 1, side = tk.face & 1;
-        const int e1 = tan1(d), e2 = tan2(d);
-        const int FA = S::dim(e1), FB = S::dim(e2);
-        const int Bd = S::dim(d);
-        const int ncell = 2 * FA * FB;
-        const LevelGeo lg = a.geo[bd.level];
-        double *out = a.slabs + (size_t)tk.slab * a.slab_stride;
-        const int mem = bd.member;
-        if (tk.type == SLAB_PROLONG) {
-            // one thread per coarse parent: its 8 children are the 2 layers x 2 x 2 fine cells
-            const LevelGeo cg = a.geo[bd.level - 1];
-            const int cs = tk.src[0];
-            const int HA = FA / 2, HB = FB / 2;
-            for (int c = threadIdx.x; c < HA * HB; c += blockDim.x) {
-                const int ca = c % HA, cb = c / HA;
-                int g0[3];                          // child (0, 0, 0), owner-level global index (unwrapped)
-                g0[d] = side ? bd.org[d] + Bd : bd.org[d] - 2;
-                g0[e1] = bd.org[e1] + 2 * ca;
-                g0[e2] = bd.org[e2] + 2 * cb;
-                int cl[3], cw[3];
-                for (int e = 0; e < 3; ++e) {
-                    const int c2 = g0[e] >= 0 ? g0[e] / 2 : -((-g0[e] + 1) / 2);   // floor(g/2)
-                    cl[e] = c2 + tk.shift[e];
-                    cw[e] = c2 + tk.cwrap[e];
-                }
-                Prolong P;
-                prolong_setup<BI, BJ, BK>(a, cs, cl, cw, cg, lg, g0, P);
-                for (int q = 0; q < 8; ++q) {
-                    const int l = q & 1, oa = (q >> 1) & 1, ob = (q >> 2) & 1;
-                    int bits[3];
-                    bits[d] = l;
-                    bits[e1] = oa;
-                    bits[e2] = ob;
-                    const int o = bits[0] | (bits[1] << 1) | (bits[2] << 2);
-                    const int ia = 2 * ca + oa, ib = 2 * cb + ob;
-                    for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = P.value(o, v);
-                }
-            }
-            continue;
-        }
-        for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-            const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
-            int g[3];                               // owner-level global index (unwrapped)
-            g[d] = side ? bd.org[d] + Bd + l : bd.org[d] - 2 + l;
-            g[e1] = bd.org[e1] + ia;
-            g[e2] = bd.org[e2] + ib;
-            double u[8];
-            if (tk.type == SLAB_INNER) {
-                const int jt = g[1], kp = g[2];
-                const int nt = lg.n[1], np = lg.n[2];
-                const size_t o = (size_t)jt * np + kp;
-                const size_t pl = (size_t)nt * np;
-                double w[8];
-                w[0] = lg.wind[0 * pl + o];
-                w[1] = lg.wind[1 * pl + o];
-                w[2] = 0.0;
-                w[3] = lg.wind[2 * pl + o];
-                w[4] = lg.wind[3 * pl + o];
-                w[5] = lg.wind[4 * pl + o];
-                w[6] = 0.0;
-                w[7] = lg.wind[5 * pl + o];
-                const MemberConst mc = a.mc[mem];
-                if (mc.enabled) {
-                    const double ts = a.t[mem] + a.tfrac * a.dt[mem];
-                    const double tau = ts - mc.t0;
-                    if (tau >= 0.0 && tau <= mc.tact) {
-                        const double R = mc.r_in;
-                        const double Rc = tau * mc.v + R - mc.r_half;
-                        double arg = (Rc * Rc + R * R - mc.r_half * mc.r_half) / (2.0 * Rc * R);
-                        arg = arg > 1.0 ? 1.0 : (arg < -1.0 ? -1.0 : arg);
-                        double cd = lg.cosd[(size_t)mem * pl + o];
-                        cd = cd > 1.0 ? 1.0 : (cd < -1.0 ? -1.0 : cd);
-                        if (cd >= arg) {
-                            w[0] = mc.rho;
-                            w[1] = mc.v;
-                            w[4] = mc.p;
-                        }
-                    }
-                }
-                prim_to_cons(w, u, gs);
-            } else if (tk.type == SLAB_RESTRICT) {
-                const LevelGeo fg = a.geo[bd.level + 1];
-                double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
-                int gw[3];
-                for (int e = 0; e < 3; ++e) gw[e] = g[e] + tk.shift[e];
-                for (int o = 0; o < 8; ++o) {
-                    const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
-                    int fgi[3], fl[3], q[3];
-                    for (int e = 0; e < 3; ++e) {
-                        fgi[e] = 2 * gw[e] + oo[e];
-                        const int fb = fgi[e] / S::dim(e);
-                        q[e] = fb - tk.fbase[e];
-                        fl[e] = fgi[e] - fb * S::dim(e);
-                    }
-                    const int fslot = tk.src[q[e1] + 2 * q[e2]];
-                    const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
-                    for (int v = 0; v < 8; ++v)
-                        num[v] += wgt * a.U[cidx<S>(fslot, v, fl[0], fl[1], fl[2])];
-                    den += wgt;
-                }
-                for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
-            }
-            for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
-        }
+        const int d = tasks[it].face >> 1;          // uniform over the work-group
+        if (d == 0) slab_task<BI, BJ, BK, 0>(a, tasks + it, sP, sOk);
+        else if (d == 1) slab_task<BI, BJ, BK, 1>(a, tasks + it, sP, sOk);
+        else slab_task<BI, BJ, BK, 2>(a, tasks + it, sP, sOk);
     }
 }
 
 // ---------------------------------------------------------------------------
-// reflux at coarse-fine faces, then the CFL rate of the corrected blocks
+// reflux at coarse-fine faces, then the CFL rates of the corrected cells
 // ---------------------------------------------------------------------------
 template <int BI, int BJ, int BK>
 __device__ inline double cell_rate(const double u[8], const RecR &rr, const RecT &tt, const RecP &pp, const Gas &gs)
@@ -645,7 +721,9 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             }
             __syncthreads();
         }
-        // floors on the corrected cells (each once, after all its faces)
+        // floors on the corrected cells (each once, after all its faces) and
+        // their CFL rates; the stage kernel took the maximum over the other cells
+        double rmax = 0.0;
         for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
             const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
             const int mk = bd.reflux_mask;
@@ -656,21 +734,20 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
             apply_floors(u, a.gas, a.rho_floor, a.p_floor);
             for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];
-        }
-        __syncthreads();
-        if (a.want_rate) {
-            double rmax = 0.0;
-            for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
-                const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
-                double u[8];
-                for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
+            if (a.want_rate) {
                 const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
                                                        lg.p[bd.org[2] + k + 2], a.gas);
                 rmax = r > rmax ? r : rmax;
             }
-            const double m = block_max(rmax, sred);
-            if (threadIdx.x < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + threadIdx.x] = threadIdx.x == 0 ? m : 0.0;
         }
+        if (a.want_rate) {
+            const double m = block_max(rmax, sred);
+            if (threadIdx.x == 0) {
+                double &r0 = a.rate[(size_t)slot * KSPLIT_MAX];
+                r0 = m > r0 ? m : r0;
+            }
+        }
+        __syncthreads();
     }
 }
 

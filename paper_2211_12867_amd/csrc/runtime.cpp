@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
+#include <unordered_set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -128,11 +130,41 @@ uint64_t morton(int i, int j, int k)
     return key;
 }
 
-bool abi_order(const Key &a, const Key &b)
+// leaves in ascending (level, Morton) order (the ABI's block order)
+std::vector<Key> abi_sorted(const std::map<Key, int> &leaves)
 {
-    if (a.l != b.l) return a.l < b.l;
-    return morton(a.i, a.j, a.k) < morton(b.i, b.j, b.k);
+    std::vector<std::pair<std::pair<int, uint64_t>, Key>> v;
+    v.reserve(leaves.size());
+    for (auto &kv : leaves)
+        v.push_back({{kv.first.l, morton(kv.first.i, kv.first.j, kv.first.k)}, kv.first});
+    std::sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    std::vector<Key> out;
+    out.reserve(v.size());
+    for (auto &e : v) out.push_back(e.second);
+    return out;
 }
+
+// hash code of a block key (indices are below 2^20 on every level)
+inline uint64_t kcode(const Key &k)
+{
+    return ((uint64_t)k.l << 60) | ((uint64_t)(k.i & 0xFFFFF) << 40) | ((uint64_t)(k.j & 0xFFFFF) << 20) |
+           (uint64_t)(k.k & 0xFFFFF);
+}
+
+// hashed view of a leaf map: key -> local slot
+struct LeafIndex {
+    std::unordered_map<uint64_t, int> h;
+    explicit LeafIndex(const std::map<Key, int> &leaves)
+    {
+        h.reserve(2 * leaves.size() + 1);
+        for (auto &kv : leaves) h.emplace(kcode(kv.first), kv.second);
+    }
+    int find(const Key &k) const   // local slot, or -1
+    {
+        auto it = h.find(kcode(k));
+        return it == h.end() ? -1 : it->second;
+    }
+};
 
 struct Member {
     std::map<Key, int> leaves;     // leaf -> local slot
@@ -218,7 +250,7 @@ struct ic_sim {
     // graph
     hipGraphExec_t gexec = nullptr;
     bool graph_dirty = true;
-    int graph_stage_grid = 0;       // stage launch size the captured graph was made with
+    std::vector<int> graph_sig;     // launch sizes the captured graph was made with
     double graph_dt_fixed = -1.0;
     bool use_graph = true;
 
@@ -236,6 +268,9 @@ struct ic_sim {
     int tune_waves = 2, tune_grid = 0, tune_xcd = 0, tune_ksplit = 1;
     std::vector<hipEvent_t> ev;   // pairs
     long timed = 0;
+    // pinned staging area of the table uploads (Upload)
+    char *hstage = nullptr;
+    size_t hstage_cap = 0;
 
     int slot_of(int m, int local) const { return m * max_blocks + local; }
 };
@@ -431,32 +466,77 @@ bool wrap_idx(const ic_sim *s, int l, int idx[3])
     return true;
 }
 
+// Host-to-device uploads of small tables: queued, then staged in one pinned
+// buffer and enqueued as asynchronous copies on the sim's stream, with one
+// synchronisation at the end (a synchronous copy from pageable memory costs
+// tens of microseconds each).  Sources must stay alive until flush().
+struct Upload {
+    ic_sim *s;
+    struct Item { void *dst; const void *src; size_t n; };
+    std::vector<Item> q;
+    explicit Upload(ic_sim *sim) : s(sim) {}
+    void add(void *dst, const void *src, size_t n)
+    {
+        if (n) q.push_back({dst, src, n});
+    }
+    void flush()
+    {
+        size_t tot = 0;
+        for (const Item &e : q) tot += (e.n + 255) & ~(size_t)255;
+        if (tot > s->hstage_cap) {
+            HIPCHECK(hipStreamSynchronize(s->stream));
+            if (s->hstage) HIPCHECK(hipHostFree(s->hstage));
+            s->hstage = nullptr;
+            s->hstage_cap = 0;
+            const size_t cap = std::max(tot + tot / 2, (size_t)1 << 16);
+            if (hipHostMalloc((void **)&s->hstage, cap) != hipSuccess)
+                throw Error(IC_E_NOMEM, "pinned host allocation failed");
+            s->hstage_cap = cap;
+        }
+        size_t off = 0;
+        for (const Item &e : q) {
+            std::memcpy(s->hstage + off, e.src, e.n);
+            HIPCHECK(hipMemcpyAsync(e.dst, s->hstage + off, e.n, hipMemcpyHostToDevice, s->stream));
+            off += (e.n + 255) & ~(size_t)255;
+        }
+        HIPCHECK(hipStreamSynchronize(s->stream));   // the staging area may be reused now
+        q.clear();
+    }
+};
+
 void rebuild(ic_sim *s)
 {
     HIPCHECK(hipStreamSynchronize(s->stream));
     const int NS = s->nm * s->max_blocks;
-    s->hdesc.assign(NS, BlockDesc{});
+    // descriptors are uploaded for the used slot range of each member only
+    // (leaves take the lowest free slots); kernels read no other slot
+    if ((int)s->hdesc.size() != NS) s->hdesc.assign(NS, BlockDesc{});
+    std::vector<int> hi(s->nm, 0);
+    for (int m = 0; m < s->nm; ++m) {
+        for (auto &kv : s->mem[m].leaves) hi[m] = std::max(hi[m], kv.second + 1);
+        std::fill(s->hdesc.begin() + (size_t)m * s->max_blocks, s->hdesc.begin() + (size_t)m * s->max_blocks + hi[m],
+                  BlockDesc{});
+    }
     std::vector<int> items, mbeg(s->nm), mend(s->nm);
     std::vector<SlabTask> pass1;
     std::vector<std::vector<SlabTask>> prol(IC_MAX_LEVEL + 2);
-    std::map<std::pair<int, int>, int> regs;     // (slot, face) -> register
+    std::unordered_map<long, int> regs;          // slot * 8 + face -> register (numbered in order of first use)
     auto get_reg = [&](int slot, int face) {
-        auto it = regs.find({slot, face});
+        auto it = regs.find((long)slot * 8 + face);
         if (it != regs.end()) return it->second;
         const int r = (int)regs.size();
-        regs[{slot, face}] = r;
+        regs.emplace((long)slot * 8 + face, r);
         return r;
     };
     std::vector<RefluxTask> rf;
     int nslab = 0;
     for (int m = 0; m < s->nm; ++m) {
         Member &M = s->mem[m];
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
+        const std::vector<Key> keys = abi_sorted(M.leaves);
+        const LeafIndex idx(M.leaves);
         mbeg[m] = (int)items.size();
         for (const Key &key : keys) {
-            const int slot = s->slot_of(m, M.leaves[key]);
+            const int slot = s->slot_of(m, idx.find(key));
             items.push_back(slot);
             BlockDesc &bd = s->hdesc[slot];
             bd.level = key.l;
@@ -485,23 +565,22 @@ void rebuild(ic_sim *s)
                     }
                     continue;
                 }
-                auto same = M.leaves.find(Key{key.l, w[0], w[1], w[2]});
-                if (same != M.leaves.end()) {
-                    bd.nbr[f] = s->slot_of(m, same->second);
+                const int same = idx.find(Key{key.l, w[0], w[1], w[2]});
+                if (same >= 0) {
+                    bd.nbr[f] = s->slot_of(m, same);
                     continue;
                 }
-                auto coarse = key.l > 1 ? M.leaves.find(Key{key.l - 1, w[0] >> 1, w[1] >> 1, w[2] >> 1})
-                                        : M.leaves.end();
-                if (coarse != M.leaves.end()) {
-                    const int cslot = s->slot_of(m, coarse->second);
+                const Key ckey{key.l - 1, w[0] >> 1, w[1] >> 1, w[2] >> 1};
+                const int coarse = key.l > 1 ? idx.find(ckey) : -1;
+                if (coarse >= 0) {
+                    const int cslot = s->slot_of(m, coarse);
                     SlabTask tk{};
                     tk.type = SLAB_PROLONG;
                     tk.slab = nslab++;
                     tk.slot = slot;
                     tk.face = f;
                     tk.src[0] = cslot;
-                    const int corg[3] = {coarse->first.i * s->B[0], coarse->first.j * s->B[1],
-                                         coarse->first.k * s->B[2]};
+                    const int corg[3] = {ckey.i * s->B[0], ckey.j * s->B[1], ckey.k * s->B[2]};
                     for (int e = 0; e < 3; ++e) {
                         int cw = 0;
                         if (e == d && nbi[d] != w[d]) {
@@ -531,9 +610,9 @@ void rebuild(ic_sim *s)
                     c[d] = 2 * w[d] + (side ? 0 : 1);
                     c[e1] = 2 * w[e1] + (q & 1);
                     c[e2] = 2 * w[e2] + (q >> 1);
-                    auto fl = M.leaves.find(Key{key.l + 1, c[0], c[1], c[2]});
-                    if (fl == M.leaves.end()) throw Error(IC_E_INVALID, "forest violates 2:1 balance");
-                    tk.src[q] = s->slot_of(m, fl->second);
+                    const int fl = idx.find(Key{key.l + 1, c[0], c[1], c[2]});
+                    if (fl < 0) throw Error(IC_E_INVALID, "forest violates 2:1 balance");
+                    tk.src[q] = s->slot_of(m, fl);
                     rt.freg[q] = get_reg(tk.src[q], f ^ 1);
                 }
                 for (int e = 0; e < 3; ++e) {
@@ -596,13 +675,15 @@ void rebuild(ic_sim *s)
     grow(s->rf_tasks, rf.size() + 1);
     grow(s->rf_blocks, rfb.size() + 2);
 
-    HIPCHECK(hipMemcpy(s->desc.p, s->hdesc.data(), NS * sizeof(BlockDesc), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(s->items.p, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(s->nitems.p, &s->n_items, sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(s->mbeg.p, mbeg.data(), s->nm * sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(s->mend.p, mend.data(), s->nm * sizeof(int), hipMemcpyHostToDevice));
-    if (!all.empty())
-        HIPCHECK(hipMemcpy(s->slab_tasks.p, all.data(), all.size() * sizeof(SlabTask), hipMemcpyHostToDevice));
+    Upload up(s);
+    for (int m = 0; m < s->nm; ++m)
+        up.add(s->desc.p + (size_t)m * s->max_blocks, s->hdesc.data() + (size_t)m * s->max_blocks,
+               hi[m] * sizeof(BlockDesc));
+    up.add(s->items.p, items.data(), items.size() * sizeof(int));
+    up.add(s->nitems.p, &s->n_items, sizeof(int));
+    up.add(s->mbeg.p, mbeg.data(), s->nm * sizeof(int));
+    up.add(s->mend.p, mend.data(), s->nm * sizeof(int));
+    up.add(s->slab_tasks.p, all.data(), all.size() * sizeof(SlabTask));
     std::vector<int> ranges(2 * (IC_MAX_LEVEL + 2), 0);
     for (int l = 0; l <= IC_MAX_LEVEL + 1; ++l) {
         if (l == 0 || (l >= 2 && l <= s->max_level)) {
@@ -618,12 +699,11 @@ void rebuild(ic_sim *s)
     // 2:1 balance over all 26 neighbours rules out.
     ranges[2] = s->pass_lo[2];
     ranges[3] = s->pass_hi[s->max_level];
-    HIPCHECK(hipMemcpy(s->slab_ranges.p, ranges.data(), ranges.size() * sizeof(int), hipMemcpyHostToDevice));
-    if (!rf.empty()) {
-        HIPCHECK(hipMemcpy(s->rf_tasks.p, rf.data(), rf.size() * sizeof(RefluxTask), hipMemcpyHostToDevice));
-        HIPCHECK(hipMemcpy(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int), hipMemcpyHostToDevice));
-    }
-    HIPCHECK(hipMemcpy(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int), hipMemcpyHostToDevice));
+    up.add(s->slab_ranges.p, ranges.data(), ranges.size() * sizeof(int));
+    up.add(s->rf_tasks.p, rf.data(), rf.size() * sizeof(RefluxTask));
+    up.add(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int));
+    up.add(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int));
+    up.flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -668,14 +748,28 @@ int stage_grid(const ic_sim *s)
     return s->tune_grid > 0 ? std::min(n, s->tune_grid) : n;
 }
 
+// ghost-slab launches: one work-group per task of the pass (the kernels
+// stride over the device-side task ranges, so any size is correct)
+int slab_grid(const ic_sim *s, int pass)
+{
+    const int n = pass == 0 ? s->pass_hi[0] - s->pass_lo[0]
+                            : (s->max_level > 1 ? s->pass_hi[s->max_level] - s->pass_lo[2] : 0);
+    return grid_for(n, 8192);
+}
+
+// launch sizes of a step; a captured step graph is re-made when they change
+std::vector<int> launch_sig(const ic_sim *s)
+{
+    return {stage_grid(s), slab_grid(s, 0), slab_grid(s, 1), s->any_reflux ? grid_for(s->n_rf_blocks, 8192) : 0};
+}
+
 void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
 {
     KArgs a = base_args(s);
     a.U = Uin;
     a.tfrac = tfrac;
-    const int g = grid_for(s->n_slabs + 1, 8192);
-    s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p);
-    if (s->max_level > 1) s->L.slabs(dim3(g), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2);
+    s->L.slabs(dim3(slab_grid(s, 0)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p);
+    if (s->max_level > 1) s->L.slabs(dim3(slab_grid(s, 1)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2);
 }
 
 void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, int want_rate)
@@ -700,7 +794,7 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
         s->L.stage(dim3(g), s->stream, a, s->tune_waves);
     }
     if (s->any_reflux) {
-        const int gr = grid_for(s->nm * s->max_blocks, 8192);
+        const int gr = grid_for(s->n_rf_blocks, 8192);
         s->L.reflux(dim3(gr), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
     }
 }
@@ -709,7 +803,7 @@ void enqueue_rate(ic_sim *s)
 {
     KArgs a = base_args(s);
     a.U = s->U.p;
-    s->L.rate(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a);
+    s->L.rate(dim3(grid_for(s->n_items, 16384)), s->stream, a);
 }
 
 void enqueue_sample(ic_sim *s, int record)
@@ -739,7 +833,7 @@ void run_step(ic_sim *s, double dt_fixed_code, bool record)
         return;
     }
     if (s->graph_dirty || s->gexec == nullptr || s->graph_dt_fixed != dt_fixed_code ||
-        s->graph_stage_grid != stage_grid(s)) {
+        s->graph_sig != launch_sig(s)) {
         if (s->gexec) HIPCHECK(hipGraphExecDestroy(s->gexec));
         s->gexec = nullptr;
         hipGraph_t g;
@@ -750,7 +844,7 @@ void run_step(ic_sim *s, double dt_fixed_code, bool record)
         HIPCHECK(hipGraphDestroy(g));
         s->graph_dirty = false;
         s->graph_dt_fixed = dt_fixed_code;
-        s->graph_stage_grid = stage_grid(s);
+        s->graph_sig = launch_sig(s);
     }
     (void)record;
     HIPCHECK(hipGraphLaunch(s->gexec, s->stream));
@@ -916,7 +1010,9 @@ void update_sample_desc(ic_sim *s)
         if (!build_sample(s, m, s->sample_point[0], s->sample_point[1], s->sample_point[2], &sd[m]))
             sd[m].valid = 0;
     }
-    HIPCHECK(hipMemcpy(s->sdesc.p, sd.data(), s->nm * sizeof(SampleDesc), hipMemcpyHostToDevice));
+    Upload up(s);
+    up.add(s->sdesc.p, sd.data(), s->nm * sizeof(SampleDesc));
+    up.flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -926,8 +1022,10 @@ struct Forest {
     const ic_sim *s;
     const std::map<Key, int> &leaves;
     int maxl;
+    LeafIndex index;
+    Forest(const ic_sim *s_, const std::map<Key, int> &l, int m) : s(s_), leaves(l), maxl(m), index(l) {}
     int nblk(int l, int d) const { return s->nb[d] << (l - 1); }
-    bool has(const Key &k) const { return leaves.count(k) != 0; }
+    bool has(const Key &k) const { return index.find(k) >= 0; }
     bool wrap(int l, int idx[3]) const { return wrap_idx(s, l, idx); }
     // closures of a and b touch (face, edge or corner), through periodic directions
     bool touch(const Key &a, const Key &b) const
@@ -949,9 +1047,8 @@ struct Forest {
         return true;
     }
     // leaves at exactly `level` whose closure touches `leaf`
-    std::vector<Key> touching(const Key &leaf, int level, const std::map<Key, int> *set = nullptr) const
+    std::vector<Key> touching(const Key &leaf, int level) const
     {
-        const std::map<Key, int> &S = set ? *set : leaves;
         std::vector<Key> out;
         int lo[3], hi[3];
         const int li[3] = {leaf.i, leaf.j, leaf.k};
@@ -968,10 +1065,9 @@ struct Forest {
                     int w[3] = {i, j, k};
                     if (!wrap(level, w)) continue;
                     Key c{level, w[0], w[1], w[2]};
-                    if (!S.count(c) || c == leaf) continue;
+                    if (!has(c) || c == leaf) continue;
                     if (std::find(out.begin(), out.end(), c) != out.end()) continue;
-                    Forest F2{s, S, maxl};
-                    if (F2.touch(leaf, c)) out.push_back(c);
+                    if (touch(leaf, c)) out.push_back(c);
                 }
         return out;
     }
@@ -1037,63 +1133,92 @@ std::string describe_bad(ic_sim *s, int m, int slot, int cell)
 }
 
 
-void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int buffer_blocks,
+void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> &flags_in, int buffer_blocks,
                    std::vector<MoveTask> &moves, std::vector<int> &to_free)
 {
     Member &M = s->mem[m];
     Forest F{s, M.leaves, s->max_level};
-    std::map<Key, int> f;
+    // flags per leaf (hashed); every pass below walks the leaves in key order
+    std::unordered_map<uint64_t, int> f;
+    f.reserve(2 * M.leaves.size() + 1);
     for (auto &kv : M.leaves) {
-        auto it = flags_in.find(kv.first);
+        auto it = flags_in.find(kcode(kv.first));
         int v = it == flags_in.end() ? 0 : it->second;
         if (v == 1 && kv.first.l >= s->max_level) v = 0;
         if (v == -1 && kv.first.l <= 1) v = 0;
-        f[kv.first] = v;
+        f[kcode(kv.first)] = v;
     }
     // buffer
     std::vector<Key> orig;
-    for (auto &kv : f) if (kv.second == 1) orig.push_back(kv.first);
+    for (auto &kv : M.leaves) if (f[kcode(kv.first)] == 1) orig.push_back(kv.first);
     for (const Key &b : orig)
         for (int d = 0; d < 3; ++d)
             for (int side = 0; side < 2; ++side)
                 for (const Key &n : F.face_neighbours(b, d, side)) {
-                    if (buffer_blocks && n.l < s->max_level && n.l <= b.l) f[n] = 1;
-                    else if (f[n] == -1) f[n] = 0;
+                    int &fn = f[kcode(n)];
+                    if (buffer_blocks && n.l < s->max_level && n.l <= b.l) fn = 1;
+                    else if (fn == -1) fn = 0;
                 }
     // 2:1 closure
     bool changed = true;
     while (changed) {
         changed = false;
-        for (auto &kv : f) {
-            if (kv.second != 1 || kv.first.l < 2) continue;
-            for (const Key &n : F.touching(kv.first, kv.first.l - 1))
-                if (f[n] != 1) {
-                    f[n] = 1;
+        for (auto &kv : M.leaves) {
+            const Key &b = kv.first;
+            if (b.l < 2 || f[kcode(b)] != 1) continue;
+            for (const Key &n : F.touching(b, b.l - 1)) {
+                int &fn = f[kcode(n)];
+                if (fn != 1) {
+                    fn = 1;
                     changed = true;
                 }
+            }
         }
     }
     std::vector<Key> refined;
-    for (auto &kv : f) if (kv.second == 1) refined.push_back(kv.first);
-    std::map<Key, int> post;
-    for (auto &kv : M.leaves) if (f[kv.first] != 1) post[kv.first] = kv.second;
-    for (const Key &b : refined)
-        for (int o = 0; o < 8; ++o)
-            post[Key{b.l + 1, 2 * b.i + (o & 1), 2 * b.j + ((o >> 1) & 1), 2 * b.k + ((o >> 2) & 1)}] = -1;
-    std::map<Key, std::vector<Key>> parents;
-    for (auto &kv : f)
-        if (kv.second == -1) {
+    for (auto &kv : M.leaves) if (f[kcode(kv.first)] == 1) refined.push_back(kv.first);
+    // internal nodes (strict ancestors of leaves) of the forest after the refinements
+    std::unordered_set<uint64_t> internal;
+    internal.reserve(2 * M.leaves.size() + 8 * refined.size() + 1);
+    auto add_ancestors = [&](Key a) {
+        while (a.l > 1) {
+            a = Key{a.l - 1, a.i >> 1, a.j >> 1, a.k >> 1};
+            if (!internal.insert(kcode(a)).second) break;   // its ancestors are in already
+        }
+    };
+    for (auto &kv : M.leaves)
+        if (f[kcode(kv.first)] != 1) add_ancestors(kv.first);
+    for (const Key &b : refined) {
+        internal.insert(kcode(b));
+        add_ancestors(b);
+    }
+    // coarsening: complete sibling octets of COARSEN leaves, if the parent touches
+    // no leaf two or more levels finer in the refined forest.  Such a leaf exists
+    // exactly when a child-level cell touching the parent (indices 2p-1 .. 2p+2
+    // per direction) is an internal node: its leaves tile it, so one of them
+    // meets the shared boundary, and every such leaf lies in such a cell.
+    std::map<Key, int> parents;                   // parent -> COARSEN children
+    for (auto &kv : M.leaves)
+        if (f[kcode(kv.first)] == -1) {
             const Key &b = kv.first;
-            parents[Key{b.l - 1, b.i >> 1, b.j >> 1, b.k >> 1}].push_back(b);
+            parents[Key{b.l - 1, b.i >> 1, b.j >> 1, b.k >> 1}]++;
         }
     std::vector<Key> coarsened;
-    Forest P{s, post, s->max_level};
     for (auto &kv : parents) {
-        if (kv.second.size() != 8) continue;
+        if (kv.second != 8) continue;
+        const Key &p = kv.first;
         bool ok = true;
-        for (int l = kv.first.l + 2; l <= s->max_level && ok; ++l)
-            if (!P.touching(kv.first, l, &post).empty()) ok = false;
-        if (ok) coarsened.push_back(kv.first);
+        if (p.l + 2 <= s->max_level) {
+            const int cl = p.l + 1;
+            for (int dk = -1; dk <= 2 && ok; ++dk)
+                for (int dj = -1; dj <= 2 && ok; ++dj)
+                    for (int di = -1; di <= 2 && ok; ++di) {
+                        int w[3] = {2 * p.i + di, 2 * p.j + dj, 2 * p.k + dk};
+                        if (!wrap_idx(s, cl, w)) continue;
+                        if (internal.count(kcode(Key{cl, w[0], w[1], w[2]}))) ok = false;
+                    }
+        }
+        if (ok) coarsened.push_back(p);
     }
     // capacity check
     long nnew = (long)M.leaves.size() + 7 * (long)refined.size() - 7 * (long)coarsened.size();
@@ -1107,8 +1232,7 @@ void regrid_member(ic_sim *s, int m, const std::map<Key, int8_t> &flags_in, int 
         M.free_slots.pop_back();
         return q;
     };
-    std::map<Key, int> newleaves;
-    for (auto &kv : M.leaves) newleaves[kv.first] = kv.second;
+    std::map<Key, int> newleaves(M.leaves);
     for (const Key &p : refined) {
         const int ps = M.leaves.at(p);
         for (int o = 0; o < 8; ++o) {
@@ -1172,7 +1296,7 @@ void run_indicator(ic_sim *s, std::vector<int8_t> &fl, int level_cap)
     p.dlon_e = s->amr.dlon_earth_deg * deg;
     p.dclt_e = s->amr.dclt_earth_deg * deg;
     p.dlon_c = s->amr.dlon_cme_deg * deg;
-    s->L.indicator(dim3(grid_for(s->nm * s->max_blocks, 16384)), s->stream, a, s->flags.p, p);
+    s->L.indicator(dim3(grid_for(s->n_items, 16384)), s->stream, a, s->flags.p, p);
     HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
 }
@@ -1293,19 +1417,20 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
     std::vector<int> to_free;
     for (int m = 0; m < s->nm; ++m) {
         Member &M = s->mem[m];
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
-        std::map<Key, int8_t> f;
+        const std::vector<Key> keys = abi_sorted(M.leaves);
+        std::unordered_map<uint64_t, int8_t> f;
+        f.reserve(2 * keys.size() + 1);
         for (size_t q = 0; q < keys.size(); ++q) {
-            const int slot = s->slot_of(m, M.leaves[keys[q]]);
-            f[keys[q]] = user_flags ? user_flags[(size_t)m * s->max_blocks + q] : fl[slot];
+            const int slot = s->slot_of(m, M.leaves.at(keys[q]));
+            f[kcode(keys[q])] = user_flags ? user_flags[(size_t)m * s->max_blocks + q] : fl[slot];
         }
         regrid_member(s, m, f, s->amr.buffer_blocks, moves, to_free);
     }
     if (!moves.empty()) {
         s->moves.alloc(moves.size());
-        HIPCHECK(hipMemcpy(s->moves.p, moves.data(), moves.size() * sizeof(MoveTask), hipMemcpyHostToDevice));
+        Upload up(s);
+        up.add(s->moves.p, moves.data(), moves.size() * sizeof(MoveTask));
+        up.flush();
         KArgs a = base_args(s);
         a.U = s->U.p;
         s->L.move(dim3(grid_for((int)moves.size(), 16384)), s->stream, a, s->U.p, s->moves.p, (int)moves.size());
@@ -1641,6 +1766,7 @@ void ic_destroy(ic_sim *s)
     s->slab_ranges.release(); s->rf_tasks.release(); s->rf_blocks.release(); s->rf_nblocks.release();
     s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
     s->ring_count.release();
+    if (s->hstage) (void)hipHostFree(s->hstage);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -1721,9 +1847,7 @@ void leaf_indicator(ic_sim *s, int member, int8_t *out, int n, int level_cap, bo
     fill_ghosts(s, s->U.p, 0.0);
     std::vector<int8_t> fl((size_t)s->nm * s->max_blocks);
     run_indicator(s, fl, level_cap);
-    std::vector<Key> keys;
-    for (auto &kv : M.leaves) keys.push_back(kv.first);
-    std::sort(keys.begin(), keys.end(), abi_order);
+    const std::vector<Key> keys = abi_sorted(M.leaves);
     for (size_t q = 0; q < keys.size(); ++q) {
         const int8_t f = fl[s->slot_of(member, M.leaves[keys[q]])];
         out[q] = hot ? (int8_t)(f == IC_FLAG_REFINE) : f;
@@ -1748,9 +1872,7 @@ ic_status ic_eval_window(ic_sim *s, int member, int8_t *in, int n)
         if (member < 0 || member >= s->nm || !in) throw Error(IC_E_INVALID, "bad member or buffer");
         Member &M = s->mem[member];
         if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "buffer too small");
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
+        const std::vector<Key> keys = abi_sorted(M.leaves);
         for (size_t q = 0; q < keys.size(); ++q) in[q] = leaf_in_windows(s, member, keys[q]) ? 1 : 0;
     });
 }
@@ -1825,9 +1947,7 @@ ic_status ic_get_blocks(ic_sim *s, int member, int32_t *lvl_ijk, int *n_inout)
         check_sim(s);
         if (member < 0 || member >= s->nm || !n_inout) throw Error(IC_E_INVALID, "bad argument");
         Member &M = s->mem[member];
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
+        const std::vector<Key> keys = abi_sorted(M.leaves);
         if (!lvl_ijk || *n_inout < (int)keys.size()) {
             *n_inout = (int)keys.size();
             throw Error(IC_E_INVALID, "block buffer too small");
@@ -1848,9 +1968,7 @@ ic_status ic_get_state(ic_sim *s, int member, double *host_U, size_t n_doubles)
         check_sim(s);
         if (member < 0 || member >= s->nm || !host_U) throw Error(IC_E_INVALID, "bad argument");
         Member &M = s->mem[member];
-        std::vector<Key> keys;
-        for (auto &kv : M.leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
+        const std::vector<Key> keys = abi_sorted(M.leaves);
         const size_t per = (size_t)8 * s->NC;
         if (n_doubles < keys.size() * per) throw Error(IC_E_INVALID, "state buffer too small");
         HIPCHECK(hipStreamSynchronize(s->stream));
@@ -1983,9 +2101,7 @@ ic_status ic_eval_learned(ic_sim *s, int member, float *prob, int8_t *flags, int
         std::vector<float> p(nl);
         HIPCHECK(hipStreamSynchronize(s->stream));
         HIPCHECK(hipMemcpy(p.data(), s->mlp.prob + mb[member], nl * sizeof(float), hipMemcpyDeviceToHost));
-        std::vector<Key> keys;
-        for (auto &kv : s->mem[member].leaves) keys.push_back(kv.first);
-        std::sort(keys.begin(), keys.end(), abi_order);
+        const std::vector<Key> keys = abi_sorted(s->mem[member].leaves);
         for (int q = 0; q < nl; ++q) {
             if (prob) prob[q] = p[q];
             if (flags)
