@@ -318,11 +318,20 @@ typedef struct {
  * cache_path (a text file, one result per line; NULL = no cache), else time
  * every candidate on the current state (reps launches each; the state is not
  * changed) and append the winner to the cache.  The choice applies to later
- * steps; out may be NULL. */
+ * steps; out may be NULL.  The sim remembers the result for this work-list
+ * size (and reads the cache's results for other sizes): after each regrid the
+ * schedule of the new size is used, or, for a size without one, two waves per
+ * SIMD, one work-group per work item and the smallest k-split giving at least
+ * 512 work-groups.  Without any tuning call that rule applies from the start. */
 ic_status ic_autotune(ic_sim *sim, const char *cache_path, int reps, ic_tune_info *out);
 
-/* Force a schedule (waves_per_simd, grid, xcd_order of *tune). */
+/* Force a schedule (waves_per_simd, grid, xcd_order, ksplit of *tune); it is
+ * kept across regrids until the next ic_autotune. */
 ic_status ic_set_tuning(ic_sim *sim, const ic_tune_info *tune);
+
+/* The schedule in force (waves_per_simd, grid, xcd_order, ksplit; the other
+ * fields are zero). */
+ic_status ic_get_tuning(ic_sim *sim, ic_tune_info *tune);
 
 /* Code-unit scales in SI: [0] length m, [1] speed m/s, [2] time s, [3]
  * density kg/m^3, [4] pressure Pa, [5] field T. */

@@ -108,7 +108,7 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
-           "ic_last_error")
+           "ic_get_tuning", "ic_last_error")
 
 
 def _load():
@@ -156,6 +156,7 @@ def _load():
     L.ic_mlp_infer.argtypes = [fp, ctypes.c_long, fp, fp, fp, fp]
     L.ic_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int, P(TuneInfo)]
     L.ic_set_tuning.argtypes = [vp, P(TuneInfo)]
+    L.ic_get_tuning.argtypes = [vp, P(TuneInfo)]
     L.ic_pool_capacity.argtypes = [vp]
     L.ic_pool_capacity.restype = ctypes.c_int
     L.ic_last_error.restype = ctypes.c_char_p
@@ -422,8 +423,15 @@ class Sim:
         return t.as_dict()
 
     def set_tuning(self, waves_per_simd=2, grid=0, xcd_order=0, ksplit=1):
+        """Force a schedule; it holds across regrids until the next autotune."""
         t = TuneInfo(waves_per_simd, grid, xcd_order, 0.0, 0.0, 0, 0, ksplit)
         _check(lib.ic_set_tuning(self.h, ctypes.byref(t)))
+
+    def tuning(self):
+        """The schedule in force: (waves_per_simd, grid, xcd_order, ksplit)."""
+        t = TuneInfo()
+        _check(lib.ic_get_tuning(self.h, ctypes.byref(t)))
+        return (t.waves_per_simd, t.grid, t.xcd_order, t.ksplit)
 
     # --- learned flags ------------------------------------------------------------
     def features(self, member=0):

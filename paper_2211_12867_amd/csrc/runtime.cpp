@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -266,6 +267,10 @@ struct ic_sim {
     // the register allocation, launch grid (0 = one work-group per work item),
     // XCD-contiguous work order
     int tune_waves = 2, tune_grid = 0, tune_xcd = 0, tune_ksplit = 1;
+    // measured schedules by log2 bucket of the work-list size {waves, grid, xcd, ksplit};
+    // pinned: ic_set_tuning's schedule holds whatever the work list
+    std::map<int, std::array<int, 4>> tuned;
+    bool tune_pinned = false;
     std::vector<hipEvent_t> ev;   // pairs
     long timed = 0;
     // pinned staging area of the table uploads (Upload)
@@ -464,6 +469,35 @@ bool wrap_idx(const ic_sim *s, int l, int idx[3])
         }
     }
     return true;
+}
+
+int items_bucket(const ic_sim *s)         // log2 bucket of the work-list size
+{
+    int b = 0;
+    while ((1 << (b + 1)) <= std::max(1, s->n_items)) ++b;
+    return b;
+}
+
+void apply_tuning(ic_sim *s, int waves, int grid, int xcd, int ksplit);
+
+// Stage-kernel schedule for the current work list: the one ic_autotune measured
+// for its size bucket, else two waves per SIMD, one work-group per work item
+// and a k-split until there are >= 512 work-groups (two per CU).  A schedule
+// set by ic_set_tuning is kept.
+void select_schedule(ic_sim *s)
+{
+    if (s->tune_pinned) return;
+    int w = 2, g = 0, x = 0, ks = 1;
+    auto it = s->tuned.find(items_bucket(s));
+    if (it != s->tuned.end()) {
+        w = it->second[0];
+        g = it->second[1];
+        x = it->second[2];
+        ks = it->second[3];
+    } else {
+        while (ks < 4 && 2 * ks <= s->B[2] && s->n_items * ks < 512) ks *= 2;
+    }
+    if (w != s->tune_waves || g != s->tune_grid || x != s->tune_xcd || ks != s->tune_ksplit) apply_tuning(s, w, g, x, ks);
 }
 
 // Host-to-device uploads of small tables: queued, then staged in one pinned
@@ -704,6 +738,7 @@ void rebuild(ic_sim *s)
     up.add(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int));
     up.add(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int));
     up.flush();
+    select_schedule(s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1517,19 +1552,18 @@ void set_initial_state(ic_sim *s)
 // C ABI
 // ===========================================================================
 namespace {
-std::string tune_key(const ic_sim *s)
+// cache key of a schedule: device, block shape, variables; then "/items2^<bucket>"
+std::string tune_prefix(const ic_sim *s)
 {
     int dev = 0;
     hipDeviceProp_t prop{};
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         throw Error(IC_E_DEVICE, "hipGetDeviceProperties failed");
-    int bucket = 0;                     // work items, log2 bucket
-    while ((1 << (bucket + 1)) <= std::max(1, s->n_items)) ++bucket;
     std::string arch = prop.gcnArchName;
     for (auto &c : arch)
         if (c == ' ') c = '_';
     return arch + "/cu" + std::to_string(prop.multiProcessorCount) + "/b" + std::to_string(s->B[0]) + "x" +
-           std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar8/items2^" + std::to_string(bucket);
+           std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar8/items2^";
 }
 
 void apply_tuning(ic_sim *s, int waves, int grid, int xcd, int ksplit)
@@ -2172,6 +2206,20 @@ ic_status ic_set_tuning(ic_sim *s, const ic_tune_info *t)
         if (!t) throw Error(IC_E_INVALID, "null tuning");
         HIPCHECK(hipStreamSynchronize(s->stream));
         apply_tuning(s, t->waves_per_simd, t->grid, t->xcd_order, t->ksplit);
+        s->tune_pinned = true;
+    });
+}
+
+ic_status ic_get_tuning(ic_sim *s, ic_tune_info *t)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (!t) throw Error(IC_E_INVALID, "null tuning");
+        *t = ic_tune_info{};
+        t->waves_per_simd = s->tune_waves;
+        t->grid = s->tune_grid;
+        t->xcd_order = s->tune_xcd;
+        t->ksplit = s->tune_ksplit;
     });
 }
 
@@ -2181,16 +2229,25 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
         check_sim(s);
         if (reps < 1) throw Error(IC_E_INVALID, "reps must be >= 1");
         HIPCHECK(hipStreamSynchronize(s->stream));
-        const std::string key = tune_key(s);
+        const std::string prefix = tune_prefix(s);
+        const int bucket = items_bucket(s);
+        const std::string key = prefix + std::to_string(bucket);
         ic_tune_info res{};
-        // cache: one line per result, "key waves grid xcd ksplit ms default_ms"; the last match wins
+        // cache: one line per result, "key waves grid xcd ksplit ms default_ms"; the last match
+        // wins.  Entries of other work-list sizes on this device and block shape are kept
+        // for the schedule choice after regrids.
         if (cache_path) {
             std::FILE *f = std::fopen(cache_path, "r");
             if (f) {
                 char k[512];
                 int w, g, x, ks;
                 double ms, dms;
-                while (std::fscanf(f, "%511s %d %d %d %d %lf %lf", k, &w, &g, &x, &ks, &ms, &dms) == 7)
+                while (std::fscanf(f, "%511s %d %d %d %d %lf %lf", k, &w, &g, &x, &ks, &ms, &dms) == 7) {
+                    const std::string ks_(k);
+                    if (ks_.compare(0, prefix.size(), prefix) == 0 && ks_.size() > prefix.size() &&
+                        (w == 1 || w == 2) && g >= 0 && (x == 0 || x == 1) && (ks == 1 || ks == 2 || ks == 4) &&
+                        ks <= s->B[2])
+                        s->tuned[std::atoi(ks_.c_str() + prefix.size())] = {w, g, x, ks};
                     if (key == k) {
                         res.waves_per_simd = w;
                         res.grid = g;
@@ -2200,6 +2257,7 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
                         res.default_ms = dms;
                         res.from_cache = 1;
                     }
+                }
                 std::fclose(f);
             }
         }
@@ -2242,6 +2300,8 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
             }
         }
         apply_tuning(s, res.waves_per_simd, res.grid, res.xcd_order, res.ksplit);
+        s->tuned[bucket] = {res.waves_per_simd, res.grid, res.xcd_order, res.ksplit};
+        s->tune_pinned = false;
         if (out) *out = res;
     });
 }

@@ -10,7 +10,10 @@
 - ic_autotune leaves the state and time untouched, picks a schedule no
   slower than the default on its own measurement, and returns the same
   choice from its cache on the second call;
-- invalid schedules are rejected.
+- invalid schedules are rejected;
+- the schedule follows the work-list size across regrids: the rule for
+  untuned sizes, ic_autotune's result for its own size, ic_set_tuning's
+  schedule until the next ic_autotune.
 """
 import numpy as np
 import pytest
@@ -101,3 +104,30 @@ def test_ksplit_amr_wedge_matches_oracle():
         assert gpu.blocks() == ora.blocks()
     assert max(b[0] for b in ora.blocks()) >= 2
     gpu.close()
+
+
+def test_schedule_follows_the_work_list_size():
+    ic = _ic()
+    w = workload("learned_flags")               # 40 base blocks of 12^3
+    grid = dict(as_dict(w.grid), max_level=3)
+    sim = ic.Sim(grid, as_dict(w.wind), [as_dict(w.cmes[0])], as_dict(w.amr), max_blocks=4096)
+    refine = lambda: sim.regrid([np.ones(len(sim.blocks()), np.int8)])
+    coarsen = lambda: sim.regrid([np.full(len(sim.blocks()), -1, np.int8)])
+    # untuned: one work-group per item, k-split until >= 512 work-groups
+    assert len(sim.blocks()) == 40 and sim.tuning() == (2, 0, 0, 4)
+    refine()
+    assert len(sim.blocks()) == 320 and sim.tuning() == (2, 0, 0, 2)
+    refine()
+    assert len(sim.blocks()) == 2560 and sim.tuning() == (2, 0, 0, 1)
+    r = sim.autotune(reps=1)
+    tuned = (r["waves_per_simd"], r["grid"], r["xcd_order"], r["ksplit"])
+    assert sim.tuning() == tuned
+    coarsen()
+    assert len(sim.blocks()) == 320 and sim.tuning() == (2, 0, 0, 2)
+    refine()
+    assert len(sim.blocks()) == 2560 and sim.tuning() == tuned
+    sim.set_tuning(1, 1024, 1, 4)
+    coarsen()
+    assert len(sim.blocks()) == 320 and sim.tuning() == (1, 1024, 1, 4)
+    sim.step()
+    sim.close()
