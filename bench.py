@@ -32,7 +32,7 @@ BYTES_PER_CELL_LAUNCH = 160.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("csrc/kernels.hip", "csrc/physics.h", "csrc/kernels.h", "csrc/device.h", "build.py"):
+    for f in ("csrc/stage.hip", "csrc/common.h", "csrc/physics.h", "csrc/kernels.h", "csrc/device.h", "build.py"):
         with open(os.path.join(ROOT, "paper_2211_12867_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libicarus.so")
-SOURCES = ["kernels.hip", "mlp.hip", "runtime.cpp"]
+SOURCES = ["stage.hip", "kernels.hip", "mlp.hip", "runtime.cpp"]
 ARCH = os.environ.get("ICARUS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

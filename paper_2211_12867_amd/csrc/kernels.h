@@ -108,7 +108,7 @@ struct IndicatorParams {
     double lon_e, clt_e, dlon_e, dclt_e, dlon_c;   // radians
 };
 
-// Launch wrappers per block shape (kernels.hip); the runtime calls these.
+// Launch wrappers per block shape (kernels.hip, stage.hip); the runtime calls these.
 struct Launchers {
     void (*stage)(dim3, hipStream_t, const KArgs &, int waves);
     void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *);
@@ -123,8 +123,9 @@ void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, 
                double dt_fixed, const double *tend, double *dt_last);
 void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm);
 
-// kernel entry points (defined in kernels.hip)
+// kernel entry points (stage.hip: k_stage and its launcher; kernels.hip: the rest)
 template <int BI, int BJ, int BK, int W> __global__ void k_stage(KArgs a);
+template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves);
 template <int BI, int BJ, int BK> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
 template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);

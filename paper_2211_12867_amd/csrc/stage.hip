@@ -1,0 +1,370 @@
+// stage.hip -- the fused finite-volume stage kernel of the Icarus hot path (gfx950, CDNA4).
+//
+// k_stage is the fused finite-volume stage (paper Sect. 2.1: TVDLF with a
+// Woodward-type limiter, second order): a work-group marches along k (phi)
+// through a leaf block (or through 1/2 or 1/4 of it, for short work lists).
+// For each k-plane the primitives of the plane and of its two-cell i/j halos
+// sit in LDS; every r- and theta-face flux of the plane is computed once by
+// one thread and kept in LDS; the phi-face fluxes are computed once per column
+// in registers (each of the first 192 or fewer threads owns one (i, j) column
+// and carries the previous plane's flux, face state and the next plane's
+// primitives).  The update adds the flux differences with the finite-volume
+// metric, the hoop, Coriolis, centrifugal and gravity sources, applies the
+// floors and writes U_out = U_base + alpha dt L(U).  Meanwhile the last wave,
+// which owns no column, copies the next plane's halo and the column plane two
+// ahead from HBM into LDS asynchronously.  Halo cells come from neighbouring
+// blocks (same level), the block's own edge (outflow) or ghost slabs (inner
+// boundary, coarse-fine faces).
+#include "common.h"
+
+// ---------------------------------------------------------------------------
+// fused stage kernel
+// ---------------------------------------------------------------------------
+
+// Left and right states at the face between cells c1 and c2 of an LDS line
+// c0 c1 c2 c3 (cell stride cs, variable stride vs), reconstructed one
+// variable at a time so that only the two face states stay live.  The
+// zero-slope fallback of a cell applies when one of its two face densities or
+// pressures is not positive.
+template <class Rec>
+DEV void face_states(const double *p, int cs, int vs, const Rec &r1, const Rec &r2, double L[8], double R[8])
+{
+    bool ok1 = true, ok2 = true;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double a = p[v * vs], b = p[v * vs + cs], c = p[v * vs + 2 * cs], d = p[v * vs + 3 * cs];
+        const double s1 = mc_slope(a, b, c, r1.idm, r1.idp, r1.idc);
+        const double s2 = mc_slope(b, c, d, r2.idm, r2.idp, r2.idc);
+        L[v] = b + s1 * r1.hp;
+        R[v] = c - s2 * r2.hm;
+        if (v == 0 || v == 4) {
+            ok1 = ok1 && (b - s1 * r1.hm > 0.0) && (L[v] > 0.0);
+            ok2 = ok2 && (R[v] > 0.0) && (c + s2 * r2.hp > 0.0);
+        }
+    }
+    if (!ok1) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) L[v] = p[v * vs + cs];
+    }
+    if (!ok2) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) R[v] = p[v * vs + 2 * cs];
+    }
+}
+
+// Cell t of the 4 (BI + BJ) r/theta halo cells of plane k (two layers on each
+// side, r-halo first): its (i, j).
+template <int BI, int BJ>
+DEV void halo_cell(int t, int &i, int &j)
+{
+    if (t < 4 * BJ) {                 // r-direction halo
+        const int side = t / (2 * BJ), rem = t % (2 * BJ);
+        const int l = rem / BJ;
+        j = rem % BJ;
+        i = side ? BI + l : l - 2;
+    } else {                          // theta-direction halo
+        const int q = t - 4 * BJ;
+        const int side = q / (2 * BI), rem = q % (2 * BI);
+        const int l = rem / BI;
+        i = rem % BI;
+        j = side ? BJ + l : l - 2;
+    }
+}
+
+// Work item of linear work index w when a.xcd_order is set: the work-groups
+// of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
+// into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
+// neighbouring blocks -- which read each other's halos -- share an L2.
+__device__ inline int xcd_item(int w, int n)
+{
+    const int q = n >> 3, rem = n & 7;
+    const int x = w & 7, pos = w >> 3;
+    return x * q + (x < rem ? x : rem) + pos;
+}
+
+// W: waves per SIMD the register allocation targets (a tuning choice).
+template <int BI, int BJ, int BK, int W>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W, W)))
+k_stage(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    constexpr int PI = BI + 4, PJ = BJ + 4;
+    constexpr int NFI = (BI + 1) * BJ;
+    constexpr int NFJ = BI * (BJ + 1);
+    constexpr int NCOL = BI * BJ;
+    constexpr int NHALO = 4 * (BI + BJ);
+    static_assert(NCOL + 64 <= NT && NFI <= 2 * NT && NFJ <= 2 * NT, "plane too large for the work-group");
+    // the last wave (it owns no column) copies the next planes asynchronously into LDS
+    constexpr int CWAVE = NT / 64 - 1;
+    constexpr int NHR = 4 * BJ, NHT = 4 * BI;    // r-halo cells (first), theta-halo cells
+    constexpr int NHP = NHR * 8 * 2;             // r-halo: one 4-byte piece per lane, two per double
+    constexpr int NTP = NHT / 2 * 8;             // theta-halo rows: one 16-byte piece (two cells) per lane
+    constexpr int NCP = NCOL / 2 * 8;            // column plane: one 16-byte piece (two cells) per lane
+    static_assert(NCOL % 2 == 0 && BI % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
+
+    __shared__ double sW[8][PJ][PI];
+    __shared__ __attribute__((aligned(16))) double sCol[8][NCOL];     // conserved column plane k+2
+    __shared__ __attribute__((aligned(16))) double sHalR[8][NHR];     // conserved r-halo of plane k+1
+    __shared__ __attribute__((aligned(16))) double sHalT[8][NHT];     // conserved theta-halo of plane k+1
+    // per halo cell: address of variable 0 in plane 0 and the strides (doubles) per variable and plane
+    __shared__ const double *sHB[NHALO];
+    __shared__ int sHV[NHALO], sHK[NHALO];
+    __shared__ double sFi[8][BJ][BI + 1];
+    __shared__ double sFj[8][BJ + 1][BI];
+    __shared__ RecR sR[BI + 4];
+    __shared__ RecT sT[BJ + 4];
+    __shared__ double sred[NT / 64];
+
+    const int tid = threadIdx.x;
+    const bool col = tid < NCOL;
+    const int ci = tid % BI, cj = tid / BI;      // column owned by this thread
+    const Gas gs = a.gas;
+    const int nitems = *a.nitems;
+
+    const int ks = a.ksplit;                     // parts of the march along k per block
+    const int nwork = nitems * ks;
+    for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        const int ww = a.xcd_order ? xcd_item(wi, nwork) : wi;
+        const int it = ww / ks, part = ww % ks;
+        const int k0 = part * BK / ks, k1 = (part + 1) * BK / ks;
+        const int slot = a.items[it];
+        struct { int org[3]; int reflux_mask; } bd;
+        const int mem = a.desc[slot].member;
+        for (int e = 0; e < 3; ++e) bd.org[e] = a.desc[slot].org[e];
+        bd.reflux_mask = a.desc[slot].reflux_mask;
+        const double dt = a.dt[mem];
+        if (dt <= 0.0) continue;                 // member finished: state stays in place
+        const LevelGeo lg = a.geo[a.desc[slot].level];
+        const double adt = a.alpha * dt;
+
+        __syncthreads();
+        for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
+        for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
+
+        // --- prologue: column primitives of planes k0 and k0+1, phi-face k0-1/2
+        // registers carried along k: Wn = W(k+1), wL = face state of cell k at
+        // k+1/2, Fm = flux at k-1/2; W(k) of the own column sits in LDS
+        double Wn[8], wL[8], Fm[8];
+        int badc = -1;                           // first non-physical input cell of this column
+        if (col) {
+            double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
+            ghosted8<S>(a, a.U, slot, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
+            const RecP pm1 = lg.p[bd.org[2] + k0 - 1 + 2], p0 = lg.p[bd.org[2] + k0 + 2];
+            reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
+            reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
+            rusanov<2>(hi, R0, Fm, gs);
+            const int r = k0 == 0 ? a.desc[slot].freg[4] : -1;
+            if (r >= 0)
+                for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
+        }
+        // halos of plane k0, by all threads; the halo address table
+        for (int t = tid; t < NHALO; t += NT) {
+            int i, j;
+            halo_cell<BI, BJ>(t, i, j);
+            {
+                const double *p0 = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 0);
+                sHB[t] = p0;
+                sHV[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 1, i, j, 0) - p0);
+                sHK[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 1) - p0);
+            }
+            double u[8], w[8];
+            ghosted8<S>(a, a.U, slot, i, j, k0, u);
+            cons_to_prim(u, w, gs);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+        }
+        for (int c = tid; c < NCOL; c += NT) {
+            double u[8];
+            ghosted8<S>(a, a.U, slot, c % BI, c / BI, k0 + 2, u);
+#pragma unroll
+            for (int v = 0; v < 8; ++v) sCol[v][c] = u[v];
+        }
+        double rmax = 0.0;
+        __syncthreads();
+
+        for (int k = k0; k < k1; ++k) {
+            // plane k with its i/j halos is in LDS
+
+            // (c) r-faces of the plane: face f lies between cells f-1 and f
+            for (int t = tid; t < NFI; t += NT) {
+                const int f = t % (BI + 1), j = t / (BI + 1);
+                double L[8], R[8], fx[8];
+                face_states(&sW[0][j + 2][f], 1, PJ * PI, sR[f + 1], sR[f + 2], L, R);
+                rusanov<0>(L, R, fx, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sFi[v][j][f] = fx[v];
+                if (f == 0 || f == BI) {          // raw flux at a coarse-fine face, for the reflux
+                    const int r = a.desc[slot].freg[f == 0 ? 0 : 1];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
+                }
+            }
+            // (d) theta-faces of the plane
+            for (int t = tid; t < NFJ; t += NT) {
+                const int i = t % BI, f = t / BI;
+                double L[8], R[8], fx[8];
+                face_states(&sW[0][f][i + 2], PI, PJ * PI, sT[f + 1], sT[f + 2], L, R);
+                rusanov<1>(L, R, fx, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sFj[v][f][i] = fx[v];
+                if (f == 0 || f == BJ) {
+                    const int r = a.desc[slot].freg[f == 0 ? 2 : 3];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
+                }
+            }
+            // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
+            double Fp[8], Wnext[8];
+            if (col) {
+                double u[8], W2[8], lo1[8], w0[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) u[v] = sCol[v][tid];
+                cons_to_prim(u, W2, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
+                const RecP pk1 = lg.p[bd.org[2] + k + 3];
+                double hi1[8];
+                reconstruct(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
+                rusanov<2>(wL, lo1, Fp, gs);
+                if (k == BK - 1) {
+                    const int r = a.desc[slot].freg[5];
+                    if (r >= 0)
+                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fp[v];
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    wL[v] = hi1[v];
+                    Wnext[v] = Wn[v];
+                    Wn[v] = W2[v];
+                }
+            }
+            __syncthreads();
+
+            // (g) update of cell (ci, cj, k)
+            if (col) {
+                const RecP pk = lg.p[bd.org[2] + k + 2];
+                const RecR rr = sR[ci + 2];
+                const RecT tt = sT[cj + 2];
+                double w[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) w[v] = sW[v][cj + 2][ci + 2];
+                if (badc < 0 && unphysical(w)) badc = ci + BI * (cj + BJ * k);
+                double acc[8];
+                const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
+                const double kf = rr.rt * tt.phf * pk.iw;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    acc[v] = -(rr.ap * sFi[v][cj][ci + 1] - rr.am * sFi[v][cj][ci])
+                             - (thp * sFj[v][cj + 1][ci] - thm * sFj[v][cj][ci])
+                             - kf * (Fp[v] - Fm[v]);
+                }
+                if (!a.cart) add_sources(w, rr.rt, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
+                const size_t base = cidx<S>(slot, 0, ci, cj, k);
+                double unew[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) unew[v] = a.Ubase[base + (size_t)v * S::NC] + adt * acc[v];
+                // floors now, or after the reflux for cells on a coarse-fine face
+                const int mk = bd.reflux_mask;
+                const bool rf = (ci == 0 && (mk & 1)) || (ci == BI - 1 && (mk & 2)) || (cj == 0 && (mk & 4))
+                             || (cj == BJ - 1 && (mk & 8)) || (k == 0 && (mk & 16)) || (k == BK - 1 && (mk & 32));
+                if (!rf) apply_floors(unew, gs, a.rho_floor, a.p_floor);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
+                if (a.want_rate && !rf) {            // refluxed cells: after the reflux
+                    cons_to_prim(unew, w, gs);
+                    const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
+                                      + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
+                                      + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pk.iw;
+                    rmax = rate > rmax ? rate : rmax;
+                }
+#pragma unroll
+                for (int v = 0; v < 8; ++v) {
+                    Fm[v] = Fp[v];
+                    sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
+                }
+            } else if (k + 1 < k1 && (tid >> 6) == CWAVE) {
+                // (p) meanwhile the last wave (no column) copies the conserved halo of
+                // plane k+1 (the update reads no halo cell) and the column plane k+3
+                // (read in (e) of the next plane; this plane's copy was read before
+                // the last barrier) from HBM into LDS without staging in registers,
+                // wait once, and convert the halo to primitives
+                const int lane = tid & 63;
+                typedef __attribute__((address_space(3))) char lds_t;
+#pragma unroll 2
+                for (int q = 0; q * 64 < NHP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NHP) {
+                        const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
+                        const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NTP; ++q) {
+                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
+                    const int g = q * 64 + lane;
+                    if (g < NTP) {
+                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
+                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NCP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NCP) {
+                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
+                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
+                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
+                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);           // this wave's copies have landed
+#pragma unroll 1
+                for (int t = lane; t < NHALO; t += 64) {
+                    int i, j;
+                    halo_cell<BI, BJ>(t, i, j);
+                    double u[8], w8[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) u[v] = t < NHR ? sHalR[v][t] : sHalT[v][t - NHR];
+                    cons_to_prim(u, w8, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
+                }
+            }
+            __syncthreads();
+        }
+        if (col && badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
+        if (a.want_rate) {
+            // this part's CFL maximum; the last part clears the unused entries
+            const double m = block_max(col ? rmax : 0.0, sred);
+            if (tid == 0) a.rate[(size_t)slot * KSPLIT_MAX + part] = m;
+            if (part == ks - 1 && tid > part && tid < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + tid] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// instantiations and launch
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves)
+{
+    if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 1>), g, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2>), g, dim3(NT), 0, s, a);
+}
+
+#define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
+    template __global__ void k_stage<BI, BJ, BK, 1>(KArgs);                                        \
+    template __global__ void k_stage<BI, BJ, BK, 2>(KArgs);                                        \
+    template void launch_stage<BI, BJ, BK>(dim3, hipStream_t, const KArgs &, int);
+
+#include "shapes.inc"
+#undef IC_INSTANTIATE
