@@ -222,6 +222,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
 #pragma unroll
             for (int e = 0; e < 3; ++e) gw[e] = g[e] + tkp->shift[e];
             const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
+            const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 int fgi[3], fl[3], q[3];
@@ -232,7 +233,8 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
                     q[e] = fb - fbase[e];
                     fl[e] = fgi[e] - fb * S::dim(e);
                 }
-                const int fslot = tkp->src[q[E1] + 2 * q[E2]];
+                const int qq = q[E1] + 2 * q[E2];
+                const int fslot = qq == 0 ? src0 : (qq == 1 ? src1 : (qq == 2 ? src2 : src3));
                 const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
 #pragma unroll
                 for (int v = 0; v < 8; ++v) num[v] += wgt * a.U[cidx<S>(fslot, v, fl[0], fl[1], fl[2])];
@@ -339,15 +341,28 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             }
             __syncthreads();
         }
-        // floors on the corrected cells (each once, after all its faces) and
-        // their CFL rates; the stage kernel took the maximum over the other cells
+        // floors on the corrected cells and their CFL rates (the stage kernel took
+        // the maximum over the other cells): each corrected cell once, listed
+        // face by face, an edge cell with the first of its faces
+        int total = 0;
+        for (int q = t0; q < t1; ++q) total += S::face_cells(tasks[q].face >> 1);
         double rmax = 0.0;
-        for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
-            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
-            const int mk = bd.reflux_mask;
-            const bool rf = (i == 0 && (mk & 1)) || (i == BI - 1 && (mk & 2)) || (j == 0 && (mk & 4))
-                         || (j == BJ - 1 && (mk & 8)) || (k == 0 && (mk & 16)) || (k == BK - 1 && (mk & 32));
-            if (!rf) continue;
+        for (int w = threadIdx.x; w < total; w += blockDim.x) {
+            int q = t0, c = w;
+            while (c >= S::face_cells(tasks[q].face >> 1)) c -= S::face_cells(tasks[q].face >> 1), ++q;
+            const int d = tasks[q].face >> 1, side = tasks[q].face & 1;
+            const int e1 = tan1(d), e2 = tan2(d);
+            int loc[3];
+            loc[d] = side ? S::dim(d) - 1 : 0;
+            loc[e1] = c % S::dim(e1);
+            loc[e2] = c / S::dim(e1);
+            bool first = true;
+            for (int p = t0; p < q; ++p) {
+                const int f = tasks[p].face;
+                if (loc[f >> 1] == ((f & 1) ? S::dim(f >> 1) - 1 : 0)) first = false;
+            }
+            if (!first) continue;
+            const int i = loc[0], j = loc[1], k = loc[2];
             double u[8];
             for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
             apply_floors(u, a.gas, a.rho_floor, a.p_floor);
