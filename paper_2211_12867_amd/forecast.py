@@ -11,8 +11,11 @@ unless a name says hours or days.
     python -m paper_2211_12867_amd.forecast compare --net flags.npz ...
 """
 import argparse
+import atexit
 import json
+import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -22,7 +25,21 @@ from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_infer
 DAY = 86400.0
 HOUR = 3600.0
 SAMPLE = (1.0, 90.0, 0.0)          # r [AU], colatitude, longitude [deg] in the co-rotating frame
-TUNE_CACHE = None                  # schedule cache file of ic_autotune (None: time the candidates each call)
+TUNE_CACHE = None                  # schedule cache file of ic_autotune (None: a file of this process)
+_tune_file = None
+
+
+def _tune_cache():
+    """Cache file for ic_autotune: each block shape and work-list size is timed
+    once per process (or per TUNE_CACHE file) and looked up afterwards."""
+    global _tune_file
+    if TUNE_CACHE:
+        return TUNE_CACHE
+    if _tune_file is None:
+        fd, _tune_file = tempfile.mkstemp(prefix="icarus_tune_", suffix=".txt")
+        os.close(fd)
+        atexit.register(lambda path=_tune_file: os.path.exists(path) and os.remove(path))
+    return _tune_file
 
 
 def _log(log, msg):
@@ -36,7 +53,7 @@ def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
     g = dict(grid, max_level=1)
     sim = Sim(g, wind, [cme], dict(regrid_every=0))
     t0 = time.perf_counter()
-    sim.autotune(TUNE_CACHE)
+    sim.autotune(_tune_cache())
     steps = 0
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
@@ -85,7 +102,7 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
     t0 = time.perf_counter()
     info = None
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
-        sim.autotune(TUNE_CACHE)                 # the work list changes with the forest
+        sim.autotune(_tune_cache())              # the work list changes with the forest
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
         ts.append(sim.timeseries())
         sim.timeseries_clear()
@@ -178,7 +195,7 @@ def ensemble_run(grid, wind, cmes, amr, start, t_end_s, chunk_s=DAY / 4, log=pri
     info = None
     max_leaves = 0
     while min(sim.time(m)[0] for m in range(len(cmes))) < t_end_s * (1.0 - 1e-12):
-        sim.autotune(TUNE_CACHE)
+        sim.autotune(_tune_cache())
         info = sim.advance(min(chunk_s, t_end_s - sim.time(0)[0]))
         for m in range(len(cmes)):
             series[m].append(sim.timeseries(m))
