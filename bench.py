@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-updates/s (fp64 MHD, 1 GPU); AMR+learned flags vs equidistant to arrival"
 PEAK_HBM_GBS = 8000.0
+# schedules measured by the autotuner on MI355X (gfx950, 256 CUs); a device or
+# work-list size without an entry is timed and appended
+TUNE_CACHE = os.path.join(ROOT, "paper_2211_12867_amd", "tune_cache.txt")
 BYTES_PER_CELL_LAUNCH = 160.0
 
 
@@ -38,20 +41,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(schedule=None):
     """HBM bytes per stage launch (FETCH_SIZE + WRITE_SIZE, each scaled by a
     plain 1 GiB copy) from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source and build flags; else None."""
+    taken on the current kernel source and build flags with this schedule
+    (waves, grid, xcd_order, ksplit); else None."""
     path = os.path.join(ROOT, "profiles", "stage_traffic_equidistant_full.md")
     if not os.path.exists(path):
         return None
     vals = {}
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.split(":")[0] in ("kernel_source_hash", "bytes_per_launch_hbm"):
+            if ":" in line and line.split(":")[0] in ("kernel_source_hash", "bytes_per_launch_hbm", "schedule"):
                 k, v = line.split(":", 1)
                 vals[k] = v.strip()
     if vals.get("kernel_source_hash") != kernel_source_hash() or "bytes_per_launch_hbm" not in vals:
+        return None
+    if schedule is not None and vals.get("schedule") != ",".join(str(x) for x in schedule):
         return None
     return float(vals["bytes_per_launch_hbm"])
 
@@ -108,6 +114,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default stage schedule (profiling runs: no tuning launches in the trace)")
+    ap.add_argument("--schedule", default=None,
+                    help="force the stage schedule waves,grid,xcd_order,ksplit (e.g. 2,0,1,1) instead of tuning")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="schedule cache of the autotuner ('' = time the candidates)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale HBM counters")
     args = ap.parse_args()
@@ -129,8 +139,10 @@ def main():
     cells = g["n"][0] * g["n"][1] * g["n"][2]
     for _ in range(args.warmup):
         sim.step()
-    if not args.no_autotune:
-        sim.autotune(None, reps=3)
+    if args.schedule:
+        sim.set_tuning(*[int(x) for x in args.schedule.split(",")])
+    elif not args.no_autotune:
+        sim.autotune(args.tune_cache or None, reps=3)
     tune = dict(zip(("waves_per_simd", "grid", "xcd_order", "ksplit"), sim.tuning()))
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
     sim.step()                                  # captures the step graph for the tuned schedule
@@ -165,7 +177,7 @@ def main():
 
     bytes_launch = BYTES_PER_CELL_LAUNCH * cells
     achieved = bytes_launch / (mean_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(tuple(tune[k] for k in ("waves_per_simd", "grid", "xcd_order", "ksplit")))
     out = {
         "metric": METRIC,
         "value": cells * args.steps / el,

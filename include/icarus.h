@@ -317,8 +317,9 @@ typedef struct {
  * block shape, variable count, work-item count to a power of two) up in
  * cache_path (a text file, one result per line; NULL = no cache), else time
  * every candidate on the current state (reps launches each; the state is not
- * changed) and append the winner to the cache.  The choice applies to later
- * steps; out may be NULL.  The sim remembers the result for this work-list
+ * changed) and append the winner to the cache (candidates within 1 % of the
+ * best so far keep the earlier one; XCD-contiguous order is tried first).  The
+ * choice applies to later steps; out may be NULL.  The sim remembers the result for this work-list
  * size (and reads the cache's results for other sizes): after each regrid the
  * schedule of the new size is used, or, for a size without one, two waves per
  * SIMD, one work-group per work item and the smallest k-split giving at least

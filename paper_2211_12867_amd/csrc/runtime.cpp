@@ -2275,12 +2275,14 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
                     if (g < n) grids.push_back(g);
                 for (int w : {2, 1})
                     for (int g : grids)
-                        for (int x : {0, 1}) {
+                        for (int x : {1, 0}) {
                             apply_tuning(s, w, g, x, ks);
                             const double ms = time_stage(s, reps);
                             res.candidates++;
                             if (w == 2 && g == 0 && x == 0 && ks == 1) res.default_ms = ms;
-                            if (ms < best) {
+                            // a later candidate must be 1 % faster: near-ties keep the first in
+                            // this order (XCD-contiguous order first, for its lower HBM traffic)
+                            if (ms < 0.99 * best) {
                                 best = ms;
                                 res.waves_per_simd = w;
                                 res.grid = g;
