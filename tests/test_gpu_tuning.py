@@ -7,9 +7,10 @@
 - with 4 work-groups per block, a refined wedge with regrids (reflux and flux
   registers at coarse-fine faces, split boundaries inside blocks) matches
   the oracle;
-- ic_autotune leaves the state and time untouched, picks a schedule no
-  slower than the default on its own measurement, and returns the same
-  choice from its cache on the second call;
+- ic_autotune leaves the state and time untouched, picks a schedule at most
+  1 % slower than the default on its own measurement (near-ties keep the
+  earlier candidate), and returns the same choice from its cache on the
+  second call;
 - invalid schedules are rejected;
 - the schedule follows the work-list size across regrids: the rule for
   untuned sizes, ic_autotune's result for its own size, ic_set_tuning's
@@ -63,7 +64,8 @@ def test_autotune_keeps_state_and_caches(tmp_path):
     cache = str(tmp_path / "tune.txt")
     r1 = sim.autotune(cache, reps=2)
     assert r1["from_cache"] == 0 and r1["candidates"] >= 4
-    assert r1["stage_ms"] <= r1["default_ms"]
+    # a candidate replaces an earlier one only when 1 % faster
+    assert r1["stage_ms"] <= r1["default_ms"] / 0.99
     assert np.array_equal(sim.state()[1], U0) and sim.time()[0] == t0
     r2 = sim.autotune(cache, reps=2)
     assert r2["from_cache"] == 1
