@@ -10,9 +10,10 @@
 // and carries the previous plane's flux, face state and the next plane's
 // primitives).  The update adds the flux differences with the finite-volume
 // metric, the hoop, Coriolis, centrifugal and gravity sources, applies the
-// floors and writes U_out = U_base + alpha dt L(U).  Meanwhile the last wave,
-// which owns no column, copies the next plane's halo and the column plane two
-// ahead from HBM into LDS asynchronously.  Halo cells come from neighbouring
+// floors and writes U_out = U_base + alpha dt L(U).  The last wave, which owns
+// no column, starts the asynchronous HBM-to-LDS copy of the next plane's halo
+// when a plane begins; during the update it converts that halo to primitives
+// and copies the column plane three ahead.  Halo cells come from neighbouring
 // blocks (same level), the block's own edge (outflow) or ghost slabs (inner
 // boundary, coarse-fine faces).
 #include "common.h"
@@ -128,10 +129,11 @@ k_stage(KArgs a)
         const int it = ww / ks, part = ww % ks;
         const int k0 = part * BK / ks, k1 = (part + 1) * BK / ks;
         const int slot = a.items[it];
-        struct { int org[3]; int reflux_mask; } bd;
+        struct { int org[3]; int reflux_mask; int freg[6]; } bd;
         const int mem = a.desc[slot].member;
         for (int e = 0; e < 3; ++e) bd.org[e] = a.desc[slot].org[e];
         bd.reflux_mask = a.desc[slot].reflux_mask;
+        for (int e = 0; e < 6; ++e) bd.freg[e] = a.desc[slot].freg[e];
         const double dt = a.dt[mem];
         if (dt <= 0.0) continue;                 // member finished: state stays in place
         const LevelGeo lg = a.geo[a.desc[slot].level];
@@ -189,6 +191,34 @@ k_stage(KArgs a)
 
         for (int k = k0; k < k1; ++k) {
             // plane k with its i/j halos is in LDS
+            if (k + 1 < k1 && (tid >> 6) == CWAVE) {
+                // the last wave starts the copies of the conserved r/theta halo of
+                // plane k+1 into LDS (free since the last barrier); they land while
+                // the plane's fluxes are computed
+                const int lane = tid & 63;
+                typedef __attribute__((address_space(3))) char lds_t;
+#pragma unroll 2
+                for (int q = 0; q * 64 < NHP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NHP) {
+                        const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
+                        const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NTP; ++q) {
+                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
+                    const int g = q * 64 + lane;
+                    if (g < NTP) {
+                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
+                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+            }
 
             // (c) r-faces of the plane: face f lies between cells f-1 and f
             for (int t = tid; t < NFI; t += NT) {
@@ -199,7 +229,7 @@ k_stage(KArgs a)
 #pragma unroll
                 for (int v = 0; v < 8; ++v) sFi[v][j][f] = fx[v];
                 if (f == 0 || f == BI) {          // raw flux at a coarse-fine face, for the reflux
-                    const int r = a.desc[slot].freg[f == 0 ? 0 : 1];
+                    const int r = bd.freg[f == 0 ? 0 : 1];
                     if (r >= 0)
                         for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
                 }
@@ -213,7 +243,7 @@ k_stage(KArgs a)
 #pragma unroll
                 for (int v = 0; v < 8; ++v) sFj[v][f][i] = fx[v];
                 if (f == 0 || f == BJ) {
-                    const int r = a.desc[slot].freg[f == 0 ? 2 : 3];
+                    const int r = bd.freg[f == 0 ? 2 : 3];
                     if (r >= 0)
                         for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
                 }
@@ -232,7 +262,7 @@ k_stage(KArgs a)
                 reconstruct(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
                 rusanov<2>(wL, lo1, Fp, gs);
                 if (k == BK - 1) {
-                    const int r = a.desc[slot].freg[5];
+                    const int r = bd.freg[5];
                     if (r >= 0)
                         for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fp[v];
                 }
@@ -288,45 +318,13 @@ k_stage(KArgs a)
                     sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
                 }
             } else if (k + 1 < k1 && (tid >> 6) == CWAVE) {
-                // (p) meanwhile the last wave (no column) copies the conserved halo of
-                // plane k+1 (the update reads no halo cell) and the column plane k+3
-                // (read in (e) of the next plane; this plane's copy was read before
-                // the last barrier) from HBM into LDS without staging in registers,
-                // wait once, and convert the halo to primitives
+                // (p) meanwhile the last wave (no column) converts the halo of plane
+                // k+1 (copied since the start of this plane) to primitives, then
+                // copies the column plane k+3 (read in (e) of the next plane; this
+                // plane's copy was read before the last barrier) from HBM into LDS
                 const int lane = tid & 63;
                 typedef __attribute__((address_space(3))) char lds_t;
-#pragma unroll 2
-                for (int q = 0; q * 64 < NHP; ++q) {
-                    const int g = q * 64 + lane;
-                    if (g < NHP) {
-                        const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
-                        const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
-                        __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
-                    }
-                }
-#pragma unroll 2
-                for (int q = 0; q * 64 < NTP; ++q) {
-                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
-                    const int g = q * 64 + lane;
-                    if (g < NTP) {
-                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
-                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
-                        __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
-                    }
-                }
-#pragma unroll 2
-                for (int q = 0; q * 64 < NCP; ++q) {
-                    const int g = q * 64 + lane;
-                    if (g < NCP) {
-                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
-                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
-                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
-                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
-                    }
-                }
-                __builtin_amdgcn_s_waitcnt(0);           // this wave's copies have landed
+                __builtin_amdgcn_s_waitcnt(0);           // the halo copies have landed
 #pragma unroll 1
                 for (int t = lane; t < NHALO; t += 64) {
                     int i, j;
@@ -338,6 +336,17 @@ k_stage(KArgs a)
 #pragma unroll
                     for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
                 }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NCP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NCP) {
+                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
+                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
+                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
+                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);           // column plane k+3 has landed
             }
             __syncthreads();
         }
