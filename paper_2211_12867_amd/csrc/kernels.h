@@ -111,7 +111,7 @@ struct IndicatorParams {
 // Launch wrappers per block shape (kernels.hip, stage.hip); the runtime calls these.
 struct Launchers {
     void (*stage)(dim3, hipStream_t, const KArgs &, int waves);
-    void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *);
+    void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *, int pass);
     void (*reflux)(dim3, hipStream_t, const KArgs &, const RefluxTask *, const int *, const int *);
     void (*rate)(dim3, hipStream_t, const KArgs &);
     void (*indicator)(dim3, hipStream_t, const KArgs &, int8_t *, const IndicatorParams &);
@@ -126,7 +126,7 @@ void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int n
 // kernel entry points (stage.hip: k_stage and its launcher; kernels.hip: the rest)
 template <int BI, int BJ, int BK, int W> __global__ void k_stage(KArgs a);
 template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves);
-template <int BI, int BJ, int BK> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
+template <int BI, int BJ, int BK, int PASS> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
 template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);
 template <int BI, int BJ, int BK>

@@ -73,7 +73,7 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // that every per-direction index below is a register, not private memory).
 // Slab layout: element ((v * 2 + l) * FB + b) * FA + a, layer l = 0 nearest
 // the low side.  sP, sOk: LDS for the prolongation's per-parent values.
-template <int BI, int BJ, int BK, int D>
+template <int BI, int BJ, int BK, int D, int PASS>
 DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
 {
     using S = Shape<BI, BJ, BK>;
@@ -85,7 +85,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
     const LevelGeo lg = a.geo[bd.level];
     double *out = a.slabs + (size_t)tkp->slab * a.slab_stride;
     const int g0d = side ? bd.org[D] + Bd : bd.org[D] - 2;     // owner-level index of layer 0 along D
-    if (type == SLAB_PROLONG) {
+    if (PASS == 1) {                                    // SLAB_PROLONG
         // children = 2 layers x 2 x 2 fine cells per coarse parent
         constexpr int HA = FA / 2, HB = FB / 2, NP = HA * HB;
         const LevelGeo cg = a.geo[bd.level - 1];
@@ -173,20 +173,19 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         __syncthreads();                            // sP and sOk are reused by the next task
         return;
     }
-    const Gas gs = a.gas;
-    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
-        const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
-        int g[3];                                   // owner-level global index (unwrapped)
-        g[D] = g0d + l;
-        g[E1] = bd.org[E1] + ia;
-        g[E2] = bd.org[E2] + ib;
-        double u[8];
-        if (type == SLAB_INNER) {
+    if (type == SLAB_INNER) {
+        const Gas gs = a.gas;
+        for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+            const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
+            int g[3];                               // owner-level global index (unwrapped)
+            g[D] = g0d + l;
+            g[E1] = bd.org[E1] + ia;
+            g[E2] = bd.org[E2] + ib;
             const int jt = g[1], kp = g[2];
             const int nt = lg.n[1], np = lg.n[2];
             const size_t o = (size_t)jt * np + kp;
             const size_t pl = (size_t)nt * np;
-            double w[8];
+            double w[8], u[8];
             w[0] = lg.wind[0 * pl + o];
             w[1] = lg.wind[1 * pl + o];
             w[2] = 0.0;
@@ -215,51 +214,67 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
                 }
             }
             prim_to_cons(w, u, gs);
-        } else {                                    // SLAB_RESTRICT
-            const LevelGeo fg = a.geo[bd.level + 1];
-            double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
-            int gw[3];
 #pragma unroll
-            for (int e = 0; e < 3; ++e) gw[e] = g[e] + tkp->shift[e];
-            const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
-            const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
+            for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
+        }
+        return;
+    }
+    // SLAB_RESTRICT: one thread per ghost cell and half of the variables (32
+    // independent loads each, issued together)
+    const LevelGeo fg = a.geo[bd.level + 1];
+    const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
+    const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
+    const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
+    for (int e = threadIdx.x; e < 2 * NCELL; e += blockDim.x) {
+        const int c = e % NCELL, h = e / NCELL;
+        const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
+        int gw[3];                                  // owner-level global index, wrapped
+        gw[D] = g0d + l + shift[D];
+        gw[E1] = bd.org[E1] + ia + shift[E1];
+        gw[E2] = bd.org[E2] + ib + shift[E2];
+        // volume factors of the two children along each direction
+        const double wr[2] = {fg.r[2 * gw[0] + 2].vw, fg.r[2 * gw[0] + 3].vw};
+        const double wt[2] = {fg.t[2 * gw[1] + 2].vw, fg.t[2 * gw[1] + 3].vw};
+        const double wp[2] = {fg.p[2 * gw[2] + 2].vw, fg.p[2 * gw[2] + 3].vw};
+        double num[4] = {0, 0, 0, 0}, den = 0.0;
 #pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                int fgi[3], fl[3], q[3];
+        for (int o = 0; o < 8; ++o) {
+            int fl[3], q[3];
 #pragma unroll
-                for (int e = 0; e < 3; ++e) {
-                    fgi[e] = 2 * gw[e] + ((o >> e) & 1);
-                    const int fb = fgi[e] / S::dim(e);
-                    q[e] = fb - fbase[e];
-                    fl[e] = fgi[e] - fb * S::dim(e);
-                }
-                const int qq = q[E1] + 2 * q[E2];
-                const int fslot = qq == 0 ? src0 : (qq == 1 ? src1 : (qq == 2 ? src2 : src3));
-                const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) num[v] += wgt * a.U[cidx<S>(fslot, v, fl[0], fl[1], fl[2])];
-                den += wgt;
+            for (int d = 0; d < 3; ++d) {
+                const int fgi = 2 * gw[d] + ((o >> d) & 1);
+                const int fb = fgi / S::dim(d);
+                q[d] = fb - fbase[d];
+                fl[d] = fgi - fb * S::dim(d);
             }
+            const int qq = q[E1] + 2 * q[E2];
+            const int fslot = qq == 0 ? src0 : (qq == 1 ? src1 : (qq == 2 ? src2 : src3));
+            const double wgt = wr[o & 1] * wt[(o >> 1) & 1] * wp[(o >> 2) & 1];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) u[v] = num[v] / den;
+            for (int v = 0; v < 4; ++v) num[v] += wgt * a.U[cidx<S>(fslot, 4 * h + v, fl[0], fl[1], fl[2])];
+            den += wgt;
         }
 #pragma unroll
-        for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
+        for (int v = 0; v < 4; ++v) out[((size_t)((4 * h + v) * 2 + l) * FB + ib) * FA + ia] = num[v] / den;
     }
 }
 
-template <int BI, int BJ, int BK>
-__global__ void __launch_bounds__(NT) k_slabs(KArgs a, const SlabTask *tasks, const int *range)
+// PASS 0: inner-boundary and restriction slabs; PASS 1: prolongation slabs
+// (separate kernels, so that each is compiled for its own register needs)
+template <int BI, int BJ, int BK, int PASS>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 4 : 1)))
+k_slabs(KArgs a, const SlabTask *tasks, const int *range)
 {
     using S = Shape<BI, BJ, BK>;
-    __shared__ double sP[S::MAXFACE / 4 * 32];
-    __shared__ int sOk[S::MAXFACE / 4];
+    constexpr int NPL = PASS == 1 ? S::MAXFACE / 4 : 1;
+    __shared__ double sP[NPL * 32];
+    __shared__ int sOk[NPL];
     const int t0 = range[0], t1 = range[1];
     for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
         const int d = tasks[it].face >> 1;          // uniform over the work-group
-        if (d == 0) slab_task<BI, BJ, BK, 0>(a, tasks + it, sP, sOk);
-        else if (d == 1) slab_task<BI, BJ, BK, 1>(a, tasks + it, sP, sOk);
-        else slab_task<BI, BJ, BK, 2>(a, tasks + it, sP, sOk);
+        if (d == 0) slab_task<BI, BJ, BK, 0, PASS>(a, tasks + it, sP, sOk);
+        else if (d == 1) slab_task<BI, BJ, BK, 1, PASS>(a, tasks + it, sP, sOk);
+        else slab_task<BI, BJ, BK, 2, PASS>(a, tasks + it, sP, sOk);
     }
 }
 
@@ -643,7 +658,8 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
 // instantiations for the supported block shapes
 // ---------------------------------------------------------------------------
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
-    template __global__ void k_slabs<BI, BJ, BK>(KArgs, const SlabTask *, const int *);            \
+    template __global__ void k_slabs<BI, BJ, BK, 0>(KArgs, const SlabTask *, const int *);         \
+    template __global__ void k_slabs<BI, BJ, BK, 1>(KArgs, const SlabTask *, const int *);         \
     template __global__ void k_reflux<BI, BJ, BK>(KArgs, const RefluxTask *, const int *, const int *); \
     template __global__ void k_rate<BI, BJ, BK>(KArgs);                                            \
     template __global__ void k_indicator<BI, BJ, BK>(KArgs, int8_t *, int, double, double, double, \
@@ -662,9 +678,10 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
 namespace {
 template <int BI, int BJ, int BK>
 struct L {
-    static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r)
+    static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r, int pass)
     {
-        hipLaunchKernelGGL((k_slabs<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, r);
+        if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, 0>), g, dim3(NT), 0, s, a, t, r);
+        else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, 1>), g, dim3(NT), 0, s, a, t, r);
     }
     static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *b, const int *n)
     {

@@ -803,8 +803,8 @@ void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
     KArgs a = base_args(s);
     a.U = Uin;
     a.tfrac = tfrac;
-    s->L.slabs(dim3(slab_grid(s, 0)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p);
-    if (s->max_level > 1) s->L.slabs(dim3(slab_grid(s, 1)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2);
+    s->L.slabs(dim3(slab_grid(s, 0)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p, 0);
+    if (s->max_level > 1) s->L.slabs(dim3(slab_grid(s, 1)), s->stream, a, s->slab_tasks.p, s->slab_ranges.p + 2, 1);
 }
 
 void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, int want_rate)
