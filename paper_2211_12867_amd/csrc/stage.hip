@@ -4,8 +4,10 @@
 // Woodward-type limiter, second order): a work-group marches along k (phi)
 // through a leaf block (or through 1/2 or 1/4 of it, for short work lists).
 // For each k-plane the primitives of the plane and of its two-cell i/j halos
-// sit in LDS; every r- and theta-face flux of the plane is computed once by
-// one thread and kept in LDS; the phi-face fluxes are computed once per column
+// sit in LDS; every cell is reconstructed once per direction, and every r- and
+// theta-face flux of the plane is computed once by one thread (which takes the
+// left state from its neighbouring lane through LDS) and kept in LDS; the
+// phi-face fluxes are computed once per column
 // in registers (each of the first 192 or fewer threads owns one (i, j) column
 // and carries the previous plane's flux, face state and the next plane's
 // primitives).  The update adds the flux differences with the finite-volume
@@ -21,37 +23,6 @@
 // ---------------------------------------------------------------------------
 // fused stage kernel
 // ---------------------------------------------------------------------------
-
-// Left and right states at the face between cells c1 and c2 of an LDS line
-// c0 c1 c2 c3 (cell stride cs, variable stride vs), reconstructed one
-// variable at a time so that only the two face states stay live.  The
-// zero-slope fallback of a cell applies when one of its two face densities or
-// pressures is not positive.
-template <class Rec>
-DEV void face_states(const double *p, int cs, int vs, const Rec &r1, const Rec &r2, double L[8], double R[8])
-{
-    bool ok1 = true, ok2 = true;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const double a = p[v * vs], b = p[v * vs + cs], c = p[v * vs + 2 * cs], d = p[v * vs + 3 * cs];
-        const double s1 = mc_slope(a, b, c, r1.idm, r1.idp, r1.idc);
-        const double s2 = mc_slope(b, c, d, r2.idm, r2.idp, r2.idc);
-        L[v] = b + s1 * r1.hp;
-        R[v] = c - s2 * r2.hm;
-        if (v == 0 || v == 4) {
-            ok1 = ok1 && (b - s1 * r1.hm > 0.0) && (L[v] > 0.0);
-            ok2 = ok2 && (R[v] > 0.0) && (c + s2 * r2.hp > 0.0);
-        }
-    }
-    if (!ok1) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) L[v] = p[v * vs + cs];
-    }
-    if (!ok2) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) R[v] = p[v * vs + 2 * cs];
-    }
-}
 
 // Cell t of the 4 (BI + BJ) r/theta halo cells of plane k (two layers on each
 // side, r-halo first): its (i, j).
@@ -220,32 +191,85 @@ k_stage(KArgs a)
                 }
             }
 
-            // (c) r-faces of the plane: face f lies between cells f-1 and f
-            for (int t = tid; t < NFI; t += NT) {
-                const int f = t % (BI + 1), j = t / (BI + 1);
-                double L[8], R[8], fx[8];
-                face_states(&sW[0][j + 2][f], 1, PJ * PI, sR[f + 1], sR[f + 2], L, R);
-                rusanov<0>(L, R, fx, gs);
+            // (c) r-faces of the plane.  A row of lanes takes the cells c = -1 .. BI
+            // of one j: each lane reconstructs its cell's two face states once,
+            // passes the upper one to the next lane through LDS (a row lies within
+            // one wave, whose LDS accesses stay in order) and computes the flux at
+            // its lower face f = c, between cells c-1 and c.
+            {
+                constexpr int RL = BI + 2, RPW = 64 / RL;
+                static_assert((BJ + RPW - 1) / RPW <= NT / 64, "r-face rows per wave");
+                const int lane = tid & 63, c = lane % RL - 1;
+                const int j = (tid >> 6) * RPW + lane / RL;
+                const bool act = lane < RPW * RL && j < BJ;
+                double lo[8], hi[8];
+                if (act) {
+                    double wm[8], w0[8], wp[8];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) sFi[v][j][f] = fx[v];
-                if (f == 0 || f == BI) {          // raw flux at a coarse-fine face, for the reflux
-                    const int r = bd.freg[f == 0 ? 0 : 1];
-                    if (r >= 0)
-                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
+                    for (int v = 0; v < 8; ++v) {
+                        wm[v] = sW[v][j + 2][c + 1];
+                        w0[v] = sW[v][j + 2][c + 2];
+                        wp[v] = sW[v][j + 2][c + 3];
+                    }
+                    const RecR rc = sR[c + 2];
+                    reconstruct(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    if (c < BI)
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) sFi[v][j][c + 1] = hi[v];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (act && c >= 0) {
+                    double L[8], fx[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) L[v] = sFi[v][j][c];
+                    rusanov<0>(L, lo, fx, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sFi[v][j][c] = fx[v];
+                    if (c == 0 || c == BI) {      // raw flux at a coarse-fine face, for the reflux
+                        const int r = bd.freg[c == 0 ? 0 : 1];
+                        if (r >= 0)
+                            for (int v = 0; v < 8; ++v)
+                                a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
+                    }
                 }
             }
-            // (d) theta-faces of the plane
-            for (int t = tid; t < NFJ; t += NT) {
-                const int i = t % BI, f = t / BI;
-                double L[8], R[8], fx[8];
-                face_states(&sW[0][f][i + 2], PI, PJ * PI, sT[f + 1], sT[f + 2], L, R);
-                rusanov<1>(L, R, fx, gs);
+            // (d) theta-faces of the plane, the same way along j: a column of lanes
+            // takes the cells c = -1 .. BJ of one i (the columns of a wave interleaved)
+            {
+                constexpr int CL = BJ + 2, CPW = 64 / CL;
+                static_assert((BI + CPW - 1) / CPW <= NT / 64, "theta-face columns per wave");
+                const int lane = tid & 63, c = lane / CPW - 1;
+                const int i = (tid >> 6) * CPW + lane % CPW;
+                const bool act = lane < CPW * CL && i < BI;
+                double lo[8], hi[8];
+                if (act) {
+                    double wm[8], w0[8], wp[8];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) sFj[v][f][i] = fx[v];
-                if (f == 0 || f == BJ) {
-                    const int r = bd.freg[f == 0 ? 2 : 3];
-                    if (r >= 0)
-                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
+                    for (int v = 0; v < 8; ++v) {
+                        wm[v] = sW[v][c + 1][i + 2];
+                        w0[v] = sW[v][c + 2][i + 2];
+                        wp[v] = sW[v][c + 3][i + 2];
+                    }
+                    const RecT rc = sT[c + 2];
+                    reconstruct(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    if (c < BJ)
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) sFj[v][c + 1][i] = hi[v];
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (act && c >= 0) {
+                    double L[8], fx[8];
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) L[v] = sFj[v][c][i];
+                    rusanov<1>(L, lo, fx, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sFj[v][c][i] = fx[v];
+                    if (c == 0 || c == BJ) {
+                        const int r = bd.freg[c == 0 ? 2 : 3];
+                        if (r >= 0)
+                            for (int v = 0; v < 8; ++v)
+                                a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
+                    }
                 }
             }
             // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
