@@ -291,6 +291,70 @@ __device__ inline double cell_rate(const double u[8], const RecR &rr, const RecT
          + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pp.iw;
 }
 
+// Reflux at one coarse-fine face of a coarse block, face direction D (a
+// template parameter: every per-direction index stays in registers): for each
+// cell behind the face, U += +-adt (A_c F_c - sum of the 4 fine A F) / V_c,
+// the fine faces summed in fixed order.
+template <int BI, int BJ, int BK, int D>
+DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd, const LevelGeo &lg,
+                     const LevelGeo &fg, int slot, double adt)
+{
+    using S = Shape<BI, BJ, BK>;
+    constexpr int E1 = tan1(D), E2 = tan2(D);
+    constexpr int FA = S::dim(E1), FB = S::dim(E2);
+    const int side = tkp->face & 1;
+    const int reg4[4] = {tkp->freg[0], tkp->freg[1], tkp->freg[2], tkp->freg[3]};
+    const double *Fc = a.freg + (size_t)tkp->creg * a.reg_stride;
+    for (int c = threadIdx.x; c < FA * FB; c += blockDim.x) {
+        const int ia = c % FA, ib = c / FA;
+        int loc[3];
+        loc[D] = side ? S::dim(D) - 1 : 0;
+        loc[E1] = ia;
+        loc[E2] = ib;
+        int g[3];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) g[e] = bd.org[e] + loc[e];
+        const RecR rr = lg.r[g[0] + 2];
+        const RecT tt = lg.t[g[1] + 2];
+        const RecP pp = lg.p[g[2] + 2];
+        const double Vc = rr.vw * tt.vw * pp.vw;
+        double ac;
+        if (D == 0) ac = side ? rr.ap : rr.am;
+        else if (D == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
+        else ac = rr.rt * tt.phf * pp.iw;
+        const int gf = 2 * (bd.org[D] + (side ? S::dim(D) : 0));   // fine face index along D
+        double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int ob = 0; ob < 2; ++ob) {
+#pragma unroll
+            for (int oa = 0; oa < 2; ++oa) {
+                const int fa = 2 * ia + oa, fb = 2 * ib + ob;
+                const int qa = fa / FA, qb = fb / FB;
+                const int qq = qa + 2 * qb;
+                const int reg = qq == 0 ? reg4[0] : (qq == 1 ? reg4[1] : (qq == 2 ? reg4[2] : reg4[3]));
+                int fgl[3];
+                fgl[D] = gf;
+                fgl[E1] = 2 * g[E1] + oa;
+                fgl[E2] = 2 * g[E2] + ob;
+                double A;
+                if (D == 0) A = fg.r[fgl[0] + 2].r2f * fg.t[fgl[1] + 2].vw * fg.p[fgl[2] + 2].vw;
+                else if (D == 1) A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].sf * fg.p[fgl[2] + 2].vw;
+                else A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].dth;
+                const double *F = a.freg + (size_t)reg * a.reg_stride;
+                const int la = fa - qa * FA, lb = fb - qb * FB;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const double corr = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
+            const size_t o = cidx<S>(slot, v, loc[0], loc[1], loc[2]);
+            a.Uout[o] += side ? adt * corr : -adt * corr;
+        }
+    }
+}
+
 template <int BI, int BJ, int BK>
 __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks)
 {
@@ -306,54 +370,10 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
         const double adt = a.alpha * dt;
         const LevelGeo lg = a.geo[bd.level], fg = a.geo[bd.level + 1];
         for (int q = t0; q < t1; ++q) {
-            const RefluxTask tk = tasks[q];
-            const int d = tk.face >> 1, side = tk.face & 1;
-            const int e1 = tan1(d), e2 = tan2(d);
-            const int FA = S::dim(e1), FB = S::dim(e2);
-            for (int c = threadIdx.x; c < FA * FB; c += blockDim.x) {
-                const int ia = c % FA, ib = c / FA;
-                int loc[3];
-                loc[d] = side ? S::dim(d) - 1 : 0;
-                loc[e1] = ia;
-                loc[e2] = ib;
-                int g[3];
-                for (int e = 0; e < 3; ++e) g[e] = bd.org[e] + loc[e];
-                const RecR rr = lg.r[g[0] + 2];
-                const RecT tt = lg.t[g[1] + 2];
-                const RecP pp = lg.p[g[2] + 2];
-                const double Vc = rr.vw * tt.vw * pp.vw;
-                double ac;
-                if (d == 0) ac = side ? rr.ap : rr.am;
-                else if (d == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
-                else ac = rr.rt * tt.phf * pp.iw;
-                // fine face index along d (global, fine level) and fine tangential cells
-                const int gf = 2 * (bd.org[d] + (side ? S::dim(d) : 0));
-                double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-                for (int ob = 0; ob < 2; ++ob) {
-                    for (int oa = 0; oa < 2; ++oa) {
-                        const int fa = 2 * ia + oa, fb = 2 * ib + ob;
-                        const int qa = fa / FA, qb = fb / FB;
-                        const int reg = tk.freg[qa + 2 * qb];
-                        int fgl[3];
-                        fgl[d] = gf;
-                        fgl[e1] = 2 * g[e1] + oa;
-                        fgl[e2] = 2 * g[e2] + ob;
-                        double A;
-                        if (d == 0) A = fg.r[fgl[0] + 2].r2f * fg.t[fgl[1] + 2].vw * fg.p[fgl[2] + 2].vw;
-                        else if (d == 1) A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].sf * fg.p[fgl[2] + 2].vw;
-                        else A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].dth;
-                        const double *F = a.freg + (size_t)reg * a.reg_stride;
-                        const int la = fa - qa * FA, lb = fb - qb * FB;
-                        for (int v = 0; v < 8; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
-                    }
-                }
-                const double *Fc = a.freg + (size_t)tk.creg * a.reg_stride;
-                for (int v = 0; v < 8; ++v) {
-                    const double corr = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
-                    const size_t o = cidx<S>(slot, v, loc[0], loc[1], loc[2]);
-                    a.Uout[o] += side ? adt * corr : -adt * corr;
-                }
-            }
+            const int d = tasks[q].face >> 1;          // uniform over the work-group
+            if (d == 0) reflux_face<BI, BJ, BK, 0>(a, tasks + q, bd, lg, fg, slot, adt);
+            else if (d == 1) reflux_face<BI, BJ, BK, 1>(a, tasks + q, bd, lg, fg, slot, adt);
+            else reflux_face<BI, BJ, BK, 2>(a, tasks + q, bd, lg, fg, slot, adt);
             __syncthreads();
         }
         // floors on the corrected cells and their CFL rates (the stage kernel took
@@ -366,18 +386,17 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             int q = t0, c = w;
             while (c >= S::face_cells(tasks[q].face >> 1)) c -= S::face_cells(tasks[q].face >> 1), ++q;
             const int d = tasks[q].face >> 1, side = tasks[q].face & 1;
-            const int e1 = tan1(d), e2 = tan2(d);
-            int loc[3];
-            loc[d] = side ? S::dim(d) - 1 : 0;
-            loc[e1] = c % S::dim(e1);
-            loc[e2] = c / S::dim(e1);
+            int i, j, k;                               // the cell: index c on face (d, side)
+            if (d == 0) i = side ? BI - 1 : 0, j = c % BJ, k = c / BJ;
+            else if (d == 1) i = c % BI, j = side ? BJ - 1 : 0, k = c / BI;
+            else i = c % BI, j = c / BI, k = side ? BK - 1 : 0;
             bool first = true;
             for (int p = t0; p < q; ++p) {
-                const int f = tasks[p].face;
-                if (loc[f >> 1] == ((f & 1) ? S::dim(f >> 1) - 1 : 0)) first = false;
+                const int f = tasks[p].face, dd = f >> 1;
+                const int x = dd == 0 ? i : (dd == 1 ? j : k);
+                if (x == ((f & 1) ? S::dim(dd) - 1 : 0)) first = false;
             }
             if (!first) continue;
-            const int i = loc[0], j = loc[1], k = loc[2];
             double u[8];
             for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
             apply_floors(u, a.gas, a.rho_floor, a.p_floor);
