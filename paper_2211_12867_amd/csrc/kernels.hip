@@ -639,11 +639,10 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
     using S = Shape<BI, BJ, BK>;
     const int m = blockIdx.x;
     if (m >= nmembers || threadIdx.x != 0) return;
-    const SampleDesc s = sd[m];
-    if (!s.valid) return;
+    if (!sd[m].valid) return;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = 0; q < 8; ++q) {
-        const SampleEntry e = s.e[q];
+        const SampleEntry &e = sd[m].e[q];      // read in place (no private copy of the descriptor)
         double u[8];
         if (e.kind == 0) {
             for (int v = 0; v < 8; ++v) u[v] = a.U[cidx<S>(e.slot, v, e.cell[0], e.cell[1], e.cell[2])];
