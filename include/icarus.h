@@ -318,7 +318,9 @@ typedef struct {
  * cache_path (a text file, one result per line; NULL = no cache), else time
  * every candidate on the current state (reps launches each; the state is not
  * changed) and append the winner to the cache (candidates within 1 % of the
- * best so far keep the earlier one; XCD-contiguous order is tried first).  The
+ * best so far keep the earlier one; XCD-contiguous order is tried first; one
+ * wave per SIMD is tried only while the launch has fewer than two work-groups
+ * per CU).  The
  * choice applies to later steps; out may be NULL.  The sim remembers the result for this work-list
  * size (and reads the cache's results for other sizes): after each regrid the
  * schedule of the new size is used, or, for a size without one, two waves per

@@ -53,7 +53,7 @@ def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
     g = dict(grid, max_level=1)
     sim = Sim(g, wind, [cme], dict(regrid_every=0))
     t0 = time.perf_counter()
-    sim.autotune(_tune_cache())
+    sim.autotune(_tune_cache(), reps=3)
     steps = 0
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
@@ -102,7 +102,7 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
     t0 = time.perf_counter()
     info = None
     while sim.time()[0] < t_end_s * (1.0 - 1e-12):
-        sim.autotune(_tune_cache())              # the work list changes with the forest
+        sim.autotune(_tune_cache(), reps=3)      # the work list changes with the forest
         info = sim.advance(min(chunk_s, t_end_s - sim.time()[0]))
         ts.append(sim.timeseries())
         sim.timeseries_clear()
@@ -195,7 +195,7 @@ def ensemble_run(grid, wind, cmes, amr, start, t_end_s, chunk_s=DAY / 4, log=pri
     info = None
     max_leaves = 0
     while min(sim.time(m)[0] for m in range(len(cmes))) < t_end_s * (1.0 - 1e-12):
-        sim.autotune(_tune_cache())
+        sim.autotune(_tune_cache(), reps=3)
         info = sim.advance(min(chunk_s, t_end_s - sim.time(0)[0]))
         for m in range(len(cmes)):
             series[m].append(sim.timeseries(m))
