@@ -82,7 +82,11 @@ k_stage(KArgs a)
     __shared__ const double *sHB[NHALO];
     __shared__ int sHV[NHALO], sHK[NHALO];
     __shared__ double sFi[8][BJ][BI + 1];
-    __shared__ double sFj[8][BJ + 1][BI];
+    // theta fluxes; rows padded so that the lanes of (d), which walk the rows,
+    // spread over the LDS banks (a row of 16 doubles would map every second row
+    // onto the same banks)
+    constexpr int SJ = BI % 8 == 0 ? BI + 4 : BI;
+    __shared__ double sFj[8][BJ + 1][SJ];
     __shared__ RecR sR[BI + 4];
     __shared__ RecT sT[BJ + 4];
     __shared__ double sred[NT / 64];
