@@ -166,9 +166,9 @@ def test_regrid_data_movement():
     assert e <= 1e-12, e
 
 
-def _amr_wedge(max_level=3):
-    grid = dict(geometry="spherical", x0=(0.1, 60.0, 0.0), x1=(1.1, 120.0, 90.0), n=(32, 16, 16),
-                block=(8, 8, 8), stretched_r=True, max_level=max_level, periodic=(False, False, False),
+def _amr_wedge(max_level=3, n=(32, 16, 16), block=(8, 8, 8)):
+    grid = dict(geometry="spherical", x0=(0.1, 60.0, 0.0), x1=(1.1, 120.0, 90.0), n=n,
+                block=block, stretched_r=True, max_level=max_level, periodic=(False, False, False),
                 gamma=1.5, cfl=0.4)
     from synthetic import Wind
     wind = as_dict(Wind(seed=3))
@@ -180,9 +180,13 @@ def _amr_wedge(max_level=3):
     return grid, wind, cme, amr
 
 
-def test_stretched_amr_wedge_flags_forest_and_state():
+@pytest.mark.parametrize("n,block", [((32, 16, 16), (8, 8, 8)), ((32, 24, 24), (16, 12, 12))])
+def test_stretched_amr_wedge_flags_forest_and_state(n, block):
+    """Three cycles of steps, flags on identical states and regrids; the second
+    case has the non-cubic blocks of the equidistant benchmark (k-split 4 by
+    the schedule rule for 8 base blocks)."""
     ic = _ic()
-    grid, wind, cme, amr = _amr_wedge()
+    grid, wind, cme, amr = _amr_wedge(n=n, block=block)
     ora = solver.Solver(grid, wind, cme, amr)
     gpu = ic.Sim(grid, wind, [cme], amr)
     gpu.set_state(*ora.state(), 0.0)
