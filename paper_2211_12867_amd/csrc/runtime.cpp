@@ -16,6 +16,8 @@
 #include <unordered_set>
 #include <stdexcept>
 #include <string>
+#include <exception>
+#include <thread>
 #include <vector>
 
 #include "../../include/icarus.h"
@@ -500,6 +502,33 @@ void select_schedule(ic_sim *s)
     if (w != s->tune_waves || g != s->tune_grid || x != s->tune_xcd || ks != s->tune_ksplit) apply_tuning(s, w, g, x, ks);
 }
 
+// f(m) for every member m, on up to 8 host threads when there are several
+// members (members are independent); the first exception is rethrown.
+template <class F>
+void for_members(int nm, F &&f)
+{
+    const int nt = std::min({nm, 8, (int)std::max(1u, std::thread::hardware_concurrency())});
+    if (nt <= 1) {
+        for (int m = 0; m < nm; ++m) f(m);
+        return;
+    }
+    std::vector<std::exception_ptr> err(nm);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t]() {
+            for (int m = t; m < nm; m += nt) {
+                try {
+                    f(m);
+                } catch (...) {
+                    err[m] = std::current_exception();
+                }
+            }
+        });
+    for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 // Host-to-device uploads of small tables: queued, then staged in one pinned
 // buffer and enqueued as asynchronous copies on the sim's stream, with one
 // synchronisation at the end (a synchronous copy from pageable memory costs
@@ -545,33 +574,39 @@ void rebuild(ic_sim *s)
     // descriptors are uploaded for the used slot range of each member only
     // (leaves take the lowest free slots); kernels read no other slot
     if ((int)s->hdesc.size() != NS) s->hdesc.assign(NS, BlockDesc{});
+    // Per member in parallel (members share no block): slab and flux-register
+    // numbers are member-local, then offset by the counts of the members
+    // before it, which gives the same numbering as one pass over the members
+    // in order (registers are keyed by slot, and slots belong to one member).
+    struct Lists {
+        std::vector<int> items;
+        std::vector<SlabTask> pass1;
+        std::vector<std::vector<SlabTask>> prol;
+        std::vector<RefluxTask> rf;
+        int nslab = 0, nreg = 0;
+    };
+    std::vector<Lists> ml(s->nm);
     std::vector<int> hi(s->nm, 0);
-    for (int m = 0; m < s->nm; ++m) {
+    for_members(s->nm, [&](int m) {
+        Lists &L = ml[m];
+        L.prol.resize(IC_MAX_LEVEL + 2);
         for (auto &kv : s->mem[m].leaves) hi[m] = std::max(hi[m], kv.second + 1);
         std::fill(s->hdesc.begin() + (size_t)m * s->max_blocks, s->hdesc.begin() + (size_t)m * s->max_blocks + hi[m],
                   BlockDesc{});
-    }
-    std::vector<int> items, mbeg(s->nm), mend(s->nm);
-    std::vector<SlabTask> pass1;
-    std::vector<std::vector<SlabTask>> prol(IC_MAX_LEVEL + 2);
-    std::unordered_map<long, int> regs;          // slot * 8 + face -> register (numbered in order of first use)
-    auto get_reg = [&](int slot, int face) {
-        auto it = regs.find((long)slot * 8 + face);
-        if (it != regs.end()) return it->second;
-        const int r = (int)regs.size();
-        regs.emplace((long)slot * 8 + face, r);
-        return r;
-    };
-    std::vector<RefluxTask> rf;
-    int nslab = 0;
-    for (int m = 0; m < s->nm; ++m) {
+        std::unordered_map<long, int> regs;      // slot * 8 + face -> register (numbered in order of first use)
+        auto get_reg = [&](int slot, int face) {
+            auto it = regs.find((long)slot * 8 + face);
+            if (it != regs.end()) return it->second;
+            const int r = (int)regs.size();
+            regs.emplace((long)slot * 8 + face, r);
+            return r;
+        };
         Member &M = s->mem[m];
         const std::vector<Key> keys = abi_sorted(M.leaves);
         const LeafIndex idx(M.leaves);
-        mbeg[m] = (int)items.size();
         for (const Key &key : keys) {
             const int slot = s->slot_of(m, idx.find(key));
-            items.push_back(slot);
+            L.items.push_back(slot);
             BlockDesc &bd = s->hdesc[slot];
             bd.level = key.l;
             bd.member = m;
@@ -589,11 +624,11 @@ void rebuild(ic_sim *s)
                     if (kind == IC_BC_INNER) {
                         SlabTask tk{};
                         tk.type = SLAB_INNER;
-                        tk.slab = nslab++;
+                        tk.slab = L.nslab++;
                         tk.slot = slot;
                         tk.face = f;
                         bd.nbr[f] = slab_code(tk.slab);
-                        pass1.push_back(tk);
+                        L.pass1.push_back(tk);
                     } else {
                         bd.nbr[f] = NBR_OUTFLOW;
                     }
@@ -610,7 +645,7 @@ void rebuild(ic_sim *s)
                     const int cslot = s->slot_of(m, coarse);
                     SlabTask tk{};
                     tk.type = SLAB_PROLONG;
-                    tk.slab = nslab++;
+                    tk.slab = L.nslab++;
                     tk.slot = slot;
                     tk.face = f;
                     tk.src[0] = cslot;
@@ -626,13 +661,13 @@ void rebuild(ic_sim *s)
                     }
                     bd.nbr[f] = slab_code(tk.slab);
                     bd.freg[f] = get_reg(slot, f);
-                    prol[key.l].push_back(tk);
+                    L.prol[key.l].push_back(tk);
                     continue;
                 }
                 // finer neighbours: the four children of the neighbour region on this face
                 SlabTask tk{};
                 tk.type = SLAB_RESTRICT;
-                tk.slab = nslab++;
+                tk.slab = L.nslab++;
                 tk.slot = slot;
                 tk.face = f;
                 const int e1 = tan1(d), e2 = tan2(d);
@@ -662,12 +697,50 @@ void rebuild(ic_sim *s)
                 bd.freg[f] = get_reg(slot, f);
                 bd.reflux_mask |= 1 << f;
                 rt.creg = bd.freg[f];
-                rf.push_back(rt);
-                pass1.push_back(tk);
+                L.rf.push_back(rt);
+                L.pass1.push_back(tk);
             }
         }
-        mend[m] = (int)items.size();
+        L.nreg = (int)regs.size();
+    });
+    std::vector<int> slab_off(s->nm + 1, 0), reg_off(s->nm + 1, 0);
+    for (int m = 0; m < s->nm; ++m) {
+        slab_off[m + 1] = slab_off[m] + ml[m].nslab;
+        reg_off[m + 1] = reg_off[m] + ml[m].nreg;
     }
+    for_members(s->nm, [&](int m) {
+        Lists &L = ml[m];
+        const int so = slab_off[m], ro = reg_off[m];
+        if (so == 0 && ro == 0) return;
+        for (int slot : L.items) {
+            BlockDesc &bd = s->hdesc[slot];
+            for (int f = 0; f < 6; ++f) {
+                if (bd.nbr[f] <= slab_code(0)) bd.nbr[f] = slab_code(nbr_slab(bd.nbr[f]) + so);
+                if (bd.freg[f] >= 0) bd.freg[f] += ro;
+            }
+        }
+        for (auto &tk : L.pass1) tk.slab += so;
+        for (auto &v : L.prol)
+            for (auto &tk : v) tk.slab += so;
+        for (auto &rt : L.rf) {
+            rt.creg += ro;
+            for (int q = 0; q < 4; ++q) rt.freg[q] += ro;
+        }
+    });
+    std::vector<int> items, mbeg(s->nm), mend(s->nm);
+    std::vector<SlabTask> pass1;
+    std::vector<std::vector<SlabTask>> prol(IC_MAX_LEVEL + 2);
+    std::vector<RefluxTask> rf;
+    for (int m = 0; m < s->nm; ++m) {
+        Lists &L = ml[m];
+        mbeg[m] = (int)items.size();
+        items.insert(items.end(), L.items.begin(), L.items.end());
+        mend[m] = (int)items.size();
+        pass1.insert(pass1.end(), L.pass1.begin(), L.pass1.end());
+        for (int l = 0; l < IC_MAX_LEVEL + 2; ++l) prol[l].insert(prol[l].end(), L.prol[l].begin(), L.prol[l].end());
+        rf.insert(rf.end(), L.rf.begin(), L.rf.end());
+    }
+    const int nslab = slab_off[s->nm];
     // task lists: pass 1 (inner + restrict), then prolongation by owner level
     std::vector<SlabTask> all = pass1;
     s->pass_lo[0] = 0;
@@ -692,7 +765,7 @@ void rebuild(ic_sim *s)
     }
     s->n_items = (int)items.size();
     s->n_slabs = nslab;
-    s->n_regs = (int)regs.size();
+    s->n_regs = reg_off[s->nm];
     s->n_rf_blocks = (int)rfb.size() / 2;
     s->any_reflux = !rf.empty();
 
@@ -1448,9 +1521,10 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
     } else if (!user_flags) {
         plain_flags(s, fl);
     }
-    std::vector<MoveTask> moves;
-    std::vector<int> to_free;
-    for (int m = 0; m < s->nm; ++m) {
+    // members in parallel; moves and freed slots concatenated in member order
+    std::vector<std::vector<MoveTask>> mv(s->nm);
+    std::vector<std::vector<int>> fr(s->nm);
+    for_members(s->nm, [&](int m) {
         Member &M = s->mem[m];
         std::unordered_map<uint64_t, int8_t> f;
         f.reserve(2 * M.leaves.size() + 1);
@@ -1460,7 +1534,13 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
         } else {
             for (auto &kv : M.leaves) f[kcode(kv.first)] = fl[s->slot_of(m, kv.second)];
         }
-        regrid_member(s, m, f, s->amr.buffer_blocks, moves, to_free);
+        regrid_member(s, m, f, s->amr.buffer_blocks, mv[m], fr[m]);
+    });
+    std::vector<MoveTask> moves;
+    std::vector<int> to_free;
+    for (int m = 0; m < s->nm; ++m) {
+        moves.insert(moves.end(), mv[m].begin(), mv[m].end());
+        to_free.insert(to_free.end(), fr[m].begin(), fr[m].end());
     }
     if (!moves.empty()) {
         s->moves.alloc(moves.size());
