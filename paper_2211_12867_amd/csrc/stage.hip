@@ -14,10 +14,11 @@
 // metric, the hoop, Coriolis, centrifugal and gravity sources, applies the
 // floors and writes U_out = U_base + alpha dt L(U).  The last wave, which owns
 // no column, starts the asynchronous HBM-to-LDS copy of the next plane's halo
-// when a plane begins; during the update it converts that halo to primitives
-// and copies the column plane three ahead.  Halo cells come from neighbouring
-// blocks (same level), the block's own edge (outflow) or ghost slabs (inner
-// boundary, coarse-fine faces).
+// once its share of the plane's r/theta fluxes is done; during the update it
+// starts the copy of the column plane three ahead, waits for both and converts
+// the halo to primitives.  Halo cells come from neighbouring blocks (same
+// level), the block's own edge (outflow) or ghost slabs (inner boundary,
+// coarse-fine faces).  The block's phi metric records sit in LDS.
 #include "common.h"
 
 // ---------------------------------------------------------------------------
@@ -25,14 +26,14 @@
 // ---------------------------------------------------------------------------
 
 // Cell t of the 4 (BI + BJ) r/theta halo cells of plane k (two layers on each
-// side, r-halo first): its (i, j).
+// side, r-halo first, its two layers of one j adjacent): its (i, j).
 template <int BI, int BJ>
 DEV void halo_cell(int t, int &i, int &j)
 {
     if (t < 4 * BJ) {                 // r-direction halo
         const int side = t / (2 * BJ), rem = t % (2 * BJ);
-        const int l = rem / BJ;
-        j = rem % BJ;
+        const int l = rem % 2;
+        j = rem / 2;
         i = side ? BI + l : l - 2;
     } else {                          // theta-direction halo
         const int q = t - 4 * BJ;
@@ -70,6 +71,7 @@ k_stage(KArgs a)
     constexpr int CWAVE = NT / 64 - 1;
     constexpr int NHR = 4 * BJ, NHT = 4 * BI;    // r-halo cells (first), theta-halo cells
     constexpr int NHP = NHR * 8 * 2;             // r-halo: one 4-byte piece per lane, two per double
+    constexpr int NHQ = NHR / 2 * 8;             // r-halo between same-level blocks: one 16-byte piece (two layers) per lane
     constexpr int NTP = NHT / 2 * 8;             // theta-halo rows: one 16-byte piece (two cells) per lane
     constexpr int NCP = NCOL / 2 * 8;            // column plane: one 16-byte piece (two cells) per lane
     static_assert(NCOL % 2 == 0 && BI % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
@@ -89,6 +91,7 @@ k_stage(KArgs a)
     __shared__ double sFj[8][BJ + 1][SJ];
     __shared__ RecR sR[BI + 4];
     __shared__ RecT sT[BJ + 4];
+    __shared__ RecP sP[BK + 4];
     __shared__ double sred[NT / 64];
 
     const int tid = threadIdx.x;
@@ -108,6 +111,9 @@ k_stage(KArgs a)
         const int mem = a.desc[slot].member;
         for (int e = 0; e < 3; ++e) bd.org[e] = a.desc[slot].org[e];
         bd.reflux_mask = a.desc[slot].reflux_mask;
+        // both r-neighbours on the same level: the two halo layers of a row are
+        // adjacent cells of the neighbour (else an outflow copy or a ghost slab)
+        const bool rpair = a.desc[slot].nbr[0] >= 0 && a.desc[slot].nbr[1] >= 0;
         for (int e = 0; e < 6; ++e) bd.freg[e] = a.desc[slot].freg[e];
         const double dt = a.dt[mem];
         if (dt <= 0.0) continue;                 // member finished: state stays in place
@@ -117,6 +123,8 @@ k_stage(KArgs a)
         __syncthreads();
         for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
+        for (int m = tid; m < BK + 4; m += NT) sP[m] = lg.p[bd.org[2] + m];
+        __syncthreads();
 
         // --- prologue: column primitives of planes k0 and k0+1, phi-face k0-1/2
         // registers carried along k: Wn = W(k+1), wL = face state of cell k at
@@ -129,7 +137,7 @@ k_stage(KArgs a)
             ghosted8<S>(a, a.U, slot, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
             ghosted8<S>(a, a.U, slot, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
             ghosted8<S>(a, a.U, slot, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
-            const RecP pm1 = lg.p[bd.org[2] + k0 - 1 + 2], p0 = lg.p[bd.org[2] + k0 + 2];
+            const RecP pm1 = sP[k0 + 1], p0 = sP[k0 + 2];
             reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
             reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
             rusanov<2>(hi, R0, Fm, gs);
@@ -166,35 +174,6 @@ k_stage(KArgs a)
 
         for (int k = k0; k < k1; ++k) {
             // plane k with its i/j halos is in LDS
-            if (k + 1 < k1 && (tid >> 6) == CWAVE) {
-                // the last wave starts the copies of the conserved r/theta halo of
-                // plane k+1 into LDS (free since the last barrier); they land while
-                // the plane's fluxes are computed
-                const int lane = tid & 63;
-                typedef __attribute__((address_space(3))) char lds_t;
-#pragma unroll 2
-                for (int q = 0; q * 64 < NHP; ++q) {
-                    const int g = q * 64 + lane;
-                    if (g < NHP) {
-                        const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
-                        const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
-                        __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
-                    }
-                }
-#pragma unroll 2
-                for (int q = 0; q * 64 < NTP; ++q) {
-                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
-                    const int g = q * 64 + lane;
-                    if (g < NTP) {
-                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
-                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
-                        __builtin_amdgcn_global_load_lds((const void *)src,
-                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
-                    }
-                }
-            }
-
             // (c) r-faces of the plane.  A row of lanes takes the cells c = -1 .. BI
             // of one j: each lane reconstructs its cell's two face states once,
             // passes the upper one to the next lane through LDS (a row lies within
@@ -276,6 +255,50 @@ k_stage(KArgs a)
                     }
                 }
             }
+            if (k + 1 < k1 && (tid >> 6) == CWAVE) {
+                // the last wave, done with its LDS work of this phase, starts the
+                // copies of the conserved r/theta halo of plane k+1 into LDS (read
+                // before the last barrier); they land while the other waves finish
+                // the plane's fluxes (a wave's LDS accesses wait for its own copies
+                // into LDS, so it issues them after its own reads)
+                const int lane = tid & 63;
+                typedef __attribute__((address_space(3))) char lds_t;
+                if (rpair) {
+#pragma unroll 2
+                    for (int q = 0; q * 64 < NHQ; ++q) {
+                        const int g = q * 64 + lane;
+                        if (g < NHQ) {
+                            const int v = g / (NHR / 2), cell = 2 * (g % (NHR / 2));
+                            const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
+                            __builtin_amdgcn_global_load_lds((const void *)src,
+                                                             (lds_t *)((lds_t *)&sHalR[0][0] + q * 1024), 16, 0, 0);
+                        }
+                    }
+                } else {
+#pragma unroll 2
+                    for (int q = 0; q * 64 < NHP; ++q) {
+                        const int g = q * 64 + lane;
+                        if (g < NHP) {
+                            const int v = g / (2 * NHR), cell = (g >> 1) % NHR, half = g & 1;
+                            const char *src = (const char *)(sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell]) + 4 * half;
+                            __builtin_amdgcn_global_load_lds((const void *)src,
+                                                             (lds_t *)((lds_t *)&sHalR[0][0] + q * 256), 4, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll 2
+                for (int q = 0; q * 64 < NTP; ++q) {
+                    // theta-halo rows are contiguous in i in a block, a slab or an outflow copy
+                    const int g = q * 64 + lane;
+                    if (g < NTP) {
+                        const int v = g / (NHT / 2), cell = NHR + 2 * (g % (NHT / 2));
+                        const double *src = sHB[cell] + v * sHV[cell] + (k + 1) * sHK[cell];
+                        __builtin_amdgcn_global_load_lds((const void *)src,
+                                                         (lds_t *)((lds_t *)&sHalT[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+            }
+
             // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
             double Fp[8], Wnext[8];
             if (col) {
@@ -285,7 +308,7 @@ k_stage(KArgs a)
                 cons_to_prim(u, W2, gs);
 #pragma unroll
                 for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
-                const RecP pk1 = lg.p[bd.org[2] + k + 3];
+                const RecP pk1 = sP[k + 3];
                 double hi1[8];
                 reconstruct(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
                 rusanov<2>(wL, lo1, Fp, gs);
@@ -305,7 +328,7 @@ k_stage(KArgs a)
 
             // (g) update of cell (ci, cj, k)
             if (col) {
-                const RecP pk = lg.p[bd.org[2] + k + 2];
+                const RecP pk = sP[k + 2];
                 const RecR rr = sR[ci + 2];
                 const RecT tt = sT[cj + 2];
                 double w[8];
@@ -346,13 +369,24 @@ k_stage(KArgs a)
                     sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
                 }
             } else if (k + 1 < k1 && (tid >> 6) == CWAVE) {
-                // (p) meanwhile the last wave (no column) converts the halo of plane
-                // k+1 (copied since the start of this plane) to primitives, then
-                // copies the column plane k+3 (read in (e) of the next plane; this
-                // plane's copy was read before the last barrier) from HBM into LDS
+                // (p) meanwhile the last wave (no column) starts the copy of the
+                // column plane k+3 from HBM into LDS (read in (e) of the next plane;
+                // this plane's copy was read before the last barrier), waits for it
+                // and for the halo copies of plane k+1, and converts that halo to
+                // primitives
                 const int lane = tid & 63;
                 typedef __attribute__((address_space(3))) char lds_t;
-                __builtin_amdgcn_s_waitcnt(0);           // the halo copies have landed
+#pragma unroll 2
+                for (int q = 0; q * 64 < NCP; ++q) {
+                    const int g = q * 64 + lane;
+                    if (g < NCP) {
+                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
+                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
+                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
+                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0);           // column plane k+3 and the halo have landed
 #pragma unroll 1
                 for (int t = lane; t < NHALO; t += 64) {
                     int i, j;
@@ -364,17 +398,6 @@ k_stage(KArgs a)
 #pragma unroll
                     for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
                 }
-#pragma unroll 2
-                for (int q = 0; q * 64 < NCP; ++q) {
-                    const int g = q * 64 + lane;
-                    if (g < NCP) {
-                        const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
-                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
-                        __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
-                                                         (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
-                    }
-                }
-                __builtin_amdgcn_s_waitcnt(0);           // column plane k+3 has landed
             }
             __syncthreads();
         }
