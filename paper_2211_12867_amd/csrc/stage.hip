@@ -44,6 +44,58 @@ DEV void halo_cell(int t, int &i, int &j)
     }
 }
 
+// The six face codes of a block (BlockDesc::nbr), held in scalar registers.
+struct Faces {
+    int n0, n1, n2, n3, n4, n5;
+};
+
+DEV int face_code(const Faces &nb, int f)
+{
+    return f == 0 ? nb.n0 : f == 1 ? nb.n1 : f == 2 ? nb.n2 : f == 3 ? nb.n3 : f == 4 ? nb.n4 : nb.n5;
+}
+
+// Address of variable v of the cell (i, j, k) of block `slot`, where at most
+// one index lies in the two ghost layers (interior, same-level neighbour,
+// outflow copy of the edge cell or ghost slab), with the block's face codes
+// in registers: the cases of ghosted_addr without a descriptor load per
+// lane.  With i = j = 0 it gives the start of a k-plane, whose cells are
+// contiguous in i, then j, in a block, a slab and an outflow copy.
+template <class S>
+DEV const double *cell_addr(const double *__restrict__ U, const double *__restrict__ slabs, long slab_stride,
+                            int slot, const Faces &nb, int v, int i, int j, int k)
+{
+    int idx[3] = {i, j, k};
+    int d = -1;
+    if (i < 0 || i >= S::B0) d = 0;
+    else if (j < 0 || j >= S::B1) d = 1;
+    else if (k < 0 || k >= S::B2) d = 2;
+    if (d < 0) return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+    const int Bd = S::dim(d);
+    const int side = idx[d] >= Bd ? 1 : 0;
+    const int l = side ? idx[d] - Bd : idx[d] + 2;
+    const int code = face_code(nb, 2 * d + side);
+    if (code >= 0) {
+        idx[d] = side ? l : Bd - 2 + l;
+        return U + (size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+    }
+    if (code == NBR_OUTFLOW) {
+        idx[d] = side ? Bd - 1 : 0;
+        return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+    }
+    const int a = idx[tan1(d)], b = idx[tan2(d)];
+    const int FA = S::dim(tan1(d)), FB = S::dim(tan2(d));
+    return slabs + (size_t)nbr_slab(code) * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a;
+}
+
+// Conserved state of the column (ci, cj) in k-plane k (possibly a ghost plane).
+template <class S>
+DEV void column8(const KArgs &a, int slot, const Faces &nb, int ci, int cj, int k, double u[8])
+{
+    const int off = ci + S::B0 * cj;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) u[v] = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, 0, 0, k)[off];
+}
+
 // Work item of linear work index w when a.xcd_order is set: the work-groups
 // of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
 // into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
@@ -107,6 +159,7 @@ k_stage(KArgs a)
         const int it = ww / ks, part = ww % ks;
         const int k0 = part * BK / ks, k1 = (part + 1) * BK / ks;
         const int slot = a.items[it];
+        // block descriptor in scalar registers (only constant indices into bd)
         struct { int org[3]; int reflux_mask; int freg[6]; } bd;
         const int mem = a.desc[slot].member;
         for (int e = 0; e < 3; ++e) bd.org[e] = a.desc[slot].org[e];
@@ -115,6 +168,10 @@ k_stage(KArgs a)
         // adjacent cells of the neighbour (else an outflow copy or a ghost slab)
         const bool rpair = a.desc[slot].nbr[0] >= 0 && a.desc[slot].nbr[1] >= 0;
         for (int e = 0; e < 6; ++e) bd.freg[e] = a.desc[slot].freg[e];
+        const int *dn = a.desc[slot].nbr;
+        const Faces nb{__builtin_amdgcn_readfirstlane(dn[0]), __builtin_amdgcn_readfirstlane(dn[1]),
+                       __builtin_amdgcn_readfirstlane(dn[2]), __builtin_amdgcn_readfirstlane(dn[3]),
+                       __builtin_amdgcn_readfirstlane(dn[4]), __builtin_amdgcn_readfirstlane(dn[5])};
         const double dt = a.dt[mem];
         if (dt <= 0.0) continue;                 // member finished: state stays in place
         const LevelGeo lg = a.geo[a.desc[slot].level];
@@ -133,39 +190,58 @@ k_stage(KArgs a)
         int badc = -1;                           // first non-physical input cell of this column
         if (col) {
             double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
-            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
-            ghosted8<S>(a, a.U, slot, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
+            column8<S>(a, slot, nb, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
+            column8<S>(a, slot, nb, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
+            column8<S>(a, slot, nb, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
+            column8<S>(a, slot, nb, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
             const RecP pm1 = sP[k0 + 1], p0 = sP[k0 + 2];
             reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
             reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
             rusanov<2>(hi, R0, Fm, gs);
-            const int r = k0 == 0 ? a.desc[slot].freg[4] : -1;
+            const int r = k0 == 0 ? bd.freg[4] : -1;
             if (r >= 0)
                 for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
 #pragma unroll
             for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
         }
-        // halos of plane k0, by all threads; the halo address table
-        for (int t = tid; t < NHALO; t += NT) {
-            int i, j;
-            halo_cell<BI, BJ>(t, i, j);
-            {
-                const double *p0 = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 0);
-                sHB[t] = p0;
-                sHV[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 1, i, j, 0) - p0);
-                sHK[t] = (int)(ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, 0, i, j, 1) - p0);
-            }
-            double u[8], w[8];
-            ghosted8<S>(a, a.U, slot, i, j, k0, u);
-            cons_to_prim(u, w, gs);
+        // halos of plane k0 and the halo address table (a halo cell's address
+        // is affine in v and in k within the block's k-range), by the threads
+        // that own no column, beside the column prologue; all loads first
+        if (!col) {
+            constexpr int NSP = NT - NCOL, HIT = (NHALO + NSP - 1) / NSP;
+            double u[HIT][8];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+            for (int h = 0; h < HIT; ++h) {
+                const int t = tid - NCOL + h * NSP;
+                if (t < NHALO) {
+                    int i, j;
+                    halo_cell<BI, BJ>(t, i, j);
+                    const double *p0 = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 0, i, j, 0);
+                    const int hv = (int)(cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 1, i, j, 0) - p0);
+                    const int hk = (int)(cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 0, i, j, 1) - p0);
+                    sHB[t] = p0;
+                    sHV[t] = hv;
+                    sHK[t] = hk;
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) u[h][v] = p0[v * hv + k0 * hk];
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < HIT; ++h) {
+                const int t = tid - NCOL + h * NSP;
+                if (t < NHALO) {
+                    int i, j;
+                    halo_cell<BI, BJ>(t, i, j);
+                    double w[8];
+                    cons_to_prim(u[h], w, gs);
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+                }
+            }
         }
         for (int c = tid; c < NCOL; c += NT) {
             double u[8];
-            ghosted8<S>(a, a.U, slot, c % BI, c / BI, k0 + 2, u);
+            column8<S>(a, slot, nb, c % BI, c / BI, k0 + 2, u);
 #pragma unroll
             for (int v = 0; v < 8; ++v) sCol[v][c] = u[v];
         }
@@ -209,7 +285,7 @@ k_stage(KArgs a)
 #pragma unroll
                     for (int v = 0; v < 8; ++v) sFi[v][j][c] = fx[v];
                     if (c == 0 || c == BI) {      // raw flux at a coarse-fine face, for the reflux
-                        const int r = bd.freg[c == 0 ? 0 : 1];
+                        const int r = c == 0 ? bd.freg[0] : bd.freg[1];
                         if (r >= 0)
                             for (int v = 0; v < 8; ++v)
                                 a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
@@ -248,7 +324,7 @@ k_stage(KArgs a)
 #pragma unroll
                     for (int v = 0; v < 8; ++v) sFj[v][c][i] = fx[v];
                     if (c == 0 || c == BJ) {
-                        const int r = bd.freg[c == 0 ? 2 : 3];
+                        const int r = c == 0 ? bd.freg[2] : bd.freg[3];
                         if (r >= 0)
                             for (int v = 0; v < 8; ++v)
                                 a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
@@ -381,7 +457,7 @@ k_stage(KArgs a)
                     const int g = q * 64 + lane;
                     if (g < NCP) {
                         const int v = g / (NCOL / 2), pr = g % (NCOL / 2);
-                        const double *base = ghosted_addr<S>(a.U, a.desc, a.slabs, a.slab_stride, slot, v, 0, 0, k + 3);
+                        const double *base = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, 0, 0, k + 3);
                         __builtin_amdgcn_global_load_lds((const void *)(base + 2 * pr),
                                                          (lds_t *)((lds_t *)&sCol[0][0] + q * 1024), 16, 0, 0);
                     }
