@@ -86,6 +86,58 @@ __device__ inline const double *ghosted_addr(const double *__restrict__ U, const
     return slabs + (size_t)s * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a;
 }
 
+// The six face codes of a block (BlockDesc::nbr), held in scalar registers.
+struct Faces {
+    int n0, n1, n2, n3, n4, n5;
+};
+
+// Face codes of block `slot` (the same for every lane of the work-group).
+__device__ inline Faces load_faces(const BlockDesc *desc, int slot)
+{
+    const int *dn = desc[slot].nbr;
+    return Faces{__builtin_amdgcn_readfirstlane(dn[0]), __builtin_amdgcn_readfirstlane(dn[1]),
+                 __builtin_amdgcn_readfirstlane(dn[2]), __builtin_amdgcn_readfirstlane(dn[3]),
+                 __builtin_amdgcn_readfirstlane(dn[4]), __builtin_amdgcn_readfirstlane(dn[5])};
+}
+
+DEV int face_code(const Faces &nb, int f)
+{
+    return f == 0 ? nb.n0 : f == 1 ? nb.n1 : f == 2 ? nb.n2 : f == 3 ? nb.n3 : f == 4 ? nb.n4 : nb.n5;
+}
+
+// Address of variable v of the cell (i, j, k) of block `slot`, where at most
+// one index lies in the two ghost layers (interior, same-level neighbour,
+// outflow copy of the edge cell or ghost slab), with the block's face codes
+// in registers: the cases of ghosted_addr without a descriptor load per
+// lane.  With i = j = 0 it gives the start of a k-plane, whose cells are
+// contiguous in i, then j, in a block, a slab and an outflow copy.
+template <class S>
+DEV const double *cell_addr(const double *__restrict__ U, const double *__restrict__ slabs, long slab_stride,
+                            int slot, const Faces &nb, int v, int i, int j, int k)
+{
+    int idx[3] = {i, j, k};
+    int d = -1;
+    if (i < 0 || i >= S::B0) d = 0;
+    else if (j < 0 || j >= S::B1) d = 1;
+    else if (k < 0 || k >= S::B2) d = 2;
+    if (d < 0) return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+    const int Bd = S::dim(d);
+    const int side = idx[d] >= Bd ? 1 : 0;
+    const int l = side ? idx[d] - Bd : idx[d] + 2;
+    const int code = face_code(nb, 2 * d + side);
+    if (code >= 0) {
+        idx[d] = side ? l : Bd - 2 + l;
+        return U + (size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+    }
+    if (code == NBR_OUTFLOW) {
+        idx[d] = side ? Bd - 1 : 0;
+        return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+    }
+    const int a = idx[tan1(d)], b = idx[tan2(d)];
+    const int FA = S::dim(tan1(d)), FB = S::dim(tan2(d));
+    return slabs + (size_t)nbr_slab(code) * slab_stride + ((size_t)(v * 2 + l) * FB + b) * FA + a;
+}
+
 template <class S>
 __device__ inline double ghosted(const double *__restrict__ U, const BlockDesc *__restrict__ desc,
                                  const double *__restrict__ slabs, long slab_stride, int slot, int v,

@@ -90,6 +90,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         constexpr int HA = FA / 2, HB = FB / 2, NP = HA * HB;
         const LevelGeo cg = a.geo[bd.level - 1];
         const int cs = tkp->src[0];
+        const Faces cnb = load_faces(a.desc, cs);   // the coarse parent block's face codes
         const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
         const int cwrap[3] = {tkp->cwrap[0], tkp->cwrap[1], tkp->cwrap[2]};
         // (1) per parent and variable: coarse value and minmod slopes along r, theta, phi
@@ -108,7 +109,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             }
             const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
             const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
-            const double uc = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, cl[0], cl[1], cl[2]);
+            const double uc = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, cl[0], cl[1], cl[2]);
             double *P = sP + (c * 8 + v) * 4;
             P[0] = uc;
 #pragma unroll
@@ -116,8 +117,8 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
                 int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
                 lm[e] -= 1;
                 lp[e] += 1;
-                const double um = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lm[0], lm[1], lm[2]);
-                const double up = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, cs, v, lp[0], lp[1], lp[2]);
+                const double um = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lm[0], lm[1], lm[2]);
+                const double up = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lp[0], lp[1], lp[2]);
                 const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
                 P[1 + e] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
             }
@@ -498,6 +499,11 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int slot = a.items[it];
         const BlockDesc bd = a.desc[slot];
+        const Faces nb = load_faces(a.desc, slot);
+        auto cell8 = [&](int i, int j, int k, double u[8]) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = *cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, i, j, k);
+        };
         const LevelGeo lg = a.geo[bd.level];
         const double lon_c = a.mc[bd.member].lon_cme;
         const int cme_on = a.mc[bd.member].enabled;
@@ -517,7 +523,7 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
                 if (cme_on) win = win && fabs(wrap(pp.pc - lon_c)) <= dlon_c;
             }
             double u[8], w0[8];
-            ghosted8<S>(a, a.U, slot, ijk[0], ijk[1], ijk[2], u);
+            cell8(ijk[0], ijk[1], ijk[2], u);
             cons_to_prim<true>(u, w0, a.gas);
             const double r0 = w0[0];
             const double s0 = sqrt(w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]);
@@ -527,9 +533,9 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
                 lo[d] -= 1;
                 hi[d] += 1;
                 double wl[8], wh[8];
-                ghosted8<S>(a, a.U, slot, lo[0], lo[1], lo[2], u);
+                cell8(lo[0], lo[1], lo[2], u);
                 cons_to_prim<true>(u, wl, a.gas);
-                ghosted8<S>(a, a.U, slot, hi[0], hi[1], hi[2], u);
+                cell8(hi[0], hi[1], hi[2], u);
                 cons_to_prim<true>(u, wh, a.gas);
                 const double rl = wl[0], rh = wh[0];
                 const double sl = sqrt(wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
