@@ -848,11 +848,24 @@ KArgs base_args(ic_sim *s)
 
 int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
 
+// Launch size for n work items, rounded up to one of 8 steps per power of two
+// (1400 -> 1408, 1433 -> 1536): the kernels stride over device-side counts and
+// let surplus work-groups exit, so a size that covers n is enough, and a
+// captured step graph survives regrids that move n within one step.
+int quant_grid(int n, int cap)
+{
+    n = std::max(1, n);
+    int b = 1;
+    while (b * 2 <= n) b *= 2;
+    const int step = std::max(1, b / 8);
+    return std::max(1, std::min((n + step - 1) / step * step, cap));
+}
+
 // stage launch: one work-group per work item, or a persistent grid of
 // tune_grid work-groups striding over the work list
 int stage_grid(const ic_sim *s)
 {
-    const int n = std::max(1, s->n_items * s->tune_ksplit);
+    const int n = quant_grid(s->n_items * s->tune_ksplit, 1 << 30);
     return s->tune_grid > 0 ? std::min(n, s->tune_grid) : n;
 }
 
@@ -862,13 +875,15 @@ int slab_grid(const ic_sim *s, int pass)
 {
     const int n = pass == 0 ? s->pass_hi[0] - s->pass_lo[0]
                             : (s->max_level > 1 ? s->pass_hi[s->max_level] - s->pass_lo[2] : 0);
-    return grid_for(n, 8192);
+    return quant_grid(n, 8192);
 }
+
+int reflux_grid(const ic_sim *s) { return s->any_reflux ? quant_grid(s->n_rf_blocks, 8192) : 0; }
 
 // launch sizes of a step; a captured step graph is re-made when they change
 std::vector<int> launch_sig(const ic_sim *s)
 {
-    return {stage_grid(s), slab_grid(s, 0), slab_grid(s, 1), s->any_reflux ? grid_for(s->n_rf_blocks, 8192) : 0};
+    return {stage_grid(s), slab_grid(s, 0), slab_grid(s, 1), reflux_grid(s)};
 }
 
 void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
@@ -901,10 +916,7 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
     } else {
         s->L.stage(dim3(g), s->stream, a, s->tune_waves);
     }
-    if (s->any_reflux) {
-        const int gr = grid_for(s->n_rf_blocks, 8192);
-        s->L.reflux(dim3(gr), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
-    }
+    if (s->any_reflux) s->L.reflux(dim3(reflux_grid(s)), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
 }
 
 void enqueue_rate(ic_sim *s)
