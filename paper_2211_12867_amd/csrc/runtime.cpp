@@ -12,8 +12,6 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
-#include <unordered_map>
-#include <unordered_set>
 #include <stdexcept>
 #include <string>
 #include <exception>
@@ -154,18 +152,81 @@ inline uint64_t kcode(const Key &k)
            (uint64_t)(k.k & 0xFFFFF);
 }
 
+// Hash map from a nonzero 64-bit key (a kcode: level >= 1 sets the top bits)
+// to an int: open addressing with linear probing, power-of-two capacity kept
+// at most half full, multiplicative (Fibonacci) hashing.  Lookups only; the
+// regrid never iterates over it, so its order does not matter.
+struct FlatMap {
+    std::vector<uint64_t> keys;
+    std::vector<int> vals;
+    size_t mask = 0, count = 0;
+    int shift = 64;
+    explicit FlatMap(size_t n = 0) { reserve(n); }
+    size_t pos(uint64_t k) const { return (size_t)((k * 0x9E3779B97F4A7C15ull) >> shift); }
+    void reserve(size_t n)
+    {
+        size_t cap = 16;
+        int bits = 4;
+        while (cap < 2 * n + 2) {
+            cap *= 2;
+            ++bits;
+        }
+        if (cap <= keys.size()) return;
+        std::vector<uint64_t> ok(cap, 0);
+        std::vector<int> ov(cap, 0);
+        ok.swap(keys);
+        ov.swap(vals);
+        mask = cap - 1;
+        shift = 64 - bits;
+        for (size_t q = 0; q < ok.size(); ++q)
+            if (ok[q]) {
+                size_t r = pos(ok[q]);
+                while (keys[r]) r = (r + 1) & mask;
+                keys[r] = ok[q];
+                vals[r] = ov[q];
+            }
+    }
+    const int *find(uint64_t k) const
+    {
+        for (size_t q = pos(k);; q = (q + 1) & mask) {
+            if (keys[q] == k) return &vals[q];
+            if (!keys[q]) return nullptr;
+        }
+    }
+    // the value of k, inserted as 0 if absent (the reference lasts until the next insertion)
+    int &operator[](uint64_t k)
+    {
+        if (2 * (count + 1) > keys.size()) reserve(count + 1);
+        for (size_t q = pos(k);; q = (q + 1) & mask) {
+            if (keys[q] == k) return vals[q];
+            if (!keys[q]) {
+                keys[q] = k;
+                vals[q] = 0;
+                ++count;
+                return vals[q];
+            }
+        }
+    }
+    bool insert(uint64_t k)    // true if k was absent (value 0)
+    {
+        const size_t before = count;
+        (*this)[k];
+        return count != before;
+    }
+    bool contains(uint64_t k) const { return find(k) != nullptr; }
+};
+
 // hashed view of a leaf map: key -> local slot
 struct LeafIndex {
-    std::unordered_map<uint64_t, int> h;
-    explicit LeafIndex(const std::map<Key, int> &leaves)
+    FlatMap h;
+    explicit LeafIndex(const std::map<Key, int> &leaves) : h(leaves.size())
     {
-        h.reserve(2 * leaves.size() + 1);
-        for (auto &kv : leaves) h.emplace(kcode(kv.first), kv.second);
+        for (auto &kv : leaves) h[kcode(kv.first)] = kv.second;
     }
     int find(const Key &k) const   // local slot, or -1
     {
-        auto it = h.find(kcode(k));
-        return it == h.end() ? -1 : it->second;
+        const int *v = h.find(kcode(k));
+        return v ? *v : -1;
     }
 };
 
@@ -593,13 +654,11 @@ void rebuild(ic_sim *s)
         for (auto &kv : s->mem[m].leaves) hi[m] = std::max(hi[m], kv.second + 1);
         std::fill(s->hdesc.begin() + (size_t)m * s->max_blocks, s->hdesc.begin() + (size_t)m * s->max_blocks + hi[m],
                   BlockDesc{});
-        std::unordered_map<long, int> regs;      // slot * 8 + face -> register (numbered in order of first use)
+        FlatMap regs(64);                        // slot * 8 + face + 1 -> register + 1 (numbered in order of first use)
         auto get_reg = [&](int slot, int face) {
-            auto it = regs.find((long)slot * 8 + face);
-            if (it != regs.end()) return it->second;
-            const int r = (int)regs.size();
-            regs.emplace((long)slot * 8 + face, r);
-            return r;
+            int &v = regs[(uint64_t)slot * 8 + face + 1];
+            if (v == 0) v = (int)regs.count;     // just inserted: the next number
+            return v - 1;
         };
         Member &M = s->mem[m];
         const std::vector<Key> keys = abi_sorted(M.leaves);
@@ -701,7 +760,7 @@ void rebuild(ic_sim *s)
                 L.pass1.push_back(tk);
             }
         }
-        L.nreg = (int)regs.size();
+        L.nreg = (int)regs.count;
     });
     std::vector<int> slab_off(s->nm + 1, 0), reg_off(s->nm + 1, 0);
     for (int m = 0; m < s->nm; ++m) {
@@ -1253,17 +1312,16 @@ std::string describe_bad(ic_sim *s, int m, int slot, int cell)
 }
 
 
-void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> &flags_in, int buffer_blocks,
+void regrid_member(ic_sim *s, int m, const FlatMap &flags_in, int buffer_blocks,
                    std::vector<MoveTask> &moves, std::vector<int> &to_free)
 {
     Member &M = s->mem[m];
     Forest F{s, M.leaves, s->max_level};
     // flags per leaf (hashed); every pass below walks the leaves in key order
-    std::unordered_map<uint64_t, int> f;
-    f.reserve(2 * M.leaves.size() + 1);
+    FlatMap f(2 * M.leaves.size() + 1);
     for (auto &kv : M.leaves) {
-        auto it = flags_in.find(kcode(kv.first));
-        int v = it == flags_in.end() ? 0 : it->second;
+        const int *fi = flags_in.find(kcode(kv.first));
+        int v = fi ? *fi : 0;
         if (v == 1 && kv.first.l >= s->max_level) v = 0;
         if (v == -1 && kv.first.l <= 1) v = 0;
         f[kcode(kv.first)] = v;
@@ -1298,12 +1356,11 @@ void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> 
     std::vector<Key> refined;
     for (auto &kv : M.leaves) if (f[kcode(kv.first)] == 1) refined.push_back(kv.first);
     // internal nodes (strict ancestors of leaves) of the forest after the refinements
-    std::unordered_set<uint64_t> internal;
-    internal.reserve(2 * M.leaves.size() + 8 * refined.size() + 1);
+    FlatMap internal(2 * M.leaves.size() + 8 * refined.size() + 1);
     auto add_ancestors = [&](Key a) {
         while (a.l > 1) {
             a = Key{a.l - 1, a.i >> 1, a.j >> 1, a.k >> 1};
-            if (!internal.insert(kcode(a)).second) break;   // its ancestors are in already
+            if (!internal.insert(kcode(a))) break;      // its ancestors are in already
         }
     };
     for (auto &kv : M.leaves)
@@ -1335,7 +1392,7 @@ void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> 
                     for (int di = -1; di <= 2 && ok; ++di) {
                         int w[3] = {2 * p.i + di, 2 * p.j + dj, 2 * p.k + dk};
                         if (!wrap_idx(s, cl, w)) continue;
-                        if (internal.count(kcode(Key{cl, w[0], w[1], w[2]}))) ok = false;
+                        if (internal.contains(kcode(Key{cl, w[0], w[1], w[2]}))) ok = false;
                     }
         }
         if (ok) coarsened.push_back(p);
@@ -1352,13 +1409,14 @@ void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> 
         M.free_slots.pop_back();
         return q;
     };
-    std::map<Key, int> newleaves(M.leaves);
+    // applied to the leaf map in place: refined leaves and the children of
+    // coarsened parents are disjoint, so every lookup below sees the old leaf
     for (const Key &p : refined) {
         const int ps = M.leaves.at(p);
         for (int o = 0; o < 8; ++o) {
             Key ch{p.l + 1, 2 * p.i + (o & 1), 2 * p.j + ((o >> 1) & 1), 2 * p.k + ((o >> 2) & 1)};
             const int cs = alloc_slot();
-            newleaves[ch] = cs;
+            M.leaves[ch] = cs;
             MoveTask t{};
             t.type = MOVE_PROLONG;
             t.dst = s->slot_of(m, cs);
@@ -1370,7 +1428,7 @@ void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> 
             t.org[2] = ch.k * s->B[2];
             moves.push_back(t);
         }
-        newleaves.erase(p);
+        M.leaves.erase(p);
         to_free.push_back(s->slot_of(m, ps));
     }
     for (const Key &p : coarsened) {
@@ -1386,13 +1444,12 @@ void regrid_member(ic_sim *s, int m, const std::unordered_map<uint64_t, int8_t> 
             Key ch{p.l + 1, 2 * p.i + (o & 1), 2 * p.j + ((o >> 1) & 1), 2 * p.k + ((o >> 2) & 1)};
             const int cs = M.leaves.at(ch);
             t.src[o] = s->slot_of(m, cs);
-            newleaves.erase(ch);
+            M.leaves.erase(ch);
             to_free.push_back(s->slot_of(m, cs));
         }
-        newleaves[p] = pslot;
+        M.leaves[p] = pslot;
         moves.push_back(t);
     }
-    M.leaves.swap(newleaves);
 }
 
 // plain criterion on the current state (ghosts must be filled) into fl, per
@@ -1538,8 +1595,7 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
     std::vector<std::vector<int>> fr(s->nm);
     for_members(s->nm, [&](int m) {
         Member &M = s->mem[m];
-        std::unordered_map<uint64_t, int8_t> f;
-        f.reserve(2 * M.leaves.size() + 1);
+        FlatMap f(M.leaves.size());
         if (user_flags) {                             // given in the ABI block order
             const std::vector<Key> keys = abi_sorted(M.leaves);
             for (size_t q = 0; q < keys.size(); ++q) f[kcode(keys[q])] = user_flags[(size_t)m * s->max_blocks + q];
