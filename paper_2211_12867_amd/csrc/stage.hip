@@ -53,6 +53,42 @@ DEV void column8(const KArgs &a, int slot, const Faces &nb, int ci, int cj, int 
     for (int v = 0; v < 8; ++v) u[v] = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, 0, 0, k)[off];
 }
 
+// Halo cells of one r- or theta-face of a block (d = 0 or 1): the cell of
+// layer l (0 nearest the low side), in-face index a (j on an r-face, i on a
+// theta-face), plane k and variable v is at base + l sl + a sa + k sk + v sv
+// in the same-level neighbour, the block's own edge (outflow) or the ghost
+// slab -- the cases of cell_addr, resolved once per face.
+struct FaceMap {
+    const double *base;
+    int sl, sa, sk, sv;
+};
+
+template <class S>
+DEV FaceMap face_map(const KArgs &a, int slot, const Faces &nb, int d, int side)
+{
+    const int Bd = S::dim(d);
+    const int code = face_code(nb, 2 * d + side);
+    FaceMap m;
+    if (code >= 0 || code == NBR_OUTFLOW) {
+        const int blk = code >= 0 ? code : slot;
+        const int i0 = code >= 0 ? (side ? 0 : Bd - 2) : (side ? Bd - 1 : 0);   // layer 0 along d
+        const int sl = code >= 0 ? 1 : 0;
+        m.base = a.U + (size_t)blk * 8 * S::NC + (d == 0 ? i0 : S::B0 * i0);
+        m.sl = d == 0 ? sl : S::B0 * sl;
+        m.sa = d == 0 ? S::B0 : 1;
+        m.sk = S::B0 * S::B1;
+        m.sv = S::NC;
+    } else {
+        const int FA = d == 0 ? S::B1 : S::B0, FB = S::B2;    // slab layout of cell_addr
+        m.base = a.slabs + (size_t)nbr_slab(code) * a.slab_stride;
+        m.sl = FB * FA;
+        m.sa = 1;
+        m.sk = FA;
+        m.sv = 2 * FB * FA;
+    }
+    return m;
+}
+
 // Work item of linear work index w when a.xcd_order is set: the work-groups
 // of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
 // into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
@@ -163,6 +199,8 @@ k_stage(KArgs a)
         // that own no column, beside the column prologue; all loads first
         if (!col) {
             constexpr int NSP = NT - NCOL, HIT = (NHALO + NSP - 1) / NSP;
+            const FaceMap fm[4] = {face_map<S>(a, slot, nb, 0, 0), face_map<S>(a, slot, nb, 0, 1),
+                                   face_map<S>(a, slot, nb, 1, 0), face_map<S>(a, slot, nb, 1, 1)};
             double u[HIT][8];
 #pragma unroll
             for (int h = 0; h < HIT; ++h) {
@@ -170,9 +208,17 @@ k_stage(KArgs a)
                 if (t < NHALO) {
                     int i, j;
                     halo_cell<BI, BJ>(t, i, j);
-                    const double *p0 = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 0, i, j, 0);
-                    const int hv = (int)(cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 1, i, j, 0) - p0);
-                    const int hk = (int)(cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 0, i, j, 1) - p0);
+                    const bool rh = t < NHR;                  // r-halo, else theta-halo
+                    const int idx = rh ? i : j, bd_ = rh ? BI : BJ;
+                    const int side = idx >= bd_ ? 1 : 0, l = side ? idx - bd_ : idx + 2, q = rh ? j : i;
+                    const int f = (rh ? 0 : 2) + side;
+                    const FaceMap &m0 = fm[0], &m1 = fm[1], &m2 = fm[2], &m3 = fm[3];
+                    const double *fb = f == 0 ? m0.base : f == 1 ? m1.base : f == 2 ? m2.base : m3.base;
+                    const int fl = f == 0 ? m0.sl : f == 1 ? m1.sl : f == 2 ? m2.sl : m3.sl;
+                    const int fa = f == 0 ? m0.sa : f == 1 ? m1.sa : f == 2 ? m2.sa : m3.sa;
+                    const int hk = f == 0 ? m0.sk : f == 1 ? m1.sk : f == 2 ? m2.sk : m3.sk;
+                    const int hv = f == 0 ? m0.sv : f == 1 ? m1.sv : f == 2 ? m2.sv : m3.sv;
+                    const double *p0 = fb + l * fl + q * fa;
                     sHB[t] = p0;
                     sHV[t] = hv;
                     sHK[t] = hk;
