@@ -171,7 +171,7 @@ k_stage(KArgs a)
         for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
         for (int m = tid; m < BK + 4; m += NT) sP[m] = lg.p[bd.org[2] + m];
-        __syncthreads();
+        // (the metric tables are read after the barrier that ends the prologue)
 
         // --- prologue: column primitives of planes k0 and k0+1, phi-face k0-1/2
         // registers carried along k: Wn = W(k+1), wL = face state of cell k at
@@ -184,7 +184,7 @@ k_stage(KArgs a)
             column8<S>(a, slot, nb, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
             column8<S>(a, slot, nb, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
             column8<S>(a, slot, nb, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
-            const RecP pm1 = sP[k0 + 1], p0 = sP[k0 + 2];
+            const RecP pm1 = lg.p[bd.org[2] + k0 + 1], p0 = lg.p[bd.org[2] + k0 + 2];
             reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
             reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
             rusanov<2>(hi, R0, Fm, gs);
