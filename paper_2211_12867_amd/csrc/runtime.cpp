@@ -14,7 +14,10 @@
 #include <map>
 #include <stdexcept>
 #include <string>
+#include <condition_variable>
 #include <exception>
+#include <functional>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -563,29 +566,97 @@ void select_schedule(ic_sim *s)
     if (w != s->tune_waves || g != s->tune_grid || x != s->tune_xcd || ks != s->tune_ksplit) apply_tuning(s, w, g, x, ks);
 }
 
-// f(m) for every member m, on up to 8 host threads when there are several
-// members (members are independent); the first exception is rethrown.
+// Host worker threads kept for the life of the process (starting threads for
+// every call cost ~0.1 ms each, several times per regrid).  run(n, f) calls
+// f(0 .. n-1) on the workers and the calling thread; indices are handed out
+// under the mutex, and run returns only when no worker holds f any more.
+// One run at a time.  (A process that forks after the first run gets no
+// workers in the child: runs there would wait forever; the library does not
+// fork.)
+class HostPool {
+public:
+    static HostPool &get()
+    {
+        static HostPool pool(std::min(16, (int)std::max(1u, std::thread::hardware_concurrency())) - 1);
+        return pool;
+    }
+    int workers() const { return (int)th_.size(); }
+    void run(int n, const std::function<void(int)> &f)
+    {
+        std::lock_guard<std::mutex> one(run_mu_);
+        std::unique_lock<std::mutex> g(mu_);
+        job_ = &f;
+        n_ = n;
+        next_ = 0;
+        cv_work_.notify_all();
+        while (next_ < n_) {
+            const int i = next_++;
+            ++active_;
+            g.unlock();
+            f(i);
+            g.lock();
+            --active_;
+        }
+        cv_done_.wait(g, [&] { return active_ == 0; });
+        job_ = nullptr;
+        n_ = 0;
+    }
+    ~HostPool()
+    {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_work_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+
+private:
+    explicit HostPool(int nw)
+    {
+        for (int t = 0; t < nw; ++t) th_.emplace_back([this] { loop(); });
+    }
+    void loop()
+    {
+        std::unique_lock<std::mutex> g(mu_);
+        for (;;) {
+            cv_work_.wait(g, [&] { return stop_ || (job_ && next_ < n_); });
+            if (stop_) return;
+            const int i = next_++;
+            const std::function<void(int)> *f = job_;
+            ++active_;
+            g.unlock();
+            (*f)(i);
+            g.lock();
+            if (--active_ == 0) cv_done_.notify_all();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex mu_, run_mu_;
+    std::condition_variable cv_work_, cv_done_;
+    const std::function<void(int)> *job_ = nullptr;
+    int n_ = 0, next_ = 0, active_ = 0;
+    bool stop_ = false;
+};
+
+// f(m) for every member m, on the host pool when there are several members
+// (members are independent); the first exception (in member order) is rethrown.
 template <class F>
 void for_members(int nm, F &&f)
 {
-    const int nt = std::min({nm, 8, (int)std::max(1u, std::thread::hardware_concurrency())});
-    if (nt <= 1) {
+    if (nm <= 1 || HostPool::get().workers() == 0) {
         for (int m = 0; m < nm; ++m) f(m);
         return;
     }
     std::vector<std::exception_ptr> err(nm);
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t)
-        th.emplace_back([&, t]() {
-            for (int m = t; m < nm; m += nt) {
-                try {
-                    f(m);
-                } catch (...) {
-                    err[m] = std::current_exception();
-                }
-            }
-        });
-    for (auto &x : th) x.join();
+    const std::function<void(int)> job = [&](int m) {
+        try {
+            f(m);
+        } catch (...) {
+            err[m] = std::current_exception();
+        }
+    };
+    HostPool::get().run(nm, job);
     for (auto &e : err)
         if (e) std::rethrow_exception(e);
 }
@@ -767,31 +838,30 @@ void rebuild(ic_sim *s)
         slab_off[m + 1] = slab_off[m] + ml[m].nslab;
         reg_off[m + 1] = reg_off[m] + ml[m].nreg;
     }
-    for_members(s->nm, [&](int m) {
-        Lists &L = ml[m];
-        const int so = slab_off[m], ro = reg_off[m];
-        if (so == 0 && ro == 0) return;
-        for (int slot : L.items) {
-            BlockDesc &bd = s->hdesc[slot];
-            for (int f = 0; f < 6; ++f) {
-                if (bd.nbr[f] <= slab_code(0)) bd.nbr[f] = slab_code(nbr_slab(bd.nbr[f]) + so);
-                if (bd.freg[f] >= 0) bd.freg[f] += ro;
-            }
-        }
-        for (auto &tk : L.pass1) tk.slab += so;
-        for (auto &v : L.prol)
-            for (auto &tk : v) tk.slab += so;
-        for (auto &rt : L.rf) {
-            rt.creg += ro;
-            for (int q = 0; q < 4; ++q) rt.freg[q] += ro;
-        }
-    });
+    // offsets and concatenation in member order (serial: cheap next to the leaf loop)
     std::vector<int> items, mbeg(s->nm), mend(s->nm);
     std::vector<SlabTask> pass1;
     std::vector<std::vector<SlabTask>> prol(IC_MAX_LEVEL + 2);
     std::vector<RefluxTask> rf;
     for (int m = 0; m < s->nm; ++m) {
         Lists &L = ml[m];
+        const int so = slab_off[m], ro = reg_off[m];
+        if (so != 0 || ro != 0) {
+            for (int slot : L.items) {
+                BlockDesc &bd = s->hdesc[slot];
+                for (int f = 0; f < 6; ++f) {
+                    if (bd.nbr[f] <= slab_code(0)) bd.nbr[f] = slab_code(nbr_slab(bd.nbr[f]) + so);
+                    if (bd.freg[f] >= 0) bd.freg[f] += ro;
+                }
+            }
+            for (auto &tk : L.pass1) tk.slab += so;
+            for (auto &v : L.prol)
+                for (auto &tk : v) tk.slab += so;
+            for (auto &rt : L.rf) {
+                rt.creg += ro;
+                for (int q = 0; q < 4; ++q) rt.freg[q] += ro;
+            }
+        }
         mbeg[m] = (int)items.size();
         items.insert(items.end(), L.items.begin(), L.items.end());
         mend[m] = (int)items.size();
