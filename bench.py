@@ -1,7 +1,7 @@
 """Benchmark: zone-updates/s of the fp64 MHD step on one MI355X.
 
 A step is one full two-stage step of the hot path (ghost fill, both
-finite-volume stages, CFL dt, time update) over the equidistant full domain
+finite-volume stages, CFL dt, time update, sample) over the equidistant full domain
 r in [0.1, 2] AU x theta in [30, 150] deg x phi in [0, 360) deg with
 512 x 60 x 180 cells (2,400 blocks of 16 x 12 x 12), seeded wind and cone
 CME, starting from the relaxation initial state.  One zone-update is one leaf
@@ -145,14 +145,16 @@ def main():
         sim.autotune(args.tune_cache or None, reps=3)
     tune = dict(zip(("waves_per_simd", "grid", "xcd_order", "ksplit"), sim.tuning()))
     print("bench: schedule %s" % tune, file=sys.stderr, flush=True)
-    sim.step()                                  # captures the step graph for the tuned schedule
-    # timed region: the captured step graph replayed, no per-launch events
+    n0 = sim.step()["steps"]                    # captures the step graph for the tuned schedule
+    # timed region: exactly K steps of the captured step graph in one advance
+    # call (the library reads the time back every 20 steps, not after each
+    # step), no per-launch events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for q in range(args.steps):
-        sim.step()
+    info = sim.advance(1e12, max_steps=args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    assert info["steps"] - n0 == args.steps, (info["steps"], n0, args.steps)
     # kernel time of the dominant kernel: HIP events around every stage launch on
     # the library's stream, over a separate pass of the same steps
     sim.set_kernel_timing(True)

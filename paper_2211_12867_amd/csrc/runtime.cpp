@@ -342,6 +342,11 @@ struct ic_sim {
     // pinned staging area of the table uploads (Upload)
     char *hstage = nullptr;
     size_t hstage_cap = 0;
+    // pinned landing area of the per-step status (non-physical flags, step
+    // count, t, dt), read back with one synchronisation per ic_step
+    char *hstat = nullptr;
+    bool tend_finite = false;       // an ic_advance end time is in tend (else "no end")
+    int leaves_per_level0[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // member 0, kept by rebuild
 
     int slot_of(int m, int local) const { return m * max_blocks + local; }
 };
@@ -940,6 +945,9 @@ void rebuild(ic_sim *s)
     up.add(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int));
     up.add(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int));
     up.flush();
+    for (int l = 0; l < 8; ++l) s->leaves_per_level0[l] = 0;
+    for (auto &kv : s->mem[0].leaves)
+        if (kv.first.l <= 8) s->leaves_per_level0[kv.first.l - 1]++;
     select_schedule(s);
 }
 
@@ -1130,8 +1138,7 @@ void fill_info(ic_sim *s, ic_info *out)
     out->dt_s = dtl * kT0;
     out->zone_updates = s->zone_updates;
     out->leaves = (int)s->mem[0].leaves.size();
-    for (auto &kv : s->mem[0].leaves)
-        if (kv.first.l <= 8) out->leaves_per_level[kv.first.l - 1]++;
+    for (int l = 0; l < 8; ++l) out->leaves_per_level[l] = s->leaves_per_level0[l];
 }
 
 long total_cells(const ic_sim *s)
@@ -2020,6 +2027,7 @@ void ic_destroy(ic_sim *s)
     s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
     s->ring_count.release();
     if (s->hstage) (void)hipHostFree(s->hstage);
+    if (s->hstat) (void)hipHostFree(s->hstat);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
     delete s;
 }
@@ -2029,13 +2037,45 @@ ic_status ic_step(ic_sim *s, double dt_fixed_s, ic_info *out)
     return guard(s, [&]() {
         check_sim(s);
         if (dt_fixed_s < 0.0) throw Error(IC_E_INVALID, "negative dt");
-        std::vector<double> big(s->nm, 1e300);
-        HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        if (s->tend_finite) {
+            std::vector<double> big(s->nm, 1e300);
+            HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+            HIPCHECK(hipStreamSynchronize(s->stream));
+            s->tend_finite = false;
+        }
         run_step(s, dt_fixed_s / kT0, true);
         s->zone_updates += (double)total_cells(s);
         s->host_steps++;
-        check_bad(s);
-        fill_info(s, out);
+        // the non-physical flags and the counters in one round trip
+        if (!s->hstat && hipHostMalloc((void **)&s->hstat, 8 * (size_t)s->nm + 64) != hipSuccess) {
+            s->hstat = nullptr;
+            throw Error(IC_E_NOMEM, "pinned host status buffer");
+        }
+        int *hbad = (int *)s->hstat;
+        char *tail = s->hstat + ((8 * (size_t)s->nm + 15) / 16) * 16;
+        long *hst = (long *)tail;
+        double *ht = (double *)(tail + 8), *hdt = (double *)(tail + 16);
+        HIPCHECK(hipMemcpyAsync(hbad, s->bad.p, 2 * s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipMemcpyAsync(hst, s->nsteps.p, sizeof(long), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipMemcpyAsync(ht, s->t.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipMemcpyAsync(hdt, s->dt_last.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        for (int m = 0; m < s->nm; ++m)
+            if (hbad[2 * m]) {
+                s->poisoned = true;
+                throw Error(IC_E_UNPHYSICAL, "member " + std::to_string(m) +
+                                                 ": a leaf cell has rho <= 0, p <= 0 or a non-finite value" +
+                                                 describe_bad(s, m, hbad[2 * m] - 1, hbad[2 * m + 1]));
+            }
+        if (out) {
+            std::memset(out, 0, sizeof(*out));
+            out->steps = *hst;
+            out->t_s = *ht * kT0;
+            out->dt_s = *hdt * kT0;
+            out->zone_updates = s->zone_updates;
+            out->leaves = (int)s->mem[0].leaves.size();
+            for (int l = 0; l < 8; ++l) out->leaves_per_level[l] = s->leaves_per_level0[l];
+        }
     });
 }
 
@@ -2049,6 +2089,7 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
         HIPCHECK(hipStreamSynchronize(s->stream));
         for (int m = 0; m < s->nm; ++m) tend[m] = t[m] + dt_s / kT0;
         HIPCHECK(hipMemcpyAsync(s->tend.p, tend.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        s->tend_finite = true;
         const int every = (s->max_level > 1 && s->amr.regrid_every > 0) ? s->amr.regrid_every : 0;
         long done = 0;
         // zone updates: per member, the steps it took (a member past its end time
@@ -2075,6 +2116,8 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
         }
         std::vector<double> big(s->nm, 1e300);
         HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        s->tend_finite = false;
         fill_info(s, out);
     });
 }
