@@ -6,6 +6,8 @@
 - ic_advance with regrids every few steps (the captured step graph replayed
   across forest changes) matches the oracle doing the same, including the
   time series recorded at the sample point after every step.
+- K calls of ic_step and one ic_advance of K steps agree bit for bit, and an
+  advance that ends at its end time leaves no end time for later steps.
 """
 import numpy as np
 import pytest
@@ -83,3 +85,32 @@ def test_advance_with_regrids_matches_oracle():
     assert np.allclose(ts[:, 0], ref[:, 0], rtol=1e-12)
     assert np.allclose(ts[:, 1:], ref[:, 1:], rtol=1e-9, atol=1e-12 * np.abs(ref[:, 1:]).max())
     gpu.close()
+
+
+def test_step_and_advance_agree_and_end_times_do_not_leak():
+    """K single steps and one advance of K steps give the same state, time and
+    step count; an advance that stops at its end time leaves no end time
+    behind (the next single step takes a full CFL step)."""
+    import paper_2211_12867_amd as ic
+    wind = as_dict(Wind(seed=7))
+    cme = as_dict(Cme(t_start_s=0.0, duration_s=6 * 3600.0, v_kms=1200.0, half_width_deg=30.0,
+                      colat_deg=90.0, lon_deg=20.0, n_cm3=1200.0, T_K=0.8e6))
+    g = _grid(1)
+    a = ic.Sim(g, wind, [cme])
+    b = ic.Sim(g, wind, [cme])
+    infos = [a.step() for _ in range(6)]
+    ib = b.advance(1e12, max_steps=6)
+    assert [i["steps"] for i in infos] == list(range(1, 7))
+    assert ib["steps"] == 6 and ib["t_s"] == infos[-1]["t_s"]
+    assert a.time() == b.time()
+    assert np.array_equal(a.state()[1], b.state()[1])
+    # an advance to a time inside the next step clips that step to the end time
+    t0 = b.time()[0]
+    dt_full = infos[-1]["dt_s"]
+    ic2 = b.advance(0.25 * dt_full)
+    assert ic2["t_s"] == pytest.approx(t0 + 0.25 * dt_full, rel=1e-12)
+    # the next single step is a full CFL step again, not held at the old end time
+    i3 = b.step()
+    assert i3["t_s"] > ic2["t_s"] + 0.5 * dt_full
+    a.close()
+    b.close()
