@@ -101,7 +101,14 @@ def cpu_baseline(seconds_target=15.0):
         if el > seconds_target or steps >= 50:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": cells * steps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu,
             "sample": "%d steps of the %d x 60 x 180 inner-radius part of the same grid (%.1f s)"
                       % (steps, nr, el)}
 
