@@ -168,7 +168,8 @@ struct Launchers {
     void (*rate)(dim3, hipStream_t, const KArgs &);
     void (*indicator)(dim3, hipStream_t, const KArgs &, int8_t *, const IndicatorParams &);
     void (*move)(dim3, hipStream_t, const KArgs &, double *, const MoveTask *, int);
-    void (*sample)(dim3, hipStream_t, const KArgs &, const SampleDesc *, int, double *, double *, int *, int, int);
+    void (*sample)(dim3, hipStream_t, const KArgs &, const SampleDesc *, int, double *, double *, int *, int, int,
+                   double *, long *);
 };
 bool get_launchers(int bi, int bj, int bk, Launchers *out);
 void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, int nm, double cfl,
@@ -189,7 +190,7 @@ template <int BI, int BJ, int BK>
 __global__ void k_move(KArgs a, double *Unew, const MoveTask *tasks, int ntasks);
 template <int BI, int BJ, int BK>
 __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
-                         int *ring_count, int ring_cap, int record);
+                         int *ring_count, int ring_cap, int record, double *t_step, long *nsteps);
 
 __global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, double cfl,
                      double dt_fixed, const double *tend, double *dt_last);

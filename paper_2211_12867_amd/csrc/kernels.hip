@@ -636,15 +636,21 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
 }
 
 // ---------------------------------------------------------------------------
-// point sampling (trilinear between cell centres), one work-group per member
+// point sampling (trilinear between cell centres), one work-group per member;
+// with t_step set it first ends the step (t += dt, step count + 1, for a
+// member with dt > 0), so that the sample carries the new time
 // ---------------------------------------------------------------------------
 template <int BI, int BJ, int BK>
 __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
-                         int *ring_count, int ring_cap, int record)
+                         int *ring_count, int ring_cap, int record, double *t_step, long *nsteps)
 {
     using S = Shape<BI, BJ, BK>;
     const int m = blockIdx.x;
     if (m >= nmembers || threadIdx.x != 0) return;
+    if (t_step && a.dt[m] > 0.0) {
+        t_step[m] += a.dt[m];
+        nsteps[m] += 1;
+    }
     if (!sd[m].valid) return;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int q = 0; q < 8; ++q) {
@@ -672,7 +678,7 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
     if (record) {
         const int c = ring_count[m];
         double *r = ring + ((size_t)m * ring_cap + (c % ring_cap)) * 9;
-        r[0] = a.t[m];
+        r[0] = t_step ? t_step[m] : a.t[m];
         for (int v = 0; v < 8; ++v) r[1 + v] = acc[v];
         ring_count[m] = c + 1;
     }
@@ -691,7 +697,7 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
                                                      double, double);                              \
     template __global__ void k_move<BI, BJ, BK>(KArgs, double *, const MoveTask *, int);           \
     template __global__ void k_sample<BI, BJ, BK>(KArgs, const SampleDesc *, int, double *, double *, \
-                                                  int *, int, int);
+                                                  int *, int, int, double *, long *);
 
 #include "shapes.inc"
 #undef IC_INSTANTIATE
@@ -723,9 +729,10 @@ struct L {
         hipLaunchKernelGGL((k_move<BI, BJ, BK>), g, dim3(NT), 0, s, a, Un, t, n);
     }
     static void sample(dim3 g, hipStream_t s, const KArgs &a, const SampleDesc *sd, int nm, double *out,
-                       double *ring, int *cnt, int cap, int rec)
+                       double *ring, int *cnt, int cap, int rec, double *t_step, long *nsteps)
     {
-        hipLaunchKernelGGL((k_sample<BI, BJ, BK>), g, dim3(64), 0, s, a, sd, nm, out, ring, cnt, cap, rec);
+        hipLaunchKernelGGL((k_sample<BI, BJ, BK>), g, dim3(64), 0, s, a, sd, nm, out, ring, cnt, cap, rec, t_step,
+                           nsteps);
     }
 };
 }  // namespace

@@ -1063,12 +1063,13 @@ void enqueue_rate(ic_sim *s)
     s->L.rate(dim3(grid_for(s->n_items, 16384)), s->stream, a);
 }
 
-void enqueue_sample(ic_sim *s, int record)
+// sample at the point; end_step: the same launch first ends the step (t += dt)
+void enqueue_sample(ic_sim *s, int record, bool end_step = false)
 {
     KArgs a = base_args(s);
     a.U = s->U.p;
     s->L.sample(dim3(s->nm), s->stream, a, s->sdesc.p, s->nm, s->sout.p, s->ring.p, s->ring_count.p,
-                s->ring_cap, record);
+                s->ring_cap, record, end_step ? s->t.p : nullptr, end_step ? s->nsteps.p : nullptr);
 }
 
 void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
@@ -1079,8 +1080,8 @@ void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
     stage(s, s->U.p, s->U.p, s->Us.p, 0.5, 0);
     fill_ghosts(s, s->Us.p, 0.5);
     stage(s, s->Us.p, s->U.p, s->U.p, 1.0, 1);
-    launch_time(s->stream, s->t.p, s->dt.p, s->nsteps.p, s->nm);
-    if (record) enqueue_sample(s, 1);
+    if (record) enqueue_sample(s, 1, true);       // ends the step and records the sample
+    else launch_time(s->stream, s->t.p, s->dt.p, s->nsteps.p, s->nm);
 }
 
 void run_step(ic_sim *s, double dt_fixed_code, bool record)
@@ -2188,7 +2189,8 @@ ic_status ic_sample(ic_sim *s, int member, double r_au, double colat_deg, double
         HIPCHECK(hipMemcpy(tmp.p, all.data(), s->nm * sizeof(SampleDesc), hipMemcpyHostToDevice));
         KArgs a = base_args(s);
         a.U = s->U.p;
-        s->L.sample(dim3(s->nm), s->stream, a, tmp.p, s->nm, s->sout.p, s->ring.p, s->ring_count.p, s->ring_cap, 0);
+        s->L.sample(dim3(s->nm), s->stream, a, tmp.p, s->nm, s->sout.p, s->ring.p, s->ring_count.p, s->ring_cap, 0,
+                    nullptr, nullptr);
         HIPCHECK(hipMemcpyAsync(prim_out, s->sout.p + member * 8, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         HIPCHECK(hipStreamSynchronize(s->stream));
         tmp.release();
