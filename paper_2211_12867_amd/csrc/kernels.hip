@@ -455,12 +455,24 @@ __global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, do
     __shared__ double sred[NT / 64];
     for (int m = blockIdx.x; m < nmembers; m += gridDim.x) {
         double r = 0.0;
-        for (int q = mbeg[m] + threadIdx.x; q < mend[m]; q += blockDim.x) {
+        const int q1 = mend[m];
+        // four work items per thread and pass: their slot loads, then their
+        // rate loads, are in flight together (the maximum is order-free)
+        for (int q0 = mbeg[m] + threadIdx.x; q0 < q1; q0 += 4 * blockDim.x) {
+            int sl[4];
 #pragma unroll
-            for (int p = 0; p < KSPLIT_MAX; ++p) {
-                const double x = a.rate[(size_t)a.items[q] * KSPLIT_MAX + p];
-                r = x > r ? x : r;
+            for (int u = 0; u < 4; ++u) {
+                const int q = q0 + u * (int)blockDim.x;
+                sl[u] = q < q1 ? a.items[q] : -1;
             }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (sl[u] >= 0)
+#pragma unroll
+                    for (int p = 0; p < KSPLIT_MAX; ++p) {
+                        const double x = a.rate[(size_t)sl[u] * KSPLIT_MAX + p];
+                        r = x > r ? x : r;
+                    }
         }
         const double mx = block_max(r, sred);
         if (threadIdx.x == 0) {
@@ -645,15 +657,16 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
                          int *ring_count, int ring_cap, int record, double *t_step, long *nsteps)
 {
     using S = Shape<BI, BJ, BK>;
+    __shared__ double sw[8][9];                 // per stencil entry: primitives, then its weight
     const int m = blockIdx.x;
-    if (m >= nmembers || threadIdx.x != 0) return;
-    if (t_step && a.dt[m] > 0.0) {
+    if (m >= nmembers) return;
+    if (threadIdx.x == 0 && t_step && a.dt[m] > 0.0) {
         t_step[m] += a.dt[m];
         nsteps[m] += 1;
     }
-    if (!sd[m].valid) return;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = 0; q < 8; ++q) {
+    if (!sd[m].valid) return;                   // the same for the whole work-group
+    const int q = threadIdx.x;                  // entries on 8 threads, loads in flight together
+    if (q < 8) {
         const SampleEntry &e = sd[m].e[q];      // read in place (no private copy of the descriptor)
         double u[8];
         if (e.kind == 0) {
@@ -672,8 +685,14 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
         }
         double w[8];
         cons_to_prim(u, w, a.gas);
-        for (int v = 0; v < 8; ++v) acc[v] += e.w * w[v];
+        for (int v = 0; v < 8; ++v) sw[q][v] = w[v];
+        sw[q][8] = e.w;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = 0; e < 8; ++e)                 // summed in entry order
+        for (int v = 0; v < 8; ++v) acc[v] += sw[e][8] * sw[e][v];
     for (int v = 0; v < 8; ++v) out[m * 8 + v] = acc[v];
     if (record) {
         const int c = ring_count[m];
