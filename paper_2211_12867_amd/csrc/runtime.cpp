@@ -2033,50 +2033,88 @@ void ic_destroy(ic_sim *s)
     delete s;
 }
 
+// Pinned host landing area of the per-step status: per member the
+// non-physical flags, t and the step count, then dt_last of member 0, and a
+// host-to-device area for the end times.  Reads go through one async copy per
+// array and one synchronisation.
+struct Status {
+    int *bad;       // [2 nm]
+    double *t;      // [nm]
+    long *ns;       // [nm]
+    double *dtl;    // [1]
+    double *tend;   // [nm], host-to-device
+};
+
+Status status_buffer(ic_sim *s)
+{
+    const size_t nm = (size_t)s->nm, a = ((8 * nm + 63) / 64) * 64;
+    if (!s->hstat) {
+        if (hipHostMalloc((void **)&s->hstat, 4 * a + 64) != hipSuccess) {
+            s->hstat = nullptr;
+            throw Error(IC_E_NOMEM, "pinned host status buffer");
+        }
+    }
+    Status st;
+    st.bad = (int *)s->hstat;
+    st.t = (double *)(s->hstat + a);
+    st.ns = (long *)(s->hstat + 2 * a);
+    st.tend = (double *)(s->hstat + 3 * a);
+    st.dtl = (double *)(s->hstat + 4 * a);
+    return st;
+}
+
+// enqueue the status copies (device to pinned host), synchronise, and fail on
+// a non-physical cell
+Status read_status(ic_sim *s)
+{
+    Status st = status_buffer(s);
+    HIPCHECK(hipMemcpyAsync(st.bad, s->bad.p, 2 * s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipMemcpyAsync(st.t, s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipMemcpyAsync(st.ns, s->nsteps.p, s->nm * sizeof(long), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipMemcpyAsync(st.dtl, s->dt_last.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHECK(hipStreamSynchronize(s->stream));
+    for (int m = 0; m < s->nm; ++m)
+        if (st.bad[2 * m]) {
+            s->poisoned = true;
+            throw Error(IC_E_UNPHYSICAL, "member " + std::to_string(m) +
+                                             ": a leaf cell has rho <= 0, p <= 0 or a non-finite value" +
+                                             describe_bad(s, m, st.bad[2 * m] - 1, st.bad[2 * m + 1]));
+        }
+    return st;
+}
+
+void info_from_status(const ic_sim *s, const Status &st, ic_info *out)
+{
+    if (!out) return;
+    std::memset(out, 0, sizeof(*out));
+    out->steps = st.ns[0];
+    out->t_s = st.t[0] * kT0;
+    out->dt_s = *st.dtl * kT0;
+    out->zone_updates = s->zone_updates;
+    out->leaves = (int)s->mem[0].leaves.size();
+    for (int l = 0; l < 8; ++l) out->leaves_per_level[l] = s->leaves_per_level0[l];
+}
+
+// end times back to "none" (asynchronous from the pinned area)
+void clear_tend(ic_sim *s)
+{
+    Status st = status_buffer(s);
+    for (int m = 0; m < s->nm; ++m) st.tend[m] = 1e300;
+    HIPCHECK(hipMemcpyAsync(s->tend.p, st.tend, s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    s->tend_finite = false;
+}
+
 ic_status ic_step(ic_sim *s, double dt_fixed_s, ic_info *out)
 {
     return guard(s, [&]() {
         check_sim(s);
         if (dt_fixed_s < 0.0) throw Error(IC_E_INVALID, "negative dt");
-        if (s->tend_finite) {
-            std::vector<double> big(s->nm, 1e300);
-            HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
-            HIPCHECK(hipStreamSynchronize(s->stream));
-            s->tend_finite = false;
-        }
+        if (s->tend_finite) clear_tend(s);
         run_step(s, dt_fixed_s / kT0, true);
         s->zone_updates += (double)total_cells(s);
         s->host_steps++;
-        // the non-physical flags and the counters in one round trip
-        if (!s->hstat && hipHostMalloc((void **)&s->hstat, 8 * (size_t)s->nm + 64) != hipSuccess) {
-            s->hstat = nullptr;
-            throw Error(IC_E_NOMEM, "pinned host status buffer");
-        }
-        int *hbad = (int *)s->hstat;
-        char *tail = s->hstat + ((8 * (size_t)s->nm + 15) / 16) * 16;
-        long *hst = (long *)tail;
-        double *ht = (double *)(tail + 8), *hdt = (double *)(tail + 16);
-        HIPCHECK(hipMemcpyAsync(hbad, s->bad.p, 2 * s->nm * sizeof(int), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipMemcpyAsync(hst, s->nsteps.p, sizeof(long), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipMemcpyAsync(ht, s->t.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipMemcpyAsync(hdt, s->dt_last.p, sizeof(double), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
-        for (int m = 0; m < s->nm; ++m)
-            if (hbad[2 * m]) {
-                s->poisoned = true;
-                throw Error(IC_E_UNPHYSICAL, "member " + std::to_string(m) +
-                                                 ": a leaf cell has rho <= 0, p <= 0 or a non-finite value" +
-                                                 describe_bad(s, m, hbad[2 * m] - 1, hbad[2 * m + 1]));
-            }
-        if (out) {
-            std::memset(out, 0, sizeof(*out));
-            out->steps = *hst;
-            out->t_s = *ht * kT0;
-            out->dt_s = *hdt * kT0;
-            out->zone_updates = s->zone_updates;
-            out->leaves = (int)s->mem[0].leaves.size();
-            for (int l = 0; l < 8; ++l) out->leaves_per_level[l] = s->leaves_per_level0[l];
-        }
+        const Status st = read_status(s);          // one round trip
+        info_from_status(s, st, out);
     });
 }
 
@@ -2085,41 +2123,35 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
     return guard(s, [&]() {
         check_sim(s);
         if (!(dt_s >= 0.0) || max_steps < 0) throw Error(IC_E_INVALID, "negative duration or step limit");
-        std::vector<double> t(s->nm), tend(s->nm);
-        HIPCHECK(hipMemcpyAsync(t.data(), s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
-        for (int m = 0; m < s->nm; ++m) tend[m] = t[m] + dt_s / kT0;
-        HIPCHECK(hipMemcpyAsync(s->tend.p, tend.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
+        Status st = read_status(s);
+        std::vector<double> tend(s->nm);
+        std::vector<long> ns(st.ns, st.ns + s->nm);
+        for (int m = 0; m < s->nm; ++m) tend[m] = st.t[m] + dt_s / kT0;
+        // the pinned end-time area is not written again before the next synchronisation
+        for (int m = 0; m < s->nm; ++m) st.tend[m] = tend[m];
+        HIPCHECK(hipMemcpyAsync(s->tend.p, st.tend, s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
         s->tend_finite = true;
         const int every = (s->max_level > 1 && s->amr.regrid_every > 0) ? s->amr.regrid_every : 0;
         long done = 0;
         // zone updates: per member, the steps it took (a member past its end time
         // takes dt = 0 and does no work) times its leaf cells (fixed within a batch)
-        std::vector<long> ns(s->nm), ns1(s->nm);
-        HIPCHECK(hipMemcpyAsync(ns.data(), s->nsteps.p, s->nm * sizeof(long), hipMemcpyDeviceToHost, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
         while (done < max_steps) {
             const long batch = std::min<long>(max_steps - done, every > 0 ? every : 20);
             for (long q = 0; q < batch; ++q) run_step(s, 0.0, true);
             done += batch;
-            check_bad(s);
-            HIPCHECK(hipMemcpyAsync(t.data(), s->t.p, s->nm * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-            HIPCHECK(hipMemcpyAsync(ns1.data(), s->nsteps.p, s->nm * sizeof(long), hipMemcpyDeviceToHost, s->stream));
-            HIPCHECK(hipStreamSynchronize(s->stream));
+            st = read_status(s);
             for (int m = 0; m < s->nm; ++m) {
-                s->zone_updates += (double)(ns1[m] - ns[m]) * (double)s->mem[m].leaves.size() * s->NC;
-                ns[m] = ns1[m];
+                s->zone_updates += (double)(st.ns[m] - ns[m]) * (double)s->mem[m].leaves.size() * s->NC;
+                ns[m] = st.ns[m];
             }
             bool all = true;
-            for (int m = 0; m < s->nm; ++m) all = all && t[m] >= tend[m];
+            for (int m = 0; m < s->nm; ++m) all = all && st.t[m] >= tend[m];
             if (all) break;
             if (every > 0) do_regrid(s, nullptr);
         }
-        std::vector<double> big(s->nm, 1e300);
-        HIPCHECK(hipMemcpyAsync(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice, s->stream));
-        HIPCHECK(hipStreamSynchronize(s->stream));
-        s->tend_finite = false;
-        fill_info(s, out);
+        clear_tend(s);
+        st = read_status(s);
+        info_from_status(s, st, out);
     });
 }
 
