@@ -175,18 +175,17 @@ DEV double mc_slope(double wm, double w0, double wp, double idm, double idp, dou
 DEV void reconstruct(const double wm[8], const double w0[8], const double wp[8], double idm,
                      double idp, double idc, double hm, double hp, double lo[8], double hi[8])
 {
+    double s[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) s[v] = mc_slope(wm[v], w0[v], wp[v], idm, idp, idc);
+    // the density and pressure face values decide; a zero slope gives w0 - 0 * h = w0 exactly
+    const bool ok = w0[0] - s[0] * hm > 0.0 && w0[0] + s[0] * hp > 0.0 && w0[4] - s[4] * hm > 0.0 &&
+                    w0[4] + s[4] * hp > 0.0;
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-        const double s = mc_slope(wm[v], w0[v], wp[v], idm, idp, idc);
-        lo[v] = w0[v] - s * hm;
-        hi[v] = w0[v] + s * hp;
-    }
-    if (!(lo[0] > 0.0 && hi[0] > 0.0 && lo[4] > 0.0 && hi[4] > 0.0)) {
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            lo[v] = w0[v];
-            hi[v] = w0[v];
-        }
+        const double sv = ok ? s[v] : 0.0;
+        lo[v] = w0[v] - sv * hm;
+        hi[v] = w0[v] + sv * hp;
     }
 }
 
