@@ -165,14 +165,21 @@ void ic_destroy(ic_sim *sim);
 /* One two-stage step of every member (paper Sect. 2.1: second order in time):
  * U* = U^n + dt/2 L(U^n) with ghosts at t^n, U^{n+1} = U^n + dt L(U*) with
  * ghosts at t^n + dt/2.  dt_fixed_s > 0 forces dt; 0 takes the CFL dt of
- * each member.  out may be NULL.  Returns IC_E_UNPHYSICAL if a leaf cell
- * went non-physical. */
+ * each member.  out may be NULL.  Returns IC_E_UNPHYSICAL (sim poisoned) if
+ * a stage input or the step's result holds rho <= 0, p <= 0 or a
+ * non-finite value in a leaf cell. */
 ic_status ic_step(ic_sim *sim, double dt_fixed_s, ic_info *out);
 
-/* Advance every member by dt_s (the last step is clipped to land on t + dt_s),
- * at most max_steps steps, regridding every amr->regrid_every steps when
- * max_level > 1, and recording the sample point after every step
- * (ic_timeseries). */
+/* Time evolution with solution-driven refinement (Sect. 2.1, 3): advance
+ * every member by dt_s (the last step is clipped to land on t + dt_s), at most
+ * max_steps steps, recording the sample point after every step
+ * (ic_timeseries).  When max_level > 1 the forest is rebuilt by the plain or
+ * learned criterion (amr->source) after every amr->regrid_every steps; the
+ * count runs across calls (steps taken by ic_step count too, any regrid
+ * restarts it), so advancing in pieces regrids after the same steps as one
+ * advance over the whole span.  Returns IC_E_UNPHYSICAL (sim poisoned) if a
+ * stage input or a step's result holds rho <= 0, p <= 0 or a non-finite
+ * value. */
 ic_status ic_advance(ic_sim *sim, double dt_s, long max_steps, ic_info *out);
 
 /* Rebuild every member's forest (Sect. 3): flags NULL evaluates the plain
@@ -200,18 +207,21 @@ ic_status ic_eval_hot(ic_sim *sim, int member, int8_t *hot, int n);
  * use_windows = 0).  Learned flags ask for refinement only on such leaves. */
 ic_status ic_eval_window(ic_sim *sim, int member, int8_t *in, int n);
 
-/* Primitive variables (rho, v_r, v_theta, v_phi, p, B_r, B_theta, B_phi), code
- * units, at a point: trilinear interpolation between the cell centres of the
+/* Time series at Earth (Sect. 3.1 compares the runs by the solar-wind
+ * variables recorded at Earth): primitive variables (rho, v_r, v_theta,
+ * v_phi, p, B_r, B_theta, B_phi), code units, at a point: trilinear interpolation between the cell centres of the
  * level of the finest leaf containing the point (cells of a coarser leaf
  * count with their covering value, cells under finer leaves with the
  * volume-weighted mean of their children).  IC_E_OUTSIDE outside the domain. */
 ic_status ic_sample(ic_sim *sim, int member, double r_au, double colat_deg, double lon_deg,
                     double prim_out[8]);
 
-/* Point recorded after every step by ic_advance (default (1 AU, 90, 0)). */
+/* Point recorded after every step by ic_advance and ic_step (default (1 AU,
+ * 90, 0): Earth in the co-rotating frame, Sect. 3.1). */
 ic_status ic_set_sample_point(ic_sim *sim, double r_au, double colat_deg, double lon_deg);
 
-/* Recorded samples of a member: out[s * 9 + 0] = t [s], out[s * 9 + 1..8] =
+/* Recorded time series at the sample point (Sect. 3.1), one entry per step:
+ * out[s * 9 + 0] = t [s], out[s * 9 + 1..8] =
  * primitives (code units); *n_inout is the capacity in samples on entry and
  * the count written on return (the most recent ones if the record is longer).
  * ic_timeseries_clear drops the record. */
@@ -223,17 +233,50 @@ ic_status ic_timeseries_clear(ic_sim *sim);
  * leaf count on return; IC_E_INVALID if the capacity is too small. */
 ic_status ic_get_blocks(ic_sim *sim, int member, int32_t *lvl_ijk, int *n_inout);
 
-/* Copy a member's conserved state to host_U ([block][8][bk][bj][bi], code
- * units); n_doubles must be >= leaves * 8 * cells per block. */
+/* Copy a member's conserved state (the finite-volume cell averages of the
+ * eight conserved MHD variables, Sect. 2.1) to host_U ([block][8][bk][bj][bi],
+ * code units, blocks in ic_get_blocks order); n_doubles must be >= leaves * 8
+ * * cells per block.  Synchronises the stream. */
 ic_status ic_get_state(ic_sim *sim, int member, double *host_U, size_t n_doubles);
 
-/* Replace a member's forest and state: n_blocks leaves (level, i, j, k) that
- * tile the domain, with data host_U in the same layout, at time t_s. */
+/* Replace a member's block forest (Sect. 3: blocks of 2:1-balanced levels)
+ * and state: n_blocks leaves (level, i, j, k) that tile the domain without
+ * overlap and keep 2:1 balance, with data host_U in the ic_get_state layout,
+ * at time t_s (a checkpoint restart).  IC_E_INVALID for a forest that does
+ * not tile or balance, IC_E_CAPACITY beyond the pool.  The regrid step count
+ * restarts; the floor counts are kept. */
 ic_status ic_set_state(ic_sim *sim, int member, const int32_t *lvl_ijk, int n_blocks,
                        const double *host_U, double t_s);
 
 /* Time and last dt of a member [s]. */
 ic_status ic_get_time(ic_sim *sim, int member, double *t_s, double *dt_s);
+
+/* Small-value floors acted on (the paper's scheme is not positivity
+ * preserving and it does not say how small values are treated; see
+ * ic_phys_cfg): the number of cell updates of a member since ic_create at
+ * which the density floor (*rho_floors) and the pressure floor (*p_floors)
+ * changed the state, counted in every stage.  Either pointer may be NULL.
+ * Synchronises the stream. */
+ic_status ic_floor_counts(ic_sim *sim, int member, long *rho_floors, long *p_floors);
+
+/* Shock diagnostics of a radial-speed series at a point (Sect. 3.1: arrival
+ * time and shock width, the time from arrival to the maximum speed after the
+ * jump; Sect. 3.2: peak speed and average gradient of the shock).  t_s[n]
+ * ascending sample times [s], v[n] the speeds (any unit), t_cme_s the CME
+ * start, window_s the span after it searched for the peak, min_jump the
+ * smallest rise (unit of v) counted as a shock.  v_pre = v at t_cme_s (linear
+ * between samples), v_max = the largest sample in [t_cme_s, t_cme_s +
+ * window_s] (the first of equal ones), arrival = the first upward crossing of
+ * v_pre + (v_max - v_pre)/2 inside the window by a segment that starts at or
+ * after t_cme_s, linear between samples.  out[0] arrival - t_cme_s [s],
+ * out[1] width = t(v_max) - arrival [s], out[2] v_pre, out[3] v_max (the peak
+ * speed), out[4] average gradient (v_max - level at arrival) / width [unit of
+ * v per s], out[5] t(v_max) [s].  out[0], out[1], out[4] are NaN without an
+ * arrival (no crossing, or v_max - v_pre < min_jump).  Host computation on
+ * plain arrays (ic_timeseries gives v_r in column 2); IC_E_INVALID for null
+ * pointers, n < 0 or times out of order. */
+ic_status ic_shock_diagnostics(const double *t_s, const double *v, int n, double t_cme_s, double window_s,
+                               double min_jump, double out[6]);
 
 /* ---- learned refinement flags -------------------------------------------
  * A per-block network predicts whether the plain criterion will ask for

@@ -56,21 +56,28 @@ RHO_FLOOR = 1.0e-6
 P_FLOOR = 1.0e-9
 
 
-def apply_floors(U, gamma, rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
-    """Floors on a conserved array [8, ...] (in place); returns the cell count changed."""
+def apply_floors(U, gamma, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, counts=None):
+    """Floors on a conserved array [8, ...] (in place); returns the number of
+    floor actions (density-floored cells plus pressure-floored cells).  counts,
+    if a list [n_rho, n_p], has the two numbers added to it."""
     n = 0
     low = U[0] < rho_floor
-    if np.any(low):
+    n_rho = int(low.sum())
+    if n_rho:
         U[1:4] = np.where(low, 0.0, U[1:4])
         U[0] = np.where(low, rho_floor, U[0])
-        n += int(low.sum())
+        n += n_rho
     kin = 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0]
     mag = 0.5 * (U[5] ** 2 + U[6] ** 2 + U[7] ** 2)
     p = (gamma - 1.0) * (U[4] - kin - mag)
     lowp = p < p_floor
-    if np.any(lowp):
+    n_p = int(lowp.sum())
+    if n_p:
         U[4] = np.where(lowp, p_floor / (gamma - 1.0) + kin + mag, U[4])
-        n += int(lowp.sum())
+        n += n_p
+    if counts is not None:
+        counts[0] += n_rho
+        counts[1] += n_p
     return n
 
 
@@ -88,6 +95,7 @@ class Solver:
     def __init__(self, grid, wind=None, cme=None, amr=None, omega=None, gm=None, t0_s=0.0,
                  initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
+        self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
         self.grid.setdefault("periodic", (False, False, False))
@@ -416,11 +424,11 @@ class Solver:
         L1, _ = self.operator(Un, self.t)
         Us = {b: Un[b] + (0.5 * dt) * L1[b] for b in Un}
         for u in Us.values():
-            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor)
+            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
         L2, _ = self.operator(Us, self.t + 0.5 * dt)
         self.U = {b: Un[b] + dt * L2[b] for b in Un}
         for u in self.U.values():
-            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor)
+            self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
         self.t += dt
         self.steps += 1
         return dt
@@ -642,6 +650,7 @@ class PatchSolver:
     def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind",
                  rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
+        self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
         self.grid.setdefault("periodic", (False, False, False))
@@ -716,10 +725,10 @@ class PatchSolver:
         Un = self.U
         L1 = self.operator(Un, self.t)
         Us = Un + (0.5 * dt) * L1
-        self.floored += apply_floors(Us, self.gamma, self.rho_floor, self.p_floor)
+        self.floored += apply_floors(Us, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
         L2 = self.operator(Us, self.t + 0.5 * dt)
         self.U = Un + dt * L2
-        self.floored += apply_floors(self.U, self.gamma, self.rho_floor, self.p_floor)
+        self.floored += apply_floors(self.U, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
         self.t += dt
         return dt
 

@@ -108,7 +108,7 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
-           "ic_get_tuning", "ic_last_error")
+           "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_last_error")
 
 
 def _load():
@@ -140,6 +140,9 @@ def _load():
     L.ic_set_state.argtypes = [vp, ctypes.c_int, P(ctypes.c_int32), ctypes.c_int, P(ctypes.c_double),
                                ctypes.c_double]
     L.ic_get_time.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
+    L.ic_floor_counts.argtypes = [vp, ctypes.c_int, P(ctypes.c_long), P(ctypes.c_long)]
+    dp = P(ctypes.c_double)
+    L.ic_shock_diagnostics.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     L.ic_units.argtypes = [P(ctypes.c_double)]
     L.ic_units.restype = None
     L.ic_block_supported.argtypes = [ctypes.c_int] * 3
@@ -406,6 +409,12 @@ class Sim:
         _check(lib.ic_get_time(self.h, member, ctypes.byref(t), ctypes.byref(dt)))
         return t.value, dt.value
 
+    def floor_counts(self, member=0):
+        """(density-floored, pressure-floored) cell updates since creation."""
+        a, b = ctypes.c_long(), ctypes.c_long()
+        _check(lib.ic_floor_counts(self.h, member, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     # --- measurement ------------------------------------------------------------
     def set_kernel_timing(self, enable):
         _check(lib.ic_set_kernel_timing(self.h, int(bool(enable))))
@@ -510,21 +519,24 @@ def mlp_init(seed=0):
     return p
 
 
-def arrival(t_h, v, t_cme_h, window_h=96.0):
-    """Shock arrival after the CME start [h] and width [h] from a v_r series: v_pre =
-    v_r at the CME start, v_max = max within window_h after it, arrival = first
-    crossing of v_pre + (v_max - v_pre)/2 (linear between samples), width =
-    t(v_max) - arrival.  Returns (nan, nan) without a crossing."""
-    t_h = np.asarray(t_h, dtype=np.float64)
-    v = np.asarray(v, dtype=np.float64)
-    v_pre = float(np.interp(t_cme_h, t_h, v))
-    idx = np.nonzero((t_h >= t_cme_h) & (t_h <= t_cme_h + window_h))[0]
-    if len(idx) == 0:
-        return float("nan"), float("nan")
-    imax = int(idx[np.argmax(v[idx])])
-    thr = v_pre + 0.5 * (float(v[imax]) - v_pre)
-    for a in idx[1:] if idx[0] == 0 else idx:
-        if v[a - 1] < thr <= v[a]:
-            ta = t_h[a - 1] + (thr - v[a - 1]) * (t_h[a] - t_h[a - 1]) / (v[a] - v[a - 1])
-            return float(ta - t_cme_h), float(t_h[imax] - ta)
-    return float("nan"), float("nan")
+def shock_diagnostics(t_s, v, t_cme_s, window_s=96 * 3600.0, min_jump=0.0):
+    """ic_shock_diagnostics: dict(arrival_s, width_s, v_pre, v_max, gradient,
+    t_max_s) of a radial-speed series (times in s, speeds in any unit)."""
+    t = np.ascontiguousarray(t_s, dtype=np.float64)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    if t.shape != vv.shape or t.ndim != 1:
+        raise ValueError("t_s and v must be 1-D arrays of one length")
+    out = (ctypes.c_double * 6)()
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib.ic_shock_diagnostics(t.ctypes.data_as(dp), vv.ctypes.data_as(dp), len(t), float(t_cme_s),
+                                    float(window_s), float(min_jump), out))
+    keys = ("arrival_s", "width_s", "v_pre", "v_max", "gradient", "t_max_s")
+    return dict(zip(keys, list(out)))
+
+
+def arrival(t_h, v, t_cme_h, window_h=96.0, min_jump=0.0):
+    """Shock arrival after the CME start [h] and width [h] of a v_r series with
+    times in hours (ic_shock_diagnostics); (nan, nan) without an arrival."""
+    d = shock_diagnostics(np.asarray(t_h, dtype=np.float64) * 3600.0, v, t_cme_h * 3600.0, window_h * 3600.0,
+                          min_jump)
+    return d["arrival_s"] / 3600.0, d["width_s"] / 3600.0

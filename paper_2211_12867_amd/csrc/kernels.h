@@ -27,6 +27,7 @@ struct KArgs {
     const double *t;           // per member
     double *rate;              // per slot
     int *bad;                  // per member: [2m] = 1 + slot of the first non-physical cell, [2m+1] = its cell
+    unsigned long long *floors; // per member: [2m] cells the density floor acted on, [2m+1] the pressure floor
     long slab_stride;          // doubles per slab
     long reg_stride;           // doubles per flux register
     double alpha;              // stage weight of dt (1/2 or 1)

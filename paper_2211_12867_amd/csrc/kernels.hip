@@ -383,6 +383,7 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
         int total = 0;
         for (int q = t0; q < t1; ++q) total += S::face_cells(tasks[q].face >> 1);
         double rmax = 0.0;
+        int badc = -1, nfr = 0, nfp = 0;
         for (int w = threadIdx.x; w < total; w += blockDim.x) {
             int q = t0, c = w;
             while (c >= S::face_cells(tasks[q].face >> 1)) c -= S::face_cells(tasks[q].face >> 1), ++q;
@@ -400,13 +401,23 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             if (!first) continue;
             double u[8];
             for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
-            apply_floors(u, a.gas, a.rho_floor, a.p_floor);
+            const int f = apply_floors(u, a.gas, a.rho_floor, a.p_floor);
+            nfr += f & 1;
+            nfp += f >> 1;
             for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];
             if (a.want_rate) {
+                double w[8];
+                cons_to_prim(u, w, a.gas);
+                if (badc < 0 && unphysical(w)) badc = i + BI * (j + BJ * k);
                 const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
                                                        lg.p[bd.org[2] + k + 2], a.gas);
                 rmax = r > rmax ? r : rmax;
             }
+        }
+        if (badc >= 0 && atomicCAS(&a.bad[2 * bd.member], 0, slot + 1) == 0) a.bad[2 * bd.member + 1] = badc;
+        if (nfr | nfp) {
+            atomicAdd(&a.floors[2 * bd.member], (unsigned long long)nfr);
+            atomicAdd(&a.floors[2 * bd.member + 1], (unsigned long long)nfp);
         }
         if (a.want_rate) {
             const double m = block_max(rmax, sred);

@@ -211,16 +211,23 @@ DEV void add_sources(const double w[8], double rt, double ctil, double rc, doubl
 
 // Small-value floors on a conserved state: density first (a cell below the
 // density floor takes it at zero velocity), then pressure (energy raised).
-DEV void apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
+// Returns which floors acted: bit 0 density, bit 1 pressure.
+DEV int apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
 {
+    int fired = 0;
     if (u[0] < rho_min) {
         u[0] = rho_min;
         u[1] = 0.0;
         u[2] = 0.0;
         u[3] = 0.0;
+        fired = 1;
     }
     const double kin = 0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) * IC_RCP(u[0]);
     const double mag = 0.5 * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);
     const double p = gs.gm1 * (u[4] - kin - mag);
-    if (p < p_min) u[4] = p_min * gs.igm1 + kin + mag;
+    if (p < p_min) {
+        u[4] = p_min * gs.igm1 + kin + mag;
+        fired |= 2;
+    }
+    return fired;
 }

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <stdexcept>
 #include <string>
@@ -291,6 +292,7 @@ struct ic_sim {
     DBuf<int> items, nitems, mbeg, mend;
     DBuf<double> dt, t, tend, dt_last, rate;
     DBuf<int> bad;
+    DBuf<unsigned long long> floors;   // per member: cells the density / pressure floor acted on
     DBuf<long> nsteps;
     DBuf<SlabTask> slab_tasks;
     DBuf<int> slab_ranges;        // [2 * (IC_MAX_LEVEL + 2)]
@@ -312,6 +314,7 @@ struct ic_sim {
     std::vector<BlockDesc> hdesc;
     double zone_updates = 0.0;
     long host_steps = 0;
+    long since_regrid = 0;          // steps since the last regrid (ic_advance regrids when it reaches regrid_every)
     double sample_point[3] = {1.0, 90.0, 0.0};
 
     // graph
@@ -968,6 +971,7 @@ KArgs base_args(ic_sim *s)
     a.t = s->t.p;
     a.rate = s->rate.p;
     a.bad = s->bad.p;
+    a.floors = s->floors.p;
     a.slab_stride = s->slab_stride;
     a.reg_stride = s->reg_stride;
     a.gas.g = s->phys.gamma;
@@ -1700,6 +1704,7 @@ void do_regrid(ic_sim *s, const int8_t *user_flags)
     }
     for (int slot : to_free) s->mem[slot / s->max_blocks].free_slots.push_back(slot % s->max_blocks);
     s->n_regrids++;
+    s->since_regrid = 0;
     rebuild(s);
     update_sample_desc(s);
     enqueue_rate(s);
@@ -1966,6 +1971,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         s->dt_last.alloc(s->nm);
         s->rate.alloc(NS * KSPLIT_MAX);
         s->bad.alloc(2 * s->nm);
+        s->floors.alloc(2 * s->nm);
         s->nsteps.alloc(s->nm);
         s->slab_ranges.alloc(2 * (IC_MAX_LEVEL + 2));
         s->rf_nblocks.alloc(1);
@@ -1983,6 +1989,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         HIPCHECK(hipMemcpy(s->dt_last.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(s->tend.p, big.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemset(s->bad.p, 0, 2 * s->nm * sizeof(int)));
+        HIPCHECK(hipMemset(s->floors.p, 0, 2 * s->nm * sizeof(unsigned long long)));
         HIPCHECK(hipMemset(s->nsteps.p, 0, s->nm * sizeof(long)));
         HIPCHECK(hipMemset(s->ring_count.p, 0, s->nm * sizeof(int)));
         HIPCHECK(hipMemset(s->rate.p, 0, NS * KSPLIT_MAX * sizeof(double)));
@@ -2023,7 +2030,7 @@ void ic_destroy(ic_sim *s)
     s->U.release(); s->Us.release(); s->slabs.release(); s->freg.release(); s->desc.release();
     s->geo.release(); s->mc.release(); s->items.release(); s->nitems.release(); s->mbeg.release();
     s->mend.release(); s->dt.release(); s->t.release(); s->tend.release(); s->dt_last.release();
-    s->rate.release(); s->bad.release(); s->nsteps.release(); s->slab_tasks.release();
+    s->rate.release(); s->bad.release(); s->floors.release(); s->nsteps.release(); s->slab_tasks.release();
     s->slab_ranges.release(); s->rf_tasks.release(); s->rf_blocks.release(); s->rf_nblocks.release();
     s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
     s->ring_count.release();
@@ -2113,6 +2120,7 @@ ic_status ic_step(ic_sim *s, double dt_fixed_s, ic_info *out)
         run_step(s, dt_fixed_s / kT0, true);
         s->zone_updates += (double)total_cells(s);
         s->host_steps++;
+        s->since_regrid++;
         const Status st = read_status(s);          // one round trip
         info_from_status(s, st, out);
     });
@@ -2133,21 +2141,30 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
         s->tend_finite = true;
         const int every = (s->max_level > 1 && s->amr.regrid_every > 0) ? s->amr.regrid_every : 0;
         long done = 0;
-        // zone updates: per member, the steps it took (a member past its end time
-        // takes dt = 0 and does no work) times its leaf cells (fixed within a batch)
+        // The regrid cadence counts steps across calls (since_regrid): a batch
+        // runs the steps still due before the next regrid, and the regrid
+        // follows the step that completes the count, so advancing in pieces
+        // gives the forests of one advance over the whole span.  Zone updates:
+        // per member, the steps it took (a member past its end time takes dt = 0
+        // and does no work) times its leaf cells (fixed within a batch).
+        if (every > 0 && s->since_regrid >= every) do_regrid(s, nullptr);
         while (done < max_steps) {
-            const long batch = std::min<long>(max_steps - done, every > 0 ? every : 20);
+            const long due = every > 0 ? every - s->since_regrid : 20;
+            const long batch = std::min<long>(max_steps - done, due);
             for (long q = 0; q < batch; ++q) run_step(s, 0.0, true);
             done += batch;
             st = read_status(s);
+            long taken = 0;
             for (int m = 0; m < s->nm; ++m) {
                 s->zone_updates += (double)(st.ns[m] - ns[m]) * (double)s->mem[m].leaves.size() * s->NC;
+                taken = std::max(taken, st.ns[m] - ns[m]);
                 ns[m] = st.ns[m];
             }
+            s->since_regrid += taken;
+            if (every > 0 && s->since_regrid >= every) do_regrid(s, nullptr);
             bool all = true;
             for (int m = 0; m < s->nm; ++m) all = all && st.t[m] >= tend[m];
             if (all) break;
-            if (every > 0) do_regrid(s, nullptr);
         }
         clear_tend(s);
         st = read_status(s);
@@ -2358,6 +2375,7 @@ ic_status ic_set_state(ic_sim *s, int member, const int32_t *lvl_ijk, int n_bloc
         HIPCHECK(hipMemcpy(s->t.p + member, &tc, sizeof(double), hipMemcpyHostToDevice));
         const int zero[2] = {0, 0};
         HIPCHECK(hipMemcpy(s->bad.p + 2 * member, zero, 2 * sizeof(int), hipMemcpyHostToDevice));
+        s->since_regrid = 0;
         rebuild(s);
         update_sample_desc(s);
         enqueue_rate(s);
@@ -2376,6 +2394,72 @@ ic_status ic_get_time(ic_sim *s, int member, double *t_s, double *dt_s)
         HIPCHECK(hipStreamSynchronize(s->stream));
         if (t_s) *t_s = t * kT0;
         if (dt_s) *dt_s = d * kT0;
+    });
+}
+
+ic_status ic_floor_counts(ic_sim *s, int member, long *rho_floors, long *p_floors)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm) throw Error(IC_E_INVALID, "bad member");
+        unsigned long long c[2] = {0, 0};
+        HIPCHECK(hipMemcpyAsync(c, s->floors.p + 2 * member, sizeof(c), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        if (rho_floors) *rho_floors = (long)c[0];
+        if (p_floors) *p_floors = (long)c[1];
+    });
+}
+
+ic_status ic_shock_diagnostics(const double *t_s, const double *v, int n, double t_cme_s, double window_s,
+                               double min_jump, double out[6])
+{
+    return guard(nullptr, [&]() {
+        if (!t_s || !v || !out || n < 0 || !(window_s >= 0.0)) throw Error(IC_E_INVALID, "bad argument");
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        for (int q = 0; q < 6; ++q) out[q] = nan;
+        if (n == 0) return;
+        for (int q = 1; q < n; ++q)
+            if (!(t_s[q] >= t_s[q - 1])) throw Error(IC_E_INVALID, "sample times must ascend");
+        // speed before the shock: v at the CME start, linear between the samples
+        // around it (the first or last sample outside the recorded span)
+        double v_pre;
+        if (t_cme_s <= t_s[0]) v_pre = v[0];
+        else if (t_cme_s >= t_s[n - 1]) v_pre = v[n - 1];
+        else {
+            int q = 1;
+            while (t_s[q] < t_cme_s) ++q;
+            const double h = t_s[q] - t_s[q - 1];
+            v_pre = (t_s[q] == t_cme_s || !(h > 0.0)) ? v[q]
+                                                       : v[q - 1] + (t_cme_s - t_s[q - 1]) * (v[q] - v[q - 1]) / h;
+        }
+        out[2] = v_pre;
+        // peak speed inside [t_cme, t_cme + window] (first sample of the maximum)
+        int qmax = -1;
+        for (int q = 0; q < n; ++q)
+            if (t_s[q] >= t_cme_s && t_s[q] <= t_cme_s + window_s && (qmax < 0 || v[q] > v[qmax])) qmax = q;
+        if (qmax < 0) {
+            out[3] = v_pre;
+            return;
+        }
+        const double v_max = v[qmax];
+        out[3] = v_max;
+        out[5] = t_s[qmax];
+        if (v_max - v_pre < min_jump) return;
+        // arrival: the first upward crossing of the half-rise level inside the
+        // window by a segment that starts at or after the CME start
+        const double thr = v_pre + 0.5 * (v_max - v_pre);
+        const double tol = 1e-12 * std::max(1.0, std::fabs(t_cme_s));
+        for (int q = 1; q < n; ++q) {
+            if (!(t_s[q] >= t_cme_s && t_s[q] <= t_cme_s + window_s)) continue;
+            if (v[q - 1] < thr && thr <= v[q] && t_s[q - 1] >= t_cme_s - tol) {
+                const double ta = t_s[q - 1] + (thr - v[q - 1]) * (t_s[q] - t_s[q - 1]) / (v[q] - v[q - 1]);
+                out[0] = ta - t_cme_s;
+                out[1] = t_s[qmax] - ta;
+                // mean slope of v from the arrival (v = thr) to the peak
+                out[4] = out[1] > 0.0 ? (v_max - thr) / out[1] : nan;
+                return;
+            }
+        }
     });
 }
 

@@ -177,7 +177,8 @@ k_stage(KArgs a)
         // registers carried along k: Wn = W(k+1), wL = face state of cell k at
         // k+1/2, Fm = flux at k-1/2; W(k) of the own column sits in LDS
         double Wn[8], wL[8], Fm[8];
-        int badc = -1;                           // first non-physical input cell of this column
+        int badc = -1;                           // first non-physical input (or stage-2 output) cell of this column
+        int nfr = 0, nfp = 0;                    // cells of this column the density / pressure floor acted on
         if (col) {
             double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
             column8<S>(a, slot, nb, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
@@ -429,11 +430,18 @@ k_stage(KArgs a)
                 const int mk = bd.reflux_mask;
                 const bool rf = (ci == 0 && (mk & 1)) || (ci == BI - 1 && (mk & 2)) || (cj == 0 && (mk & 4))
                              || (cj == BJ - 1 && (mk & 8)) || (k == 0 && (mk & 16)) || (k == BK - 1 && (mk & 32));
-                if (!rf) apply_floors(unew, gs, a.rho_floor, a.p_floor);
+                if (!rf) {
+                    const int f = apply_floors(unew, gs, a.rho_floor, a.p_floor);
+                    nfr += f & 1;
+                    nfp += f >> 1;
+                }
 #pragma unroll
                 for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
                 if (a.want_rate && !rf) {            // refluxed cells: after the reflux
                     cons_to_prim(unew, w, gs);
+                    // the step's result: a non-finite value created in this stage
+                    // would otherwise drop out of the CFL maximum unnoticed
+                    if (badc < 0 && unphysical(w)) badc = ci + BI * (cj + BJ * k);
                     const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
                                       + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
                                       + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pk.iw;
@@ -478,6 +486,10 @@ k_stage(KArgs a)
             __syncthreads();
         }
         if (col && badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
+        if (col && (nfr | nfp)) {
+            atomicAdd(&a.floors[2 * mem], (unsigned long long)nfr);
+            atomicAdd(&a.floors[2 * mem + 1], (unsigned long long)nfp);
+        }
         if (a.want_rate) {
             // this part's CFL maximum; the last part clears the unused entries
             const double m = block_max(col ? rmax : 0.0, sred);

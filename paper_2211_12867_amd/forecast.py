@@ -20,7 +20,7 @@ import time
 
 import numpy as np
 
-from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, arrival, mlp_infer, mlp_init, mlp_train, units
+from . import IC_SOURCE_LEARNED_JUDGED, IC_SOURCE_PLAIN, Sim, mlp_infer, mlp_init, mlp_train, shock_diagnostics, units
 
 DAY = 86400.0
 HOUR = 3600.0
@@ -68,18 +68,22 @@ def relax(grid, wind, cme, t_end_s, chunk_s=DAY, log=print):
 MIN_JUMP_KMS = 100.0   # a rise of v_r smaller than this within the window is no shock arrival
 
 
-def _series_arrival(ts, t_cme_s, window_h=96.0):
-    """(t [h], v_r [km/s]) of the record and the shock arrival and width [h]
-    (half-rise crossing after the CME start; NaN without a rise of at least
-    MIN_JUMP_KMS)."""
+def _series_diagnostics(ts, t_cme_s, window_h=96.0):
+    """(t [h], v_r [km/s]) of the record and its shock diagnostics
+    (ic_shock_diagnostics: arrival and width [h], peak speed [km/s], average
+    gradient [km/s per h]; NaN without a rise of at least MIN_JUMP_KMS)."""
     t_h = ts[:, 0] / HOUR
     v = ts[:, 2] * units()["speed_m_s"] / 1e3
-    t0 = t_cme_s / HOUR
-    win = (t_h >= t0) & (t_h <= t0 + window_h)
-    if not win.any() or v[win].max() - np.interp(t0, t_h, v) < MIN_JUMP_KMS:
-        return t_h, v, float("nan"), float("nan")
-    a, w = arrival(t_h, v, t0, window_h)
-    return t_h, v, a, w
+    d = shock_diagnostics(ts[:, 0], v, t_cme_s, window_h * HOUR, MIN_JUMP_KMS)
+    out = dict(arrival_h=d["arrival_s"] / HOUR, width_h=d["width_s"] / HOUR, peak_kms=d["v_max"],
+               gradient_kms_h=d["gradient"] * HOUR, v_pre_kms=d["v_pre"])
+    return t_h, v, out
+
+
+def _series_arrival(ts, t_cme_s, window_h=96.0):
+    """(t [h], v_r [km/s], arrival [h], width [h]) of the record."""
+    t_h, v, d = _series_diagnostics(ts, t_cme_s, window_h)
+    return t_h, v, d["arrival_h"], d["width_h"]
 
 
 def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4, log=print, max_blocks=0):
@@ -112,8 +116,10 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
                 time.perf_counter() - t0))
     wall = time.perf_counter() - t0
     ts = np.concatenate(ts) if ts else np.zeros((0, 9))
-    t_h, v, a, w = _series_arrival(ts, cme["t_start_s"])
-    out = dict(arrival_h=a, width_h=w, wall_s=wall, steps=info["steps"] if info else 0,
+    t_h, v, diag = _series_diagnostics(ts, cme["t_start_s"])
+    a, w = diag["arrival_h"], diag["width_h"]
+    out = dict(arrival_h=a, width_h=w, peak_kms=diag["peak_kms"], gradient_kms_h=diag["gradient_kms_h"],
+               wall_s=wall, steps=info["steps"] if info else 0,
                leaf_block_steps=((info["zone_updates"] if info else 0.0) - zu0) / cells, max_leaves=max_leaves,
                regrid_stats=sim.regrid_stats(), t_h=t_h, v_kms=v)
     sim.close()

@@ -7,6 +7,9 @@
   parameter group's gradient to 5e-3 in relative L2 norm (the two sides
   differ only in fp32 accumulation order, which moves a bf16 rounding by one
   unit now and then); sizes 1 (one ragged tile), 37, 300 rows;
+- element by element: on inputs whose forward sums are exact in fp32, every
+  gradient element lies within the bound propagated from the bf16 rounding
+  points and fp32 accumulation (tests/mlp_bounds.py);
 - one Adam step of ic_mlp_train (the whole set as one batch) equals the
   oracle's Adam step on the oracle's gradient: every parameter whose
   gradient is not near zero moves by the same amount;
@@ -95,6 +98,22 @@ def test_gradient_matches_oracle(n):
         ref = grad_o[a:b]
         e = np.linalg.norm(grad[a:b] - ref) / max(np.linalg.norm(ref), 1e-30)
         assert e <= 5e-3, (name, e)
+
+
+@pytest.mark.parametrize("n", [1, 37, 300])
+def test_gradient_matches_oracle_elementwise(n):
+    """Every gradient element within the bound propagated from the bf16
+    rounding points and fp32 accumulation (mlp_bounds), on inputs whose
+    forward sums are exact in fp32, so both sides hold the same activations."""
+    import mlp_bounds as mb
+    ic = _ic()
+    x, y, p = mb.exact_problem(n, seed=n)
+    g, bound, amb, loss_o = mb.gradient_bound(x, y, p, 2.5)
+    grad, loss = ic.mlp_grad(x, y, p, pos_weight=2.5)
+    assert abs(loss - loss_o) <= 1e-5 * abs(loss_o), (loss, loss_o)
+    err = np.abs(grad.astype(np.float64) - g)
+    over = np.nonzero(err > bound)[0]
+    assert len(over) == 0, (n, amb, [(int(q), float(err[q]), float(bound[q])) for q in over[:5]])
 
 
 def test_one_adam_step_matches_oracle():
