@@ -154,7 +154,7 @@ def test_equidistant_full_cfl_segment_from_the_initial_state():
     ora = solver.PatchSolver(g, wind, cme)
     bl, U = gpu.state()
     bo, Uo = ora.to_blocks(g["block"])
-    assert bl == bo and rel_err(U, Uo) <= 1e-15
+    assert bl == bo and rel_err(U, Uo) <= 1e-14      # the same initial condition up to rounding
     _segment(ic, g, wind, cme, ora, gpu)
     gpu.close()
 
