@@ -329,6 +329,24 @@ ic_status ic_mlp_train(const float *raw, const uint8_t *y, long n, const ic_mlp_
 ic_status ic_mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std,
                        float *prob);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * probabilities of ic_mlp_infer with every array on the device and no
+ * allocation of any kind.  raw_dev [n x 512], params_dev [IC_MLP_NPARAM],
+ * mean_dev and std_dev [512] (std must be positive; the values are not
+ * checked on the host), prob_dev [n]: device pointers owned by the caller.
+ * The work is enqueued on hip_stream (NULL = the null stream) and the call
+ * returns without synchronising; prob_dev is valid once the stream has
+ * completed it.  Intermediate values live in a fixed device scratch of the
+ * library (one copy per device, about 6.2 MiB, held until the process
+ * ends), so n may not exceed IC_MLP_NOALLOC_ROWS (IC_E_INVALID).  Every call
+ * on a device shares that scratch: calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.  Results
+ * equal ic_mlp_infer's bit for bit. */
+#define IC_MLP_NOALLOC_ROWS 4096
+ic_status ic_mlp_infer_noalloc(const float *raw_dev, long n, const float *params_dev, const float *mean_dev,
+                               const float *std_dev, float *prob_dev, void *hip_stream);
+
 /* One forward and backward pass on n rows of already normalised inputs
  * (fp32, rounded to bf16 inside): gradient of the mean weighted BCE in
  * params layout, and the loss. */

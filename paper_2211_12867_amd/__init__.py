@@ -108,7 +108,7 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
-           "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_last_error")
+           "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_mlp_infer_noalloc", "ic_last_error")
 
 
 def _load():
@@ -157,6 +157,7 @@ def _load():
     L.ic_mlp_train.argtypes = [fp, u8p, ctypes.c_long, P(MlpHparams), fp, fp, fp, fp]
     L.ic_mlp_grad.argtypes = [fp, u8p, ctypes.c_int, ctypes.c_float, fp, fp, fp]
     L.ic_mlp_infer.argtypes = [fp, ctypes.c_long, fp, fp, fp, fp]
+    L.ic_mlp_infer_noalloc.argtypes = [vp, ctypes.c_long, vp, vp, vp, vp, vp]
     L.ic_autotune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int, P(TuneInfo)]
     L.ic_set_tuning.argtypes = [vp, P(TuneInfo)]
     L.ic_get_tuning.argtypes = [vp, P(TuneInfo)]
@@ -505,6 +506,18 @@ def mlp_infer(raw, params, mean, std):
     ps = [np.ascontiguousarray(a, dtype=np.float32) for a in (params, mean, std)]
     _check(lib.ic_mlp_infer(_fptr(raw), len(raw), *[_fptr(a) for a in ps], _fptr(prob)))
     return prob
+
+
+MLP_NOALLOC_ROWS = 4096
+
+
+def mlp_infer_noalloc(raw_dev, n, params_dev, mean_dev, std_dev, prob_dev, stream=None):
+    """ic_mlp_infer_noalloc on device arrays given by address (e.g. a torch
+    tensor's data_ptr()); enqueued on stream (default: torch's current
+    stream), no synchronisation and no allocation."""
+    st = stream if stream is not None else _current_stream()
+    _check(lib.ic_mlp_infer_noalloc(ctypes.c_void_p(raw_dev), int(n), ctypes.c_void_p(params_dev),
+                                    ctypes.c_void_p(mean_dev), ctypes.c_void_p(std_dev), ctypes.c_void_p(prob_dev), st))
 
 
 def mlp_init(seed=0):

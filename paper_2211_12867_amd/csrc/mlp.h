@@ -55,3 +55,13 @@ void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float
 void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp, float *params, float *mean_out,
                float *std_out, float *loss_epochs);
 void mlp_infer(const float *raw, long n, const float *params, const float *mean, const float *std, float *prob);
+
+// rows of one allocation-free inference call (the fixed device scratch holds
+// their bf16 inputs and hidden layers)
+#ifndef IC_MLP_NOALLOC_ROWS
+#define IC_MLP_NOALLOC_ROWS 4096
+#endif
+// Inference on device arrays with no allocation: scratch is a file-scope
+// device array of mlp.hip, shared by every call on a device.  Enqueued on s.
+void mlp_infer_noalloc(const float *raw, long n, const float *params, const float *mean, const float *std,
+                       float *prob, hipStream_t s);

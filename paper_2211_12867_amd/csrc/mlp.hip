@@ -15,6 +15,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -203,6 +205,13 @@ __global__ void k_normalise(const float *raw, const float *mean, const float *is
     if (q >= n * IC_MLP_IN) return;
     const int f = (int)(q % IC_MLP_IN);
     xb[q] = f2bf((raw[q] - mean[f]) * istd[f]);
+}
+
+// 1 / std per input (fp32 division, correctly rounded as on the host)
+__global__ void k_istd(const float *std, float *istd)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < IC_MLP_IN) istd[f] = 1.0f / std[f];
 }
 
 // minibatch gather: rows order[b0 + q] of the normalised inputs and labels
@@ -497,4 +506,74 @@ void mlp_infer(const float *raw, long n, const float *params, const float *mean,
         if (hipMemcpy(prob + b0, d.prob, m * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
             throw std::runtime_error("hipMemcpy failed");
     }
+}
+
+// ---------------------------------------------------------------------------
+// inference without allocation
+// ---------------------------------------------------------------------------
+// The scratch of the allocation-free entry point: bf16 weights, 1/std, and
+// the bf16 inputs and both hidden layers of up to IC_MLP_NOALLOC_ROWS rows
+// (6.2 MiB), one copy per device for the life of the process.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is a host-side stand-in).
+namespace {
+constexpr size_t na_align(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaWb = 0;
+constexpr size_t kNaIstd = kNaWb + na_align((size_t)IC_MLP_NPARAM * sizeof(uint16_t));
+constexpr size_t kNaX = kNaIstd + na_align((size_t)IC_MLP_IN * sizeof(float));
+constexpr size_t kNaH1 = kNaX + (size_t)IC_MLP_NOALLOC_ROWS * IC_MLP_IN * sizeof(uint16_t);
+constexpr size_t kNaH2 = kNaH1 + (size_t)IC_MLP_NOALLOC_ROWS * IC_MLP_HID * sizeof(uint16_t);
+constexpr size_t kNaBytes = kNaH2 + (size_t)IC_MLP_NOALLOC_ROWS * IC_MLP_HID * sizeof(uint16_t);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+unsigned char *g_na_scratch[kNaMaxDevices];   // device address of each device's copy, once resolved
+std::mutex g_na_mu;
+
+// Device address of the current device's scratch, resolved on the first call
+// on that device.
+unsigned char *noalloc_scratch()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) throw std::runtime_error("hipGetDevice failed");
+    if (dev < 0 || dev >= kNaMaxDevices) throw std::runtime_error("device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            throw std::runtime_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_na_scratch[dev] = (unsigned char *)p;
+    }
+    return g_na_scratch[dev];
+}
+}  // namespace
+
+void mlp_infer_noalloc(const float *raw, long n, const float *params, const float *mean, const float *std,
+                       float *prob, hipStream_t s)
+{
+    if (n < 0 || n > IC_MLP_NOALLOC_ROWS) throw std::invalid_argument("row count outside 0 .. IC_MLP_NOALLOC_ROWS");
+    unsigned char *base = noalloc_scratch();
+    if (n == 0) return;
+    uint16_t *wb = (uint16_t *)(base + kNaWb);
+    float *istd = (float *)(base + kNaIstd);
+    uint16_t *xb = (uint16_t *)(base + kNaX);
+    uint16_t *h1 = (uint16_t *)(base + kNaH1);
+    uint16_t *h2 = (uint16_t *)(base + kNaH2);
+    // every scratch element read below is written first in this call: nothing to clear
+    hipLaunchKernelGGL(k_istd, dim3((IC_MLP_IN + 255) / 256), dim3(256), 0, s, std, istd);
+    hipLaunchKernelGGL(k_to_bf16, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, params, wb, (long)IC_MLP_NPARAM);
+    hipLaunchKernelGGL(k_normalise, dim3((n * IC_MLP_IN + 255) / 256), dim3(256), 0, s, raw, mean, istd, n, xb);
+    gemm(s, xb, IC_MLP_IN, 1, wb + IC_MLP_OFF_W1, IC_MLP_HID, 1, (int)n, IC_MLP_HID, IC_MLP_IN, params + IC_MLP_OFF_B1,
+         1, nullptr, h1, IC_MLP_HID);
+    gemm(s, h1, IC_MLP_HID, 1, wb + IC_MLP_OFF_W2, IC_MLP_HID, 1, (int)n, IC_MLP_HID, IC_MLP_HID,
+         params + IC_MLP_OFF_B2, 1, nullptr, h2, IC_MLP_HID);
+    hipLaunchKernelGGL(k_head, dim3((n + 255) / 256), dim3(256), 0, s, h2, wb + IC_MLP_OFF_W3, params + IC_MLP_OFF_B3,
+                       (int)n, (const uint8_t *)nullptr, 0.f, (float *)nullptr, prob, (float *)nullptr,
+                       (float *)nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw std::runtime_error(std::string("launch failed: ") + hipGetErrorString(e));
 }

@@ -2578,6 +2578,25 @@ ic_status ic_mlp_infer(const float *raw, long n, const float *params, const floa
     });
 }
 
+ic_status ic_mlp_infer_noalloc(const float *raw_dev, long n, const float *params_dev, const float *mean_dev,
+                               const float *std_dev, float *prob_dev, void *hip_stream)
+{
+    static_assert(IC_MLP_NOALLOC_ROWS == 4096, "the header's row limit");
+    return guard(nullptr, [&]() {
+        if (!raw_dev || !params_dev || !mean_dev || !std_dev || !prob_dev || n < 0)
+            throw Error(IC_E_INVALID, "bad argument");
+        if (n > IC_MLP_NOALLOC_ROWS)
+            throw Error(IC_E_INVALID, "ic_mlp_infer_noalloc: " + std::to_string(n) + " rows exceed the limit of " +
+                                          std::to_string(IC_MLP_NOALLOC_ROWS) + " (the fixed scratch)");
+        try {
+            mlp_infer_noalloc(raw_dev, n, params_dev, mean_dev, std_dev, prob_dev, (hipStream_t)hip_stream);
+        } catch (const std::invalid_argument &e) {
+            throw Error(IC_E_INVALID, e.what());
+        } catch (const std::runtime_error &e) {
+            throw Error(IC_E_DEVICE, e.what());
+        }
+    });
+}
 
 ic_status ic_set_tuning(ic_sim *s, const ic_tune_info *t)
 {
