@@ -78,16 +78,32 @@ def measured_valu():
             "source": "profiles/stage_valu_equidistant_full.md"}
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The oracle (plain fp64 C core with OpenMP) on a bounded sample of the
-    workload: the same grid spacing over the inner 64 radial cells."""
-    import numpy as np  # noqa: F401
+def _cpu_model():
+    """CPU model name from lscpu (fallback /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=20).stdout
+        for line in out.splitlines():
+            if line.split(":")[0].strip() == "Model name":
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown"
+
+
+def _oracle_sample(nr, seconds_target, max_steps):
+    """Steps of the oracle on the inner nr radial cells of the equidistant grid
+    (same spacing); returns (zone-updates/s, steps, seconds, cells)."""
     from oracle import solver
     from synthetic import as_dict, workload
     w = workload("equidistant_full")
     g = as_dict(w.grid)
     dr = (g["x1"][0] - g["x0"][0]) / g["n"][0]
-    nr = 64
     g["n"] = (nr, g["n"][1], g["n"][2])
     g["x1"] = (g["x0"][0] + nr * dr, g["x1"][1], g["x1"][2])
     s = solver.PatchSolver(g, as_dict(w.wind), as_dict(w.cmes[0]))
@@ -98,19 +114,42 @@ def cpu_baseline(seconds_target=15.0):
         s.step()
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds_target or steps >= 50:
+        if el > seconds_target or steps >= max_steps:
             break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cpu = "unknown"
+    return cells * steps / el, steps, el, cells
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The oracle (plain fp64 C core with OpenMP) on a bounded sample of the
+    workload: the same grid spacing over the inner 64 radial cells, on every
+    core the process may run on (affinity mask, capped by OMP_NUM_THREADS when
+    set), and on one thread (inner 16 radial cells, a child process)."""
+    import subprocess
+    affinity = len(os.sched_getaffinity(0))
+    threads = affinity
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    # the oracle's OpenMP runtime starts on first use: fix its team here
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    rate, steps, el, cells = _oracle_sample(64, seconds_target, 50)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import sys, json; sys.path.insert(0, %r); import bench; "
+            "print(json.dumps(bench._oracle_sample(16, 10.0, 8)))" % ROOT)
+    single = None
     try:
-        with open("/proc/cpuinfo") as fh:
-            cpu = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
-    return {"value": cells * steps / el, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
-            "cpu": cpu,
-            "sample": "%d steps of the %d x 60 x 180 inner-radius part of the same grid (%.1f s)"
-                      % (steps, nr, el)}
+        res = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                             text=True, env=env, timeout=120)
+        r1, s1, e1, c1 = json.loads(res.stdout.strip().splitlines()[-1])
+        single = {"value": r1, "cores": 1, "sample": "%d steps of the 16 x 60 x 180 inner-radius part (%.1f s)"
+                                                       % (s1, e1)}
+    except (OSError, subprocess.SubprocessError, ValueError, IndexError):
+        single = None
+    return {"value": rate, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "cpu": _cpu_model(), "affinity_cpus": affinity,
+            "sample": "%d steps of the 64 x 60 x 180 inner-radius part of the same grid (%.1f s, %d threads)"
+                      % (steps, el, threads),
+            "single_thread": single}
 
 
 def main():
