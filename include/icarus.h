@@ -85,7 +85,18 @@ typedef struct {
  * frame rotation rate [rad/s] about the theta = 0 axis, G M_sun [m^3 s^-2],
  * small-value floors in code units applied to every stage result (a cell with
  * rho < rho_floor takes rho_floor at zero velocity; then a cell with
- * p < p_floor has its energy raised to give p = p_floor; 0 disables). */
+ * p < p_floor has its energy raised to give p = p_floor; 0 disables).
+ * Scheme (Sect. 2.1: TVDLF with the Woodward limiter in the paper's runs; its
+ * code offers other scheme and limiter combinations): limiter of the
+ * primitive reconstruction, IC_LIM_MC (monotonised central, the Woodward
+ * form; the default), IC_LIM_MINMOD or IC_LIM_VANLEER (harmonic mean of the
+ * one-sided differences); scheme IC_SCHEME_TWO_STAGE (U* = U^n + dt/2 L(U^n),
+ * U^{n+1} = U^n + dt L(U*); the default) or IC_SCHEME_HANCOCK (the one-step
+ * TVDLF: the predictor U* = U^n + dt/2 L_H(U^n) takes each cell's own physical
+ * fluxes at its reconstructed face states, no interface solver, then the same
+ * conservative second stage). */
+enum { IC_LIM_MC = 0, IC_LIM_MINMOD = 1, IC_LIM_VANLEER = 2 };
+enum { IC_SCHEME_TWO_STAGE = 0, IC_SCHEME_HANCOCK = 1 };
 typedef struct {
     double gamma;
     double cfl;
@@ -93,6 +104,8 @@ typedef struct {
     double gm;
     double rho_floor;
     double p_floor;
+    int limiter;
+    int scheme;
 } ic_phys_cfg;
 
 /* Inner-boundary wind at r_in (Sect. 2.1): v_r = v_min + (v_max - v_min)

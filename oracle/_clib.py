@@ -30,7 +30,10 @@ class Patch(ctypes.Structure):
                 ("f0", ctypes.POINTER(ctypes.c_double)),
                 ("f1", ctypes.POINTER(ctypes.c_double)),
                 ("f2", ctypes.POINTER(ctypes.c_double)),
-                ("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("gm", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("gm", ctypes.c_double),
+                ("limiter", ctypes.c_int)]
+
+LIMITERS = {"mc": 0, "minmod": 1, "vanleer": 2}
 
 
 _lib = None
@@ -52,6 +55,10 @@ def lib():
         L.ora_rusanov.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, dp]
         L.ora_mc_slope.argtypes = [ctypes.c_double] * 6
         L.ora_mc_slope.restype = ctypes.c_double
+        L.ora_slope.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
+        L.ora_slope.restype = ctypes.c_double
+        L.ora_rhs_hancock.argtypes = [pp, dp, dp]
+        L.ora_rhs_hancock.restype = ctypes.c_int
         L.ora_sources.argtypes = [dp] + [ctypes.c_double] * 7 + [dp]
         L.ora_rhs.argtypes = [pp, dp, dp, dp, dp, dp]
         L.ora_rhs.restype = ctypes.c_int
@@ -109,14 +116,18 @@ def mc_slope(wm, w0, wp, xm, x0, xp):
     return lib().ora_mc_slope(wm, w0, wp, xm, x0, xp)
 
 
+def slope(limiter, wm, w0, wp, xm, x0, xp):
+    return lib().ora_slope(LIMITERS[limiter], wm, w0, wp, xm, x0, xp)
+
+
 class PatchGeom:
     """Keeps the face arrays alive for a Patch struct."""
 
-    def __init__(self, f0, f1, f2, cartesian, gamma, omega, gm):
+    def __init__(self, f0, f1, f2, cartesian, gamma, omega, gm, limiter="mc"):
         self.f = [_vec(f0), _vec(f1), _vec(f2)]
         self.n = tuple(len(a) - 5 for a in self.f)
         self.s = Patch(self.n[0], self.n[1], self.n[2], 1 if cartesian else 0,
-                       _p(self.f[0]), _p(self.f[1]), _p(self.f[2]), gamma, omega, gm)
+                       _p(self.f[0]), _p(self.f[1]), _p(self.f[2]), gamma, omega, gm, LIMITERS[limiter])
 
 
 def rhs(pg, G, want_fluxes=True):
@@ -130,6 +141,16 @@ def rhs(pg, G, want_fluxes=True):
     F2 = np.empty((NV, nk + 1, nj, ni))
     bad = lib().ora_rhs(ctypes.byref(pg.s), _p(G), _p(L), _p(F0), _p(F1), _p(F2))
     return L, (F0, F1, F2), bad
+
+
+def rhs_hancock(pg, G):
+    """Hancock predictor operator of a ghosted patch.  Returns (L, n_bad)."""
+    ni, nj, nk = pg.n
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    assert G.shape == (NV, nk + 4, nj + 4, ni + 4)
+    L = np.empty((NV, nk, nj, ni))
+    bad = lib().ora_rhs_hancock(ctypes.byref(pg.s), _p(G), _p(L))
+    return L, bad
 
 
 def max_rate(pg, G):

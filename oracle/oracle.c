@@ -10,12 +10,16 @@
  * and time, two ghost layers):
  *   - conserved <-> primitive variables and the fast magnetosonic speed;
  *   - the ideal-MHD flux along one coordinate direction;
- *   - the monotonised-central limited slope of one primitive on a
- *     non-uniform coordinate (the Woodward & Colella form);
+ *   - the limited slope of one primitive on a non-uniform coordinate: the
+ *     monotonised-central limiter (the Woodward & Colella form, the paper's
+ *     choice), minmod or van Leer (the paper names further limiters among the
+ *     combinations its code offers);
  *   - the local Lax-Friedrichs (Rusanov) interface flux;
  *   - the spatial operator L(U) of a ghosted patch: flux differences over the
  *     finite volume plus the spherical hoop terms, Coriolis, centrifugal and
  *     solar-gravity sources;
+ *   - the Hancock predictor operator: the same differences of each cell's own
+ *     physical fluxes at its reconstructed face states (no interface solver);
  *   - the CFL rate, and the per-cell refinement-indicator quantities
  *     (Loehner-type second-derivative estimator and div V).
  *
@@ -47,6 +51,7 @@ typedef struct {
     double gamma;
     double omega;          /* rotation rate of the frame about the theta = 0 axis */
     double gm;             /* G * M_sun */
+    int limiter;           /* 0 monotonised central, 1 minmod, 2 van Leer */
 } ora_patch;
 
 /* ------------------------------------------------------------------------ */
@@ -146,6 +151,21 @@ double ora_mc_slope(double wm, double w0, double wp, double xm, double x0, doubl
     return dc > 0.0 ? a : -a;
 }
 
+/* limited slope by limiter kind (0 monotonised central, 1 minmod, 2 van
+ * Leer): with the one-sided differences dm, dp of the primitive, zero where
+ * they differ in sign or one vanishes; otherwise
+ *   minmod:   the one of smaller magnitude,
+ *   van Leer: their harmonic mean 2 dm dp / (dm + dp). */
+double ora_slope(int limiter, double wm, double w0, double wp, double xm, double x0, double xp)
+{
+    if (limiter == 0) return ora_mc_slope(wm, w0, wp, xm, x0, xp);
+    double dm = (w0 - wm) / (x0 - xm);
+    double dp = (wp - w0) / (xp - x0);
+    if (dm * dp <= 0.0) return 0.0;
+    if (limiter == 1) return fabs(dm) < fabs(dp) ? dm : dp;
+    return 2.0 * dm * dp / (dm + dp);
+}
+
 /*
  * Source terms of a cell with primitive state w (spherical geometry only).
  *   rtinv = 1/r in its finite-volume form 3(r+^2 - r-^2) / (2(r+^3 - r-^3))
@@ -225,7 +245,7 @@ static void reconstruct(const ora_patch *p, const double *U, int d, int c, int a
     double flo = face(p, d, c), fhi = face(p, d, c + 1);
     double s[NV];
     for (int v = 0; v < NV; ++v) {
-        s[v] = ora_mc_slope(wm[v], w0[v], wp[v], xm, x0, xp);
+        s[v] = ora_slope(p->limiter, wm[v], w0[v], wp[v], xm, x0, xp);
         w_lo[v] = w0[v] - s[v] * (x0 - flo);
         w_hi[v] = w0[v] + s[v] * (fhi - x0);
     }
@@ -352,6 +372,57 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
                 }
                 for (int v = 0; v < NV; ++v)
                     L[(((size_t)v * nk + k) * nj + j) * ni + i] = acc[v];
+            }
+        }
+    }
+    return bad;
+}
+
+/*
+ * Hancock predictor operator on the interior of a ghosted patch: for each
+ * cell and direction, the cell's reconstructed face states (limiter as in
+ * ora_rhs) give the physical fluxes F(w_lo), F(w_hi) at its own lower and
+ * upper faces; L = -(1/V) sum_d [A+ F(w_hi) - A- F(w_lo)] + sources at the
+ * cell state.  No interface solver: the predictor U* = U + (dt/2) L gives
+ * the half-step state from which the corrector computes the TVDLF fluxes.
+ * Returns the number of interior cells with rho <= 0, p <= 0 or a
+ * non-finite value.
+ */
+int ora_rhs_hancock(const ora_patch *p, const double *U, double *L)
+{
+    const int ni = p->ni, nj = p->nj, nk = p->nk;
+    int bad = 0;
+    #pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int k = 0; k < nk; ++k) {
+        for (int j = 0; j < nj; ++j) {
+            for (int i = 0; i < ni; ++i) {
+                double w[NV], acc[NV];
+                cell_prim(p, U, i, j, k, w);
+                int ok = w[0] > 0.0 && w[4] > 0.0;
+                for (int v = 0; v < NV; ++v) ok = ok && isfinite(w[v]);
+                if (!ok) bad += 1;
+                for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+                int c[3] = {i, j, k};
+                for (int d = 0; d < 3; ++d) {
+                    double lo[NV], hi[NV], flo[NV], fhi[NV], am, ap;
+                    reconstruct(p, U, d, c[d], c[(d + 1) % 3], c[(d + 2) % 3], lo, hi);
+                    ora_flux(lo, d, p->gamma, flo);
+                    ora_flux(hi, d, p->gamma, fhi);
+                    metric(p, d, i, j, k, &am, &ap);
+                    for (int v = 0; v < NV; ++v) acc[v] -= ap * fhi[v] - am * flo[v];
+                }
+                if (!p->cartesian) {
+                    double rm = face(p, 0, i), rp = face(p, 0, i + 1);
+                    double tm = face(p, 1, j), tp = face(p, 1, j + 1);
+                    double rtinv = 1.5 * (rp * rp - rm * rm) / (rp * rp * rp - rm * rm * rm);
+                    double dmu = cos(tm) - cos(tp);
+                    double ctil = (sin(tp) - sin(tm)) / dmu;
+                    double tc = centre(p, 1, j);
+                    double S[NV];
+                    ora_sources(w, rtinv, ctil, centre(p, 0, i), sin(tc), cos(tc), p->omega, p->gm, S);
+                    for (int v = 0; v < NV; ++v) acc[v] += S[v];
+                }
+                for (int v = 0; v < NV; ++v) L[(((size_t)v * nk + k) * nj + j) * ni + i] = acc[v];
             }
         }
     }

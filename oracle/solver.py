@@ -4,6 +4,12 @@ Time step (paper Sect. 2.1, second order in time; two-stage midpoint form):
     stage 1: ghosts at t^n,        U*      = U^n + (dt/2) L(U^n)
     stage 2: ghosts at t^n + dt/2, U^{n+1} = U^n +  dt    L(U*)
     dt = C_cfl / max_cells sum_d (|v_d| + c_f,d) / dx_d, computed on U^n.
+Scheme variants (Sect. 2.1 names further scheme and limiter combinations):
+the limiter of the reconstruction (monotonised central, minmod, van Leer),
+and the Hancock one-step form, whose first stage is the predictor
+U* = U^n + (dt/2) L_H(U^n) (each cell's own physical fluxes at its
+reconstructed face states; no interface solver, no reflux), followed by the
+same second stage.
 
 Block AMR (Sect. 3): every leaf carries two face-ghost layers per face.  Face
 ghosts come from a same-level neighbour (copy), from finer neighbours
@@ -93,8 +99,10 @@ class Solver:
     """Block-forest solver.  State: dict leaf -> U[8, bk, bj, bi] (code units)."""
 
     def __init__(self, grid, wind=None, cme=None, amr=None, omega=None, gm=None, t0_s=0.0,
-                 initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
+                 initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage"):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
+        self.limiter, self.scheme = limiter, scheme
+        assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
@@ -141,7 +149,7 @@ class Solver:
             g = self.geo[leaf[0]]
             f = [g.faces(d, *self.cell_range(leaf, d)) for d in range(3)]
             self._patch[leaf] = _clib.PatchGeom(f[0], f[1], f[2], self.cart, self.gamma,
-                                                self.omega, self.gm)
+                                                self.omega, self.gm, self.limiter)
         return self._patch[leaf]
 
     def centres(self, leaf, d, lo=0, hi=None):
@@ -354,6 +362,18 @@ class Solver:
         self._reflux(L, F)
         return L, G
 
+    def predictor(self, U, t):
+        """Hancock predictor operator L_H(U) of every leaf (ghosts at t)."""
+        G = self.ghosted(U, t)
+        L = {}
+        bad = 0
+        for leaf in self.forest.leaves:
+            L[leaf], nb = _clib.rhs_hancock(self.patch(leaf), G[leaf])
+            bad += nb
+        if bad:
+            raise UnphysicalState("%d cells with rho <= 0, p <= 0 or non-finite values" % bad)
+        return L
+
     def _reflux(self, L, F):
         B = self.B
         for leaf in sorted(self.forest.leaves):
@@ -421,7 +441,10 @@ class Solver:
             if t_end is not None:
                 dt = min(dt, t_end - self.t)
         Un = self.U
-        L1, _ = self.operator(Un, self.t)
+        if self.scheme == "hancock":
+            L1 = self.predictor(Un, self.t)
+        else:
+            L1, _ = self.operator(Un, self.t)
         Us = {b: Un[b] + (0.5 * dt) * L1[b] for b in Un}
         for u in Us.values():
             self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
@@ -648,8 +671,10 @@ class PatchSolver:
     an independent check of the block decomposition and as the CPU baseline."""
 
     def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind",
-                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR):
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage"):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
+        self.limiter, self.scheme = limiter, scheme
+        assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
         self.grid.setdefault("geometry", "spherical")
@@ -665,7 +690,7 @@ class PatchSolver:
         self.n = self.geo.n
         self.r_in = self.geo.f[0][2]
         self.pg = _clib.PatchGeom(self.geo.f[0], self.geo.f[1], self.geo.f[2], self.cart,
-                                  self.gamma, self.omega, self.gm)
+                                  self.gamma, self.omega, self.gm, limiter)
         self.t = units.time_code(t0_s)
         ni, nj, nk = self.n
         if initial == "wind" and wind is not None and not self.cart:
@@ -714,6 +739,12 @@ class PatchSolver:
             raise UnphysicalState("%d unphysical cells" % bad)
         return L
 
+    def predictor(self, U, t):
+        L, bad = _clib.rhs_hancock(self.pg, self.ghosted(U, t))
+        if bad:
+            raise UnphysicalState("%d unphysical cells" % bad)
+        return L
+
     def cfl_dt(self):
         G = np.zeros((NV,) + tuple(x + 4 for x in self.n[::-1]))
         G[:, 2:-2, 2:-2, 2:-2] = self.U
@@ -723,7 +754,7 @@ class PatchSolver:
         if dt is None:
             dt = self.cfl_dt()
         Un = self.U
-        L1 = self.operator(Un, self.t)
+        L1 = self.predictor(Un, self.t) if self.scheme == "hancock" else self.operator(Un, self.t)
         Us = Un + (0.5 * dt) * L1
         self.floored += apply_floors(Us, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
         L2 = self.operator(Us, self.t + 0.5 * dt)

@@ -163,7 +163,8 @@ struct IndicatorParams {
 
 // Launch wrappers per block shape (kernels.hip, stage.hip); the runtime calls these.
 struct Launchers {
-    void (*stage)(dim3, hipStream_t, const KArgs &, int waves);
+    void (*stage)(dim3, hipStream_t, const KArgs &, int waves, int limiter);
+    void (*hancock)(dim3, hipStream_t, const KArgs &, int limiter);
     void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *, int pass);
     void (*reflux)(dim3, hipStream_t, const KArgs &, const RefluxTask *, const int *, const int *);
     void (*rate)(dim3, hipStream_t, const KArgs &);
@@ -178,8 +179,10 @@ void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, 
 void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm);
 
 // kernel entry points (stage.hip: k_stage and its launcher; kernels.hip: the rest)
-template <int BI, int BJ, int BK, int W> __global__ void k_stage(KArgs a);
-template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves);
+template <int BI, int BJ, int BK, int W, int LIM> __global__ void k_stage(KArgs a);
+template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter);
+template <int BI, int BJ, int BK, int LIM> __global__ void k_hancock(KArgs a);
+template <int BI, int BJ, int BK> void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter);
 template <int BI, int BJ, int BK, int PASS> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
 template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);

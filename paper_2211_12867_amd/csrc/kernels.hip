@@ -430,6 +430,108 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Hancock predictor (the one-step TVDLF form): U* = U + alpha dt L_H(U), L_H
+// the finite-volume difference of each cell's own physical fluxes at its
+// reconstructed lower and upper face states, plus the sources at the cell
+// state; no interface solver and no reflux (the corrector, a stage-kernel
+// launch from U*, is conservative).  One work-group per leaf block, one
+// thread per cell; neighbours along each axis through cell_addr (one index
+// at most in the ghost layers).  Floors and the input check as in k_stage.
+// ---------------------------------------------------------------------------
+template <class S>
+DEV void prim_at(const KArgs &a, int slot, const Faces &nb, int i, int j, int k, double w[8])
+{
+    double u[8];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) u[v] = *cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, i, j, k);
+    cons_to_prim(u, w, a.gas);
+}
+
+template <int BI, int BJ, int BK, int LIM>
+__global__ void __launch_bounds__(NT) k_hancock(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    const int n = *a.nitems;
+    const Gas gs = a.gas;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = a.items[it];
+        const int mem = a.desc[slot].member;
+        const double dt = a.dt[mem];
+        if (dt <= 0.0) continue;
+        const double adt = a.alpha * dt;
+        const LevelGeo lg = a.geo[a.desc[slot].level];
+        const int o0 = a.desc[slot].org[0], o1 = a.desc[slot].org[1], o2 = a.desc[slot].org[2];
+        const Faces nb = load_faces(a.desc, slot);
+        int badc = -1, nfr = 0, nfp = 0;
+        for (int c = threadIdx.x; c < S::NC; c += NT) {
+            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+            double w0[8], acc[8];
+            prim_at<S>(a, slot, nb, i, j, k, w0);
+            if (badc < 0 && unphysical(w0)) badc = c;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) acc[v] = 0.0;
+            const RecR rr = lg.r[o0 + i + 2];
+            const RecT tt = lg.t[o1 + j + 2];
+            const RecP pk = lg.p[o2 + k + 2];
+            {   // r
+                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                prim_at<S>(a, slot, nb, i - 1, j, k, wm);
+                prim_at<S>(a, slot, nb, i + 1, j, k, wp);
+                reconstruct<LIM>(wm, w0, wp, rr.idm, rr.idp, rr.idc, rr.hm, rr.hp, lo, hi);
+                phys_flux<0>(lo, fl, gs);
+                phys_flux<0>(hi, fh, gs);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[v] -= rr.ap * fh[v] - rr.am * fl[v];
+            }
+            {   // theta
+                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                prim_at<S>(a, slot, nb, i, j - 1, k, wm);
+                prim_at<S>(a, slot, nb, i, j + 1, k, wp);
+                reconstruct<LIM>(wm, w0, wp, tt.idm, tt.idp, tt.idc, tt.hm, tt.hp, lo, hi);
+                phys_flux<1>(lo, fl, gs);
+                phys_flux<1>(hi, fh, gs);
+                const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[v] -= thp * fh[v] - thm * fl[v];
+            }
+            {   // phi
+                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                prim_at<S>(a, slot, nb, i, j, k - 1, wm);
+                prim_at<S>(a, slot, nb, i, j, k + 1, wp);
+                reconstruct<LIM>(wm, w0, wp, pk.idm, pk.idp, pk.idc, pk.hm, pk.hp, lo, hi);
+                phys_flux<2>(lo, fl, gs);
+                phys_flux<2>(hi, fh, gs);
+                const double kf = rr.rt * tt.phf * pk.iw;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[v] -= kf * fh[v] - kf * fl[v];
+            }
+            if (!a.cart) add_sources(w0, rr.rt, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
+            double unew[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) unew[v] = a.Ubase[cidx<S>(slot, v, i, j, k)] + adt * acc[v];
+            const int f = apply_floors(unew, gs, a.rho_floor, a.p_floor);
+            nfr += f & 1;
+            nfp += f >> 1;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = unew[v];
+        }
+        if (badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
+        if (nfr | nfp) {
+            atomicAdd(&a.floors[2 * mem], (unsigned long long)nfr);
+            atomicAdd(&a.floors[2 * mem + 1], (unsigned long long)nfp);
+        }
+    }
+}
+
+template <int BI, int BJ, int BK>
+void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter)
+{
+    if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+    else if (limiter == LIM_VANLEER) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_MC>), g, dim3(NT), 0, s, a);
+}
+
 // CFL rate of every leaf (after create, set_state, regrid)
 template <int BI, int BJ, int BK>
 __global__ void __launch_bounds__(NT) k_rate(KArgs a)
@@ -771,7 +873,8 @@ bool get_launchers(int bi, int bj, int bk, Launchers *out)
 {
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
     if (bi == BI && bj == BJ && bk == BK) {                                                        \
-        *out = Launchers{&launch_stage<BI, BJ, BK>, &L<BI, BJ, BK>::slabs, &L<BI, BJ, BK>::reflux,     \
+        *out = Launchers{&launch_stage<BI, BJ, BK>, &launch_hancock<BI, BJ, BK>, &L<BI, BJ, BK>::slabs, \
+                         &L<BI, BJ, BK>::reflux,                                                   \
                          &L<BI, BJ, BK>::rate, &L<BI, BJ, BK>::indicator, &L<BI, BJ, BK>::move,    \
                          &L<BI, BJ, BK>::sample};                                                  \
         return true;                                                                               \

@@ -160,6 +160,27 @@ DEV void rusanov(const double wl[8], const double wr[8], double f[8], const Gas 
     }
 }
 
+// Physical ideal-MHD flux of a primitive state along D: rho v_n, rho v_n v -
+// B_n B + p_tot e_n, (E + p_tot) v_n - B_n (v.B), v_n B - B_n v (B_n part 0).
+template <int D>
+DEV void phys_flux(const double w[8], double f[8], const Gas &gs)
+{
+    const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
+    const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
+    const double pt = w[4] + 0.5 * b2;
+    const double E = w[4] * gs.igm1 + 0.5 * w[0] * v2 + 0.5 * b2;
+    const double vn = w[1 + D], bn = w[5 + D];
+    const double vb = w[1] * w[5] + w[2] * w[6] + w[3] * w[7];
+    const double m = w[0] * vn;
+    f[0] = m;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        f[1 + q] = m * w[1 + q] - bn * w[5 + q] + (q == D ? pt : 0.0);
+        f[5 + q] = q == D ? 0.0 : vn * w[5 + q] - bn * w[1 + q];
+    }
+    f[4] = (E + pt) * vn - bn * vb;
+}
+
 // Monotonised-central slope on a non-uniform coordinate (reciprocal spacings given).
 DEV double mc_slope(double wm, double w0, double wp, double idm, double idp, double idc)
 {
@@ -170,14 +191,33 @@ DEV double mc_slope(double wm, double w0, double wp, double idm, double idp, dou
     return (dm * dp <= 0.0) ? 0.0 : copysign(a, dc);
 }
 
+// Limiters of the reconstruction (the paper's runs use the monotonised-central
+// "Woodward" form; its code offers others): zero where the one-sided
+// differences differ in sign or one vanishes, else LIM_MINMOD the one of
+// smaller magnitude, LIM_VANLEER their harmonic mean 2 dm dp / (dm + dp).
+enum { LIM_MC = 0, LIM_MINMOD = 1, LIM_VANLEER = 2 };
+
+template <int LIM>
+DEV double limited_slope(double wm, double w0, double wp, double idm, double idp, double idc)
+{
+    if (LIM == LIM_MC) return mc_slope(wm, w0, wp, idm, idp, idc);
+    const double dm = (w0 - wm) * idm;
+    const double dp = (wp - w0) * idp;
+    double sl;
+    if (LIM == LIM_MINMOD) sl = fabs(dm) < fabs(dp) ? dm : dp;
+    else sl = 2.0 * dm * dp * IC_RCP(dm + dp);
+    return (dm * dp <= 0.0) ? 0.0 : sl;
+}
+
 // Face values of a cell from its neighbours along one direction; falls back to
 // zero slope for all variables if a face density or pressure is not positive.
+template <int LIM = LIM_MC>
 DEV void reconstruct(const double wm[8], const double w0[8], const double wp[8], double idm,
                      double idp, double idc, double hm, double hp, double lo[8], double hi[8])
 {
     double s[8];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) s[v] = mc_slope(wm[v], w0[v], wp[v], idm, idp, idc);
+    for (int v = 0; v < 8; ++v) s[v] = limited_slope<LIM>(wm[v], w0[v], wp[v], idm, idp, idc);
     // the density and pressure face values decide; a zero slope gives w0 - 0 * h = w0 exactly
     const bool ok = w0[0] - s[0] * hm > 0.0 && w0[0] + s[0] * hp > 0.0 && w0[4] - s[4] * hm > 0.0 &&
                     w0[4] + s[4] * hp > 0.0;

@@ -1050,14 +1050,27 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, s->stream));
-        s->L.stage(dim3(g), s->stream, a, s->tune_waves);
+        s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);
         HIPCHECK(hipEventRecord(e1, s->stream));
         s->ev.push_back(e0);
         s->ev.push_back(e1);
     } else {
-        s->L.stage(dim3(g), s->stream, a, s->tune_waves);
+        s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);
     }
     if (s->any_reflux) s->L.reflux(dim3(reflux_grid(s)), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
+}
+
+// Hancock predictor into Uout (the first stage of the one-step form): one
+// work-group per work item
+void predictor(ic_sim *s, double *Uin, double *Uout)
+{
+    KArgs a = base_args(s);
+    a.U = Uin;
+    a.Ubase = Uin;
+    a.Uout = Uout;
+    a.alpha = 0.5;
+    a.want_rate = 0;
+    s->L.hancock(dim3(quant_grid(s->n_items, 1 << 30)), s->stream, a, s->phys.limiter);
 }
 
 void enqueue_rate(ic_sim *s)
@@ -1081,7 +1094,8 @@ void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
     KArgs a = base_args(s);
     launch_dt(s->stream, a, s->mbeg.p, s->mend.p, s->nm, s->phys.cfl, dt_fixed_code, s->tend.p, s->dt_last.p);
     fill_ghosts(s, s->U.p, 0.0);
-    stage(s, s->U.p, s->U.p, s->Us.p, 0.5, 0);
+    if (s->phys.scheme == IC_SCHEME_HANCOCK) predictor(s, s->U.p, s->Us.p);
+    else stage(s, s->U.p, s->U.p, s->Us.p, 0.5, 0);
     fill_ghosts(s, s->Us.p, 0.5);
     stage(s, s->Us.p, s->U.p, s->U.p, 1.0, 1);
     if (record) enqueue_sample(s, 1, true);       // ends the step and records the sample
@@ -1821,12 +1835,12 @@ double time_stage(ic_sim *s, int reps)
     a.alpha = 0.5;
     a.want_rate = 0;
     const int g = stage_grid(s);
-    s->L.stage(dim3(g), s->stream, a, s->tune_waves);      // warm-up
+    s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);      // warm-up
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
     HIPCHECK(hipEventRecord(e0, s->stream));
-    for (int r = 0; r < reps; ++r) s->L.stage(dim3(g), s->stream, a, s->tune_waves);
+    for (int r = 0; r < reps; ++r) s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);
     HIPCHECK(hipEventRecord(e1, s->stream));
     HIPCHECK(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -1871,6 +1885,9 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
             throw Error(IC_E_INVALID, "max_level must be in 1.." + std::to_string(IC_MAX_LEVEL));
         if (grid->max_level > 1 && !amr) throw Error(IC_E_INVALID, "max_level > 1 needs an amr config");
         if (!(phys->gamma > 1.0) || !(phys->cfl > 0.0)) throw Error(IC_E_INVALID, "gamma must exceed 1 and cfl be positive");
+        if (phys->limiter < IC_LIM_MC || phys->limiter > IC_LIM_VANLEER) throw Error(IC_E_INVALID, "unknown limiter");
+        if (phys->scheme != IC_SCHEME_TWO_STAGE && phys->scheme != IC_SCHEME_HANCOCK)
+            throw Error(IC_E_INVALID, "unknown time scheme");
         s = new ic_sim();
         s->grid = *grid;
         s->phys = *phys;

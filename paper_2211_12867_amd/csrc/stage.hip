@@ -100,8 +100,9 @@ __device__ inline int xcd_item(int w, int n)
     return x * q + (x < rem ? x : rem) + pos;
 }
 
-// W: waves per SIMD the register allocation targets (a tuning choice).
-template <int BI, int BJ, int BK, int W>
+// W: waves per SIMD the register allocation targets (a tuning choice); LIM:
+// the limiter of the reconstruction (LIM_MC, the paper's, by default).
+template <int BI, int BJ, int BK, int W, int LIM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W, W)))
 k_stage(KArgs a)
 {
@@ -186,8 +187,8 @@ k_stage(KArgs a)
             column8<S>(a, slot, nb, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
             column8<S>(a, slot, nb, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
             const RecP pm1 = lg.p[bd.org[2] + k0 + 1], p0 = lg.p[bd.org[2] + k0 + 2];
-            reconstruct(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
-            reconstruct(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
+            reconstruct<LIM>(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
+            reconstruct<LIM>(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
             rusanov<2>(hi, R0, Fm, gs);
             const int r = k0 == 0 ? bd.freg[4] : -1;
             if (r >= 0)
@@ -272,7 +273,7 @@ k_stage(KArgs a)
                         wp[v] = sW[v][j + 2][c + 3];
                     }
                     const RecR rc = sR[c + 2];
-                    reconstruct(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    reconstruct<LIM>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
                     if (c < BI)
 #pragma unroll
                         for (int v = 0; v < 8; ++v) sFi[v][j][c + 1] = hi[v];
@@ -311,7 +312,7 @@ k_stage(KArgs a)
                         wp[v] = sW[v][c + 3][i + 2];
                     }
                     const RecT rc = sT[c + 2];
-                    reconstruct(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    reconstruct<LIM>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
                     if (c < BJ)
 #pragma unroll
                         for (int v = 0; v < 8; ++v) sFj[v][c + 1][i] = hi[v];
@@ -387,7 +388,7 @@ k_stage(KArgs a)
                 for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
                 const RecP pk1 = sP[k + 3];
                 double hi1[8];
-                reconstruct(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
+                reconstruct<LIM>(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
                 rusanov<2>(wL, lo1, Fp, gs);
                 if (k == BK - 1) {
                     const int r = bd.freg[5];
@@ -502,17 +503,22 @@ k_stage(KArgs a)
 // ---------------------------------------------------------------------------
 // instantiations and launch
 // ---------------------------------------------------------------------------
+// the other limiters are built for two waves per SIMD only
 template <int BI, int BJ, int BK>
-void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves)
+void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter)
 {
-    if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 1>), g, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2>), g, dim3(NT), 0, s, a);
+    if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+    else if (limiter == LIM_VANLEER) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+    else if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 1, LIM_MC>), g, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_MC>), g, dim3(NT), 0, s, a);
 }
 
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
-    template __global__ void k_stage<BI, BJ, BK, 1>(KArgs);                                        \
-    template __global__ void k_stage<BI, BJ, BK, 2>(KArgs);                                        \
-    template void launch_stage<BI, BJ, BK>(dim3, hipStream_t, const KArgs &, int);
+    template __global__ void k_stage<BI, BJ, BK, 1, LIM_MC>(KArgs);                                \
+    template __global__ void k_stage<BI, BJ, BK, 2, LIM_MC>(KArgs);                                \
+    template __global__ void k_stage<BI, BJ, BK, 2, LIM_MINMOD>(KArgs);                            \
+    template __global__ void k_stage<BI, BJ, BK, 2, LIM_VANLEER>(KArgs);                           \
+    template void launch_stage<BI, BJ, BK>(dim3, hipStream_t, const KArgs &, int, int);
 
 #include "shapes.inc"
 #undef IC_INSTANTIATE
