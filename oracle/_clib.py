@@ -58,6 +58,8 @@ def lib():
         L.ora_slope.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
         L.ora_slope.restype = ctypes.c_double
         L.ora_rhs_hancock.argtypes = [pp, dp, dp]
+        L.ora_divb.argtypes = [pp, dp, dp]
+        L.ora_divb.restype = None
         L.ora_rhs_hancock.restype = ctypes.c_int
         L.ora_sources.argtypes = [dp] + [ctypes.c_double] * 7 + [dp]
         L.ora_rhs.argtypes = [pp, dp, dp, dp, dp, dp]
@@ -151,6 +153,15 @@ def rhs_hancock(pg, G):
     L = np.empty((NV, nk, nj, ni))
     bad = lib().ora_rhs_hancock(ctypes.byref(pg.s), _p(G), _p(L))
     return L, bad
+
+
+def divb(pg, G):
+    """Discrete div B of the interior cells of a ghosted patch, [nk, nj, ni]."""
+    ni, nj, nk = pg.n
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    D = np.empty((nk, nj, ni))
+    lib().ora_divb(ctypes.byref(pg.s), _p(G), _p(D))
+    return D
 
 
 def max_rate(pg, G):

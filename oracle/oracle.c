@@ -21,7 +21,8 @@
  *   - the Hancock predictor operator: the same differences of each cell's own
  *     physical fluxes at its reconstructed face states (no interface solver);
  *   - the CFL rate, and the per-cell refinement-indicator quantities
- *     (Loehner-type second-derivative estimator and div V).
+ *     (Loehner-type second-derivative estimator and div V);
+ *   - the discrete divergence of B per cell (for the parabolic cleaning).
  *
  * Everything is written straight from the equations with no blocking, no
  * fusion and no precomputed reciprocals.  Divisions are divisions.  Build with
@@ -510,5 +511,31 @@ void ora_indicator(const ora_patch *p, const double *U, double eps,
                 E_v[o] = den_v > 0.0 ? sqrt(num_v / den_v) : 0.0;
                 divv[o] = dv;
                 divscale[o] = ds;
+            }
+}
+
+/*
+ * Discrete div B of every interior cell: (1/V) sum_d [A+ Bt+ - A- Bt-], Bt the
+ * mean of the two cells' face-normal field components at the face (the same
+ * face-mean form as div V of the indicator).  D is [k][j][i].
+ */
+void ora_divb(const ora_patch *p, const double *U, double *D)
+{
+    for (int k = 0; k < p->nk; ++k)
+        for (int j = 0; j < p->nj; ++j)
+            for (int i = 0; i < p->ni; ++i) {
+                double dv = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int lo[3] = {i, j, k}, hi[3] = {i, j, k};
+                    lo[d] -= 1;
+                    hi[d] += 1;
+                    double b0 = U[gix(p, 5 + d, i, j, k)];
+                    double bl = 0.5 * (U[gix(p, 5 + d, lo[0], lo[1], lo[2])] + b0);
+                    double bh = 0.5 * (b0 + U[gix(p, 5 + d, hi[0], hi[1], hi[2])]);
+                    double am, ap;
+                    metric(p, d, i, j, k, &am, &ap);
+                    dv += ap * bh - am * bl;
+                }
+                D[((size_t)k * p->nj + j) * p->ni + i] = dv;
             }
 }

@@ -11,6 +11,16 @@ U* = U^n + (dt/2) L_H(U^n) (each cell's own physical fluxes at its
 reconstructed face states; no interface solver, no reflux), followed by the
 same second stage.
 
+Parabolic div B cleaning (Sect. 2.1 applies it in every run; off by default
+here): after each stage's update (reflux and floors included) the field of
+the stage result moves by dB = alpha C_d h^2 grad(D), D the discrete div B of
+the stage input (face-mean form), grad(D) by central differences of D between
+the face neighbours in physical components, h^2 = 1 / sum_d dx_d^-2 with the
+cell widths of the CFL rate, alpha the stage weight (1/2, 1); the energy
+moves by B_in . dB.  A gradient component that would need D across a
+physical boundary or a level change is zero (the cleaning stays out of the
+cells on those faces).
+
 Block AMR (Sect. 3): every leaf carries two face-ghost layers per face.  Face
 ghosts come from a same-level neighbour (copy), from finer neighbours
 (volume-weighted restriction of the 8 children of each ghost cell) or from a
@@ -87,6 +97,36 @@ def apply_floors(U, gamma, rho_floor=RHO_FLOOR, p_floor=P_FLOOR, counts=None):
     return n
 
 
+def _cleaning_metric(cart, c, w, sp):
+    """(dx, gs): per direction, the cell widths of the CFL rate (dr, r_c dtheta,
+    r_c sin(theta_c) dphi) and the spacings of the central gradient in physical
+    components (x_{m+1} - x_{m-1}, times r_c and r_c sin(theta_c)), shaped to
+    broadcast over [k, j, i].  c: centres of cells -1 .. n, w: widths of cells
+    0 .. n-1, sp: centre spacings per direction."""
+    shape = lambda a, d: a.reshape([-1 if e == 2 - d else 1 for e in range(3)])
+    if cart:
+        return [shape(w[d], d) for d in range(3)], [shape(sp[d], d) for d in range(3)]
+    rc, tc = shape(c[0][1:-1], 0), shape(c[1][1:-1], 1)
+    dx = [shape(w[0], 0), rc * shape(w[1], 1), rc * np.sin(tc) * shape(w[2], 2)]
+    gs = [shape(sp[0], 0), rc * shape(sp[1], 1), rc * np.sin(tc) * shape(sp[2], 2)]
+    return dx, gs
+
+
+def _apply_cleaning(u, G, Dp, dx, gs, coef):
+    """u += the cleaning increment: dB_d = coef h^2 (D_{+d} - D_{-d}) / gs_d (0
+    where a neighbour's D is missing, NaN in Dp), E += B_in . dB."""
+    h2 = 1.0 / (1.0 / dx[0] ** 2 + 1.0 / dx[1] ** 2 + 1.0 / dx[2] ** 2)
+    Bin = G[5:8, 2:-2, 2:-2, 2:-2]
+    for d in range(3):
+        ax = 2 - d
+        hi, lo = [slice(1, -1)] * 3, [slice(1, -1)] * 3
+        hi[ax], lo[ax] = slice(2, None), slice(0, -2)
+        grad = (Dp[tuple(hi)] - Dp[tuple(lo)]) / gs[d]
+        dB = coef * h2 * np.where(np.isnan(grad), 0.0, grad)
+        u[4] += Bin[d] * dB
+        u[5 + d] += dB
+
+
 # refinement-criterion readings: Loehner eps, thresholds, weights, the
 # Earth/CME windows of Sect. 3.2, regrid cadence and buffer
 AMR_DEFAULTS = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
@@ -99,9 +139,10 @@ class Solver:
     """Block-forest solver.  State: dict leaf -> U[8, bk, bj, bi] (code units)."""
 
     def __init__(self, grid, wind=None, cme=None, amr=None, omega=None, gm=None, t0_s=0.0,
-                 initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage"):
+                 initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage",
+                 divb_cd=0.0):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
-        self.limiter, self.scheme = limiter, scheme
+        self.limiter, self.scheme, self.divb_cd = limiter, scheme, float(divb_cd)
         assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
@@ -372,7 +413,39 @@ class Solver:
             bad += nb
         if bad:
             raise UnphysicalState("%d cells with rho <= 0, p <= 0 or non-finite values" % bad)
-        return L
+        return L, G
+
+    def _widths(self, leaf):
+        """Per-direction arrays (broadcast over [k, j, i]) of the cell widths of
+        the CFL rate and the central-difference spacings of the gradient."""
+        g = self.geo[leaf[0]]
+        rng = [self.cell_range(leaf, d) for d in range(3)]
+        c = [np.array([g.centre(d, m) for m in range(lo - 1, hi + 1)]) for d, (lo, hi) in enumerate(rng)]
+        w = [np.array([g.width(d, m) for m in range(lo, hi)]) for d, (lo, hi) in enumerate(rng)]
+        sp = [c[d][2:] - c[d][:-2] for d in range(3)]       # x_{m+1} - x_{m-1}
+        return _cleaning_metric(self.cart, c, w, sp)
+
+    def clean(self, Unew, G, alpha):
+        """Parabolic div B cleaning of a stage result Unew (dict, in place) from
+        the ghosted stage input G."""
+        D = {leaf: _clib.divb(self.patch(leaf), G[leaf]) for leaf in self.forest.leaves}
+        B = self.B
+        for leaf in self.forest.leaves:
+            Dp = np.full(tuple(b + 2 for b in B[::-1]), np.nan)
+            Dp[1:-1, 1:-1, 1:-1] = D[leaf]
+            for d in range(3):
+                ax = 2 - d
+                for side in (0, 1):
+                    nbs = self.forest.face_neighbours(leaf, d, side)
+                    if len(nbs) != 1 or nbs[0][0] != leaf[0]:
+                        continue                        # boundary or level change: no D there
+                    src = [slice(None)] * 3
+                    src[ax] = slice(B[d] - 1, B[d]) if side == 0 else slice(0, 1)
+                    dst = [slice(1, -1)] * 3
+                    dst[ax] = slice(0, 1) if side == 0 else slice(B[d] + 1, B[d] + 2)
+                    Dp[tuple(dst)] = D[nbs[0]][tuple(src)]
+            dx, gs = self._widths(leaf)
+            _apply_cleaning(Unew[leaf], G[leaf], Dp, dx, gs, alpha * self.divb_cd)
 
     def _reflux(self, L, F):
         B = self.B
@@ -442,16 +515,20 @@ class Solver:
                 dt = min(dt, t_end - self.t)
         Un = self.U
         if self.scheme == "hancock":
-            L1 = self.predictor(Un, self.t)
+            L1, G1 = self.predictor(Un, self.t)
         else:
-            L1, _ = self.operator(Un, self.t)
+            L1, G1 = self.operator(Un, self.t)
         Us = {b: Un[b] + (0.5 * dt) * L1[b] for b in Un}
         for u in Us.values():
             self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
-        L2, _ = self.operator(Us, self.t + 0.5 * dt)
+        if self.divb_cd > 0.0:
+            self.clean(Us, G1, 0.5)
+        L2, G2 = self.operator(Us, self.t + 0.5 * dt)
         self.U = {b: Un[b] + dt * L2[b] for b in Un}
         for u in self.U.values():
             self.floored += apply_floors(u, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
+        if self.divb_cd > 0.0:
+            self.clean(self.U, G2, 1.0)
         self.t += dt
         self.steps += 1
         return dt
@@ -671,9 +748,9 @@ class PatchSolver:
     an independent check of the block decomposition and as the CPU baseline."""
 
     def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind",
-                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage"):
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
-        self.limiter, self.scheme = limiter, scheme
+        self.limiter, self.scheme, self.divb_cd = limiter, scheme, float(divb_cd)
         assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
@@ -745,6 +822,28 @@ class PatchSolver:
             raise UnphysicalState("%d unphysical cells" % bad)
         return L
 
+    def clean(self, Unew, Uin, t, alpha):
+        """Parabolic div B cleaning of Unew (in place) from the stage input Uin
+        (ghosts at t): the forest form on one patch; periodic directions wrap."""
+        G = self.ghosted(Uin, t)
+        D = _clib.divb(self.pg, G)
+        Dp = np.pad(D, 1, mode="constant", constant_values=np.nan)
+        for d in range(3):
+            if self.bc[d][0] == "periodic":
+                ax = 2 - d
+                lo, hi = [slice(1, -1)] * 3, [slice(1, -1)] * 3
+                src_lo, src_hi = [slice(None)] * 3, [slice(None)] * 3
+                lo[ax], hi[ax] = slice(0, 1), slice(-1, None)
+                src_lo[ax], src_hi[ax] = slice(-1, None), slice(0, 1)
+                Dp[tuple(lo)] = D[tuple(src_lo)]
+                Dp[tuple(hi)] = D[tuple(src_hi)]
+        g = self.geo
+        c = [geometry.centres(g.f[d])[1:-1] for d in range(3)]      # cells -1 .. n
+        w = [np.diff(g.f[d])[2:-2] for d in range(3)]
+        sp = [c[d][2:] - c[d][:-2] for d in range(3)]
+        dx, gs = _cleaning_metric(self.cart, c, w, sp)
+        _apply_cleaning(Unew, G, Dp, dx, gs, alpha * self.divb_cd)
+
     def cfl_dt(self):
         G = np.zeros((NV,) + tuple(x + 4 for x in self.n[::-1]))
         G[:, 2:-2, 2:-2, 2:-2] = self.U
@@ -757,9 +856,13 @@ class PatchSolver:
         L1 = self.predictor(Un, self.t) if self.scheme == "hancock" else self.operator(Un, self.t)
         Us = Un + (0.5 * dt) * L1
         self.floored += apply_floors(Us, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
+        if self.divb_cd > 0.0:
+            self.clean(Us, Un, self.t, 0.5)
         L2 = self.operator(Us, self.t + 0.5 * dt)
         self.U = Un + dt * L2
         self.floored += apply_floors(self.U, self.gamma, self.rho_floor, self.p_floor, self.floor_counts)
+        if self.divb_cd > 0.0:
+            self.clean(self.U, Us, self.t + 0.5 * dt, 1.0)
         self.t += dt
         return dt
 
