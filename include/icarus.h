@@ -94,7 +94,15 @@ typedef struct {
  * U^{n+1} = U^n + dt L(U*); the default) or IC_SCHEME_HANCOCK (the one-step
  * TVDLF: the predictor U* = U^n + dt/2 L_H(U^n) takes each cell's own physical
  * fluxes at its reconstructed face states, no interface solver, then the same
- * conservative second stage). */
+ * conservative second stage).  divb_cd > 0 turns on the parabolic div B
+ * cleaning the paper applies (Sect. 2.1), off by default: after each stage
+ * (reflux and floors included) B += alpha divb_cd h^2 grad(div B) with alpha
+ * the stage weight (1/2, 1), div B of the stage input in face-mean form,
+ * central differences between face neighbours in physical components,
+ * h^2 = 1 / sum_d dx_d^-2 (the CFL widths), and E += B_in . dB; no gradient
+ * component across a physical boundary or a level change; divb_cd in [0, 1]
+ * (a Fourier mode decays by 1 - alpha divb_cd (h/dx)^2 sin^2(k dx) per
+ * application). */
 enum { IC_LIM_MC = 0, IC_LIM_MINMOD = 1, IC_LIM_VANLEER = 2 };
 enum { IC_SCHEME_TWO_STAGE = 0, IC_SCHEME_HANCOCK = 1 };
 typedef struct {
@@ -106,6 +114,7 @@ typedef struct {
     double p_floor;
     int limiter;
     int scheme;
+    double divb_cd;
 } ic_phys_cfg;
 
 /* Inner-boundary wind at r_in (Sect. 2.1): v_r = v_min + (v_max - v_min)

@@ -51,7 +51,7 @@ class GridCfg(ctypes.Structure):
 class PhysCfg(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
                 ("gm", ctypes.c_double), ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
-                ("limiter", ctypes.c_int), ("scheme", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("scheme", ctypes.c_int), ("divb_cd", ctypes.c_double)]
 
 
 LIMITERS = {"mc": 0, "minmod": 1, "vanleer": 2}
@@ -277,14 +277,14 @@ class Sim:
     """One library sim: n_members runs of the same grid and wind, one CME each."""
 
     def __init__(self, grid, wind=None, cmes=None, amr=None, omega=None, gm=None, max_blocks=0, stream=None,
-                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage"):
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0):
         self.grid = grid
         g = grid_cfg(grid, max_blocks)
         cart = g.geometry == IC_GEOM_CARTESIAN
         p = PhysCfg(float(_get(grid, "gamma", 1.5)), float(_get(grid, "cfl", 0.4)),
                     0.0 if cart else (OMEGA_SUN if omega is None else float(omega)),
                     0.0 if cart else (GM_SUN if gm is None else float(gm)),
-                    float(rho_floor), float(p_floor), LIMITERS[limiter], SCHEMES[scheme])
+                    float(rho_floor), float(p_floor), LIMITERS[limiter], SCHEMES[scheme], float(divb_cd))
         w = wind_cfg(wind) if wind is not None else None
         if cmes is None or len(cmes) == 0:
             self.n_members = 1

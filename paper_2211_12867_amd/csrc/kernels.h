@@ -39,6 +39,8 @@ struct KArgs {
     int want_rate;
     int xcd_order;             // stage kernel: XCD-contiguous runs of the work list
     int ksplit;                // stage kernel: work-groups per block, each marching over BK / ksplit planes
+    double *divb;              // parabolic cleaning: div B of the stage input per slot and cell
+    double divb_cd;            // parabolic cleaning coefficient C_d (0 = off)
 };
 
 // CFL maxima are kept per block and k-part: rate[slot * KSPLIT_MAX + part]
@@ -165,6 +167,8 @@ struct IndicatorParams {
 struct Launchers {
     void (*stage)(dim3, hipStream_t, const KArgs &, int waves, int limiter);
     void (*hancock)(dim3, hipStream_t, const KArgs &, int limiter);
+    void (*divb)(dim3, hipStream_t, const KArgs &);
+    void (*clean)(dim3, hipStream_t, const KArgs &);
     void (*slabs)(dim3, hipStream_t, const KArgs &, const SlabTask *, const int *, int pass);
     void (*reflux)(dim3, hipStream_t, const KArgs &, const RefluxTask *, const int *, const int *);
     void (*rate)(dim3, hipStream_t, const KArgs &);
@@ -182,6 +186,8 @@ void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int n
 template <int BI, int BJ, int BK, int W, int LIM> __global__ void k_stage(KArgs a);
 template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter);
 template <int BI, int BJ, int BK, int LIM> __global__ void k_hancock(KArgs a);
+template <int BI, int BJ, int BK> __global__ void k_divb(KArgs a);
+template <int BI, int BJ, int BK> __global__ void k_clean(KArgs a);
 template <int BI, int BJ, int BK> void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter);
 template <int BI, int BJ, int BK, int PASS> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);

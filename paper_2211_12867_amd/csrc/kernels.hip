@@ -532,6 +532,130 @@ void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter)
     else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_MC>), g, dim3(NT), 0, s, a);
 }
 
+// ---------------------------------------------------------------------------
+// parabolic div B cleaning (a stage option): k_divb forms D = div B of the
+// stage input per cell (face-mean form, (1/V) sum_d [A+ Bt+ - A- Bt-], ghosts
+// filled); after the stage, its reflux and floors, k_clean moves the stage
+// result by dB = alpha C_d h^2 grad D (central differences of D between face
+// neighbours in physical components, h^2 = 1 / sum_d dx_d^-2 with the CFL
+// widths) and E by B_in . dB.  A neighbour across a block face is read from
+// the same-level neighbour block's D; across a boundary or a level change the
+// gradient component is zero.  In the second stage k_clean also takes the
+// output check and the CFL maxima (the stage and reflux kernels leave them).
+// ---------------------------------------------------------------------------
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_divb(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    const int n = *a.nitems;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = a.items[it];
+        const LevelGeo lg = a.geo[a.desc[slot].level];
+        const int o0 = a.desc[slot].org[0], o1 = a.desc[slot].org[1], o2 = a.desc[slot].org[2];
+        const Faces nb = load_faces(a.desc, slot);
+        for (int c = threadIdx.x; c < S::NC; c += NT) {
+            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+            const RecR rr = lg.r[o0 + i + 2];
+            const RecT tt = lg.t[o1 + j + 2];
+            const RecP pk = lg.p[o2 + k + 2];
+            const double *U = a.U;
+            const double b0 = *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 5, i, j, k);
+            const double b1 = *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 6, i, j, k);
+            const double b2 = *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 7, i, j, k);
+            const double rl = 0.5 * (*cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 5, i - 1, j, k) + b0);
+            const double rh = 0.5 * (b0 + *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 5, i + 1, j, k));
+            const double tl = 0.5 * (*cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 6, i, j - 1, k) + b1);
+            const double th = 0.5 * (b1 + *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 6, i, j + 1, k));
+            const double pl = 0.5 * (*cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 7, i, j, k - 1) + b2);
+            const double ph = 0.5 * (b2 + *cell_addr<S>(U, a.slabs, a.slab_stride, slot, nb, 7, i, j, k + 1));
+            const double kf = rr.rt * tt.phf * pk.iw;
+            double dv = rr.ap * rh - rr.am * rl;
+            dv += rr.rt * tt.thp * th - rr.rt * tt.thm * tl;
+            dv += kf * ph - kf * pl;
+            a.divb[(size_t)slot * S::NC + c] = dv;
+        }
+    }
+}
+
+template <int BI, int BJ, int BK>
+__global__ void __launch_bounds__(NT) k_clean(KArgs a)
+{
+    using S = Shape<BI, BJ, BK>;
+    __shared__ double sred[NT / 64];
+    const int n = *a.nitems;
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int slot = a.items[it];
+        const int mem = a.desc[slot].member;
+        const double dt = a.dt[mem];
+        if (dt <= 0.0) continue;                      // uniform over the work-group
+        const LevelGeo lg = a.geo[a.desc[slot].level];
+        const int o0 = a.desc[slot].org[0], o1 = a.desc[slot].org[1], o2 = a.desc[slot].org[2];
+        const Faces nb = load_faces(a.desc, slot);
+        const double coef = a.alpha * a.divb_cd;
+        const double *D = a.divb + (size_t)slot * S::NC;
+        double rmax = 0.0;
+        int badc = -1;
+        for (int c = threadIdx.x; c < S::NC; c += NT) {
+            const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
+            const int idx[3] = {i, j, k};
+            const RecR rr = lg.r[o0 + i + 2];
+            const RecT tt = lg.t[o1 + j + 2];
+            const RecP pk = lg.p[o2 + k + 2];
+            // D at the two face neighbours along d; NaN-free flag `ok`
+            double g[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int st = d == 0 ? 1 : (d == 1 ? BI : BI * BJ);
+                const int Bd = d == 0 ? BI : (d == 1 ? BJ : BK);
+                bool ok = true;
+                double dm, dp;
+                if (idx[d] > 0) dm = D[c - st];
+                else {
+                    const int code = face_code(nb, 2 * d);
+                    ok = ok && code >= 0;
+                    dm = code >= 0 ? a.divb[(size_t)code * S::NC + c + (Bd - 1) * st] : 0.0;
+                }
+                if (idx[d] < Bd - 1) dp = D[c + st];
+                else {
+                    const int code = face_code(nb, 2 * d + 1);
+                    ok = ok && code >= 0;
+                    dp = code >= 0 ? a.divb[(size_t)code * S::NC + c - (Bd - 1) * st] : 0.0;
+                }
+                const double isp = d == 0 ? rr.idc : (d == 1 ? rr.irc * tt.idc : rr.irc * tt.isinc * pk.idc);
+                g[d] = ok ? (dp - dm) * isp : 0.0;
+            }
+            const double ix = rr.icfl, iy = rr.irc * tt.icfl, iz = rr.irc * tt.isinc * pk.iw;
+            const double h2 = 1.0 / (ix * ix + iy * iy + iz * iz);
+            const double ch = coef * h2;
+            const size_t base = cidx<S>(slot, 0, i, j, k);
+            double u[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) u[v] = a.Uout[base + (size_t)v * S::NC];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double db = ch * g[d];
+                u[4] += a.U[base + (size_t)(5 + d) * S::NC] * db;
+                u[5 + d] += db;
+            }
+            a.Uout[base + 4 * (size_t)S::NC] = u[4];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) a.Uout[base + (size_t)(5 + d) * S::NC] = u[5 + d];
+            if (a.want_rate) {
+                double w[8];
+                cons_to_prim(u, w, a.gas);
+                if (badc < 0 && unphysical(w)) badc = c;
+                const double r = cell_rate<BI, BJ, BK>(u, rr, tt, pk, a.gas);
+                rmax = r > rmax ? r : rmax;
+            }
+        }
+        if (badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
+        if (a.want_rate) {
+            const double m = block_max(rmax, sred);
+            if (threadIdx.x < KSPLIT_MAX) a.rate[(size_t)slot * KSPLIT_MAX + threadIdx.x] = threadIdx.x == 0 ? m : 0.0;
+        }
+    }
+}
+
 // CFL rate of every leaf (after create, set_state, regrid)
 template <int BI, int BJ, int BK>
 __global__ void __launch_bounds__(NT) k_rate(KArgs a)
@@ -824,6 +948,8 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
     template __global__ void k_slabs<BI, BJ, BK, 1>(KArgs, const SlabTask *, const int *);         \
     template __global__ void k_reflux<BI, BJ, BK>(KArgs, const RefluxTask *, const int *, const int *); \
     template __global__ void k_rate<BI, BJ, BK>(KArgs);                                            \
+    template __global__ void k_divb<BI, BJ, BK>(KArgs);                                            \
+    template __global__ void k_clean<BI, BJ, BK>(KArgs);                                           \
     template __global__ void k_indicator<BI, BJ, BK>(KArgs, int8_t *, int, double, double, double, \
                                                      double, double, int, double, double, double,  \
                                                      double, double);                              \
@@ -850,6 +976,8 @@ struct L {
         hipLaunchKernelGGL((k_reflux<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, b, n);
     }
     static void rate(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_rate<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void divb(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_divb<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void clean(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_clean<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
     static void indicator(dim3 g, hipStream_t s, const KArgs &a, int8_t *f, const IndicatorParams &p)
     {
         hipLaunchKernelGGL((k_indicator<BI, BJ, BK>), g, dim3(NT), 0, s, a, f, p.max_level, p.eps, p.tol_r,
@@ -873,8 +1001,8 @@ bool get_launchers(int bi, int bj, int bk, Launchers *out)
 {
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
     if (bi == BI && bj == BJ && bk == BK) {                                                        \
-        *out = Launchers{&launch_stage<BI, BJ, BK>, &launch_hancock<BI, BJ, BK>, &L<BI, BJ, BK>::slabs, \
-                         &L<BI, BJ, BK>::reflux,                                                   \
+        *out = Launchers{&launch_stage<BI, BJ, BK>, &launch_hancock<BI, BJ, BK>, &L<BI, BJ, BK>::divb,  \
+                         &L<BI, BJ, BK>::clean, &L<BI, BJ, BK>::slabs, &L<BI, BJ, BK>::reflux,       \
                          &L<BI, BJ, BK>::rate, &L<BI, BJ, BK>::indicator, &L<BI, BJ, BK>::move,    \
                          &L<BI, BJ, BK>::sample};                                                  \
         return true;                                                                               \

@@ -286,6 +286,7 @@ struct ic_sim {
 
     // device state
     DBuf<double> U, Us, slabs, freg;
+    DBuf<double> divb;              // parabolic cleaning: div B of the stage input (when C_d > 0)
     DBuf<BlockDesc> desc;
     DBuf<LevelGeo> geo;
     DBuf<MemberConst> mc;
@@ -984,6 +985,8 @@ KArgs base_args(ic_sim *s)
     a.cart = s->cart ? 1 : 0;
     a.xcd_order = s->tune_xcd;
     a.ksplit = s->tune_ksplit;
+    a.divb = s->divb.p;
+    a.divb_cd = s->phys.divb_cd;
     return a;
 }
 
@@ -1038,6 +1041,8 @@ void fill_ghosts(ic_sim *s, double *Uin, double tfrac)
 
 void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, int want_rate)
 {
+    // with the cleaning, the CFL maxima and the output check follow it (clean)
+    if (s->phys.divb_cd > 0.0) want_rate = 0;
     KArgs a = base_args(s);
     a.U = Uin;
     a.Ubase = Ubase;
@@ -1058,6 +1063,26 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
         s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);
     }
     if (s->any_reflux) s->L.reflux(dim3(reflux_grid(s)), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
+}
+
+// div B of the stage input Uin (ghosts filled) into s->divb
+void divb(ic_sim *s, double *Uin)
+{
+    KArgs a = base_args(s);
+    a.U = Uin;
+    s->L.divb(dim3(quant_grid(s->n_items, 1 << 30)), s->stream, a);
+}
+
+// parabolic cleaning of the stage result Uout from the stage input Uin (its
+// div B in s->divb); want_rate: the stage's output check and CFL maxima here
+void clean(ic_sim *s, double *Uin, double *Uout, double alpha, int want_rate)
+{
+    KArgs a = base_args(s);
+    a.U = Uin;
+    a.Uout = Uout;
+    a.alpha = alpha;
+    a.want_rate = want_rate;
+    s->L.clean(dim3(quant_grid(s->n_items, 1 << 30)), s->stream, a);
 }
 
 // Hancock predictor into Uout (the first stage of the one-step form): one
@@ -1093,11 +1118,16 @@ void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
 {
     KArgs a = base_args(s);
     launch_dt(s->stream, a, s->mbeg.p, s->mend.p, s->nm, s->phys.cfl, dt_fixed_code, s->tend.p, s->dt_last.p);
+    const bool cleaning = s->phys.divb_cd > 0.0;
     fill_ghosts(s, s->U.p, 0.0);
+    if (cleaning) divb(s, s->U.p);
     if (s->phys.scheme == IC_SCHEME_HANCOCK) predictor(s, s->U.p, s->Us.p);
     else stage(s, s->U.p, s->U.p, s->Us.p, 0.5, 0);
+    if (cleaning) clean(s, s->U.p, s->Us.p, 0.5, 0);
     fill_ghosts(s, s->Us.p, 0.5);
+    if (cleaning) divb(s, s->Us.p);
     stage(s, s->Us.p, s->U.p, s->U.p, 1.0, 1);
+    if (cleaning) clean(s, s->Us.p, s->U.p, 1.0, 1);
     if (record) enqueue_sample(s, 1, true);       // ends the step and records the sample
     else launch_time(s->stream, s->t.p, s->dt.p, s->nsteps.p, s->nm);
 }
@@ -1888,6 +1918,8 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         if (phys->limiter < IC_LIM_MC || phys->limiter > IC_LIM_VANLEER) throw Error(IC_E_INVALID, "unknown limiter");
         if (phys->scheme != IC_SCHEME_TWO_STAGE && phys->scheme != IC_SCHEME_HANCOCK)
             throw Error(IC_E_INVALID, "unknown time scheme");
+        if (!(phys->divb_cd >= 0.0 && phys->divb_cd <= 1.0))
+            throw Error(IC_E_INVALID, "the cleaning coefficient divb_cd must lie in [0, 1]");
         s = new ic_sim();
         s->grid = *grid;
         s->phys = *phys;
@@ -1977,6 +2009,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         const size_t NS = (size_t)s->nm * s->max_blocks;
         s->U.alloc(NS * 8 * s->NC);
         s->Us.alloc(NS * 8 * s->NC);
+        if (s->phys.divb_cd > 0.0) s->divb.alloc(NS * s->NC);
         s->desc.alloc(NS);
         s->items.alloc(NS);
         s->nitems.alloc(1);
@@ -2044,7 +2077,7 @@ void ic_destroy(ic_sim *s)
     for (auto &L : s->lv) {
         L.dr.release(); L.dt.release(); L.dp.release(); L.dwind.release(); L.dcosd.release();
     }
-    s->U.release(); s->Us.release(); s->slabs.release(); s->freg.release(); s->desc.release();
+    s->U.release(); s->Us.release(); s->divb.release(); s->slabs.release(); s->freg.release(); s->desc.release();
     s->geo.release(); s->mc.release(); s->items.release(); s->nitems.release(); s->mbeg.release();
     s->mend.release(); s->dt.release(); s->t.release(); s->tend.release(); s->dt_last.release();
     s->rate.release(); s->bad.release(); s->floors.release(); s->nsteps.release(); s->slab_tasks.release();
