@@ -282,23 +282,26 @@ ic_status ic_get_time(ic_sim *sim, int member, double *t_s, double *dt_s);
 ic_status ic_floor_counts(ic_sim *sim, int member, long *rho_floors, long *p_floors);
 
 /* Shock diagnostics of a radial-speed series at a point (Sect. 3.1: arrival
- * time and shock width, the time from arrival to the maximum speed after the
- * jump; Sect. 3.2: peak speed and average gradient of the shock).  t_s[n]
- * ascending sample times [s], v[n] the speeds (any unit), t_cme_s the CME
- * start, window_s the span after it searched for the peak, min_jump the
- * smallest rise (unit of v) counted as a shock.  v_pre = v at t_cme_s (linear
- * between samples), v_max = the largest sample in [t_cme_s, t_cme_s +
- * window_s] (the first of equal ones), arrival = the first upward crossing of
- * v_pre + (v_max - v_pre)/2 inside the window by a segment that starts at or
- * after t_cme_s, linear between samples.  out[0] arrival - t_cme_s [s],
- * out[1] width = t(v_max) - arrival [s], out[2] v_pre, out[3] v_max (the peak
- * speed), out[4] average gradient (v_max - level at arrival) / width [unit of
- * v per s], out[5] t(v_max) [s].  out[0], out[1], out[4] are NaN without an
- * arrival (no crossing, or v_max - v_pre < min_jump).  Host computation on
- * plain arrays (ic_timeseries gives v_r in column 2); IC_E_INVALID for null
- * pointers, n < 0 or times out of order. */
+ * time and shock width, the time it takes from the arrival to reach the
+ * maximum speed after the speed jump; Sect. 3.2: peak speed and average
+ * gradient of the shock).  t_s[n] ascending sample times [s], v[n] the speeds
+ * (any unit), t_cme_s the CME start, window_s the span after it searched for
+ * the peak, min_jump the smallest rise (unit of v) counted as a shock.
+ * v_pre = v at t_cme_s (linear between samples), v_max = the largest sample
+ * in [t_cme_s, t_cme_s + window_s] (the first of equal ones; the peak speed),
+ * arrival = the first upward crossing of v_pre + (v_max - v_pre)/2 inside
+ * the window by a segment that starts at or after t_cme_s, linear between
+ * samples; the top of the jump = the first sample from the end of that
+ * segment on after which v no longer rises (or the window's last sample).  out[0]
+ * arrival - t_cme_s [s], out[1] width = t(top) - arrival [s], out[2] v_pre,
+ * out[3] v_max, out[4] average gradient (v_top - level at arrival) / width
+ * [unit of v per s], out[5] t(top) [s], out[6] v_top, out[7] t(v_max) [s].
+ * out[0], out[1], out[4], out[5], out[6] are NaN without an arrival (no
+ * crossing, or v_max - v_pre < min_jump).  Host computation on plain arrays
+ * (ic_timeseries gives v_r in column 2); IC_E_INVALID for null pointers,
+ * n < 0 or times out of order. */
 ic_status ic_shock_diagnostics(const double *t_s, const double *v, int n, double t_cme_s, double window_s,
-                               double min_jump, double out[6]);
+                               double min_jump, double out[8]);
 
 /* ---- learned refinement flags -------------------------------------------
  * A per-block network predicts whether the plain criterion will ask for

@@ -539,16 +539,17 @@ def mlp_init(seed=0):
 
 def shock_diagnostics(t_s, v, t_cme_s, window_s=96 * 3600.0, min_jump=0.0):
     """ic_shock_diagnostics: dict(arrival_s, width_s, v_pre, v_max, gradient,
-    t_max_s) of a radial-speed series (times in s, speeds in any unit)."""
+    t_top_s, v_top, t_max_s) of a radial-speed series (times in s, speeds in
+    any unit)."""
     t = np.ascontiguousarray(t_s, dtype=np.float64)
     vv = np.ascontiguousarray(v, dtype=np.float64)
     if t.shape != vv.shape or t.ndim != 1:
         raise ValueError("t_s and v must be 1-D arrays of one length")
-    out = (ctypes.c_double * 6)()
+    out = (ctypes.c_double * 8)()
     dp = ctypes.POINTER(ctypes.c_double)
     _check(lib.ic_shock_diagnostics(t.ctypes.data_as(dp), vv.ctypes.data_as(dp), len(t), float(t_cme_s),
                                     float(window_s), float(min_jump), out))
-    keys = ("arrival_s", "width_s", "v_pre", "v_max", "gradient", "t_max_s")
+    keys = ("arrival_s", "width_s", "v_pre", "v_max", "gradient", "t_top_s", "v_top", "t_max_s")
     return dict(zip(keys, list(out)))
 
 

@@ -2461,12 +2461,12 @@ ic_status ic_floor_counts(ic_sim *s, int member, long *rho_floors, long *p_floor
 }
 
 ic_status ic_shock_diagnostics(const double *t_s, const double *v, int n, double t_cme_s, double window_s,
-                               double min_jump, double out[6])
+                               double min_jump, double out[8])
 {
     return guard(nullptr, [&]() {
         if (!t_s || !v || !out || n < 0 || !(window_s >= 0.0)) throw Error(IC_E_INVALID, "bad argument");
         const double nan = std::numeric_limits<double>::quiet_NaN();
-        for (int q = 0; q < 6; ++q) out[q] = nan;
+        for (int q = 0; q < 8; ++q) out[q] = nan;
         if (n == 0) return;
         for (int q = 1; q < n; ++q)
             if (!(t_s[q] >= t_s[q - 1])) throw Error(IC_E_INVALID, "sample times must ascend");
@@ -2484,29 +2484,38 @@ ic_status ic_shock_diagnostics(const double *t_s, const double *v, int n, double
         }
         out[2] = v_pre;
         // peak speed inside [t_cme, t_cme + window] (first sample of the maximum)
-        int qmax = -1;
+        int qmax = -1, qlast = -1;
         for (int q = 0; q < n; ++q)
-            if (t_s[q] >= t_cme_s && t_s[q] <= t_cme_s + window_s && (qmax < 0 || v[q] > v[qmax])) qmax = q;
+            if (t_s[q] >= t_cme_s && t_s[q] <= t_cme_s + window_s) {
+                if (qmax < 0 || v[q] > v[qmax]) qmax = q;
+                qlast = q;
+            }
         if (qmax < 0) {
             out[3] = v_pre;
             return;
         }
         const double v_max = v[qmax];
         out[3] = v_max;
-        out[5] = t_s[qmax];
+        out[7] = t_s[qmax];
         if (v_max - v_pre < min_jump) return;
         // arrival: the first upward crossing of the half-rise level inside the
-        // window by a segment that starts at or after the CME start
+        // window by a segment that starts at or after the CME start; the top of
+        // the jump: the first sample from the segment's end on after which the
+        // speed no longer rises (or the window's last sample)
         const double thr = v_pre + 0.5 * (v_max - v_pre);
         const double tol = 1e-12 * std::max(1.0, std::fabs(t_cme_s));
         for (int q = 1; q < n; ++q) {
             if (!(t_s[q] >= t_cme_s && t_s[q] <= t_cme_s + window_s)) continue;
             if (v[q - 1] < thr && thr <= v[q] && t_s[q - 1] >= t_cme_s - tol) {
                 const double ta = t_s[q - 1] + (thr - v[q - 1]) * (t_s[q] - t_s[q - 1]) / (v[q] - v[q - 1]);
+                int top = q;
+                while (top < qlast && v[top + 1] > v[top]) ++top;
                 out[0] = ta - t_cme_s;
-                out[1] = t_s[qmax] - ta;
-                // mean slope of v from the arrival (v = thr) to the peak
-                out[4] = out[1] > 0.0 ? (v_max - thr) / out[1] : nan;
+                out[1] = t_s[top] - ta;
+                out[5] = t_s[top];
+                out[6] = v[top];
+                // mean slope of v from the arrival (v = thr) to the top of the jump
+                out[4] = out[1] > 0.0 ? (v[top] - thr) / out[1] : nan;
                 return;
             }
         }

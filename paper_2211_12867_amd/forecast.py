@@ -9,6 +9,7 @@ unless a name says hours or days.
 
     python -m paper_2211_12867_amd.forecast train  --out flags.npz ...
     python -m paper_2211_12867_amd.forecast compare --net flags.npz ...
+    python -m paper_2211_12867_amd.forecast fig1 --out fig1.npz
 """
 import argparse
 import atexit
@@ -123,6 +124,34 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
                leaf_block_steps=((info["zone_updates"] if info else 0.0) - zu0) / cells, max_leaves=max_leaves,
                regrid_stats=sim.regrid_stats(), t_h=t_h, v_kms=v)
     sim.close()
+    return out
+
+
+def stretching_comparison(relax_days=14.0, cme_days=3.0, log=print):
+    """The low-resolution pair of paper Sect. 2.2 (Fig. 1): the same seeded
+    wind and cone CME (the full-domain workload's) on the equidistant grid of
+    300 radial cells (1.362 R_sun at 1 AU) and on the radially stretched grid
+    of 60 cells (10.7 R_sun at 1 AU), 24 x 96 angular cells, no refinement;
+    each relaxes from the initial state and runs cme_days after the CME
+    start.  Returns {name: cme_run's dict plus dr_1au_rsun}."""
+    from synthetic import as_dict, workload
+    w = workload("equidistant_full")
+    wind = as_dict(w.wind)
+    cme = dict(as_dict(w.cmes[0]), t_start_s=relax_days * DAY)
+    base = dict(geometry="spherical", x0=(0.1, 30.0, 0.0), x1=(2.0, 150.0, 360.0), block=(12, 12, 12),
+                periodic=(False, False, True), max_level=1, gamma=1.5, cfl=0.4)
+    rsun = units()["length_m"] / 6.957e8
+    out = {}
+    for name, n, stretched in (("low_equidistant", (300, 24, 96), False), ("low_stretched", (60, 24, 96), True)):
+        g = dict(base, n=n, stretched_r=stretched)
+        _log(log, "== %s %s" % (name, n))
+        r = cme_run(g, wind, cme, dict(regrid_every=0), None, (relax_days + cme_days) * DAY, log=log, chunk_s=DAY)
+        if stretched:
+            q = (2.0 / 0.1) ** (1.0 / n[0])
+            r["dr_1au_rsun"] = (q ** 0.5 - q ** -0.5) * rsun
+        else:
+            r["dr_1au_rsun"] = 1.9 / n[0] * rsun
+        out[name] = r
     return out
 
 
@@ -259,6 +288,10 @@ def main(argv=None):
     c.add_argument("--skip-equidistant", action="store_true")
     c.add_argument("--out")
     c.add_argument("--only", help="comma-separated subset of the AMR runs")
+    f = sub.add_parser("fig1", help="low resolution, equidistant vs radially stretched: series at Earth")
+    f.add_argument("--relax-days", type=float, default=14.0)
+    f.add_argument("--cme-days", type=float, default=3.0)
+    f.add_argument("--out")
     e = sub.add_parser("ensemble", help="the 32-member cone-CME ensemble on the stretched 3-level grid")
     e.add_argument("--members", type=int, default=32)
     e.add_argument("--relax-days", type=float, default=14.0)
@@ -311,6 +344,16 @@ def main(argv=None):
                     cme_days=args.cme_days, epochs=args.epochs, loss=[float(v) for v in loss])
         save_network(args.out, params, mean, std, meta)
         log("trained: %s" % json.dumps(meta))
+        return 0
+
+    if args.cmd == "fig1":
+        res = stretching_comparison(args.relax_days, args.cme_days, log=log)
+        keys = ("arrival_h", "width_h", "peak_kms", "gradient_kms_h", "wall_s", "steps", "dr_1au_rsun")
+        summary = {k: {q: v[q] for q in keys} for k, v in res.items()}
+        log(json.dumps(summary))
+        if args.out:
+            np.savez(args.out, **{"%s_%s" % (k, q): res[k][q] for k in res for q in ("t_h", "v_kms")},
+                     summary=np.array(json.dumps(summary)))
         return 0
 
     if args.cmd == "ensemble":

@@ -1,6 +1,6 @@
 """Shock diagnostics at a point (paper Sect. 3.1: arrival time and shock width,
-the time from arrival to the maximum speed after the jump; Sect. 3.2: peak
-speed and average gradient of the shock).
+the time from arrival to the maximum speed after the speed jump, read as the
+top of the jump; Sect. 3.2: peak speed and average gradient of the shock).
 
 The oracle's diagnostics are pinned by closed-form series; the library's
 ic_shock_diagnostics (a host computation, so these run without a GPU) must
@@ -27,8 +27,21 @@ def test_oracle_triangle_closed_forms():
     t = np.arange(0.0, 100.0, 0.5)
     d = analysis.diagnostics(t, _tri(t), 5.0, 96.0)
     assert abs(d["arrival"] + 5.0 - 43.0) < 1e-12 and abs(d["width"] - 3.0) < 1e-12
-    assert d["v_pre"] == 400.0 and d["v_max"] == 800.0 and d["t_max"] == 46.0
+    assert d["v_pre"] == 400.0 and d["v_max"] == 800.0 and d["t_max"] == 46.0 and d["t_top"] == 46.0
     assert abs(d["gradient"] - 200.0 / 3.0) < 1e-12
+
+
+def test_oracle_width_ends_at_the_top_of_the_jump():
+    """A jump to 700 topping out at 46, a dip, then the driver's hump to 800
+    at 60: the level is 400 + (800 - 400)/2 = 600, crossed on the jump at
+    t = 40 + 6 * 200/300 = 44; the width runs to the top of the jump (46), not
+    to the later maximum, and the average gradient is (700 - 600)/2."""
+    t = np.arange(0.0, 100.0, 0.5)
+    v = np.interp(t, [0, 40, 46, 52, 60, 100], [400, 400, 700, 650, 800, 450])
+    d = analysis.diagnostics(t, v, 5.0, 96.0)
+    assert abs(d["arrival"] + 5.0 - 44.0) < 1e-12 and abs(d["width"] - 2.0) < 1e-12
+    assert d["t_top"] == 46.0 and d["v_top"] == 700.0 and d["t_max"] == 60.0 and d["v_max"] == 800.0
+    assert abs(d["gradient"] - 50.0) < 1e-12
 
 
 def test_oracle_tanh_ramp_gradient():
@@ -41,8 +54,10 @@ def test_oracle_tanh_ramp_gradient():
     d = analysis.diagnostics(t, v, 10.0, 96.0)
     assert abs(d["arrival"] + 10.0 - ta) < 1e-9
     level = d["v_pre"] + 0.5 * (d["v_max"] - d["v_pre"])
-    assert abs(d["gradient"] - (d["v_max"] - level) / d["width"]) < 1e-12
-    assert abs(d["t_max"] - (d["arrival"] + 10.0 + d["width"])) < 1e-9
+    assert abs(d["gradient"] - (d["v_top"] - level) / d["width"]) < 1e-12
+    assert abs(d["t_top"] - (d["arrival"] + 10.0 + d["width"])) < 1e-9
+    # the ramp tops out where it stops rising (to rounding, at its maximum)
+    assert abs(d["v_top"] - d["v_max"]) <= 1e-12 * d["v_max"] and d["t_top"] <= d["t_max"]
 
 
 def test_oracle_exclusions():
@@ -73,6 +88,8 @@ def _series():
     out.append(("launch on a sample inside the rise", t, np.interp(t, [0, 42, 44, 100], [400, 400, 800, 800]),
                 42.5, 96.0, 0.0))
     out.append(("empty window", t, _tri(t), 200.0, 10.0, 0.0))
+    out.append(("double hump", t, np.interp(t, [0, 40, 46, 52, 60, 100], [400, 400, 700, 650, 800, 450]),
+                5.0, 96.0, 0.0))
     tt = np.arange(0.0, 120.0, 0.1)
     out.append(("tanh", tt, 400.0 + 150.0 * (1.0 + np.tanh((tt - 50.05) / 2.0)), 10.0, 96.0, 100.0))
     rng = np.random.default_rng(11)
@@ -90,7 +107,8 @@ def test_library_matches_the_oracle(case):
     ref = analysis.diagnostics(t_h, v, t0, win, jump)
     got = ic.shock_diagnostics(np.asarray(t_h) * 3600.0, v, t0 * 3600.0, win * 3600.0, jump)
     pairs = [("arrival", "arrival_s", 3600.0), ("width", "width_s", 3600.0), ("v_pre", "v_pre", 1.0),
-             ("v_max", "v_max", 1.0), ("gradient", "gradient", 1.0 / 3600.0), ("t_max", "t_max_s", 3600.0)]
+             ("v_max", "v_max", 1.0), ("gradient", "gradient", 1.0 / 3600.0), ("t_max", "t_max_s", 3600.0),
+             ("t_top", "t_top_s", 3600.0), ("v_top", "v_top", 1.0)]
     for a, b, scale in pairs:
         x, y = ref[a] * scale, got[b]
         if math.isnan(x):
