@@ -31,7 +31,7 @@ class Patch(ctypes.Structure):
                 ("f1", ctypes.POINTER(ctypes.c_double)),
                 ("f2", ctypes.POINTER(ctypes.c_double)),
                 ("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("gm", ctypes.c_double),
-                ("limiter", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("nv", ctypes.c_int)]
 
 LIMITERS = {"mc": 0, "minmod": 1, "vanleer": 2}
 
@@ -125,22 +125,24 @@ def slope(limiter, wm, w0, wp, xm, x0, xp):
 class PatchGeom:
     """Keeps the face arrays alive for a Patch struct."""
 
-    def __init__(self, f0, f1, f2, cartesian, gamma, omega, gm, limiter="mc"):
+    def __init__(self, f0, f1, f2, cartesian, gamma, omega, gm, limiter="mc", nv=NV):
         self.f = [_vec(f0), _vec(f1), _vec(f2)]
         self.n = tuple(len(a) - 5 for a in self.f)
+        self.nv = nv
         self.s = Patch(self.n[0], self.n[1], self.n[2], 1 if cartesian else 0,
-                       _p(self.f[0]), _p(self.f[1]), _p(self.f[2]), gamma, omega, gm, LIMITERS[limiter])
+                       _p(self.f[0]), _p(self.f[1]), _p(self.f[2]), gamma, omega, gm, LIMITERS[limiter], nv)
 
 
 def rhs(pg, G, want_fluxes=True):
-    """L(U) of a ghosted patch G [NV, nk+4, nj+4, ni+4].  Returns (L, (F0, F1, F2), n_bad)."""
+    """L(U) of a ghosted patch G [nv, nk+4, nj+4, ni+4].  Returns (L, (F0, F1, F2), n_bad)."""
     ni, nj, nk = pg.n
+    nv = pg.nv
     G = np.ascontiguousarray(G, dtype=np.float64)
-    assert G.shape == (NV, nk + 4, nj + 4, ni + 4)
-    L = np.empty((NV, nk, nj, ni))
-    F0 = np.empty((NV, nk, nj, ni + 1))
-    F1 = np.empty((NV, nk, nj + 1, ni))
-    F2 = np.empty((NV, nk + 1, nj, ni))
+    assert G.shape == (nv, nk + 4, nj + 4, ni + 4)
+    L = np.empty((nv, nk, nj, ni))
+    F0 = np.empty((nv, nk, nj, ni + 1))
+    F1 = np.empty((nv, nk, nj + 1, ni))
+    F2 = np.empty((nv, nk + 1, nj, ni))
     bad = lib().ora_rhs(ctypes.byref(pg.s), _p(G), _p(L), _p(F0), _p(F1), _p(F2))
     return L, (F0, F1, F2), bad
 
@@ -149,8 +151,8 @@ def rhs_hancock(pg, G):
     """Hancock predictor operator of a ghosted patch.  Returns (L, n_bad)."""
     ni, nj, nk = pg.n
     G = np.ascontiguousarray(G, dtype=np.float64)
-    assert G.shape == (NV, nk + 4, nj + 4, ni + 4)
-    L = np.empty((NV, nk, nj, ni))
+    assert G.shape == (pg.nv, nk + 4, nj + 4, ni + 4)
+    L = np.empty((pg.nv, nk, nj, ni))
     bad = lib().ora_rhs_hancock(ctypes.byref(pg.s), _p(G), _p(L))
     return L, bad
 

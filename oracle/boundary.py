@@ -168,6 +168,8 @@ def prims_to_cons(W, gamma):
     b2 = W[5] ** 2 + W[6] ** 2 + W[7] ** 2
     U[4] = W[4] / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * b2
     U[5:8] = W[5:8]
+    if len(W) > 8:
+        U[8] = rho * W[8]              # density tracer rho s
     return U
 
 
@@ -180,4 +182,6 @@ def cons_to_prims(U, gamma):
     b2 = U[5] ** 2 + U[6] ** 2 + U[7] ** 2
     W[4] = (gamma - 1.0) * (U[4] - 0.5 * rho * v2 - 0.5 * b2)
     W[5:8] = U[5:8]
+    if len(U) > 8:
+        W[8] = U[8] / rho              # CME mass fraction s
     return W

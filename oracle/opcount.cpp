@@ -119,6 +119,8 @@ int main()
     P.gamma = cd(1.5);
     P.omega = cd(0.01);
     P.gm = cd(0.0045);
+    P.limiter = 0;
+    P.nv = NV;
     const size_t ng = (size_t)NV * (nk + 4) * (nj + 4) * (ni + 4);
     std::vector<cd> U(ng), L((size_t)NV * ni * nj * nk);
     std::vector<cd> F0((size_t)NV * nk * nj * (ni + 1)), F1((size_t)NV * nk * (nj + 1) * ni),

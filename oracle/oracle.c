@@ -35,13 +35,17 @@
  *
  * Variables: U = (rho, m_r, m_theta, m_phi, E, B_r, B_theta, B_phi),
  *            W = (rho, v_r, v_theta, v_phi, p, B_r, B_theta, B_phi),
- * code units with mu_0 = 1, E = p/(gamma-1) + rho v^2/2 + B^2/2.
+ * code units with mu_0 = 1, E = p/(gamma-1) + rho v^2/2 + B^2/2.  A patch
+ * with nv = 9 carries the CME density tracer as a ninth conserved variable
+ * rho s (primitive s, the CME mass fraction): advected with the flow by the
+ * same TVDLF flux (rho s v_n and the same c_max), no source term.
  */
 #include <math.h>
 #include <stddef.h>
 #include <string.h>
 
-#define NV 8
+#define NV 8        /* MHD variables */
+#define NVMAX 9     /* with the CME density tracer rho s */
 
 typedef struct {
     int ni, nj, nk;        /* interior cells */
@@ -53,6 +57,7 @@ typedef struct {
     double omega;          /* rotation rate of the frame about the theta = 0 axis */
     double gm;             /* G * M_sun */
     int limiter;           /* 0 monotonised central, 1 minmod, 2 van Leer */
+    int nv;                /* 8, or 9 with the density tracer */
 } ora_patch;
 
 /* ------------------------------------------------------------------------ */
@@ -136,6 +141,40 @@ void ora_rusanov(const double *wl, const double *wr, int d, double gamma, double
     double cr = fabs(wr[1 + d]) + ora_fast_speed(wr, d, gamma);
     double c = cl > cr ? cl : cr;
     for (int v = 0; v < NV; ++v)
+        f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * c * (ur[v] - ul[v]);
+}
+
+/* the same with the density tracer when nv = 9: s = (rho s) / rho, its flux
+ * rho s v_n, and in the interface flux the same c_max as the MHD variables */
+static void prim_nv(int nv, const double *u, double *w, double gamma)
+{
+    ora_prim(u, w, gamma);
+    if (nv > NV) w[8] = u[8] / u[0];
+}
+
+static void cons_nv(int nv, const double *w, double *u, double gamma)
+{
+    ora_cons(w, u, gamma);
+    if (nv > NV) u[8] = w[0] * w[8];
+}
+
+static void flux_nv(int nv, const double *w, int d, double gamma, double *f)
+{
+    ora_flux(w, d, gamma, f);
+    if (nv > NV) f[8] = w[0] * w[8] * w[1 + d];
+}
+
+static void rusanov_nv(int nv, const double *wl, const double *wr, int d, double gamma, double *f)
+{
+    double fl[NVMAX], fr[NVMAX], ul[NVMAX], ur[NVMAX];
+    flux_nv(nv, wl, d, gamma, fl);
+    flux_nv(nv, wr, d, gamma, fr);
+    cons_nv(nv, wl, ul, gamma);
+    cons_nv(nv, wr, ur, gamma);
+    double cl = fabs(wl[1 + d]) + ora_fast_speed(wl, d, gamma);
+    double cr = fabs(wr[1 + d]) + ora_fast_speed(wr, d, gamma);
+    double c = cl > cr ? cl : cr;
+    for (int v = 0; v < nv; ++v)
         f[v] = 0.5 * (fl[v] + fr[v]) - 0.5 * c * (ur[v] - ul[v]);
 }
 
@@ -223,9 +262,9 @@ static double centre(const ora_patch *p, int d, int m)
 
 static void cell_prim(const ora_patch *p, const double *U, int i, int j, int k, double *w)
 {
-    double u[NV];
-    for (int v = 0; v < NV; ++v) u[v] = U[gix(p, v, i, j, k)];
-    ora_prim(u, w, p->gamma);
+    double u[NVMAX];
+    for (int v = 0; v < p->nv; ++v) u[v] = U[gix(p, v, i, j, k)];
+    prim_nv(p->nv, u, w, p->gamma);
 }
 
 /* Reconstruct cell c (index along d; the other two indices fixed) at its two
@@ -236,7 +275,7 @@ static void reconstruct(const ora_patch *p, const double *U, int d, int c, int a
                         double *w_lo, double *w_hi)
 {
     int idx[3];
-    double wm[NV], w0[NV], wp[NV];
+    double wm[NVMAX], w0[NVMAX], wp[NVMAX];
     idx[(d + 1) % 3] = a;
     idx[(d + 2) % 3] = b;
     idx[d] = c - 1; cell_prim(p, U, idx[0], idx[1], idx[2], wm);
@@ -244,14 +283,14 @@ static void reconstruct(const ora_patch *p, const double *U, int d, int c, int a
     idx[d] = c + 1; cell_prim(p, U, idx[0], idx[1], idx[2], wp);
     double xm = centre(p, d, c - 1), x0 = centre(p, d, c), xp = centre(p, d, c + 1);
     double flo = face(p, d, c), fhi = face(p, d, c + 1);
-    double s[NV];
-    for (int v = 0; v < NV; ++v) {
+    double s[NVMAX];
+    for (int v = 0; v < p->nv; ++v) {
         s[v] = ora_slope(p->limiter, wm[v], w0[v], wp[v], xm, x0, xp);
         w_lo[v] = w0[v] - s[v] * (x0 - flo);
         w_hi[v] = w0[v] + s[v] * (fhi - x0);
     }
     if (w_lo[0] <= 0.0 || w_hi[0] <= 0.0 || w_lo[4] <= 0.0 || w_hi[4] <= 0.0) {
-        for (int v = 0; v < NV; ++v) { w_lo[v] = w0[v]; w_hi[v] = w0[v]; }
+        for (int v = 0; v < p->nv; ++v) { w_lo[v] = w0[v]; w_hi[v] = w0[v]; }
     }
 }
 
@@ -318,13 +357,13 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
                 for (int i = 0; i < fn[0]; ++i) {
                     int c[3] = {i, j, k};
                     int a = c[(d + 1) % 3], b = c[(d + 2) % 3];
-                    double lo_m[NV], hi_m[NV], lo_p[NV], hi_p[NV], f[NV];
+                    double lo_m[NVMAX], hi_m[NVMAX], lo_p[NVMAX], hi_p[NVMAX], f[NVMAX];
                     /* face c[d] lies between cells c[d]-1 (left) and c[d] (right) */
                     reconstruct(p, U, d, c[d] - 1, a, b, lo_m, hi_m);
                     reconstruct(p, U, d, c[d], a, b, lo_p, hi_p);
-                    ora_rusanov(hi_m, lo_p, d, gamma, f);
+                    rusanov_nv(p->nv, hi_m, lo_p, d, gamma, f);
                     if (F) {
-                        for (int v = 0; v < NV; ++v)
+                        for (int v = 0; v < p->nv; ++v)
                             F[(((size_t)v * fn[2] + k) * fn[1] + j) * fn[0] + i] = f[v];
                     }
                 }
@@ -337,14 +376,14 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
     for (int k = 0; k < nk; ++k) {
         for (int j = 0; j < nj; ++j) {
             for (int i = 0; i < ni; ++i) {
-                double w[NV];
+                double w[NVMAX];
                 cell_prim(p, U, i, j, k, w);
                 int ok = w[0] > 0.0 && w[4] > 0.0;
-                for (int v = 0; v < NV; ++v) ok = ok && isfinite(w[v]);
+                for (int v = 0; v < p->nv; ++v) ok = ok && isfinite(w[v]);
                 if (!ok) bad += 1;
 
-                double acc[NV];
-                for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+                double acc[NVMAX];
+                for (int v = 0; v < p->nv; ++v) acc[v] = 0.0;
                 for (int d = 0; d < 3; ++d) {
                     double *F = d == 0 ? F0 : (d == 1 ? F1 : F2);
                     int fn[3] = {ni, nj, nk};
@@ -353,7 +392,7 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
                     cu[d] += 1;
                     double am, ap;
                     metric(p, d, i, j, k, &am, &ap);
-                    for (int v = 0; v < NV; ++v) {
+                    for (int v = 0; v < p->nv; ++v) {
                         double fl = F[(((size_t)v * fn[2] + cl[2]) * fn[1] + cl[1]) * fn[0] + cl[0]];
                         double fu = F[(((size_t)v * fn[2] + cu[2]) * fn[1] + cu[1]) * fn[0] + cu[0]];
                         acc[v] -= ap * fu - am * fl;
@@ -369,9 +408,9 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
                     double tc = centre(p, 1, j);
                     double S[NV];
                     ora_sources(w, rtinv, ctil, centre(p, 0, i), sin(tc), cos(tc), p->omega, p->gm, S);
-                    for (int v = 0; v < NV; ++v) acc[v] += S[v];
+                    for (int v = 0; v < NV; ++v) acc[v] += S[v];      /* no source of rho s */
                 }
-                for (int v = 0; v < NV; ++v)
+                for (int v = 0; v < p->nv; ++v)
                     L[(((size_t)v * nk + k) * nj + j) * ni + i] = acc[v];
             }
         }
@@ -397,20 +436,20 @@ int ora_rhs_hancock(const ora_patch *p, const double *U, double *L)
     for (int k = 0; k < nk; ++k) {
         for (int j = 0; j < nj; ++j) {
             for (int i = 0; i < ni; ++i) {
-                double w[NV], acc[NV];
+                double w[NVMAX], acc[NVMAX];
                 cell_prim(p, U, i, j, k, w);
                 int ok = w[0] > 0.0 && w[4] > 0.0;
-                for (int v = 0; v < NV; ++v) ok = ok && isfinite(w[v]);
+                for (int v = 0; v < p->nv; ++v) ok = ok && isfinite(w[v]);
                 if (!ok) bad += 1;
-                for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+                for (int v = 0; v < p->nv; ++v) acc[v] = 0.0;
                 int c[3] = {i, j, k};
                 for (int d = 0; d < 3; ++d) {
-                    double lo[NV], hi[NV], flo[NV], fhi[NV], am, ap;
+                    double lo[NVMAX], hi[NVMAX], flo[NVMAX], fhi[NVMAX], am, ap;
                     reconstruct(p, U, d, c[d], c[(d + 1) % 3], c[(d + 2) % 3], lo, hi);
-                    ora_flux(lo, d, p->gamma, flo);
-                    ora_flux(hi, d, p->gamma, fhi);
+                    flux_nv(p->nv, lo, d, p->gamma, flo);
+                    flux_nv(p->nv, hi, d, p->gamma, fhi);
                     metric(p, d, i, j, k, &am, &ap);
-                    for (int v = 0; v < NV; ++v) acc[v] -= ap * fhi[v] - am * flo[v];
+                    for (int v = 0; v < p->nv; ++v) acc[v] -= ap * fhi[v] - am * flo[v];
                 }
                 if (!p->cartesian) {
                     double rm = face(p, 0, i), rp = face(p, 0, i + 1);
@@ -423,7 +462,7 @@ int ora_rhs_hancock(const ora_patch *p, const double *U, double *L)
                     ora_sources(w, rtinv, ctil, centre(p, 0, i), sin(tc), cos(tc), p->omega, p->gm, S);
                     for (int v = 0; v < NV; ++v) acc[v] += S[v];
                 }
-                for (int v = 0; v < NV; ++v) L[(((size_t)v * nk + k) * nj + j) * ni + i] = acc[v];
+                for (int v = 0; v < p->nv; ++v) L[(((size_t)v * nk + k) * nj + j) * ni + i] = acc[v];
             }
         }
     }
@@ -438,7 +477,7 @@ double ora_max_rate(const ora_patch *p, const double *U)
     for (int k = 0; k < p->nk; ++k)
         for (int j = 0; j < p->nj; ++j)
             for (int i = 0; i < p->ni; ++i) {
-                double w[NV];
+                double w[NVMAX];
                 cell_prim(p, U, i, j, k, w);
                 double dx[3];
                 int m[3] = {i, j, k};
@@ -475,7 +514,7 @@ void ora_indicator(const ora_patch *p, const double *U, double eps,
         for (int j = 0; j < p->nj; ++j)
             for (int i = 0; i < p->ni; ++i) {
                 double num_r = 0, den_r = 0, num_v = 0, den_v = 0, dv = 0, ds = 0;
-                double w0[NV];
+                double w0[NVMAX];
                 cell_prim(p, U, i, j, k, w0);
                 double r0 = w0[0];
                 double s0 = sqrt(w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]);
@@ -483,7 +522,7 @@ void ora_indicator(const ora_patch *p, const double *U, double eps,
                     int lo[3] = {i, j, k}, hi[3] = {i, j, k};
                     lo[d] -= 1;
                     hi[d] += 1;
-                    double wl[NV], wh[NV];
+                    double wl[NVMAX], wh[NVMAX];
                     cell_prim(p, U, lo[0], lo[1], lo[2], wl);
                     cell_prim(p, U, hi[0], hi[1], hi[2], wh);
                     double rl = wl[0], rh = wh[0];

@@ -21,6 +21,15 @@ moves by B_in . dB.  A gradient component that would need D across a
 physical boundary or a level change is zero (the cleaning stays out of the
 cells on those faces).
 
+Density tracer (Sect. 3.1, an option): a ninth conserved variable rho s, s the
+CME mass fraction (1 in the cone CME injected at the inner boundary, 0 in the
+wind and initially), advected by the same TVDLF flux, no source; floors
+leave it.  Refinement criteria (amr "criterion"): "shock" (the Sect. 3.2
+criterion), "tracer" (Sect. 3.1: refine where the tracer is present, s >
+tracer_refine in some cell; coarsen where s <= tracer_coarsen everywhere; no
+windows) and "combined" (Sect. 3.3: inside the windows, the shock condition
+or the tracer condition).
+
 Block AMR (Sect. 3): every leaf carries two face-ghost layers per face.  Face
 ghosts come from a same-level neighbour (copy), from finer neighbours
 (volume-weighted restriction of the 8 children of each ghost cell) or from a
@@ -132,7 +141,8 @@ def _apply_cleaning(u, G, Dp, dx, gs, coef):
 AMR_DEFAULTS = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
                     lon_earth_deg=0.0, clt_earth_deg=90.0, dlon_earth_deg=30.0,
                     dclt_earth_deg=10.0, dlon_cme_deg=90.0, use_windows=True,
-                    regrid_every=10, buffer_blocks=1)
+                    regrid_every=10, buffer_blocks=1, criterion="shock",
+                    tracer_refine=0.01, tracer_coarsen=0.00125)
 
 
 class Solver:
@@ -140,9 +150,10 @@ class Solver:
 
     def __init__(self, grid, wind=None, cme=None, amr=None, omega=None, gm=None, t0_s=0.0,
                  initial="wind", rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage",
-                 divb_cd=0.0):
+                 divb_cd=0.0, tracer=False):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
         self.limiter, self.scheme, self.divb_cd = limiter, scheme, float(divb_cd)
+        self.nv = 9 if tracer else NV
         assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
@@ -178,7 +189,7 @@ class Solver:
                 self.U[b] = self.initial_block(b)
         else:
             for b in self.forest.leaves:
-                self.U[b] = np.zeros((NV,) + self.B[::-1])
+                self.U[b] = np.zeros((self.nv,) + self.B[::-1])
 
     # --- geometry -------------------------------------------------------------
     def cell_range(self, leaf, d):
@@ -190,7 +201,7 @@ class Solver:
             g = self.geo[leaf[0]]
             f = [g.faces(d, *self.cell_range(leaf, d)) for d in range(3)]
             self._patch[leaf] = _clib.PatchGeom(f[0], f[1], f[2], self.cart, self.gamma,
-                                                self.omega, self.gm, self.limiter)
+                                                self.omega, self.gm, self.limiter, self.nv)
         return self._patch[leaf]
 
     def centres(self, leaf, d, lo=0, hi=None):
@@ -204,6 +215,8 @@ class Solver:
         th = self.centres(leaf, 1)[None, :, None]
         ph = self.centres(leaf, 2)[:, None, None]
         W = boundary.initial_prims(self.wind, r, th, ph, self.r_in, self.omega, self.gamma)
+        if self.nv > NV:
+            W = np.concatenate([W, np.zeros((1,) + W.shape[1:])])      # no CME material yet
         return boundary.prims_to_cons(W, self.gamma)
 
     # --- ghost cells ----------------------------------------------------------
@@ -231,7 +244,7 @@ class Solver:
         """Ghosted arrays of all leaves for state U at code time t."""
         G = {}
         for leaf in sorted(self.forest.leaves):  # ascending level
-            g = np.zeros((NV,) + tuple(b + 4 for b in self.B[::-1]))
+            g = np.zeros((self.nv,) + tuple(b + 4 for b in self.B[::-1]))
             g[:, 2:-2, 2:-2, 2:-2] = U[leaf]
             for d in range(3):
                 for side in (0, 1):
@@ -256,6 +269,10 @@ class Solver:
                 ph = self.centres(leaf, 2)[:, None, None]
                 W = boundary.boundary_prims(self.wind, self.cme, th + 0.0 * ph, ph + 0.0 * th,
                                             self.r_in, self.omega, t)
+                if self.nv > NV:      # CME material: s = 1 inside the cone, 0 in the wind
+                    s_in = boundary.cme_mask(self.cme, th + 0.0 * ph, ph + 0.0 * th, self.r_in, t) \
+                        if self.cme is not None else np.zeros(W.shape[1:], dtype=bool)
+                    W = np.concatenate([W, s_in[None].astype(np.float64)])
                 g[sl] = boundary.prims_to_cons(W, self.gamma)    # [v, k, j, 1]
             else:
                 raise ValueError("boundary kind %r without a neighbour" % kind)
@@ -342,7 +359,7 @@ class Solver:
         volume-weighted mean of their 8 children, read from the leaves of level_c+1."""
         gf_geo = self.geo[level_c + 1]
         gw = [self._wrap_idx(level_c, d, np.asarray(gidx[d])) for d in range(3)]
-        shape = (NV, len(gw[2]), len(gw[1]), len(gw[0]))
+        shape = (self.nv, len(gw[2]), len(gw[1]), len(gw[0]))
         num = np.zeros(shape)
         den = np.zeros(shape[1:])
         for o in range(8):
@@ -465,7 +482,7 @@ class Solver:
                             loc[d], loc[t1], loc[t2] = nd, a, b
                             glob = [loc[e] + self.cell_range(leaf, e)[0] for e in range(3)]
                             Vc = gc.volume(*glob)
-                            acc = np.zeros(NV)
+                            acc = np.zeros(self.nv)
                             for ob in (0, 1):
                                 for oa in (0, 1):
                                     fg = [0, 0, 0]
@@ -498,7 +515,7 @@ class Solver:
     def max_rate(self, U):
         best = 0.0
         for leaf in self.forest.leaves:
-            g = np.zeros((NV,) + tuple(b + 4 for b in self.B[::-1]))
+            g = np.zeros((self.nv,) + tuple(b + 4 for b in self.B[::-1]))
             g[:, 2:-2, 2:-2, 2:-2] = U[leaf]
             best = max(best, _clib.max_rate(self.patch(leaf), g))
         return best
@@ -576,12 +593,21 @@ class Solver:
         list, receives (leaf, kind) for cells within the near-tie margins."""
         ind, _ = self.indicator()
         a = self.amr
+        crit = a.get("criterion", "shock")
+        assert crit in ("shock", "tracer", "combined")
         out = {}
         for leaf, (E, dv, ds) in ind.items():
             win = self.window(leaf, self.cme)
             comp = dv < 0.0
             hot_r = win & comp & (E > a["tol_refine"])
             hot_c = win & comp & (E > a["tol_coarsen"])
+            if crit != "shock":
+                s = self.U[leaf][8] / self.U[leaf][0]
+                tr_r, tr_c = s > a["tracer_refine"], s > a["tracer_coarsen"]
+                if crit == "tracer":
+                    hot_r, hot_c = tr_r, tr_c
+                else:
+                    hot_r, hot_c = hot_r | (win & tr_r), hot_c | (win & tr_c)
             if ties is not None:
                 for tol in (a["tol_refine"], a["tol_coarsen"]):
                     if np.any(win & comp & (np.abs(E - tol) < 1e-9 * tol)):
@@ -650,7 +676,7 @@ class Solver:
 
     def total(self):
         """sum over leaves of V U per conserved variable."""
-        tot = np.zeros(NV)
+        tot = np.zeros(self.nv)
         for leaf, u in self.U.items():
             g = self.geo[leaf[0]]
             r = [self.cell_range(leaf, d) for d in range(3)]
@@ -658,7 +684,7 @@ class Solver:
             wj = np.array([g.volume_weight(1, x) for x in range(*r[1])])
             wk = np.array([g.volume_weight(2, x) for x in range(*r[2])])
             V = wk[:, None, None] * wj[None, :, None] * wi[None, None, :]
-            tot += (u * V).reshape(NV, -1).sum(axis=1)
+            tot += (u * V).reshape(self.nv, -1).sum(axis=1)
         return tot
 
     # --- sampling ---------------------------------------------------------------
@@ -674,7 +700,7 @@ class Solver:
             loc = [cg[d] - c[1 + d] * self.B[d] for d in range(3)]
             return self.U[c][:, loc[2], loc[1], loc[0]]
         g = self.geo[level + 1]
-        num, den = np.zeros(NV), 0.0
+        num, den = np.zeros(self.nv), 0.0
         for o in range(8):
             ch = (2 * gidx[0] + (o & 1), 2 * gidx[1] + ((o >> 1) & 1), 2 * gidx[2] + ((o >> 2) & 1))
             w = g.volume_weight(0, ch[0]) * g.volume_weight(1, ch[1]) * g.volume_weight(2, ch[2])
@@ -727,7 +753,7 @@ class Solver:
                     lo.append(g.n[d] - 2); wt.append(1.0)
                 else:
                     lo.append(m); wt.append((x[d] - c[m]) / (c[m + 1] - c[m]))
-        out = np.zeros(NV)
+        out = np.zeros(self.nv)
         for o in range(8):
             off = (o & 1, (o >> 1) & 1, (o >> 2) & 1)
             gi = []
@@ -739,7 +765,7 @@ class Solver:
                 gi.append(m)
                 w *= wt[d] if off[d] else (1.0 - wt[d])
             u = self._cell_value(lvl, gi)
-            out += w * boundary.cons_to_prims(u.reshape(NV, 1), self.gamma)[:, 0]
+            out += w * boundary.cons_to_prims(u.reshape(self.nv, 1), self.gamma)[:, 0]
         return out
 
 
@@ -748,9 +774,11 @@ class PatchSolver:
     an independent check of the block decomposition and as the CPU baseline."""
 
     def __init__(self, grid, wind=None, cme=None, omega=None, gm=None, t0_s=0.0, initial="wind",
-                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0):
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0,
+                 tracer=False):
         self.rho_floor, self.p_floor, self.floored = rho_floor, p_floor, 0
         self.limiter, self.scheme, self.divb_cd = limiter, scheme, float(divb_cd)
+        self.nv = 9 if tracer else NV
         assert scheme in ("two_stage", "hancock")
         self.floor_counts = [0, 0]         # density-floored, pressure-floored cells
         self.grid = dict(grid)
@@ -767,7 +795,7 @@ class PatchSolver:
         self.n = self.geo.n
         self.r_in = self.geo.f[0][2]
         self.pg = _clib.PatchGeom(self.geo.f[0], self.geo.f[1], self.geo.f[2], self.cart,
-                                  self.gamma, self.omega, self.gm, limiter)
+                                  self.gamma, self.omega, self.gm, limiter, self.nv)
         self.t = units.time_code(t0_s)
         ni, nj, nk = self.n
         if initial == "wind" and wind is not None and not self.cart:
@@ -775,13 +803,15 @@ class PatchSolver:
             th = np.array([self.geo.centre(1, j) for j in range(nj)])[None, :, None]
             ph = np.array([self.geo.centre(2, k) for k in range(nk)])[:, None, None]
             W = boundary.initial_prims(wind, r, th, ph, self.r_in, self.omega, self.gamma)
+            if self.nv > NV:
+                W = np.concatenate([W, np.zeros((1,) + W.shape[1:])])
             self.U = boundary.prims_to_cons(W, self.gamma)
         else:
-            self.U = np.zeros((NV, nk, nj, ni))
+            self.U = np.zeros((self.nv, nk, nj, ni))
 
     def ghosted(self, U, t):
         ni, nj, nk = self.n
-        G = np.zeros((NV, nk + 4, nj + 4, ni + 4))
+        G = np.zeros((self.nv, nk + 4, nj + 4, ni + 4))
         G[:, 2:-2, 2:-2, 2:-2] = U
         n = self.n
         for d in range(3):
@@ -804,6 +834,10 @@ class PatchSolver:
                     ph = np.array([self.geo.centre(2, k) for k in range(nk)])[:, None]
                     W = boundary.boundary_prims(self.wind, self.cme, th + 0.0 * ph, ph + 0.0 * th,
                                                 self.r_in, self.omega, t)
+                    if self.nv > NV:
+                        s_in = boundary.cme_mask(self.cme, th + 0.0 * ph, ph + 0.0 * th, self.r_in, t) \
+                            if self.cme is not None else np.zeros(W.shape[1:], dtype=bool)
+                        W = np.concatenate([W, s_in[None].astype(np.float64)])
                     G[tuple(dst)] = boundary.prims_to_cons(W, self.gamma)[:, :, :, None]
                 else:
                     raise ValueError(kind)
@@ -845,7 +879,7 @@ class PatchSolver:
         _apply_cleaning(Unew, G, Dp, dx, gs, alpha * self.divb_cd)
 
     def cfl_dt(self):
-        G = np.zeros((NV,) + tuple(x + 4 for x in self.n[::-1]))
+        G = np.zeros((self.nv,) + tuple(x + 4 for x in self.n[::-1]))
         G[:, 2:-2, 2:-2, 2:-2] = self.U
         return self.cfl / _clib.max_rate(self.pg, G)
 
@@ -873,7 +907,7 @@ class PatchSolver:
         wj = np.array([g.volume_weight(1, x) for x in range(nj)])
         wk = np.array([g.volume_weight(2, x) for x in range(nk)])
         V = wk[:, None, None] * wj[None, :, None] * wi[None, None, :]
-        return (self.U * V).reshape(NV, -1).sum(axis=1)
+        return (self.U * V).reshape(self.nv, -1).sum(axis=1)
 
     def to_blocks(self, block):
         """Split the patch state into base-level blocks, (level, Morton) order."""
