@@ -23,7 +23,8 @@
  *    rho0 v0^2, magnetic field sqrt(mu0 rho0 v0^2) (mu0 = 1); ic_units()
  *    returns these scales.
  *  - Conserved variables, 8 per cell: rho, m_r, m_theta, m_phi, E, B_r,
- *    B_theta, B_phi (x, y, z in the cartesian test geometry).
+ *    B_theta, B_phi (x, y, z in the cartesian test geometry); 9 with the
+ *    CME density tracer (ic_phys_cfg.tracer), the ninth being rho s.
  *  - Block state layout: [block][variable][k][j][i], i (r) fastest, blocks in
  *    ascending (level, Morton(i, j, k)) order, as ic_get_blocks lists them.
  *  - All GPU work is enqueued on the HIP stream given to ic_create (NULL =
@@ -102,7 +103,11 @@ typedef struct {
  * h^2 = 1 / sum_d dx_d^-2 (the CFL widths), and E += B_in . dB; no gradient
  * component across a physical boundary or a level change; divb_cd in [0, 1]
  * (a Fourier mode decays by 1 - alpha divb_cd (h/dx)^2 sin^2(k dx) per
- * application). */
+ * application).  tracer = 1 carries the CME density tracer of Sect. 3.1 as a
+ * ninth conserved variable rho s (s the CME mass fraction: 1 in the cone CME
+ * at the inner boundary, 0 in the wind and in the initial state), advected
+ * by the same TVDLF flux with the same maximum speed, no source, left alone
+ * by the floors; IC_LIM_MC only. */
 enum { IC_LIM_MC = 0, IC_LIM_MINMOD = 1, IC_LIM_VANLEER = 2 };
 enum { IC_SCHEME_TWO_STAGE = 0, IC_SCHEME_HANCOCK = 1 };
 typedef struct {
@@ -115,6 +120,7 @@ typedef struct {
     int limiter;
     int scheme;
     double divb_cd;
+    int tracer;
 } ic_phys_cfg;
 
 /* Inner-boundary wind at r_in (Sect. 2.1): v_r = v_min + (v_max - v_min)
@@ -147,7 +153,14 @@ typedef struct {
  * with parameter eps_lohner.  A block is REFINE below max_level with a hot
  * cell at tol_refine, COARSEN above level 1 with no hot cell at tol_coarsen,
  * else KEEP.  buffer_blocks = 1 refines the face neighbours of REFINE blocks
- * too.  regrid_every is the cadence ic_advance regrids at (0 = never). */
+ * too.  regrid_every is the cadence ic_advance regrids at (0 = never).
+ * criterion: IC_CRIT_SHOCK (the above, Sect. 3.2; the default),
+ * IC_CRIT_TRACER (Sect. 3.1: a cell is hot where the tracer fraction
+ * s = (rho s) / rho exceeds tracer_refine, resp. tracer_coarsen, anywhere,
+ * without windows) or IC_CRIT_COMBINED (Sect. 3.3: a cell inside the windows
+ * is hot by either condition); the latter two need the tracer and the plain
+ * source.  The learned flags and ic_eval_hot follow the shock criterion. */
+enum { IC_CRIT_SHOCK = 0, IC_CRIT_TRACER = 1, IC_CRIT_COMBINED = 2 };
 typedef struct {
     double eps_lohner, tol_refine, tol_coarsen, w_rho, w_v;
     double lon_earth_deg, clt_earth_deg, dlon_earth_deg, dclt_earth_deg, dlon_cme_deg;
@@ -158,6 +171,8 @@ typedef struct {
     int judge_every;        /* learned + judge: evaluate the plain criterion every judge_every-th regrid */
     double judge_recall;    /* fall back to the plain flags for 10 regrids below this REFINE recall */
     double learned_threshold; /* learned REFINE where the network's p >= this (<= 0: 1/2) */
+    int criterion;          /* IC_CRIT_* */
+    double tracer_refine, tracer_coarsen;   /* tracer fractions (tracer and combined criteria) */
 } ic_amr_cfg;
 
 enum { IC_SOURCE_PLAIN = 0, IC_SOURCE_LEARNED = 1, IC_SOURCE_LEARNED_JUDGED = 2 };
@@ -256,9 +271,10 @@ ic_status ic_timeseries_clear(ic_sim *sim);
 ic_status ic_get_blocks(ic_sim *sim, int member, int32_t *lvl_ijk, int *n_inout);
 
 /* Copy a member's conserved state (the finite-volume cell averages of the
- * eight conserved MHD variables, Sect. 2.1) to host_U ([block][8][bk][bj][bi],
- * code units, blocks in ic_get_blocks order); n_doubles must be >= leaves * 8
- * * cells per block.  Synchronises the stream. */
+ * eight conserved MHD variables, Sect. 2.1, then rho s with the tracer) to
+ * host_U ([block][nv][bk][bj][bi], nv = 8 or 9, code units, blocks in
+ * ic_get_blocks order); n_doubles must be >= leaves * nv * cells per block.
+ * Synchronises the stream. */
 ic_status ic_get_state(ic_sim *sim, int member, double *host_U, size_t n_doubles);
 
 /* Replace a member's block forest (Sect. 3: blocks of 2:1-balanced levels)

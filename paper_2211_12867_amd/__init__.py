@@ -51,11 +51,13 @@ class GridCfg(ctypes.Structure):
 class PhysCfg(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("omega", ctypes.c_double),
                 ("gm", ctypes.c_double), ("rho_floor", ctypes.c_double), ("p_floor", ctypes.c_double),
-                ("limiter", ctypes.c_int), ("scheme", ctypes.c_int), ("divb_cd", ctypes.c_double)]
+                ("limiter", ctypes.c_int), ("scheme", ctypes.c_int), ("divb_cd", ctypes.c_double),
+                ("tracer", ctypes.c_int)]
 
 
 LIMITERS = {"mc": 0, "minmod": 1, "vanleer": 2}
 SCHEMES = {"two_stage": 0, "hancock": 1}
+CRITERIA = {"shock": 0, "tracer": 1, "combined": 2}
 
 
 class WindCfg(ctypes.Structure):
@@ -80,7 +82,8 @@ class AmrCfg(ctypes.Structure):
                 ("dlon_cme_deg", ctypes.c_double), ("use_windows", ctypes.c_int),
                 ("regrid_every", ctypes.c_int), ("buffer_blocks", ctypes.c_int), ("source", ctypes.c_int),
                 ("judge_every", ctypes.c_int), ("judge_recall", ctypes.c_double),
-                ("learned_threshold", ctypes.c_double)]
+                ("learned_threshold", ctypes.c_double), ("criterion", ctypes.c_int),
+                ("tracer_refine", ctypes.c_double), ("tracer_coarsen", ctypes.c_double)]
 
 
 class MlpHparams(ctypes.Structure):
@@ -256,10 +259,13 @@ def amr_cfg(amr):
     defaults = dict(eps_lohner=0.01, tol_refine=0.1, tol_coarsen=0.0125, w_rho=0.5, w_v=0.5,
                     lon_earth_deg=0.0, clt_earth_deg=90.0, dlon_earth_deg=30.0, dclt_earth_deg=10.0,
                     dlon_cme_deg=90.0, use_windows=True, regrid_every=10, buffer_blocks=1, source=0,
-                    judge_every=10, judge_recall=0.9, learned_threshold=0.5)
+                    judge_every=10, judge_recall=0.9, learned_threshold=0.5,
+                    tracer_refine=0.01, tracer_coarsen=0.00125)
     for key, dv in defaults.items():
         v = _get(amr, key, dv)
         setattr(a, key, int(v) if isinstance(dv, (bool, int)) and not isinstance(dv, float) else float(v))
+    crit = _get(amr, "criterion", "shock")
+    a.criterion = CRITERIA[crit] if isinstance(crit, str) else int(crit)
     return a
 
 
@@ -277,14 +283,17 @@ class Sim:
     """One library sim: n_members runs of the same grid and wind, one CME each."""
 
     def __init__(self, grid, wind=None, cmes=None, amr=None, omega=None, gm=None, max_blocks=0, stream=None,
-                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0):
+                 rho_floor=RHO_FLOOR, p_floor=P_FLOOR, limiter="mc", scheme="two_stage", divb_cd=0.0,
+                 tracer=False):
         self.grid = grid
+        self.nv = 9 if tracer else 8
         g = grid_cfg(grid, max_blocks)
         cart = g.geometry == IC_GEOM_CARTESIAN
         p = PhysCfg(float(_get(grid, "gamma", 1.5)), float(_get(grid, "cfl", 0.4)),
                     0.0 if cart else (OMEGA_SUN if omega is None else float(omega)),
                     0.0 if cart else (GM_SUN if gm is None else float(gm)),
-                    float(rho_floor), float(p_floor), LIMITERS[limiter], SCHEMES[scheme], float(divb_cd))
+                    float(rho_floor), float(p_floor), LIMITERS[limiter], SCHEMES[scheme], float(divb_cd),
+                    1 if tracer else 0)
         w = wind_cfg(wind) if wind is not None else None
         if cmes is None or len(cmes) == 0:
             self.n_members = 1
@@ -399,14 +408,14 @@ class Sim:
 
     def state(self, member=0):
         bl = self.blocks(member)
-        U = np.zeros((len(bl), 8, self.block[2], self.block[1], self.block[0]))
+        U = np.zeros((len(bl), self.nv, self.block[2], self.block[1], self.block[0]))
         _check(lib.ic_get_state(self.h, member, U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), U.size))
         return bl, U
 
     def set_state(self, blocks, U, t_s=0.0, member=0):
         b = np.ascontiguousarray(np.asarray(blocks, dtype=np.int32).reshape(-1, 4))
         U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
-        assert U.shape == (len(b), 8, self.block[2], self.block[1], self.block[0])
+        assert U.shape == (len(b), self.nv, self.block[2], self.block[1], self.block[0])
         _check(lib.ic_set_state(self.h, member, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(b),
                                 U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(t_s)))
 

@@ -7,7 +7,7 @@
 template <class S>
 __device__ inline size_t cidx(int slot, int v, int i, int j, int k)
 {
-    return (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+    return (size_t)slot * S::NV * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
 }
 
 __device__ inline double wave_max(double x)

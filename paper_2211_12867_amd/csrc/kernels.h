@@ -2,7 +2,9 @@
 //
 // All kernels walk device-resident task lists with a grid-stride loop over
 // work-groups, so a captured graph stays valid when a regrid rewrites the
-// lists.  Block shapes are template parameters (BI x BJ x BK cells).
+// lists.  Block shapes are template parameters (BI x BJ x BK cells), and so
+// is the number of conserved variables NV (8, or 9 with the CME density
+// tracer).
 #pragma once
 #include "device.h"
 #include "physics.h"
@@ -41,15 +43,17 @@ struct KArgs {
     int ksplit;                // stage kernel: work-groups per block, each marching over BK / ksplit planes
     double *divb;              // parabolic cleaning: div B of the stage input per slot and cell
     double divb_cd;            // parabolic cleaning coefficient C_d (0 = off)
+    int nv;                    // conserved variables per cell (8, or 9 with the tracer)
 };
 
 // CFL maxima are kept per block and k-part: rate[slot * KSPLIT_MAX + part]
 #define KSPLIT_MAX 4
 
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV_ = 8>
 struct Shape {
     static constexpr int B0 = BI, B1 = BJ, B2 = BK;
     static constexpr int NC = BI * BJ * BK;
+    static constexpr int NV = NV_;              // conserved variables per cell
     __host__ __device__ static constexpr int dim(int d) { return d == 0 ? BI : (d == 1 ? BJ : BK); }
     __host__ __device__ static constexpr int face_cells(int d) { return dim(tan1(d)) * dim(tan2(d)); }
     static constexpr int MAXFACE = (BI * BJ > BI * BK ? (BI * BJ > BJ * BK ? BI * BJ : BJ * BK)
@@ -70,18 +74,18 @@ __device__ inline const double *ghosted_addr(const double *__restrict__ U, const
     if (i < 0 || i >= S::B0) d = 0;
     else if (j < 0 || j >= S::B1) d = 1;
     else if (k < 0 || k >= S::B2) d = 2;
-    if (d < 0) return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+    if (d < 0) return U + (size_t)slot * S::NV * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
     const int Bd = S::dim(d);
     const int side = idx[d] >= Bd ? 1 : 0;
     const int l = side ? idx[d] - Bd : idx[d] + 2;
     const int code = desc[slot].nbr[2 * d + side];
     if (code >= 0) {
         idx[d] = side ? l : Bd - 2 + l;
-        return U + (size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+        return U + (size_t)code * S::NV * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     if (code == NBR_OUTFLOW) {
         idx[d] = side ? Bd - 1 : 0;
-        return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+        return U + (size_t)slot * S::NV * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     const int s = nbr_slab(code);
     const int a = idx[tan1(d)], b = idx[tan2(d)];
@@ -123,18 +127,18 @@ DEV const double *cell_addr(const double *__restrict__ U, const double *__restri
     if (i < 0 || i >= S::B0) d = 0;
     else if (j < 0 || j >= S::B1) d = 1;
     else if (k < 0 || k >= S::B2) d = 2;
-    if (d < 0) return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
+    if (d < 0) return U + (size_t)slot * S::NV * S::NC + (size_t)v * S::NC + i + S::B0 * (j + S::B1 * k);
     const int Bd = S::dim(d);
     const int side = idx[d] >= Bd ? 1 : 0;
     const int l = side ? idx[d] - Bd : idx[d] + 2;
     const int code = face_code(nb, 2 * d + side);
     if (code >= 0) {
         idx[d] = side ? l : Bd - 2 + l;
-        return U + (size_t)code * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+        return U + (size_t)code * S::NV * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     if (code == NBR_OUTFLOW) {
         idx[d] = side ? Bd - 1 : 0;
-        return U + (size_t)slot * 8 * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
+        return U + (size_t)slot * S::NV * S::NC + (size_t)v * S::NC + idx[0] + S::B0 * (idx[1] + S::B1 * idx[2]);
     }
     const int a = idx[tan1(d)], b = idx[tan2(d)];
     const int FA = S::dim(tan1(d)), FB = S::dim(tan2(d));
@@ -149,18 +153,17 @@ __device__ inline double ghosted(const double *__restrict__ U, const BlockDesc *
     return *ghosted_addr<S>(U, desc, slabs, slab_stride, slot, v, i, j, k);
 }
 
-template <class S>
-__device__ inline void ghosted8(const KArgs &a, const double *U, int slot, int i, int j, int k, double u[8])
-{
-#pragma unroll
-    for (int v = 0; v < 8; ++v) u[v] = ghosted<S>(U, a.desc, a.slabs, a.slab_stride, slot, v, i, j, k);
-}
+// Refinement criteria: the Sect. 3.2 shock criterion, the Sect. 3.1 tracer
+// criterion, and their union inside the windows (Sect. 3.3).
+enum { CRIT_SHOCK = 0, CRIT_TRACER = 1, CRIT_COMBINED = 2 };
 
 struct IndicatorParams {
     int max_level;
     double eps, tol_r, tol_c, w_rho, w_v;
     int use_windows;
     double lon_e, clt_e, dlon_e, dclt_e, dlon_c;   // radians
+    int criterion;                                 // CRIT_*
+    double tr_r, tr_c;                             // tracer fractions that refine / keep a block
 };
 
 // Launch wrappers per block shape (kernels.hip, stage.hip); the runtime calls these.
@@ -177,28 +180,28 @@ struct Launchers {
     void (*sample)(dim3, hipStream_t, const KArgs &, const SampleDesc *, int, double *, double *, int *, int, int,
                    double *, long *);
 };
-bool get_launchers(int bi, int bj, int bk, Launchers *out);
+bool get_launchers(int bi, int bj, int bk, int nv, Launchers *out);
 void launch_dt(hipStream_t s, const KArgs &a, const int *mbeg, const int *mend, int nm, double cfl,
                double dt_fixed, const double *tend, double *dt_last);
 void launch_time(hipStream_t s, double *t, const double *dt, long *nsteps, int nm);
 
 // kernel entry points (stage.hip: k_stage and its launcher; kernels.hip: the rest)
-template <int BI, int BJ, int BK, int W, int LIM> __global__ void k_stage(KArgs a);
-template <int BI, int BJ, int BK> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter);
-template <int BI, int BJ, int BK, int LIM> __global__ void k_hancock(KArgs a);
-template <int BI, int BJ, int BK> __global__ void k_divb(KArgs a);
-template <int BI, int BJ, int BK> __global__ void k_clean(KArgs a);
-template <int BI, int BJ, int BK> void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter);
-template <int BI, int BJ, int BK, int PASS> __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
-template <int BI, int BJ, int BK> __global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
-template <int BI, int BJ, int BK> __global__ void k_rate(KArgs a);
-template <int BI, int BJ, int BK>
-__global__ void k_indicator(KArgs a, int8_t *flags, int max_level, double eps, double tol_r,
-                            double tol_c, double w_rho, double w_v, int use_windows, double lon_e,
-                            double clt_e, double dlon_e, double dclt_e, double dlon_c);
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV, int W, int LIM> __global__ void k_stage(KArgs a);
+template <int BI, int BJ, int BK, int NV> void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter);
+template <int BI, int BJ, int BK, int NV, int LIM> __global__ void k_hancock(KArgs a);
+template <int BI, int BJ, int BK, int NV> __global__ void k_divb(KArgs a);
+template <int BI, int BJ, int BK, int NV> __global__ void k_clean(KArgs a);
+template <int BI, int BJ, int BK, int NV> void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter);
+template <int BI, int BJ, int BK, int NV, int PASS>
+__global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
+template <int BI, int BJ, int BK, int NV>
+__global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
+template <int BI, int BJ, int BK, int NV> __global__ void k_rate(KArgs a);
+template <int BI, int BJ, int BK, int NV>
+__global__ void k_indicator(KArgs a, int8_t *flags, IndicatorParams p);
+template <int BI, int BJ, int BK, int NV>
 __global__ void k_move(KArgs a, double *Unew, const MoveTask *tasks, int ntasks);
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
                          int *ring_count, int ring_cap, int record, double *t_step, long *nsteps);
 

@@ -13,8 +13,9 @@
 // children along each direction.  A coarse cell whose linear values would
 // give any child rho <= 0 or p <= 0 hands its own value to all of them
 // (conservative either way).  value(o, v): child o = ox + 2 oy + 4 oz.
+template <int NV>
 struct Prolong {
-    double uc[8], sl[3][8], off[3][2];
+    double uc[NV], sl[3][NV], off[3][2];
     bool ok;
     DEV double linear(int o, int v) const
     {
@@ -27,15 +28,15 @@ struct Prolong {
     DEV double value(int o, int v) const { return ok ? linear(o, v) : uc[v]; }
 };
 
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3], const LevelGeo &cg,
-                       const LevelGeo &lg, const int g0[3], Prolong &P)
+                       const LevelGeo &lg, const int g0[3], Prolong<NV> &P)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
     const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
+    for (int v = 0; v < NV; ++v) {
         P.uc[v] = ghosted<S>(a.U, a.desc, a.slabs, a.slab_stride, src, v, cl[0], cl[1], cl[2]);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
@@ -73,10 +74,10 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // that every per-direction index below is a register, not private memory).
 // Slab layout: element ((v * 2 + l) * FB + b) * FA + a, layer l = 0 nearest
 // the low side.  sP, sOk: LDS for the prolongation's per-parent values.
-template <int BI, int BJ, int BK, int D, int PASS>
+template <int BI, int BJ, int BK, int NV, int D, int PASS>
 DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     constexpr int E1 = tan1(D), E2 = tan2(D);
     constexpr int FA = S::dim(E1), FB = S::dim(E2), Bd = S::dim(D);
     constexpr int NCELL = 2 * FA * FB;
@@ -94,7 +95,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
         const int cwrap[3] = {tkp->cwrap[0], tkp->cwrap[1], tkp->cwrap[2]};
         // (1) per parent and variable: coarse value and minmod slopes along r, theta, phi
-        for (int t = threadIdx.x; t < NP * 8; t += blockDim.x) {
+        for (int t = threadIdx.x; t < NP * NV; t += blockDim.x) {
             const int c = t % NP, v = t / NP;
             int g0[3];
             g0[D] = g0d;
@@ -110,7 +111,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
             const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
             const double uc = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, cl[0], cl[1], cl[2]);
-            double *P = sP + (c * 8 + v) * 4;
+            double *P = sP + (c * NV + v) * 4;
             P[0] = uc;
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
@@ -133,7 +134,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             const double off[3][2] = {{lg.r[g0[0] + 2].poff, lg.r[g0[0] + 3].poff},
                                       {lg.t[g0[1] + 2].poff, lg.t[g0[1] + 3].poff},
                                       {lg.p[g0[2] + 2].poff, lg.p[g0[2] + 3].poff}};
-            const double *P = sP + c * 32;
+            const double *P = sP + c * 4 * NV;
             bool ok = true;
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
@@ -155,10 +156,10 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         __syncthreads();
         // (3) the slab element by element (coalesced); a failing parent hands
         // its own value to its children
-        for (int e = threadIdx.x; e < 8 * NCELL; e += blockDim.x) {
+        for (int e = threadIdx.x; e < NV * NCELL; e += blockDim.x) {
             const int ia = e % FA, ib = (e / FA) % FB, l = (e / (FA * FB)) & 1, v = e / NCELL;
             const int c = (ia >> 1) + HA * (ib >> 1);
-            const double *P = sP + (c * 8 + v) * 4;
+            const double *P = sP + (c * NV + v) * 4;
             double x = P[0];
             if (sOk[c]) {
                 int g[3];
@@ -186,7 +187,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             const int nt = lg.n[1], np = lg.n[2];
             const size_t o = (size_t)jt * np + kp;
             const size_t pl = (size_t)nt * np;
-            double w[8], u[8];
+            double w[NV], u[NV];
             w[0] = lg.wind[0 * pl + o];
             w[1] = lg.wind[1 * pl + o];
             w[2] = 0.0;
@@ -195,6 +196,7 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             w[5] = lg.wind[4 * pl + o];
             w[6] = 0.0;
             w[7] = lg.wind[5 * pl + o];
+            if constexpr (NV > 8) w[8] = 0.0;         // tracer: wind material
             const int mem = bd.member;
             const MemberConst mc = a.mc[mem];
             if (mc.enabled) {
@@ -211,22 +213,25 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
                         w[0] = mc.rho;
                         w[1] = mc.v;
                         w[4] = mc.p;
+                        if constexpr (NV > 8) w[8] = 1.0;     // CME material
                     }
                 }
             }
-            prim_to_cons(w, u, gs);
+            prim_to_cons<NV>(w, u, gs);
 #pragma unroll
-            for (int v = 0; v < 8; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
+            for (int v = 0; v < NV; ++v) out[((size_t)(v * 2 + l) * FB + ib) * FA + ia] = u[v];
         }
         return;
     }
-    // SLAB_RESTRICT: one thread per ghost cell and half of the variables (32
-    // independent loads each, issued together)
+    // SLAB_RESTRICT: one thread per ghost cell and group of VG variables (the
+    // variables in NG groups; 8 VG independent loads each, issued together)
+    constexpr int NG = NV % 4 == 0 ? 2 : 3, VG = NV / NG;
+    static_assert(NG * VG == NV, "variable groups of the restriction");
     const LevelGeo fg = a.geo[bd.level + 1];
     const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
     const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
     const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
-    for (int e = threadIdx.x; e < 2 * NCELL; e += blockDim.x) {
+    for (int e = threadIdx.x; e < NG * NCELL; e += blockDim.x) {
         const int c = e % NCELL, h = e / NCELL;
         const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
         int gw[3];                                  // owner-level global index, wrapped
@@ -237,7 +242,9 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         const double wr[2] = {fg.r[2 * gw[0] + 2].vw, fg.r[2 * gw[0] + 3].vw};
         const double wt[2] = {fg.t[2 * gw[1] + 2].vw, fg.t[2 * gw[1] + 3].vw};
         const double wp[2] = {fg.p[2 * gw[2] + 2].vw, fg.p[2 * gw[2] + 3].vw};
-        double num[4] = {0, 0, 0, 0}, den = 0.0;
+        double num[VG], den = 0.0;
+#pragma unroll
+        for (int v = 0; v < VG; ++v) num[v] = 0.0;
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             int fl[3], q[3];
@@ -252,38 +259,38 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             const int fslot = qq == 0 ? src0 : (qq == 1 ? src1 : (qq == 2 ? src2 : src3));
             const double wgt = wr[o & 1] * wt[(o >> 1) & 1] * wp[(o >> 2) & 1];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) num[v] += wgt * a.U[cidx<S>(fslot, 4 * h + v, fl[0], fl[1], fl[2])];
+            for (int v = 0; v < VG; ++v) num[v] += wgt * a.U[cidx<S>(fslot, VG * h + v, fl[0], fl[1], fl[2])];
             den += wgt;
         }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[((size_t)((4 * h + v) * 2 + l) * FB + ib) * FA + ia] = num[v] / den;
+        for (int v = 0; v < VG; ++v) out[((size_t)((VG * h + v) * 2 + l) * FB + ib) * FA + ia] = num[v] / den;
     }
 }
 
 // PASS 0: inner-boundary and restriction slabs; PASS 1: prolongation slabs
 // (separate kernels, so that each is compiled for its own register needs)
-template <int BI, int BJ, int BK, int PASS>
+template <int BI, int BJ, int BK, int NV, int PASS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 4 : 1)))
 k_slabs(KArgs a, const SlabTask *tasks, const int *range)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     constexpr int NPL = PASS == 1 ? S::MAXFACE / 4 : 1;
-    __shared__ double sP[NPL * 32];
+    __shared__ double sP[NPL * 4 * NV];
     __shared__ int sOk[NPL];
     const int t0 = range[0], t1 = range[1];
     for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
         const int d = tasks[it].face >> 1;          // uniform over the work-group
-        if (d == 0) slab_task<BI, BJ, BK, 0, PASS>(a, tasks + it, sP, sOk);
-        else if (d == 1) slab_task<BI, BJ, BK, 1, PASS>(a, tasks + it, sP, sOk);
-        else slab_task<BI, BJ, BK, 2, PASS>(a, tasks + it, sP, sOk);
+        if (d == 0) slab_task<BI, BJ, BK, NV, 0, PASS>(a, tasks + it, sP, sOk);
+        else if (d == 1) slab_task<BI, BJ, BK, NV, 1, PASS>(a, tasks + it, sP, sOk);
+        else slab_task<BI, BJ, BK, NV, 2, PASS>(a, tasks + it, sP, sOk);
     }
 }
 
 // ---------------------------------------------------------------------------
 // reflux at coarse-fine faces, then the CFL rates of the corrected cells
 // ---------------------------------------------------------------------------
-template <int BI, int BJ, int BK>
-__device__ inline double cell_rate(const double u[8], const RecR &rr, const RecT &tt, const RecP &pp, const Gas &gs)
+// (the 8 MHD variables of u are read)
+__device__ inline double cell_rate(const double *u, const RecR &rr, const RecT &tt, const RecP &pp, const Gas &gs)
 {
     double w[8];
     cons_to_prim(u, w, gs);
@@ -296,11 +303,11 @@ __device__ inline double cell_rate(const double u[8], const RecR &rr, const RecT
 // template parameter: every per-direction index stays in registers): for each
 // cell behind the face, U += +-adt (A_c F_c - sum of the 4 fine A F) / V_c,
 // the fine faces summed in fixed order.
-template <int BI, int BJ, int BK, int D>
+template <int BI, int BJ, int BK, int NV, int D>
 DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd, const LevelGeo &lg,
                      const LevelGeo &fg, int slot, double adt)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     constexpr int E1 = tan1(D), E2 = tan2(D);
     constexpr int FA = S::dim(E1), FB = S::dim(E2);
     const int side = tkp->face & 1;
@@ -324,7 +331,9 @@ DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd,
         else if (D == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
         else ac = rr.rt * tt.phf * pp.iw;
         const int gf = 2 * (bd.org[D] + (side ? S::dim(D) : 0));   // fine face index along D
-        double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double sum[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sum[v] = 0.0;
 #pragma unroll
         for (int ob = 0; ob < 2; ++ob) {
 #pragma unroll
@@ -344,11 +353,11 @@ DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd,
                 const double *F = a.freg + (size_t)reg * a.reg_stride;
                 const int la = fa - qa * FA, lb = fb - qb * FB;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
+                for (int v = 0; v < NV; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
             }
         }
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
+        for (int v = 0; v < NV; ++v) {
             const double corr = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
             const size_t o = cidx<S>(slot, v, loc[0], loc[1], loc[2]);
             a.Uout[o] += side ? adt * corr : -adt * corr;
@@ -356,10 +365,10 @@ DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd,
     }
 }
 
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     __shared__ double sred[NT / 64];
     const int nb = *nblocks;
     for (int it = blockIdx.x; it < nb; it += gridDim.x) {
@@ -372,9 +381,9 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
         const LevelGeo lg = a.geo[bd.level], fg = a.geo[bd.level + 1];
         for (int q = t0; q < t1; ++q) {
             const int d = tasks[q].face >> 1;          // uniform over the work-group
-            if (d == 0) reflux_face<BI, BJ, BK, 0>(a, tasks + q, bd, lg, fg, slot, adt);
-            else if (d == 1) reflux_face<BI, BJ, BK, 1>(a, tasks + q, bd, lg, fg, slot, adt);
-            else reflux_face<BI, BJ, BK, 2>(a, tasks + q, bd, lg, fg, slot, adt);
+            if (d == 0) reflux_face<BI, BJ, BK, NV, 0>(a, tasks + q, bd, lg, fg, slot, adt);
+            else if (d == 1) reflux_face<BI, BJ, BK, NV, 1>(a, tasks + q, bd, lg, fg, slot, adt);
+            else reflux_face<BI, BJ, BK, NV, 2>(a, tasks + q, bd, lg, fg, slot, adt);
             __syncthreads();
         }
         // floors on the corrected cells and their CFL rates (the stage kernel took
@@ -399,17 +408,17 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
                 if (x == ((f & 1) ? S::dim(dd) - 1 : 0)) first = false;
             }
             if (!first) continue;
-            double u[8];
-            for (int v = 0; v < 8; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
+            double u[NV];
+            for (int v = 0; v < NV; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
             const int f = apply_floors(u, a.gas, a.rho_floor, a.p_floor);
             nfr += f & 1;
             nfp += f >> 1;
-            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];
+            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];   // the floors leave rho s
             if (a.want_rate) {
-                double w[8];
-                cons_to_prim(u, w, a.gas);
-                if (badc < 0 && unphysical(w)) badc = i + BI * (j + BJ * k);
-                const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
+                double w[NV];
+                cons_to_prim<false, NV>(u, w, a.gas);
+                if (badc < 0 && unphysical<NV>(w)) badc = i + BI * (j + BJ * k);
+                const double r = cell_rate(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
                                                        lg.p[bd.org[2] + k + 2], a.gas);
                 rmax = r > rmax ? r : rmax;
             }
@@ -440,18 +449,18 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
 // at most in the ghost layers).  Floors and the input check as in k_stage.
 // ---------------------------------------------------------------------------
 template <class S>
-DEV void prim_at(const KArgs &a, int slot, const Faces &nb, int i, int j, int k, double w[8])
+DEV void prim_at(const KArgs &a, int slot, const Faces &nb, int i, int j, int k, double *w)
 {
-    double u[8];
+    double u[S::NV];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) u[v] = *cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, i, j, k);
-    cons_to_prim(u, w, a.gas);
+    for (int v = 0; v < S::NV; ++v) u[v] = *cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, i, j, k);
+    cons_to_prim<false, S::NV>(u, w, a.gas);
 }
 
-template <int BI, int BJ, int BK, int LIM>
+template <int BI, int BJ, int BK, int NV, int LIM>
 __global__ void __launch_bounds__(NT) k_hancock(KArgs a)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     const int n = *a.nitems;
     const Gas gs = a.gas;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -466,55 +475,55 @@ __global__ void __launch_bounds__(NT) k_hancock(KArgs a)
         int badc = -1, nfr = 0, nfp = 0;
         for (int c = threadIdx.x; c < S::NC; c += NT) {
             const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
-            double w0[8], acc[8];
+            double w0[NV], acc[NV];
             prim_at<S>(a, slot, nb, i, j, k, w0);
-            if (badc < 0 && unphysical(w0)) badc = c;
+            if (badc < 0 && unphysical<NV>(w0)) badc = c;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) acc[v] = 0.0;
+            for (int v = 0; v < NV; ++v) acc[v] = 0.0;
             const RecR rr = lg.r[o0 + i + 2];
             const RecT tt = lg.t[o1 + j + 2];
             const RecP pk = lg.p[o2 + k + 2];
             {   // r
-                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                double wm[NV], wp[NV], lo[NV], hi[NV], fl[NV], fh[NV];
                 prim_at<S>(a, slot, nb, i - 1, j, k, wm);
                 prim_at<S>(a, slot, nb, i + 1, j, k, wp);
-                reconstruct<LIM>(wm, w0, wp, rr.idm, rr.idp, rr.idc, rr.hm, rr.hp, lo, hi);
-                phys_flux<0>(lo, fl, gs);
-                phys_flux<0>(hi, fh, gs);
+                reconstruct<LIM, NV>(wm, w0, wp, rr.idm, rr.idp, rr.idc, rr.hm, rr.hp, lo, hi);
+                phys_flux<0, NV>(lo, fl, gs);
+                phys_flux<0, NV>(hi, fh, gs);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) acc[v] -= rr.ap * fh[v] - rr.am * fl[v];
+                for (int v = 0; v < NV; ++v) acc[v] -= rr.ap * fh[v] - rr.am * fl[v];
             }
             {   // theta
-                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                double wm[NV], wp[NV], lo[NV], hi[NV], fl[NV], fh[NV];
                 prim_at<S>(a, slot, nb, i, j - 1, k, wm);
                 prim_at<S>(a, slot, nb, i, j + 1, k, wp);
-                reconstruct<LIM>(wm, w0, wp, tt.idm, tt.idp, tt.idc, tt.hm, tt.hp, lo, hi);
-                phys_flux<1>(lo, fl, gs);
-                phys_flux<1>(hi, fh, gs);
+                reconstruct<LIM, NV>(wm, w0, wp, tt.idm, tt.idp, tt.idc, tt.hm, tt.hp, lo, hi);
+                phys_flux<1, NV>(lo, fl, gs);
+                phys_flux<1, NV>(hi, fh, gs);
                 const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) acc[v] -= thp * fh[v] - thm * fl[v];
+                for (int v = 0; v < NV; ++v) acc[v] -= thp * fh[v] - thm * fl[v];
             }
             {   // phi
-                double wm[8], wp[8], lo[8], hi[8], fl[8], fh[8];
+                double wm[NV], wp[NV], lo[NV], hi[NV], fl[NV], fh[NV];
                 prim_at<S>(a, slot, nb, i, j, k - 1, wm);
                 prim_at<S>(a, slot, nb, i, j, k + 1, wp);
-                reconstruct<LIM>(wm, w0, wp, pk.idm, pk.idp, pk.idc, pk.hm, pk.hp, lo, hi);
-                phys_flux<2>(lo, fl, gs);
-                phys_flux<2>(hi, fh, gs);
+                reconstruct<LIM, NV>(wm, w0, wp, pk.idm, pk.idp, pk.idc, pk.hm, pk.hp, lo, hi);
+                phys_flux<2, NV>(lo, fl, gs);
+                phys_flux<2, NV>(hi, fh, gs);
                 const double kf = rr.rt * tt.phf * pk.iw;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) acc[v] -= kf * fh[v] - kf * fl[v];
+                for (int v = 0; v < NV; ++v) acc[v] -= kf * fh[v] - kf * fl[v];
             }
             if (!a.cart) add_sources(w0, rr.rt, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
-            double unew[8];
+            double unew[NV];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) unew[v] = a.Ubase[cidx<S>(slot, v, i, j, k)] + adt * acc[v];
+            for (int v = 0; v < NV; ++v) unew[v] = a.Ubase[cidx<S>(slot, v, i, j, k)] + adt * acc[v];
             const int f = apply_floors(unew, gs, a.rho_floor, a.p_floor);
             nfr += f & 1;
             nfp += f >> 1;
 #pragma unroll
-            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = unew[v];
+            for (int v = 0; v < NV; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = unew[v];
         }
         if (badc >= 0 && atomicCAS(&a.bad[2 * mem], 0, slot + 1) == 0) a.bad[2 * mem + 1] = badc;
         if (nfr | nfp) {
@@ -524,12 +533,18 @@ __global__ void __launch_bounds__(NT) k_hancock(KArgs a)
     }
 }
 
-template <int BI, int BJ, int BK>
+// the tracer (NV = 9) with the paper's limiter only
+template <int BI, int BJ, int BK, int NV>
 void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter)
 {
-    if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_MINMOD>), g, dim3(NT), 0, s, a);
-    else if (limiter == LIM_VANLEER) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_VANLEER>), g, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, LIM_MC>), g, dim3(NT), 0, s, a);
+    if constexpr (NV > 8) {
+        hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MC>), g, dim3(NT), 0, s, a);
+    } else {
+        if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+        else if (limiter == LIM_VANLEER)
+            hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MC>), g, dim3(NT), 0, s, a);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -543,10 +558,10 @@ void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter)
 // gradient component is zero.  In the second stage k_clean also takes the
 // output check and the CFL maxima (the stage and reflux kernels leave them).
 // ---------------------------------------------------------------------------
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void __launch_bounds__(NT) k_divb(KArgs a)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     const int n = *a.nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
         const int slot = a.items[it];
@@ -577,10 +592,10 @@ __global__ void __launch_bounds__(NT) k_divb(KArgs a)
     }
 }
 
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void __launch_bounds__(NT) k_clean(KArgs a)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     __shared__ double sred[NT / 64];
     const int n = *a.nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -628,9 +643,9 @@ __global__ void __launch_bounds__(NT) k_clean(KArgs a)
             const double h2 = 1.0 / (ix * ix + iy * iy + iz * iz);
             const double ch = coef * h2;
             const size_t base = cidx<S>(slot, 0, i, j, k);
-            double u[8];
+            double u[NV];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) u[v] = a.Uout[base + (size_t)v * S::NC];
+            for (int v = 0; v < NV; ++v) u[v] = a.Uout[base + (size_t)v * S::NC];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const double db = ch * g[d];
@@ -641,10 +656,10 @@ __global__ void __launch_bounds__(NT) k_clean(KArgs a)
 #pragma unroll
             for (int d = 0; d < 3; ++d) a.Uout[base + (size_t)(5 + d) * S::NC] = u[5 + d];
             if (a.want_rate) {
-                double w[8];
-                cons_to_prim(u, w, a.gas);
-                if (badc < 0 && unphysical(w)) badc = c;
-                const double r = cell_rate<BI, BJ, BK>(u, rr, tt, pk, a.gas);
+                double w[NV];
+                cons_to_prim<false, NV>(u, w, a.gas);
+                if (badc < 0 && unphysical<NV>(w)) badc = c;
+                const double r = cell_rate(u, rr, tt, pk, a.gas);
                 rmax = r > rmax ? r : rmax;
             }
         }
@@ -657,10 +672,10 @@ __global__ void __launch_bounds__(NT) k_clean(KArgs a)
 }
 
 // CFL rate of every leaf (after create, set_state, regrid)
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void __launch_bounds__(NT) k_rate(KArgs a)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     __shared__ double sred[NT / 64];
     const int n = *a.nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -671,11 +686,11 @@ __global__ void __launch_bounds__(NT) k_rate(KArgs a)
         int bad = -1;
         for (int c = threadIdx.x; c < S::NC; c += blockDim.x) {
             const int i = c % BI, j = (c / BI) % BJ, k = c / (BI * BJ);
-            double u[8], w[8];
-            for (int v = 0; v < 8; ++v) u[v] = a.U[cidx<S>(slot, v, i, j, k)];
-            cons_to_prim(u, w, a.gas);
-            if (bad < 0 && unphysical(w)) bad = c;
-            const double r = cell_rate<BI, BJ, BK>(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
+            double u[NV], w[NV];
+            for (int v = 0; v < NV; ++v) u[v] = a.U[cidx<S>(slot, v, i, j, k)];
+            cons_to_prim<false, NV>(u, w, a.gas);
+            if (bad < 0 && unphysical<NV>(w)) bad = c;
+            const double r = cell_rate(u, lg.r[bd.org[0] + i + 2], lg.t[bd.org[1] + j + 2],
                                                    lg.p[bd.org[2] + k + 2], a.gas);
             rmax = r > rmax ? r : rmax;
         }
@@ -734,15 +749,18 @@ __global__ void k_time(double *t, const double *dt, long *nsteps, int nmembers)
 
 // ---------------------------------------------------------------------------
 // refinement indicator: Loehner(rho, |v|) with div V < 0 inside the windows
+// (shock criterion); the tracer fraction s = (rho s) / rho above a threshold
+// anywhere (tracer criterion); or either inside the windows (combined)
 // ---------------------------------------------------------------------------
 #pragma clang fp contract(off)
-template <int BI, int BJ, int BK>
-__global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int max_level, double eps,
-                                                  double tol_r, double tol_c, double w_rho, double w_v,
-                                                  int use_windows, double lon_e, double clt_e,
-                                                  double dlon_e, double dclt_e, double dlon_c)
+template <int BI, int BJ, int BK, int NV>
+__global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, IndicatorParams p)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
+    const int max_level = p.max_level, use_windows = p.use_windows;
+    const double eps = p.eps, tol_r = p.tol_r, tol_c = p.tol_c, w_rho = p.w_rho, w_v = p.w_v;
+    const double lon_e = p.lon_e, clt_e = p.clt_e, dlon_e = p.dlon_e, dclt_e = p.dclt_e, dlon_c = p.dlon_c;
+    const int crit = NV > 8 ? p.criterion : CRIT_SHOCK;
     const int n = *a.nitems;
     const double PI = 3.14159265358979323846;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -774,6 +792,15 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
             double u[8], w0[8];
             cell8(ijk[0], ijk[1], ijk[2], u);
             cons_to_prim<true>(u, w0, a.gas);
+            // tracer condition on the correctly rounded fraction (rho s) / rho
+            bool tr_r = false, tr_c = false;
+            if constexpr (NV > 8) {
+                if (crit != CRIT_SHOCK) {
+                    const double sf = *cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, 8, ijk[0], ijk[1], ijk[2]) / u[0];
+                    tr_r = sf > p.tr_r;
+                    tr_c = sf > p.tr_c;
+                }
+            }
             const double r0 = w0[0];
             const double s0 = sqrt(w0[1] * w0[1] + w0[2] * w0[2] + w0[3] * w0[3]);
             double num_r = 0, den_r = 0, num_v = 0, den_v = 0, dv = 0;
@@ -807,9 +834,18 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
             }
             const double E = w_rho * (den_r > 0.0 ? sqrt(num_r / den_r) : 0.0)
                            + w_v * (den_v > 0.0 ? sqrt(num_v / den_v) : 0.0);
-            if (win && dv < 0.0) {
-                if (E > tol_r) hot_r = 1;
-                if (E > tol_c) hot_c = 1;
+            if (crit == CRIT_TRACER) {
+                if (tr_r) hot_r = 1;
+                if (tr_c) hot_c = 1;
+            } else {
+                if (win && dv < 0.0) {
+                    if (E > tol_r) hot_r = 1;
+                    if (E > tol_c) hot_c = 1;
+                }
+                if (crit == CRIT_COMBINED && win) {
+                    if (tr_r) hot_r = 1;
+                    if (tr_c) hot_c = 1;
+                }
             }
         }
         hot_r = __syncthreads_or(hot_r);
@@ -827,10 +863,10 @@ __global__ void __launch_bounds__(NT) k_indicator(KArgs a, int8_t *flags, int ma
 // ---------------------------------------------------------------------------
 // regrid data movement: prolong new children, restrict new parents
 // ---------------------------------------------------------------------------
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTask *tasks, int ntasks)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     for (int it = blockIdx.x; it < ntasks; it += gridDim.x) {
         const MoveTask tk = tasks[it];
         const LevelGeo lg = a.geo[tk.level];
@@ -848,11 +884,11 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
                     cw[e] = g0[e] >> 1;
                     cl[e] = cw[e] - pd.org[e];
                 }
-                Prolong P;
-                prolong_setup<BI, BJ, BK>(a, ps, cl, cw, cg, lg, g0, P);
+                Prolong<NV> P;
+                prolong_setup<BI, BJ, BK, NV>(a, ps, cl, cw, cg, lg, g0, P);
                 for (int o = 0; o < 8; ++o) {
                     const int li = 2 * h[0] + (o & 1), lj = 2 * h[1] + ((o >> 1) & 1), lk = 2 * h[2] + ((o >> 2) & 1);
-                    for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, li, lj, lk)] = P.value(o, v);
+                    for (int v = 0; v < NV; ++v) Unew[cidx<S>(tk.dst, v, li, lj, lk)] = P.value(o, v);
                 }
             }
             continue;
@@ -863,7 +899,8 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
             for (int e = 0; e < 3; ++e) g[e] = tk.org[e] + loc[e];
             {
                 const LevelGeo fg = a.geo[tk.level + 1];
-                double num[8] = {0, 0, 0, 0, 0, 0, 0, 0}, den = 0.0;
+                double num[NV], den = 0.0;
+                for (int v = 0; v < NV; ++v) num[v] = 0.0;
                 for (int o = 0; o < 8; ++o) {
                     const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
                     int fl[3], oct = 0, fgi[3];
@@ -875,10 +912,10 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
                         fgi[e] = 2 * g[e] + oo[e];
                     }
                     const double wgt = fg.r[fgi[0] + 2].vw * fg.t[fgi[1] + 2].vw * fg.p[fgi[2] + 2].vw;
-                    for (int v = 0; v < 8; ++v) num[v] += wgt * a.U[cidx<S>(tk.src[oct], v, fl[0], fl[1], fl[2])];
+                    for (int v = 0; v < NV; ++v) num[v] += wgt * a.U[cidx<S>(tk.src[oct], v, fl[0], fl[1], fl[2])];
                     den += wgt;
                 }
-                for (int v = 0; v < 8; ++v) Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = num[v] / den;
+                for (int v = 0; v < NV; ++v) Unew[cidx<S>(tk.dst, v, loc[0], loc[1], loc[2])] = num[v] / den;
             }
         }
     }
@@ -887,13 +924,14 @@ __global__ void __launch_bounds__(NT) k_move(KArgs a, double *Unew, const MoveTa
 // ---------------------------------------------------------------------------
 // point sampling (trilinear between cell centres), one work-group per member;
 // with t_step set it first ends the step (t += dt, step count + 1, for a
-// member with dt > 0), so that the sample carries the new time
+// member with dt > 0), so that the sample carries the new time; the 8 MHD
+// primitives are sampled
 // ---------------------------------------------------------------------------
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *out, double *ring,
                          int *ring_count, int ring_cap, int record, double *t_step, long *nsteps)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     __shared__ double sw[8][9];                 // per stencil entry: primitives, then its weight
     const int m = blockIdx.x;
     if (m >= nmembers) return;
@@ -943,68 +981,78 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
 // ---------------------------------------------------------------------------
 // instantiations for the supported block shapes
 // ---------------------------------------------------------------------------
-#define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
-    template __global__ void k_slabs<BI, BJ, BK, 0>(KArgs, const SlabTask *, const int *);         \
-    template __global__ void k_slabs<BI, BJ, BK, 1>(KArgs, const SlabTask *, const int *);         \
-    template __global__ void k_reflux<BI, BJ, BK>(KArgs, const RefluxTask *, const int *, const int *); \
-    template __global__ void k_rate<BI, BJ, BK>(KArgs);                                            \
-    template __global__ void k_divb<BI, BJ, BK>(KArgs);                                            \
-    template __global__ void k_clean<BI, BJ, BK>(KArgs);                                           \
-    template __global__ void k_indicator<BI, BJ, BK>(KArgs, int8_t *, int, double, double, double, \
-                                                     double, double, int, double, double, double,  \
-                                                     double, double);                              \
-    template __global__ void k_move<BI, BJ, BK>(KArgs, double *, const MoveTask *, int);           \
-    template __global__ void k_sample<BI, BJ, BK>(KArgs, const SampleDesc *, int, double *, double *, \
-                                                  int *, int, int, double *, long *);
+#define IC_INSTANTIATE_NV(BI, BJ, BK, NV)                                                           \
+    template __global__ void k_slabs<BI, BJ, BK, NV, 0>(KArgs, const SlabTask *, const int *);     \
+    template __global__ void k_slabs<BI, BJ, BK, NV, 1>(KArgs, const SlabTask *, const int *);     \
+    template __global__ void k_reflux<BI, BJ, BK, NV>(KArgs, const RefluxTask *, const int *, const int *); \
+    template __global__ void k_rate<BI, BJ, BK, NV>(KArgs);                                        \
+    template __global__ void k_divb<BI, BJ, BK, NV>(KArgs);                                        \
+    template __global__ void k_clean<BI, BJ, BK, NV>(KArgs);                                       \
+    template __global__ void k_indicator<BI, BJ, BK, NV>(KArgs, int8_t *, IndicatorParams);        \
+    template __global__ void k_move<BI, BJ, BK, NV>(KArgs, double *, const MoveTask *, int);       \
+    template __global__ void k_sample<BI, BJ, BK, NV>(KArgs, const SampleDesc *, int, double *, double *, \
+                                                      int *, int, int, double *, long *);
+#define IC_INSTANTIATE(BI, BJ, BK) IC_INSTANTIATE_NV(BI, BJ, BK, 8) IC_INSTANTIATE_NV(BI, BJ, BK, 9)
 
 #include "shapes.inc"
 #undef IC_INSTANTIATE
+#undef IC_INSTANTIATE_NV
 
 // ---------------------------------------------------------------------------
 // launchers (kernels are launched from this translation unit)
 // ---------------------------------------------------------------------------
 namespace {
-template <int BI, int BJ, int BK>
+template <int BI, int BJ, int BK, int NV>
 struct L {
     static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r, int pass)
     {
-        if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, 0>), g, dim3(NT), 0, s, a, t, r);
-        else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, 1>), g, dim3(NT), 0, s, a, t, r);
+        if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 0>), g, dim3(NT), 0, s, a, t, r);
+        else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 1>), g, dim3(NT), 0, s, a, t, r);
     }
     static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *b, const int *n)
     {
-        hipLaunchKernelGGL((k_reflux<BI, BJ, BK>), g, dim3(NT), 0, s, a, t, b, n);
+        hipLaunchKernelGGL((k_reflux<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a, t, b, n);
     }
-    static void rate(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_rate<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
-    static void divb(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_divb<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
-    static void clean(dim3 g, hipStream_t s, const KArgs &a) { hipLaunchKernelGGL((k_clean<BI, BJ, BK>), g, dim3(NT), 0, s, a); }
+    static void rate(dim3 g, hipStream_t s, const KArgs &a)
+    {
+        hipLaunchKernelGGL((k_rate<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a);
+    }
+    static void divb(dim3 g, hipStream_t s, const KArgs &a)
+    {
+        hipLaunchKernelGGL((k_divb<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a);
+    }
+    static void clean(dim3 g, hipStream_t s, const KArgs &a)
+    {
+        hipLaunchKernelGGL((k_clean<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a);
+    }
     static void indicator(dim3 g, hipStream_t s, const KArgs &a, int8_t *f, const IndicatorParams &p)
     {
-        hipLaunchKernelGGL((k_indicator<BI, BJ, BK>), g, dim3(NT), 0, s, a, f, p.max_level, p.eps, p.tol_r,
-                           p.tol_c, p.w_rho, p.w_v, p.use_windows, p.lon_e, p.clt_e, p.dlon_e, p.dclt_e,
-                           p.dlon_c);
+        hipLaunchKernelGGL((k_indicator<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a, f, p);
     }
     static void move(dim3 g, hipStream_t s, const KArgs &a, double *Un, const MoveTask *t, int n)
     {
-        hipLaunchKernelGGL((k_move<BI, BJ, BK>), g, dim3(NT), 0, s, a, Un, t, n);
+        hipLaunchKernelGGL((k_move<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a, Un, t, n);
     }
     static void sample(dim3 g, hipStream_t s, const KArgs &a, const SampleDesc *sd, int nm, double *out,
                        double *ring, int *cnt, int cap, int rec, double *t_step, long *nsteps)
     {
-        hipLaunchKernelGGL((k_sample<BI, BJ, BK>), g, dim3(64), 0, s, a, sd, nm, out, ring, cnt, cap, rec, t_step,
-                           nsteps);
+        hipLaunchKernelGGL((k_sample<BI, BJ, BK, NV>), g, dim3(64), 0, s, a, sd, nm, out, ring, cnt, cap, rec,
+                           t_step, nsteps);
+    }
+    static Launchers get()
+    {
+        return Launchers{&launch_stage<BI, BJ, BK, NV>, &launch_hancock<BI, BJ, BK, NV>, &divb, &clean, &slabs,
+                         &reflux, &rate, &indicator, &move, &sample};
     }
 };
 }  // namespace
 
-bool get_launchers(int bi, int bj, int bk, Launchers *out)
+bool get_launchers(int bi, int bj, int bk, int nv, Launchers *out)
 {
+    if (nv != 8 && nv != 9) return false;
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
     if (bi == BI && bj == BJ && bk == BK) {                                                        \
-        *out = Launchers{&launch_stage<BI, BJ, BK>, &launch_hancock<BI, BJ, BK>, &L<BI, BJ, BK>::divb,  \
-                         &L<BI, BJ, BK>::clean, &L<BI, BJ, BK>::slabs, &L<BI, BJ, BK>::reflux,       \
-                         &L<BI, BJ, BK>::rate, &L<BI, BJ, BK>::indicator, &L<BI, BJ, BK>::move,    \
-                         &L<BI, BJ, BK>::sample};                                                  \
+        *out = nv == 8 ? L<BI, BJ, BK, 8>::get() : L<BI, BJ, BK, 9>::get();                         \
         return true;                                                                               \
     }
 #include "shapes.inc"

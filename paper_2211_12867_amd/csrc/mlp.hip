@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(256) k_features(KArgs a, const int *items, con
                     for (int i = pi * PI; i < (pi + 1) * PI; ++i) {
                         double u[8], w[8];
                         for (int v = 0; v < 8; ++v)
-                            u[v] = a.U[(size_t)slot * 8 * S::NC + (size_t)v * S::NC + i + BI * (j + BJ * k)];
+                            u[v] = a.U[((size_t)slot * a.nv + v) * S::NC + i + BI * (j + BJ * k)];
                         cons_to_prim<true>(u, w, a.gas);
                         for (int v = 0; v < 8; ++v) sum[v] += w[v];
                     }

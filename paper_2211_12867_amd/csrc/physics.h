@@ -2,6 +2,8 @@
 //
 // Variables: conserved u = (rho, m0, m1, m2, E, B0, B1, B2), primitive
 // w = (rho, v0, v1, v2, p, B0, B1, B2), mu0 = 1, E = p/(g-1) + rho v^2/2 + B^2/2.
+// NV = 9 adds the CME density tracer: conserved rho s, primitive s (the CME
+// mass fraction), advected with the flow by the same flux (no source).
 // Direction 0/1/2 = r/theta/phi (x/y/z in the cartesian test geometry).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -51,9 +53,11 @@ struct Gas {
 };
 
 // EXACT: IEEE division (the refinement indicator and the network features,
-// whose threshold decisions are kept on the correctly rounded quotient)
-template <bool EXACT = false>
-DEV void cons_to_prim(const double u[8], double w[8], const Gas &gs)
+// whose threshold decisions are kept on the correctly rounded quotient).  The
+// tracer fraction s = (rho s) / rho is always the correctly rounded quotient,
+// so that s = 1 where rho s = rho.
+template <bool EXACT = false, int NV = 8>
+DEV void cons_to_prim(const double *u, double *w, const Gas &gs)
 {
     const double ir = EXACT ? 1.0 / u[0] : IC_RCP(u[0]);
     w[0] = u[0];
@@ -66,9 +70,11 @@ DEV void cons_to_prim(const double u[8], double w[8], const Gas &gs)
     w[5] = u[5];
     w[6] = u[6];
     w[7] = u[7];
+    if constexpr (NV > 8) w[8] = u[8] / u[0];
 }
 
-DEV void prim_to_cons(const double w[8], double u[8], const Gas &gs)
+template <int NV = 8>
+DEV void prim_to_cons(const double *w, double *u, const Gas &gs)
 {
     const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
     const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
@@ -80,6 +86,7 @@ DEV void prim_to_cons(const double w[8], double u[8], const Gas &gs)
     u[5] = w[5];
     u[6] = w[6];
     u[7] = w[7];
+    if constexpr (NV > 8) u[8] = w[0] * w[8];
 }
 
 // Fast magnetosonic speed along direction D.
@@ -96,18 +103,20 @@ DEV double fast_speed(const double w[8], const Gas &gs)
     return IC_SQRT(0.5 * (a + IC_SQRT(disc)));
 }
 
-DEV bool unphysical(const double w[8])
+template <int NV = 8>
+DEV bool unphysical(const double *w)
 {
     // rho <= 0, p <= 0 or NaN (comparisons with NaN are false)
     bool ok = (w[0] > 0.0) && (w[4] > 0.0);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) ok = ok && (fabs(w[v]) <= 1.7976931348623157e308);
+    for (int v = 0; v < NV; ++v) ok = ok && (fabs(w[v]) <= 1.7976931348623157e308);
     return !ok;
 }
 
-// Local Lax-Friedrichs (Rusanov) flux along D between left state wl and right state wr.
-template <int D>
-DEV void rusanov(const double wl[8], const double wr[8], double f[8], const Gas &gs)
+// Local Lax-Friedrichs (Rusanov) flux along D between left state wl and right
+// state wr; with the tracer, its flux rho v_n s takes the same maximum speed.
+template <int D, int NV = 8>
+DEV void rusanov(const double *wl, const double *wr, double *f, const Gas &gs)
 {
     const double vl2 = wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3];
     const double vr2 = wr[1] * wr[1] + wr[2] * wr[2] + wr[3] * wr[3];
@@ -158,12 +167,14 @@ DEV void rusanov(const double wl[8], const double wr[8], double f[8], const Gas 
         }
         f[5 + q] = 0.5 * (fl + fr) - hc * (wr[5 + q] - wl[5 + q]);
     }
+    if constexpr (NV > 8) f[8] = 0.5 * (ml * wl[8] + mr * wr[8]) - hc * (wr[0] * wr[8] - wl[0] * wl[8]);
 }
 
 // Physical ideal-MHD flux of a primitive state along D: rho v_n, rho v_n v -
-// B_n B + p_tot e_n, (E + p_tot) v_n - B_n (v.B), v_n B - B_n v (B_n part 0).
-template <int D>
-DEV void phys_flux(const double w[8], double f[8], const Gas &gs)
+// B_n B + p_tot e_n, (E + p_tot) v_n - B_n (v.B), v_n B - B_n v (B_n part 0),
+// and rho v_n s for the tracer.
+template <int D, int NV = 8>
+DEV void phys_flux(const double *w, double *f, const Gas &gs)
 {
     const double v2 = w[1] * w[1] + w[2] * w[2] + w[3] * w[3];
     const double b2 = w[5] * w[5] + w[6] * w[6] + w[7] * w[7];
@@ -179,6 +190,7 @@ DEV void phys_flux(const double w[8], double f[8], const Gas &gs)
         f[5 + q] = q == D ? 0.0 : vn * w[5 + q] - bn * w[1 + q];
     }
     f[4] = (E + pt) * vn - bn * vb;
+    if constexpr (NV > 8) f[8] = m * w[8];
 }
 
 // Monotonised-central slope on a non-uniform coordinate (reciprocal spacings given).
@@ -211,18 +223,18 @@ DEV double limited_slope(double wm, double w0, double wp, double idm, double idp
 
 // Face values of a cell from its neighbours along one direction; falls back to
 // zero slope for all variables if a face density or pressure is not positive.
-template <int LIM = LIM_MC>
-DEV void reconstruct(const double wm[8], const double w0[8], const double wp[8], double idm,
-                     double idp, double idc, double hm, double hp, double lo[8], double hi[8])
+template <int LIM = LIM_MC, int NV = 8>
+DEV void reconstruct(const double *wm, const double *w0, const double *wp, double idm,
+                     double idp, double idc, double hm, double hp, double *lo, double *hi)
 {
-    double s[8];
+    double s[NV];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) s[v] = limited_slope<LIM>(wm[v], w0[v], wp[v], idm, idp, idc);
+    for (int v = 0; v < NV; ++v) s[v] = limited_slope<LIM>(wm[v], w0[v], wp[v], idm, idp, idc);
     // the density and pressure face values decide; a zero slope gives w0 - 0 * h = w0 exactly
     const bool ok = w0[0] - s[0] * hm > 0.0 && w0[0] + s[0] * hp > 0.0 && w0[4] - s[4] * hm > 0.0 &&
                     w0[4] + s[4] * hp > 0.0;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
+    for (int v = 0; v < NV; ++v) {
         const double sv = ok ? s[v] : 0.0;
         lo[v] = w0[v] - sv * hm;
         hi[v] = w0[v] + sv * hp;
@@ -250,8 +262,9 @@ DEV void add_sources(const double w[8], double rt, double ctil, double rc, doubl
 }
 
 // Small-value floors on a conserved state: density first (a cell below the
-// density floor takes it at zero velocity), then pressure (energy raised).
-// Returns which floors acted: bit 0 density, bit 1 pressure.
+// density floor takes it at zero velocity), then pressure (energy raised); the
+// tracer's rho s is left as it is.  Returns which floors acted: bit 0
+// density, bit 1 pressure.
 DEV int apply_floors(double u[8], const Gas &gs, double rho_min, double p_min)
 {
     int fired = 0;

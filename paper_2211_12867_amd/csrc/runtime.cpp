@@ -269,6 +269,7 @@ struct ic_sim {
     int nm = 1;
     int B[3] = {0, 0, 0};
     int NC = 0;
+    int nv = 8;                     // conserved variables per cell: 8, or 9 with the tracer
     int nb[3] = {0, 0, 0};         // base blocks per direction
     int max_blocks = 0;
     int max_level = 1;
@@ -987,6 +988,7 @@ KArgs base_args(ic_sim *s)
     a.ksplit = s->tune_ksplit;
     a.divb = s->divb.p;
     a.divb_cd = s->phys.divb_cd;
+    a.nv = s->nv;
     return a;
 }
 
@@ -1419,7 +1421,7 @@ std::string describe_bad(ic_sim *s, int m, int slot, int cell)
     const size_t nc = (size_t)s->B[0] * s->B[1] * s->B[2];
     double u[8];
     for (int v = 0; v < 8; ++v)
-        if (hipMemcpy(&u[v], s->U.p + (size_t)slot * 8 * nc + v * nc + cell, sizeof(double), hipMemcpyDeviceToHost) !=
+        if (hipMemcpy(&u[v], s->U.p + ((size_t)slot * s->nv + v) * nc + cell, sizeof(double), hipMemcpyDeviceToHost) !=
             hipSuccess)
             return out;
     std::snprintf(buf, sizeof buf, "; U = (%.4g, %.4g, %.4g, %.4g, %.4g, %.4g, %.4g, %.4g)", u[0], u[1], u[2], u[3],
@@ -1581,7 +1583,7 @@ void regrid_member(ic_sim *s, int m, const FlatMap &flags_in, int buffer_blocks,
 // plain criterion on the current state (ghosts must be filled) into fl, per
 // pool slot; level_cap = s->max_level gives the block flags, a huge cap gives
 // REFINE wherever a cell meets the refinement condition whatever the level
-void run_indicator(ic_sim *s, std::vector<int8_t> &fl, int level_cap)
+void run_indicator(ic_sim *s, std::vector<int8_t> &fl, int level_cap, int criterion)
 {
     KArgs a = base_args(s);
     a.U = s->U.p;
@@ -1599,12 +1601,15 @@ void run_indicator(ic_sim *s, std::vector<int8_t> &fl, int level_cap)
     p.dlon_e = s->amr.dlon_earth_deg * deg;
     p.dclt_e = s->amr.dclt_earth_deg * deg;
     p.dlon_c = s->amr.dlon_cme_deg * deg;
+    p.criterion = criterion;
+    p.tr_r = s->amr.tracer_refine;
+    p.tr_c = s->amr.tracer_coarsen;
     s->L.indicator(dim3(grid_for(s->n_items, 16384)), s->stream, a, s->flags.p, p);
     HIPCHECK(hipMemcpyAsync(fl.data(), s->flags.p, fl.size(), hipMemcpyDeviceToHost, s->stream));
     HIPCHECK(hipStreamSynchronize(s->stream));
 }
 
-void plain_flags(ic_sim *s, std::vector<int8_t> &fl) { run_indicator(s, fl, s->max_level); }
+void plain_flags(ic_sim *s, std::vector<int8_t> &fl) { run_indicator(s, fl, s->max_level, s->amr.criterion); }
 
 // network probabilities of every leaf in work-list order into s->mlp.prob
 void learned_prob(ic_sim *s)
@@ -1780,7 +1785,7 @@ ic_status guard(ic_sim *s, F &&f)
 void set_initial_state(ic_sim *s)
 {
     // relaxation start: rho ~ r^-2, v_r const, p ~ r^-2g, B_r ~ r^-2, v_phi = -omega r sin(theta)
-    std::vector<double> h((size_t)s->NC * 8);
+    std::vector<double> h((size_t)s->NC * s->nv);    // a tracer starts at 0 (no CME material)
     for (int m = 0; m < s->nm; ++m) {
         for (auto &kv : s->mem[m].leaves) {
             const Key &key = kv.first;
@@ -1816,7 +1821,7 @@ void set_initial_state(ic_sim *s)
                             h[(size_t)v * s->NC + i + s->B[0] * (j + s->B[1] * k)] = u[v];
                     }
             const int slot = s->slot_of(m, kv.second);
-            HIPCHECK(hipMemcpy(s->U.p + (size_t)slot * 8 * s->NC, h.data(), h.size() * sizeof(double),
+            HIPCHECK(hipMemcpy(s->U.p + (size_t)slot * s->nv * s->NC, h.data(), h.size() * sizeof(double),
                                hipMemcpyHostToDevice));
         }
     }
@@ -1900,7 +1905,7 @@ int ic_pool_capacity(const ic_sim *s) { return s ? s->max_blocks : 0; }
 int ic_block_supported(int bi, int bj, int bk)
 {
     Launchers L;
-    return get_launchers(bi, bj, bk, &L) ? 1 : 0;
+    return get_launchers(bi, bj, bk, 8, &L) ? 1 : 0;
 }
 
 ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_wind_cfg *wind,
@@ -1920,6 +1925,20 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
             throw Error(IC_E_INVALID, "unknown time scheme");
         if (!(phys->divb_cd >= 0.0 && phys->divb_cd <= 1.0))
             throw Error(IC_E_INVALID, "the cleaning coefficient divb_cd must lie in [0, 1]");
+        if (phys->tracer != 0 && phys->tracer != 1) throw Error(IC_E_INVALID, "tracer must be 0 or 1");
+        if (phys->tracer && phys->limiter != IC_LIM_MC)
+            throw Error(IC_E_INVALID, "the tracer is built with the IC_LIM_MC limiter only");
+        if (amr) {
+            if (amr->criterion < IC_CRIT_SHOCK || amr->criterion > IC_CRIT_COMBINED)
+                throw Error(IC_E_INVALID, "unknown refinement criterion");
+            if (amr->criterion != IC_CRIT_SHOCK && !phys->tracer)
+                throw Error(IC_E_INVALID, "the tracer and combined criteria need phys->tracer = 1");
+            if (amr->criterion != IC_CRIT_SHOCK &&
+                !(amr->tracer_refine >= amr->tracer_coarsen && amr->tracer_coarsen >= 0.0))
+                throw Error(IC_E_INVALID, "tracer thresholds need tracer_refine >= tracer_coarsen >= 0");
+            if (amr->criterion != IC_CRIT_SHOCK && amr->source != IC_SOURCE_PLAIN)
+                throw Error(IC_E_INVALID, "learned flags predict the shock criterion only");
+        }
         s = new ic_sim();
         s->grid = *grid;
         s->phys = *phys;
@@ -1951,7 +1970,8 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
             if (!(grid->x1[d] > grid->x0[d])) throw Error(IC_E_INVALID, "empty domain");
         }
         if (!s->cart && grid->x0[0] <= 0.0) throw Error(IC_E_INVALID, "r_in must be positive");
-        if (!get_launchers(s->B[0], s->B[1], s->B[2], &s->L))
+        s->nv = phys->tracer ? 9 : 8;
+        if (!get_launchers(s->B[0], s->B[1], s->B[2], s->nv, &s->L))
             throw Error(IC_E_INVALID, "block shape not built into the library");
         s->NC = s->B[0] * s->B[1] * s->B[2];
         s->r_in = s->cart ? 0.0 : grid->x0[0];
@@ -2007,8 +2027,8 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         HIPCHECK(hipMemcpy(s->mc.p, mc.data(), s->nm * sizeof(MemberConst), hipMemcpyHostToDevice));
         // pools
         const size_t NS = (size_t)s->nm * s->max_blocks;
-        s->U.alloc(NS * 8 * s->NC);
-        s->Us.alloc(NS * 8 * s->NC);
+        s->U.alloc(NS * s->nv * s->NC);
+        s->Us.alloc(NS * s->nv * s->NC);
         if (s->phys.divb_cd > 0.0) s->divb.alloc(NS * s->NC);
         s->desc.alloc(NS);
         s->items.alloc(NS);
@@ -2031,8 +2051,8 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         s->ring.alloc((size_t)s->nm * s->ring_cap * 9);
         s->ring_count.alloc(s->nm);
         int maxface = std::max(s->B[0] * s->B[1], std::max(s->B[0] * s->B[2], s->B[1] * s->B[2]));
-        s->slab_stride = 16L * maxface;
-        s->reg_stride = 8L * maxface;
+        s->slab_stride = 2L * s->nv * maxface;
+        s->reg_stride = (long)s->nv * maxface;
         std::vector<double> zeros(s->nm, 0.0), big(s->nm, 1e300);
         HIPCHECK(hipMemcpy(s->t.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
         HIPCHECK(hipMemcpy(s->dt.p, zeros.data(), s->nm * sizeof(double), hipMemcpyHostToDevice));
@@ -2242,7 +2262,8 @@ void leaf_indicator(ic_sim *s, int member, int8_t *out, int n, int level_cap, bo
     if (n < (int)M.leaves.size()) throw Error(IC_E_INVALID, "flag buffer too small");
     fill_ghosts(s, s->U.p, 0.0);
     std::vector<int8_t> fl((size_t)s->nm * s->max_blocks);
-    run_indicator(s, fl, level_cap);
+    // the look-ahead labels (hot) are the shock criterion's refinement condition
+    run_indicator(s, fl, level_cap, hot ? CRIT_SHOCK : s->amr.criterion);
     const std::vector<Key> keys = abi_sorted(M.leaves);
     for (size_t q = 0; q < keys.size(); ++q) {
         const int8_t f = fl[s->slot_of(member, M.leaves[keys[q]])];
@@ -2366,7 +2387,7 @@ ic_status ic_get_state(ic_sim *s, int member, double *host_U, size_t n_doubles)
         if (member < 0 || member >= s->nm || !host_U) throw Error(IC_E_INVALID, "bad argument");
         Member &M = s->mem[member];
         const std::vector<Key> keys = abi_sorted(M.leaves);
-        const size_t per = (size_t)8 * s->NC;
+        const size_t per = (size_t)s->nv * s->NC;
         if (n_doubles < keys.size() * per) throw Error(IC_E_INVALID, "state buffer too small");
         HIPCHECK(hipStreamSynchronize(s->stream));
         for (size_t q = 0; q < keys.size(); ++q) {
@@ -2411,7 +2432,7 @@ ic_status ic_set_state(ic_sim *s, int member, const int32_t *lvl_ijk, int n_bloc
         M.leaves.clear();
         M.free_slots.clear();
         for (int q = s->max_blocks - 1; q >= 0; --q) M.free_slots.push_back(q);
-        const size_t per = (size_t)8 * s->NC;
+        const size_t per = (size_t)s->nv * s->NC;
         HIPCHECK(hipStreamSynchronize(s->stream));
         for (int q = 0; q < n_blocks; ++q) {
             Key k{lvl_ijk[4 * q], lvl_ijk[4 * q + 1], lvl_ijk[4 * q + 2], lvl_ijk[4 * q + 3]};
@@ -2641,6 +2662,8 @@ ic_status ic_mlp_infer_noalloc(const float *raw_dev, long n, const float *params
                                const float *std_dev, float *prob_dev, void *hip_stream)
 {
     static_assert(IC_MLP_NOALLOC_ROWS == 4096, "the header's row limit");
+    static_assert(CRIT_SHOCK == IC_CRIT_SHOCK && CRIT_TRACER == IC_CRIT_TRACER && CRIT_COMBINED == IC_CRIT_COMBINED,
+                  "criterion codes of the header and the kernels");
     return guard(nullptr, [&]() {
         if (!raw_dev || !params_dev || !mean_dev || !std_dev || !prob_dev || n < 0)
             throw Error(IC_E_INVALID, "bad argument");

@@ -46,11 +46,11 @@ DEV void halo_cell(int t, int &i, int &j)
 
 // Conserved state of the column (ci, cj) in k-plane k (possibly a ghost plane).
 template <class S>
-DEV void column8(const KArgs &a, int slot, const Faces &nb, int ci, int cj, int k, double u[8])
+DEV void column_u(const KArgs &a, int slot, const Faces &nb, int ci, int cj, int k, double *u)
 {
     const int off = ci + S::B0 * cj;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) u[v] = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, 0, 0, k)[off];
+    for (int v = 0; v < S::NV; ++v) u[v] = cell_addr<S>(a.U, a.slabs, a.slab_stride, slot, nb, v, 0, 0, k)[off];
 }
 
 // Halo cells of one r- or theta-face of a block (d = 0 or 1): the cell of
@@ -73,7 +73,7 @@ DEV FaceMap face_map(const KArgs &a, int slot, const Faces &nb, int d, int side)
         const int blk = code >= 0 ? code : slot;
         const int i0 = code >= 0 ? (side ? 0 : Bd - 2) : (side ? Bd - 1 : 0);   // layer 0 along d
         const int sl = code >= 0 ? 1 : 0;
-        m.base = a.U + (size_t)blk * 8 * S::NC + (d == 0 ? i0 : S::B0 * i0);
+        m.base = a.U + (size_t)blk * S::NV * S::NC + (d == 0 ? i0 : S::B0 * i0);
         m.sl = d == 0 ? sl : S::B0 * sl;
         m.sa = d == 0 ? S::B0 : 1;
         m.sk = S::B0 * S::B1;
@@ -100,13 +100,14 @@ __device__ inline int xcd_item(int w, int n)
     return x * q + (x < rem ? x : rem) + pos;
 }
 
-// W: waves per SIMD the register allocation targets (a tuning choice); LIM:
-// the limiter of the reconstruction (LIM_MC, the paper's, by default).
-template <int BI, int BJ, int BK, int W, int LIM>
+// NV: conserved variables (8, or 9 with the tracer); W: waves per SIMD the
+// register allocation targets (a tuning choice); LIM: the limiter of the
+// reconstruction (LIM_MC, the paper's, by default).
+template <int BI, int BJ, int BK, int NV, int W, int LIM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W, W)))
 k_stage(KArgs a)
 {
-    using S = Shape<BI, BJ, BK>;
+    using S = Shape<BI, BJ, BK, NV>;
     constexpr int PI = BI + 4, PJ = BJ + 4;
     constexpr int NFI = (BI + 1) * BJ;
     constexpr int NFJ = BI * (BJ + 1);
@@ -116,25 +117,25 @@ k_stage(KArgs a)
     // the last wave (it owns no column) copies the next planes asynchronously into LDS
     constexpr int CWAVE = NT / 64 - 1;
     constexpr int NHR = 4 * BJ, NHT = 4 * BI;    // r-halo cells (first), theta-halo cells
-    constexpr int NHP = NHR * 8 * 2;             // r-halo: one 4-byte piece per lane, two per double
-    constexpr int NHQ = NHR / 2 * 8;             // r-halo between same-level blocks: one 16-byte piece (two layers) per lane
-    constexpr int NTP = NHT / 2 * 8;             // theta-halo rows: one 16-byte piece (two cells) per lane
-    constexpr int NCP = NCOL / 2 * 8;            // column plane: one 16-byte piece (two cells) per lane
+    constexpr int NHP = NHR * NV * 2;            // r-halo: one 4-byte piece per lane, two per double
+    constexpr int NHQ = NHR / 2 * NV;            // r-halo between same-level blocks: one 16-byte piece (two layers) per lane
+    constexpr int NTP = NHT / 2 * NV;            // theta-halo rows: one 16-byte piece (two cells) per lane
+    constexpr int NCP = NCOL / 2 * NV;           // column plane: one 16-byte piece (two cells) per lane
     static_assert(NCOL % 2 == 0 && BI % 2 == 0 && NCOL <= CWAVE * 64, "column plane copy layout");
 
-    __shared__ double sW[8][PJ][PI];
-    __shared__ __attribute__((aligned(16))) double sCol[8][NCOL];     // conserved column plane k+2
-    __shared__ __attribute__((aligned(16))) double sHalR[8][NHR];     // conserved r-halo of plane k+1
-    __shared__ __attribute__((aligned(16))) double sHalT[8][NHT];     // conserved theta-halo of plane k+1
+    __shared__ double sW[NV][PJ][PI];
+    __shared__ __attribute__((aligned(16))) double sCol[NV][NCOL];     // conserved column plane k+2
+    __shared__ __attribute__((aligned(16))) double sHalR[NV][NHR];     // conserved r-halo of plane k+1
+    __shared__ __attribute__((aligned(16))) double sHalT[NV][NHT];     // conserved theta-halo of plane k+1
     // per halo cell: address of variable 0 in plane 0 and the strides (doubles) per variable and plane
     __shared__ const double *sHB[NHALO];
     __shared__ int sHV[NHALO], sHK[NHALO];
-    __shared__ double sFi[8][BJ][BI + 1];
+    __shared__ double sFi[NV][BJ][BI + 1];
     // theta fluxes; rows padded so that the lanes of (d), which walk the rows,
     // spread over the LDS banks (a row of 16 doubles would map every second row
     // onto the same banks)
     constexpr int SJ = BI % 8 == 0 ? BI + 4 : BI;
-    __shared__ double sFj[8][BJ + 1][SJ];
+    __shared__ double sFj[NV][BJ + 1][SJ];
     __shared__ RecR sR[BI + 4];
     __shared__ RecT sT[BJ + 4];
     __shared__ RecP sP[BK + 4];
@@ -177,24 +178,24 @@ k_stage(KArgs a)
         // --- prologue: column primitives of planes k0 and k0+1, phi-face k0-1/2
         // registers carried along k: Wn = W(k+1), wL = face state of cell k at
         // k+1/2, Fm = flux at k-1/2; W(k) of the own column sits in LDS
-        double Wn[8], wL[8], Fm[8];
+        double Wn[NV], wL[NV], Fm[NV];
         int badc = -1;                           // first non-physical input (or stage-2 output) cell of this column
         int nfr = 0, nfp = 0;                    // cells of this column the density / pressure floor acted on
         if (col) {
-            double u[8], w0[8], w1[8], lo[8], hi[8], R0[8], Wc[8];
-            column8<S>(a, slot, nb, ci, cj, k0 - 2, u); cons_to_prim(u, w0, gs);
-            column8<S>(a, slot, nb, ci, cj, k0 - 1, u); cons_to_prim(u, w1, gs);
-            column8<S>(a, slot, nb, ci, cj, k0, u);     cons_to_prim(u, Wc, gs);
-            column8<S>(a, slot, nb, ci, cj, k0 + 1, u); cons_to_prim(u, Wn, gs);
+            double u[NV], w0[NV], w1[NV], lo[NV], hi[NV], R0[NV], Wc[NV];
+            column_u<S>(a, slot, nb, ci, cj, k0 - 2, u); cons_to_prim<false, NV>(u, w0, gs);
+            column_u<S>(a, slot, nb, ci, cj, k0 - 1, u); cons_to_prim<false, NV>(u, w1, gs);
+            column_u<S>(a, slot, nb, ci, cj, k0, u);     cons_to_prim<false, NV>(u, Wc, gs);
+            column_u<S>(a, slot, nb, ci, cj, k0 + 1, u); cons_to_prim<false, NV>(u, Wn, gs);
             const RecP pm1 = lg.p[bd.org[2] + k0 + 1], p0 = lg.p[bd.org[2] + k0 + 2];
-            reconstruct<LIM>(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
-            reconstruct<LIM>(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
-            rusanov<2>(hi, R0, Fm, gs);
+            reconstruct<LIM, NV>(w0, w1, Wc, pm1.idm, pm1.idp, pm1.idc, pm1.hm, pm1.hp, lo, hi);
+            reconstruct<LIM, NV>(w1, Wc, Wn, p0.idm, p0.idp, p0.idc, p0.hm, p0.hp, R0, wL);
+            rusanov<2, NV>(hi, R0, Fm, gs);
             const int r = k0 == 0 ? bd.freg[4] : -1;
             if (r >= 0)
-                for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
+                for (int v = 0; v < NV; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fm[v];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
+            for (int v = 0; v < NV; ++v) sW[v][cj + 2][ci + 2] = Wc[v];
         }
         // halos of plane k0 and the halo address table (a halo cell's address
         // is affine in v and in k within the block's k-range), by the threads
@@ -203,7 +204,7 @@ k_stage(KArgs a)
             constexpr int NSP = NT - NCOL, HIT = (NHALO + NSP - 1) / NSP;
             const FaceMap fm[4] = {face_map<S>(a, slot, nb, 0, 0), face_map<S>(a, slot, nb, 0, 1),
                                    face_map<S>(a, slot, nb, 1, 0), face_map<S>(a, slot, nb, 1, 1)};
-            double u[HIT][8];
+            double u[HIT][NV];
 #pragma unroll
             for (int h = 0; h < HIT; ++h) {
                 const int t = tid - NCOL + h * NSP;
@@ -225,7 +226,7 @@ k_stage(KArgs a)
                     sHV[t] = hv;
                     sHK[t] = hk;
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) u[h][v] = p0[v * hv + k0 * hk];
+                    for (int v = 0; v < NV; ++v) u[h][v] = p0[v * hv + k0 * hk];
                 }
             }
 #pragma unroll
@@ -234,18 +235,18 @@ k_stage(KArgs a)
                 if (t < NHALO) {
                     int i, j;
                     halo_cell<BI, BJ>(t, i, j);
-                    double w[8];
-                    cons_to_prim(u[h], w, gs);
+                    double w[NV];
+                    cons_to_prim<false, NV>(u[h], w, gs);
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w[v];
+                    for (int v = 0; v < NV; ++v) sW[v][j + 2][i + 2] = w[v];
                 }
             }
         }
         for (int c = tid; c < NCOL; c += NT) {
-            double u[8];
-            column8<S>(a, slot, nb, c % BI, c / BI, k0 + 2, u);
+            double u[NV];
+            column_u<S>(a, slot, nb, c % BI, c / BI, k0 + 2, u);
 #pragma unroll
-            for (int v = 0; v < 8; ++v) sCol[v][c] = u[v];
+            for (int v = 0; v < NV; ++v) sCol[v][c] = u[v];
         }
         double rmax = 0.0;
         __syncthreads();
@@ -263,33 +264,33 @@ k_stage(KArgs a)
                 const int lane = tid & 63, c = lane % RL - 1;
                 const int j = (tid >> 6) * RPW + lane / RL;
                 const bool act = lane < RPW * RL && j < BJ;
-                double lo[8], hi[8];
+                double lo[NV], hi[NV];
                 if (act) {
-                    double wm[8], w0[8], wp[8];
+                    double wm[NV], w0[NV], wp[NV];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
+                    for (int v = 0; v < NV; ++v) {
                         wm[v] = sW[v][j + 2][c + 1];
                         w0[v] = sW[v][j + 2][c + 2];
                         wp[v] = sW[v][j + 2][c + 3];
                     }
                     const RecR rc = sR[c + 2];
-                    reconstruct<LIM>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    reconstruct<LIM, NV>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
                     if (c < BI)
 #pragma unroll
-                        for (int v = 0; v < 8; ++v) sFi[v][j][c + 1] = hi[v];
+                        for (int v = 0; v < NV; ++v) sFi[v][j][c + 1] = hi[v];
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (act && c >= 0) {
-                    double L[8], fx[8];
+                    double L[NV], fx[NV];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) L[v] = sFi[v][j][c];
-                    rusanov<0>(L, lo, fx, gs);
+                    for (int v = 0; v < NV; ++v) L[v] = sFi[v][j][c];
+                    rusanov<0, NV>(L, lo, fx, gs);
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) sFi[v][j][c] = fx[v];
+                    for (int v = 0; v < NV; ++v) sFi[v][j][c] = fx[v];
                     if (c == 0 || c == BI) {      // raw flux at a coarse-fine face, for the reflux
                         const int r = c == 0 ? bd.freg[0] : bd.freg[1];
                         if (r >= 0)
-                            for (int v = 0; v < 8; ++v)
+                            for (int v = 0; v < NV; ++v)
                                 a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BJ + j] = fx[v];
                     }
                 }
@@ -302,33 +303,33 @@ k_stage(KArgs a)
                 const int lane = tid & 63, c = lane / CPW - 1;
                 const int i = (tid >> 6) * CPW + lane % CPW;
                 const bool act = lane < CPW * CL && i < BI;
-                double lo[8], hi[8];
+                double lo[NV], hi[NV];
                 if (act) {
-                    double wm[8], w0[8], wp[8];
+                    double wm[NV], w0[NV], wp[NV];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) {
+                    for (int v = 0; v < NV; ++v) {
                         wm[v] = sW[v][c + 1][i + 2];
                         w0[v] = sW[v][c + 2][i + 2];
                         wp[v] = sW[v][c + 3][i + 2];
                     }
                     const RecT rc = sT[c + 2];
-                    reconstruct<LIM>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
+                    reconstruct<LIM, NV>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
                     if (c < BJ)
 #pragma unroll
-                        for (int v = 0; v < 8; ++v) sFj[v][c + 1][i] = hi[v];
+                        for (int v = 0; v < NV; ++v) sFj[v][c + 1][i] = hi[v];
                 }
                 __builtin_amdgcn_wave_barrier();
                 if (act && c >= 0) {
-                    double L[8], fx[8];
+                    double L[NV], fx[NV];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) L[v] = sFj[v][c][i];
-                    rusanov<1>(L, lo, fx, gs);
+                    for (int v = 0; v < NV; ++v) L[v] = sFj[v][c][i];
+                    rusanov<1, NV>(L, lo, fx, gs);
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) sFj[v][c][i] = fx[v];
+                    for (int v = 0; v < NV; ++v) sFj[v][c][i] = fx[v];
                     if (c == 0 || c == BJ) {
                         const int r = c == 0 ? bd.freg[2] : bd.freg[3];
                         if (r >= 0)
-                            for (int v = 0; v < 8; ++v)
+                            for (int v = 0; v < NV; ++v)
                                 a.freg[(size_t)r * a.reg_stride + ((size_t)v * BK + k) * BI + i] = fx[v];
                     }
                 }
@@ -378,25 +379,25 @@ k_stage(KArgs a)
             }
 
             // (e) phi-face k+1/2 of the column: cells k (from LDS), k+1 and k+2
-            double Fp[8], Wnext[8];
+            double Fp[NV], Wnext[NV];
             if (col) {
-                double u[8], W2[8], lo1[8], w0[8];
+                double u[NV], W2[NV], lo1[NV], w0[NV];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) u[v] = sCol[v][tid];
-                cons_to_prim(u, W2, gs);
+                for (int v = 0; v < NV; ++v) u[v] = sCol[v][tid];
+                cons_to_prim<false, NV>(u, W2, gs);
 #pragma unroll
-                for (int v = 0; v < 8; ++v) w0[v] = sW[v][cj + 2][ci + 2];
+                for (int v = 0; v < NV; ++v) w0[v] = sW[v][cj + 2][ci + 2];
                 const RecP pk1 = sP[k + 3];
-                double hi1[8];
-                reconstruct<LIM>(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
-                rusanov<2>(wL, lo1, Fp, gs);
+                double hi1[NV];
+                reconstruct<LIM, NV>(w0, Wn, W2, pk1.idm, pk1.idp, pk1.idc, pk1.hm, pk1.hp, lo1, hi1);
+                rusanov<2, NV>(wL, lo1, Fp, gs);
                 if (k == BK - 1) {
                     const int r = bd.freg[5];
                     if (r >= 0)
-                        for (int v = 0; v < 8; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fp[v];
+                        for (int v = 0; v < NV; ++v) a.freg[(size_t)r * a.reg_stride + ((size_t)v * BJ + cj) * BI + ci] = Fp[v];
                 }
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
+                for (int v = 0; v < NV; ++v) {
                     wL[v] = hi1[v];
                     Wnext[v] = Wn[v];
                     Wn[v] = W2[v];
@@ -409,24 +410,24 @@ k_stage(KArgs a)
                 const RecP pk = sP[k + 2];
                 const RecR rr = sR[ci + 2];
                 const RecT tt = sT[cj + 2];
-                double w[8];
+                double w[NV];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) w[v] = sW[v][cj + 2][ci + 2];
-                if (badc < 0 && unphysical(w)) badc = ci + BI * (cj + BJ * k);
-                double acc[8];
+                for (int v = 0; v < NV; ++v) w[v] = sW[v][cj + 2][ci + 2];
+                if (badc < 0 && unphysical<NV>(w)) badc = ci + BI * (cj + BJ * k);
+                double acc[NV];
                 const double thm = rr.rt * tt.thm, thp = rr.rt * tt.thp;
                 const double kf = rr.rt * tt.phf * pk.iw;
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
+                for (int v = 0; v < NV; ++v) {
                     acc[v] = -(rr.ap * sFi[v][cj][ci + 1] - rr.am * sFi[v][cj][ci])
                              - (thp * sFj[v][cj + 1][ci] - thm * sFj[v][cj][ci])
                              - kf * (Fp[v] - Fm[v]);
                 }
                 if (!a.cart) add_sources(w, rr.rt, tt.ctil, rr.rc, tt.sinc, tt.cosc, a.omega, a.gm, acc);
                 const size_t base = cidx<S>(slot, 0, ci, cj, k);
-                double unew[8];
+                double unew[NV];
 #pragma unroll
-                for (int v = 0; v < 8; ++v) unew[v] = a.Ubase[base + (size_t)v * S::NC] + adt * acc[v];
+                for (int v = 0; v < NV; ++v) unew[v] = a.Ubase[base + (size_t)v * S::NC] + adt * acc[v];
                 // floors now, or after the reflux for cells on a coarse-fine face
                 const int mk = bd.reflux_mask;
                 const bool rf = (ci == 0 && (mk & 1)) || (ci == BI - 1 && (mk & 2)) || (cj == 0 && (mk & 4))
@@ -437,19 +438,19 @@ k_stage(KArgs a)
                     nfp += f >> 1;
                 }
 #pragma unroll
-                for (int v = 0; v < 8; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
+                for (int v = 0; v < NV; ++v) a.Uout[base + (size_t)v * S::NC] = unew[v];
                 if (a.want_rate && !rf) {            // refluxed cells: after the reflux
-                    cons_to_prim(unew, w, gs);
+                    cons_to_prim<false, NV>(unew, w, gs);
                     // the step's result: a non-finite value created in this stage
                     // would otherwise drop out of the CFL maximum unnoticed
-                    if (badc < 0 && unphysical(w)) badc = ci + BI * (cj + BJ * k);
+                    if (badc < 0 && unphysical<NV>(w)) badc = ci + BI * (cj + BJ * k);
                     const double rate = (fabs(w[1]) + fast_speed<0>(w, gs)) * rr.icfl
                                       + (fabs(w[2]) + fast_speed<1>(w, gs)) * rr.irc * tt.icfl
                                       + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pk.iw;
                     rmax = rate > rmax ? rate : rmax;
                 }
 #pragma unroll
-                for (int v = 0; v < 8; ++v) {
+                for (int v = 0; v < NV; ++v) {
                     Fm[v] = Fp[v];
                     sW[v][cj + 2][ci + 2] = Wnext[v];   // own cell of plane k+1; read back in (e) and (g)
                 }
@@ -476,12 +477,12 @@ k_stage(KArgs a)
                 for (int t = lane; t < NHALO; t += 64) {
                     int i, j;
                     halo_cell<BI, BJ>(t, i, j);
-                    double u[8], w8[8];
+                    double u[NV], w8[NV];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) u[v] = t < NHR ? sHalR[v][t] : sHalT[v][t - NHR];
-                    cons_to_prim(u, w8, gs);
+                    for (int v = 0; v < NV; ++v) u[v] = t < NHR ? sHalR[v][t] : sHalT[v][t - NHR];
+                    cons_to_prim<false, NV>(u, w8, gs);
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) sW[v][j + 2][i + 2] = w8[v];
+                    for (int v = 0; v < NV; ++v) sW[v][j + 2][i + 2] = w8[v];
                 }
             }
             __syncthreads();
@@ -503,22 +504,31 @@ k_stage(KArgs a)
 // ---------------------------------------------------------------------------
 // instantiations and launch
 // ---------------------------------------------------------------------------
-// the other limiters are built for two waves per SIMD only
-template <int BI, int BJ, int BK>
+// the other limiters are built for two waves per SIMD only; the tracer (NV =
+// 9) with the paper's limiter and two waves per SIMD where two work-groups'
+// LDS fits a CU (one on planes of more than 160 cells)
+template <int BI, int BJ, int BK, int NV>
 void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter)
 {
-    if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_MINMOD>), g, dim3(NT), 0, s, a);
-    else if (limiter == LIM_VANLEER) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_VANLEER>), g, dim3(NT), 0, s, a);
-    else if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, 1, LIM_MC>), g, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_stage<BI, BJ, BK, 2, LIM_MC>), g, dim3(NT), 0, s, a);
+    if constexpr (NV > 8) {
+        constexpr int W9 = BI * BJ > 160 ? 1 : 2;
+        hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, W9, LIM_MC>), g, dim3(NT), 0, s, a);
+    } else {
+        if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, 2, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+        else if (limiter == LIM_VANLEER)
+            hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, 2, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+        else if (waves == 1) hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, 1, LIM_MC>), g, dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, 2, LIM_MC>), g, dim3(NT), 0, s, a);
+    }
 }
 
 #define IC_INSTANTIATE(BI, BJ, BK)                                                                  \
-    template __global__ void k_stage<BI, BJ, BK, 1, LIM_MC>(KArgs);                                \
-    template __global__ void k_stage<BI, BJ, BK, 2, LIM_MC>(KArgs);                                \
-    template __global__ void k_stage<BI, BJ, BK, 2, LIM_MINMOD>(KArgs);                            \
-    template __global__ void k_stage<BI, BJ, BK, 2, LIM_VANLEER>(KArgs);                           \
-    template void launch_stage<BI, BJ, BK>(dim3, hipStream_t, const KArgs &, int, int);
+    template __global__ void k_stage<BI, BJ, BK, 8, 1, LIM_MC>(KArgs);                             \
+    template __global__ void k_stage<BI, BJ, BK, 8, 2, LIM_MC>(KArgs);                             \
+    template __global__ void k_stage<BI, BJ, BK, 8, 2, LIM_MINMOD>(KArgs);                         \
+    template __global__ void k_stage<BI, BJ, BK, 8, 2, LIM_VANLEER>(KArgs);                        \
+    template void launch_stage<BI, BJ, BK, 8>(dim3, hipStream_t, const KArgs &, int, int);         \
+    template void launch_stage<BI, BJ, BK, 9>(dim3, hipStream_t, const KArgs &, int, int);
 
 #include "shapes.inc"
 #undef IC_INSTANTIATE

@@ -10,6 +10,7 @@ unless a name says hours or days.
     python -m paper_2211_12867_amd.forecast train  --out flags.npz ...
     python -m paper_2211_12867_amd.forecast compare --net flags.npz ...
     python -m paper_2211_12867_amd.forecast fig1 --out fig1.npz
+    python -m paper_2211_12867_amd.forecast tracer --out tracer.npz
 """
 import argparse
 import atexit
@@ -87,22 +88,29 @@ def _series_arrival(ts, t_cme_s, window_h=96.0):
     return t_h, v, d["arrival_h"], d["width_h"]
 
 
-def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4, log=print, max_blocks=0):
+def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4, log=print, max_blocks=0,
+            tracer=False):
     """From a relaxed state (relax's dict; None starts a plain equidistant run
     from the initial state and runs it through the relaxation too) advance to
     t_end_s with regrids at amr's cadence, recording the sample point every
-    step.  network = (params, mean, std) for the learned sources.  Returns
-    dict(arrival_h, width_h, wall_s, steps, leaf_block_steps, max_leaves,
-    regrid_stats, t_h, v_kms)."""
-    sim = Sim(grid, wind, [cme], amr, max_blocks=max_blocks)
+    step.  network = (params, mean, std) for the learned sources; tracer
+    carries the CME density tracer (a relaxed wind holds no CME material:
+    rho s = 0).  Returns dict(arrival_h, width_h, wall_s, steps,
+    leaf_block_steps, max_leaves, leaves_end, max_level, regrid_stats, t_h,
+    v_kms)."""
+    sim = Sim(grid, wind, [cme], amr, max_blocks=max_blocks, tracer=tracer)
     if start is not None:
-        sim.set_state(start["blocks"], start["U"], start["t_s"])
+        U = start["U"]
+        if tracer and U.shape[1] == 8:
+            U = np.concatenate([U, np.zeros_like(U[:, :1])], axis=1)
+        sim.set_state(start["blocks"], U, start["t_s"])
     if network is not None:
         sim.mlp_set(*network)
     sim.set_sample_point(*SAMPLE)
     cells = grid["block"][0] * grid["block"][1] * grid["block"][2]
     zu0 = 0.0
     max_leaves = len(sim.blocks())
+    max_level = 1
     ts = []
     t0 = time.perf_counter()
     info = None
@@ -112,6 +120,7 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
         ts.append(sim.timeseries())
         sim.timeseries_clear()
         max_leaves = max(max_leaves, info["leaves"])
+        max_level = max([max_level] + [l + 1 for l, c in enumerate(info["leaves_per_level"]) if c > 0])
         _log(log, "cme: t = %.2f d, %d steps, %d leaves %s, %.1f s"
              % (info["t_s"] / DAY, info["steps"], info["leaves"], info["leaves_per_level"][:6],
                 time.perf_counter() - t0))
@@ -122,6 +131,7 @@ def cme_run(grid, wind, cme, amr, start, t_end_s, network=None, chunk_s=DAY / 4,
     out = dict(arrival_h=a, width_h=w, peak_kms=diag["peak_kms"], gradient_kms_h=diag["gradient_kms_h"],
                wall_s=wall, steps=info["steps"] if info else 0,
                leaf_block_steps=((info["zone_updates"] if info else 0.0) - zu0) / cells, max_leaves=max_leaves,
+               leaves_end=info["leaves"] if info else max_leaves, max_level=max_level,
                regrid_stats=sim.regrid_stats(), t_h=t_h, v_kms=v)
     sim.close()
     return out
@@ -152,6 +162,41 @@ def stretching_comparison(relax_days=14.0, cme_days=3.0, log=print):
         else:
             r["dr_1au_rsun"] = 1.9 / n[0] * rsun
         out[name] = r
+    return out
+
+
+def tracer_comparison(relax_days=14.0, cme_days=3.0, max_level=3, log=print):
+    """CME-tracing refinement (paper Sect. 3.1) against unrefined grids and the
+    shock criterion (Sect. 3.2), on the stretched AMR workload's wind and CME:
+    its base grid and the grid twice as fine everywhere (each relaxed on
+    itself), and from the base grid's relaxed wind the tracer criterion
+    (refine where CME material is, s > tracer_refine) up to levels 2 and
+    max_level and the shock criterion up to max_level.  The paper finds the
+    tracer run of three levels arriving with the uniformly twice-finer grid
+    (the CME material at level 3 in level-2 surroundings): resolving the
+    material itself does not move the shock.  Returns {name: cme_run's
+    dict}."""
+    from synthetic import as_dict, workload
+    w = workload("stretched_amr")
+    grid = dict(as_dict(w.grid), max_level=1)
+    wind = as_dict(w.wind)
+    cme = dict(as_dict(w.cmes[0]), t_start_s=relax_days * DAY)
+    amr = as_dict(w.amr)
+    t_end = (relax_days + cme_days) * DAY
+    out = {}
+    fine = dict(grid, n=tuple(2 * x for x in grid["n"]))
+    for name, g in (("base", grid), ("uniform_x2", fine)):
+        _log(log, "== %s %s" % (name, g["n"]))
+        st = relax(g, wind, cme, relax_days * DAY, log=log)
+        out[name] = cme_run(g, wind, cme, dict(amr, regrid_every=0), st, t_end, log=log)
+        if name == "base":
+            start = st
+    runs = [("tracer_L2", 2, "tracer"), ("tracer_L%d" % max_level, max_level, "tracer"),
+            ("shock_L%d" % max_level, max_level, "shock")]
+    for name, lv, crit in runs:
+        _log(log, "== %s" % name)
+        out[name] = cme_run(dict(grid, max_level=lv), wind, cme, dict(amr, criterion=crit), start, t_end,
+                            log=log, tracer=crit != "shock")
     return out
 
 
@@ -292,6 +337,11 @@ def main(argv=None):
     f.add_argument("--relax-days", type=float, default=14.0)
     f.add_argument("--cme-days", type=float, default=3.0)
     f.add_argument("--out")
+    r = sub.add_parser("tracer", help="unrefined grids vs CME-tracer refinement vs shock refinement at Earth")
+    r.add_argument("--relax-days", type=float, default=14.0)
+    r.add_argument("--cme-days", type=float, default=3.0)
+    r.add_argument("--max-level", type=int, default=3)
+    r.add_argument("--out")
     e = sub.add_parser("ensemble", help="the 32-member cone-CME ensemble on the stretched 3-level grid")
     e.add_argument("--members", type=int, default=32)
     e.add_argument("--relax-days", type=float, default=14.0)
@@ -349,6 +399,17 @@ def main(argv=None):
     if args.cmd == "fig1":
         res = stretching_comparison(args.relax_days, args.cme_days, log=log)
         keys = ("arrival_h", "width_h", "peak_kms", "gradient_kms_h", "wall_s", "steps", "dr_1au_rsun")
+        summary = {k: {q: v[q] for q in keys} for k, v in res.items()}
+        log(json.dumps(summary))
+        if args.out:
+            np.savez(args.out, **{"%s_%s" % (k, q): res[k][q] for k in res for q in ("t_h", "v_kms")},
+                     summary=np.array(json.dumps(summary)))
+        return 0
+
+    if args.cmd == "tracer":
+        res = tracer_comparison(args.relax_days, args.cme_days, args.max_level, log=log)
+        keys = ("arrival_h", "width_h", "peak_kms", "gradient_kms_h", "wall_s", "steps", "leaf_block_steps",
+                "max_leaves", "leaves_end", "max_level")
         summary = {k: {q: v[q] for q in keys} for k, v in res.items()}
         log(json.dumps(summary))
         if args.out:

@@ -41,3 +41,20 @@ def test_product_path_does_not_reach_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h", ".inc")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.replace("# oracle", ""), f
+
+
+def test_tracer_configs_are_checked_before_any_device_work():
+    """ic_create rejects tracer settings it does not support with
+    IC_E_INVALID, before touching the device (so this runs without one)."""
+    import pytest
+    import paper_2211_12867_amd as ic
+    g = dict(geometry="cartesian", x0=(0.0, 0.0, 0.0), x1=(1.0, 1.0, 1.0), n=(8, 8, 8), block=(8, 8, 8),
+             periodic=(True, True, True), max_level=2, gamma=1.5, cfl=0.4)
+    for kw, amr in ((dict(), dict(criterion="tracer")),                       # criterion without the tracer
+                    (dict(tracer=True, limiter="minmod"), dict()),            # the tracer is built for MC only
+                    (dict(tracer=True), dict(criterion="combined", source=1)),  # learned flags: shock only
+                    (dict(tracer=True), dict(criterion="tracer", tracer_refine=0.001, tracer_coarsen=0.01)),
+                    (dict(tracer=True), dict(criterion=3))):
+        with pytest.raises(ic.ICError) as ex:
+            ic.Sim(g, amr=amr, **kw)
+        assert ex.value.status == ic.IC_E_INVALID, (kw, amr)
