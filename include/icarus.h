@@ -289,6 +289,18 @@ ic_status ic_set_state(ic_sim *sim, int member, const int32_t *lvl_ijk, int n_bl
 /* Time and last dt of a member [s]. */
 ic_status ic_get_time(ic_sim *sim, int member, double *t_s, double *dt_s);
 
+/* Checkpoint clock (the paper starts its CME runs from a saved relaxed wind,
+ * Sect. 2.1 and 3.1): the member's time in code units exactly as the library
+ * holds it, and the steps ic_advance has taken since the last regrid (one
+ * count per sim, shared by the members).  ic_set_state takes its time in
+ * seconds, and t * T0 does not always convert back to the same double; a
+ * restart that must continue bit for bit calls ic_set_clock after
+ * ic_set_state (which restarts the regrid count) with the values
+ * ic_get_clock gave at the checkpoint.  IC_E_INVALID for a non-finite time
+ * or a negative count.  Both synchronise the stream. */
+ic_status ic_get_clock(ic_sim *sim, int member, double *t_code, long *since_regrid);
+ic_status ic_set_clock(ic_sim *sim, int member, double t_code, long since_regrid);
+
 /* Small-value floors acted on (the paper's scheme is not positivity
  * preserving and it does not say how small values are treated; see
  * ic_phys_cfg): the number of cell updates of a member since ic_create at

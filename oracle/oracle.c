@@ -43,6 +43,7 @@
 #include <math.h>
 #include <stddef.h>
 #include <string.h>
+#include <stdlib.h>
 
 #define NV 8        /* MHD variables */
 #define NVMAX 9     /* with the CME density tracer rho s */
@@ -336,14 +337,29 @@ static void metric(const ora_patch *p, int d, int i, int j, int k, double *am, d
  *   L   interior output [v][k][j][i]
  *   F0  face fluxes along d=0, [v][k][j][i_face], i_face = 0..ni (face i_face is
  *       the lower face of cell i_face); F1: [v][k][j_face][i]; F2: [v][k_face][j][i].
- *       Any of F0/F1/F2 may be NULL.
- * Returns the number of interior cells with rho <= 0, p <= 0 or a non-finite value.
+ *       Any of F0/F1/F2 may be NULL (a temporary buffer is used then).
+ * Returns the number of interior cells with rho <= 0, p <= 0 or a non-finite value
+ * (-1 if a temporary buffer cannot be allocated).
  */
 int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *F1, double *F2)
 {
     const int ni = p->ni, nj = p->nj, nk = p->nk;
     const double gamma = p->gamma;
     int bad = 0;
+    /* the divergence below reads the face fluxes: a direction whose buffer
+     * the caller leaves out gets a temporary one */
+    double *own[3] = {NULL, NULL, NULL};
+    double **Fs[3] = {&F0, &F1, &F2};
+    for (int d = 0; d < 3; ++d)
+        if (!*Fs[d]) {
+            size_t n = (size_t)p->nv * (nk + (d == 2)) * (nj + (d == 1)) * (ni + (d == 0));
+            own[d] = (double *)malloc(n * sizeof(double));
+            if (!own[d]) {
+                for (int e = 0; e < d; ++e) free(own[e]);
+                return -1;
+            }
+            *Fs[d] = own[d];
+        }
 
     /* interface fluxes, per direction, stored [v][k][j][i] with the face
      * direction extended by one */
@@ -362,10 +378,8 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
                     reconstruct(p, U, d, c[d] - 1, a, b, lo_m, hi_m);
                     reconstruct(p, U, d, c[d], a, b, lo_p, hi_p);
                     rusanov_nv(p->nv, hi_m, lo_p, d, gamma, f);
-                    if (F) {
-                        for (int v = 0; v < p->nv; ++v)
-                            F[(((size_t)v * fn[2] + k) * fn[1] + j) * fn[0] + i] = f[v];
-                    }
+                    for (int v = 0; v < p->nv; ++v)
+                        F[(((size_t)v * fn[2] + k) * fn[1] + j) * fn[0] + i] = f[v];
                 }
             }
         }
@@ -415,6 +429,7 @@ int ora_rhs(const ora_patch *p, const double *U, double *L, double *F0, double *
             }
         }
     }
+    for (int d = 0; d < 3; ++d) free(own[d]);
     return bad;
 }
 

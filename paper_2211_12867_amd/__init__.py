@@ -116,7 +116,8 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_get_state", "ic_set_state", "ic_get_time", "ic_units", "ic_block_supported", "ic_set_kernel_timing",
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
-           "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_mlp_infer_noalloc", "ic_last_error")
+           "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_mlp_infer_noalloc", "ic_get_clock",
+           "ic_set_clock", "ic_last_error")
 
 
 def _load():
@@ -149,6 +150,8 @@ def _load():
                                ctypes.c_double]
     L.ic_get_time.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
     L.ic_floor_counts.argtypes = [vp, ctypes.c_int, P(ctypes.c_long), P(ctypes.c_long)]
+    L.ic_get_clock.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_long)]
+    L.ic_set_clock.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_long]
     dp = P(ctypes.c_double)
     L.ic_shock_diagnostics.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
     L.ic_units.argtypes = [P(ctypes.c_double)]
@@ -423,6 +426,25 @@ class Sim:
         t, dt = ctypes.c_double(), ctypes.c_double()
         _check(lib.ic_get_time(self.h, member, ctypes.byref(t), ctypes.byref(dt)))
         return t.value, dt.value
+
+    def clock(self, member=0):
+        """(time in code units, steps since the last regrid): the exact restart clock."""
+        t, n = ctypes.c_double(), ctypes.c_long()
+        _check(lib.ic_get_clock(self.h, member, ctypes.byref(t), ctypes.byref(n)))
+        return t.value, n.value
+
+    def set_clock(self, t_code, since_regrid, member=0):
+        _check(lib.ic_set_clock(self.h, member, float(t_code), int(since_regrid)))
+
+    def checkpoint(self, member=0):
+        """Everything a bit-exact restart of the member needs: blocks, state, clock."""
+        bl, U = self.state(member)
+        t_code, since = self.clock(member)
+        return dict(blocks=bl, U=U, t_code=t_code, since_regrid=since)
+
+    def restore(self, ck, member=0):
+        self.set_state(ck["blocks"], ck["U"], ck["t_code"] * units()["time_s"], member)
+        self.set_clock(ck["t_code"], ck["since_regrid"], member)
 
     def floor_counts(self, member=0):
         """(density-floored, pressure-floored) cell updates since creation."""

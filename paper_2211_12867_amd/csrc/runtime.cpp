@@ -2468,6 +2468,31 @@ ic_status ic_get_time(ic_sim *s, int member, double *t_s, double *dt_s)
     });
 }
 
+ic_status ic_get_clock(ic_sim *s, int member, double *t_code, long *since_regrid)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm) throw Error(IC_E_INVALID, "bad member");
+        double t = 0;
+        HIPCHECK(hipMemcpyAsync(&t, s->t.p + member, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        if (t_code) *t_code = t;
+        if (since_regrid) *since_regrid = s->since_regrid;
+    });
+}
+
+ic_status ic_set_clock(ic_sim *s, int member, double t_code, long since_regrid)
+{
+    return guard(s, [&]() {
+        check_sim(s);
+        if (member < 0 || member >= s->nm) throw Error(IC_E_INVALID, "bad member");
+        if (!std::isfinite(t_code) || since_regrid < 0) throw Error(IC_E_INVALID, "bad clock");
+        HIPCHECK(hipMemcpyAsync(s->t.p + member, &t_code, sizeof(double), hipMemcpyHostToDevice, s->stream));
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        s->since_regrid = since_regrid;
+    });
+}
+
 ic_status ic_floor_counts(ic_sim *s, int member, long *rho_floors, long *p_floors)
 {
     return guard(s, [&]() {
