@@ -1844,7 +1844,7 @@ std::string tune_prefix(const ic_sim *s)
     for (auto &c : arch)
         if (c == ' ') c = '_';
     return arch + "/cu" + std::to_string(prop.multiProcessorCount) + "/b" + std::to_string(s->B[0]) + "x" +
-           std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar8/items2^";
+           std::to_string(s->B[1]) + "x" + std::to_string(s->B[2]) + "/nvar" + std::to_string(s->nv) + "/items2^";
 }
 
 void apply_tuning(ic_sim *s, int waves, int grid, int xcd, int ksplit)

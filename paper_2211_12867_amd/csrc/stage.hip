@@ -89,6 +89,16 @@ DEV FaceMap face_map(const KArgs &a, int slot, const Faces &nb, int d, int side)
     return m;
 }
 
+// A radial metric record in LDS, padded from 16 to 17 doubles: the lanes of a
+// row read the records of consecutive cells, and at a 16-double stride every
+// second record falls on the same LDS banks (a 9-way conflict on each field
+// for a row of 18 lanes); at 17 the 32 lanes of a half-wave meet 32 distinct
+// bank pairs.
+struct RecRPad {
+    RecR r;
+    double pad;
+};
+
 // Work item of linear work index w when a.xcd_order is set: the work-groups
 // of a launch go round-robin to the 8 XCDs (w % 8), so the items are split
 // into 8 contiguous runs of the (Morton-ordered) work list, one per XCD, and
@@ -136,7 +146,7 @@ k_stage(KArgs a)
     // onto the same banks)
     constexpr int SJ = BI % 8 == 0 ? BI + 4 : BI;
     __shared__ double sFj[NV][BJ + 1][SJ];
-    __shared__ RecR sR[BI + 4];
+    __shared__ RecRPad sR[BI + 4];
     __shared__ RecT sT[BJ + 4];
     __shared__ RecP sP[BK + 4];
     __shared__ double sred[NT / 64];
@@ -170,7 +180,7 @@ k_stage(KArgs a)
         const double adt = a.alpha * dt;
 
         __syncthreads();
-        for (int m = tid; m < BI + 4; m += NT) sR[m] = lg.r[bd.org[0] + m];
+        for (int m = tid; m < BI + 4; m += NT) sR[m].r = lg.r[bd.org[0] + m];
         for (int m = tid; m < BJ + 4; m += NT) sT[m] = lg.t[bd.org[1] + m];
         for (int m = tid; m < BK + 4; m += NT) sP[m] = lg.p[bd.org[2] + m];
         // (the metric tables are read after the barrier that ends the prologue)
@@ -273,7 +283,7 @@ k_stage(KArgs a)
                         w0[v] = sW[v][j + 2][c + 2];
                         wp[v] = sW[v][j + 2][c + 3];
                     }
-                    const RecR rc = sR[c + 2];
+                    const RecR rc = sR[c + 2].r;
                     reconstruct<LIM, NV>(wm, w0, wp, rc.idm, rc.idp, rc.idc, rc.hm, rc.hp, lo, hi);
                     if (c < BI)
 #pragma unroll
@@ -408,7 +418,7 @@ k_stage(KArgs a)
             // (g) update of cell (ci, cj, k)
             if (col) {
                 const RecP pk = sP[k + 2];
-                const RecR rr = sR[ci + 2];
+                const RecR rr = sR[ci + 2].r;
                 const RecT tt = sT[cj + 2];
                 double w[NV];
 #pragma unroll
