@@ -79,14 +79,20 @@ def measured_valu():
 
 
 def _cpu_model():
-    """CPU model name from lscpu (fallback /proc/cpuinfo)."""
+    """CPU model name from lscpu with its family / model / stepping numbers
+    (a virtual machine may report only a generic name); fallback /proc/cpuinfo."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
                              timeout=20).stdout
+        f = {}
         for line in out.splitlines():
-            if line.split(":")[0].strip() == "Model name":
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f.setdefault(k.strip(), v.strip())
+        if "Model name" in f:
+            extra = ", ".join("%s %s" % (k.lower(), f[k]) for k in ("CPU family", "Model", "Stepping") if k in f)
+            return f["Model name"] + (" (%s)" % extra if extra else "")
     except (OSError, subprocess.SubprocessError):
         pass
     try:
@@ -166,6 +172,8 @@ def main():
                     help="schedule cache of the autotuner ('' = time the candidates)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale HBM counters")
+    ap.add_argument("--no-forecast", action="store_true",
+                    help="skip the forecast comparison (equidistant vs learned AMR to the 1 AU arrival, ~40 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the single-run hot path has no multi-GPU path in this build "
@@ -245,9 +253,21 @@ def main():
                    "schedule": {k: tune[k] for k in ("waves_per_simd", "grid", "xcd_order", "ksplit")}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_stage<16,12,12>", "mean_launch_ms": mean_ms,
+                     "kernel": "k_stage<16, 12, 12, 8, %d, 0>" % tune["waves_per_simd"], "mean_launch_ms": mean_ms,
                      "bytes_per_launch": bytes_launch, "valu": measured_valu()},
     }
+    if not args.no_forecast:
+        # the forecast target: the learned-flag AMR runs against the equidistant
+        # run to the shock arrival at 1 AU (wall times on this GPU, each run's
+        # relaxation included); after the timed region, outside it
+        from paper_2211_12867_amd import forecast
+        print("bench: forecast comparison (equidistant vs learned AMR, 4 and 5 levels)", file=sys.stderr, flush=True)
+        res = forecast.arrival_comparison(levels=(4, 5), log=lambda m: print("bench: " + m, file=sys.stderr,
+                                                                           flush=True))
+        out["forecast"] = {"workload": "equidistant_full vs learned_flags (stretched 60x24x48, 12^3 blocks), "
+                                       "wind seed 0, cone CME 1500 km/s, relax 14 d then 3 d",
+                           "target": "arrival within 1 h of the equidistant run at >= 10x lower wall time",
+                           "runs": res}
     if not args.no_cpu_baseline:
         print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

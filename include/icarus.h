@@ -310,9 +310,9 @@ ic_status ic_set_clock(ic_sim *sim, int member, double t_code, long since_regrid
 ic_status ic_floor_counts(ic_sim *sim, int member, long *rho_floors, long *p_floors);
 
 /* Shock diagnostics of a radial-speed series at a point (Sect. 3.1: arrival
- * time and shock width, the time it takes from the arrival to reach the
- * maximum speed after the speed jump; Sect. 3.2: peak speed and average
- * gradient of the shock).  t_s[n] ascending sample times [s], v[n] the speeds
+ * time and shock width, measured from the arrival to the peak speed once the
+ * speed has jumped; Sect. 3.2: peak speed and average gradient of the
+ * shock).  t_s[n] ascending sample times [s], v[n] the speeds
  * (any unit), t_cme_s the CME start, window_s the span after it searched for
  * the peak, min_jump the smallest rise (unit of v) counted as a shock.
  * v_pre = v at t_cme_s (linear between samples), v_max = the largest sample

@@ -1,8 +1,8 @@
 """Shock diagnostics at a sample point (test infrastructure only).
 
-The paper reports the shock arrival time and the shock width, the time it
-takes from the arrival to reach the maximum speed after the speed jump
-(Sect. 3.1), and in Sect. 3.2 the peak speed and the average gradient of the
+The paper reports the shock arrival time and the shock width, measured from
+the arrival to the peak speed reached once the speed has jumped (Sect. 3.1),
+and in Sect. 3.2 the peak speed and the average gradient of the
 shock, without defining arrival.  Readings: v_pre = v_r at the CME start
 (linear between samples), v_max = the maximum of v_r within the window after
 it (4 days; the peak speed), arrival = the first time v_r crosses

@@ -200,6 +200,39 @@ def tracer_comparison(relax_days=14.0, cme_days=3.0, max_level=3, log=print):
     return out
 
 
+def arrival_comparison(levels=(4, 5), relax_days=14.0, cme_days=3.0, log=print):
+    """The forecast comparison the learned flags are for (paper Sect. 3.2,
+    Tab. 5): the equidistant full-domain run (512 x 60 x 180, its own
+    relaxation) against stretched AMR runs with the learned flags (judged, no
+    buffer, the stored network and threshold) up to each of `levels`, the same
+    seeded wind and cone CME, to the shock arrival at the sample point.  AMR
+    wall times include their shared base-grid relaxation.  Returns {name:
+    dict(arrival_h, width_h, wall_s, steps, leaf_block_steps)}, the AMR runs
+    with speedup (equidistant wall / own wall) and arrival_diff_h."""
+    net, meta = load_network(os.path.join(os.path.dirname(os.path.abspath(__file__)), "flags_net.npz"))
+    grid, wind, cme, amr, _ = _workload_parts("learned_flags")
+    t_end = (relax_days + cme_days) * DAY
+    cme = dict(cme, t_start_s=relax_days * DAY)
+    st = relax(grid, wind, cme, relax_days * DAY, log=log)
+    keys = ("arrival_h", "width_h", "wall_s", "steps", "leaf_block_steps")
+    out = {}
+    for lv in levels:
+        a = dict(amr, source=IC_SOURCE_LEARNED_JUDGED, buffer_blocks=0, learned_threshold=meta.get("threshold", 0.5))
+        _log(log, "== learned_L%d" % lv)
+        r = cme_run(dict(grid, max_level=lv), wind, cme, a, st, t_end, network=net, log=log)
+        r["wall_s"] += st["wall_s"]
+        out["learned_L%d" % lv] = {k: r[k] for k in keys}
+    g1, w1, c1, _, _ = _workload_parts("equidistant_full")
+    _log(log, "== equidistant")
+    r = cme_run(g1, w1, dict(c1, t_start_s=relax_days * DAY), dict(regrid_every=0), None, t_end, log=log, chunk_s=DAY)
+    eq = {k: r[k] for k in keys}
+    for v in out.values():
+        v["speedup"] = eq["wall_s"] / v["wall_s"]
+        v["arrival_diff_h"] = v["arrival_h"] - eq["arrival_h"]
+    out["equidistant"] = eq
+    return out
+
+
 def collect_pairs(grid, wind, cme, amr, start, t_end_s, every, log=print, max_blocks=0, keep_every=1):
     """Training pairs of a plain run (buffer and cadence as in amr): at each
     regrid time the features of every leaf that touches the refinement

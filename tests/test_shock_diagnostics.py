@@ -1,6 +1,6 @@
 """Shock diagnostics at a point (paper Sect. 3.1: arrival time and shock width,
-the time from arrival to the maximum speed after the speed jump, read as the
-top of the jump; Sect. 3.2: peak speed and average gradient of the shock).
+measured from the arrival to the peak speed once the speed has jumped, read as
+the top of the jump; Sect. 3.2: peak speed and average gradient of the shock).
 
 The oracle's diagnostics are pinned by closed-form series; the library's
 ic_shock_diagnostics (a host computation, so these run without a GPU) must
