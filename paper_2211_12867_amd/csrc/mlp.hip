@@ -13,6 +13,7 @@
 // gradients sum the fp32 values.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -23,7 +24,7 @@
 #include "kernels.h"
 #include "mlp.h"
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t f2bf(float x)
@@ -33,6 +34,7 @@ __device__ inline uint16_t f2bf(float x)
     return (uint16_t)(u >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+#define DEV_EPI __device__ __forceinline__
 
 // ---------------------------------------------------------------------------
 // features: 8 primitives x 4^3 patch means, [prim][k][j][i]
@@ -73,12 +75,20 @@ __global__ void __launch_bounds__(256) k_features(KArgs a, const int *items, con
 }
 
 // ---------------------------------------------------------------------------
-// GEMM: C = A B (+ bias, relu), bf16 operands, fp32 accumulate on
-// v_mfma_f32_16x16x16_bf16.  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
-// Work-group of 4 waves computes a 32x32 tile, one 16x16 sub-tile per wave.
-// MFMA operand layout (wave64): lane l holds row/column (l % 16) of the A/B
-// fragment and k = 4 (l / 16) + 0..3; the accumulator holds column l % 16 and
-// rows 4 (l / 16) + 0..3.
+// GEMM: C = A B (+ bias, relu), bf16 operands, fp32 accumulate on gfx950's
+// v_mfma_f32_16x16x32_bf16.  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
+// A work-group of 4 waves computes a 64x64 tile of C, each wave a 32x32
+// quarter as 2x2 MFMA blocks of 16x16.  K advances in steps of 32 staged
+// through LDS: As[m][k] and Bt[n][k] with k contiguous, so that a lane's
+// MFMA operand -- row (A) or column (B) l % 16 and eight consecutive k,
+// 8 (l / 16) + 0..7 -- is one 16-byte LDS read (rows padded by 8 bf16 to
+// spread them over the banks); the global loads of a stage run along
+// whichever of m/k (A) or k/n (B) is contiguous in memory.  The accumulator
+// holds column l % 16 and rows 4 (l / 16) + 0..3 of a block.
+// Split K (gridDim.z > 1, weight gradients with K = the batch rows): each
+// z-slice accumulates its share of the k-steps and writes fp32 partials
+// P[z][m][n]; k_gemm_reduce sums them in slice order (deterministic) and
+// applies the epilogue.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
     const uint16_t *A;
@@ -91,35 +101,80 @@ struct GemmArgs {
     float *Cf;
     uint16_t *Cb;
     long ldc;
+    float *P;                 // split-K partials [gridDim.z][M][N] (gridDim.z > 1)
 };
+
+DEV_EPI void gemm_store(const GemmArgs &g, int m, int n, float v)
+{
+    if (g.bias) v += g.bias[n];
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    if (g.Cf) g.Cf[(long)m * g.ldc + n] = v;
+    if (g.Cb) g.Cb[(long)m * g.ldc + n] = f2bf(v);
+}
 
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int m0 = blockIdx.y * 32 + (wave & 1) * 16;
-    const int n0 = blockIdx.x * 32 + (wave >> 1) * 16;
-    const int r = lane & 15, kq = (lane >> 4) * 4;
-    float4_t acc = {0.f, 0.f, 0.f, 0.f};
-    const bool mok = m0 + r < g.M, nok = n0 + r < g.N;
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
-        short4_t av, bv;
-        for (int t = 0; t < 4; ++t) {
-            const int k = k0 + kq + t;
-            av[t] = (mok && k < g.K) ? (short)g.A[(long)(m0 + r) * g.sam + (long)k * g.sak] : (short)0;
-            bv[t] = (nok && k < g.K) ? (short)g.B[(long)k * g.sbk + (long)(n0 + r) * g.sbn] : (short)0;
+    constexpr int KP = 40;                         // padded row of 32 bf16
+    __shared__ __attribute__((aligned(16))) uint16_t As[64 * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[64 * KP];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int nstep = (g.K + 31) / 32;
+    const int s0 = (int)((long)nstep * blockIdx.z / gridDim.z), s1 = (int)((long)nstep * (blockIdx.z + 1) / gridDim.z);
+    const bool a_k = g.sak == 1, b_n = g.sbn == 1;
+    float4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int st = s0; st < s1; ++st) {
+        const int k0 = st * 32;
+        __syncthreads();                           // the previous stage's operands are consumed
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = e * 256 + tid;
+            const int am = a_k ? idx >> 5 : idx & 63, ak = a_k ? idx & 31 : idx >> 6;
+            const int gm = m0 + am, gka = k0 + ak;
+            As[am * KP + ak] = (gm < g.M && gka < g.K) ? g.A[(long)gm * g.sam + (long)gka * g.sak] : (uint16_t)0;
+            const int bn = b_n ? idx & 63 : idx >> 5, bk = b_n ? idx >> 6 : idx & 31;
+            const int gn = n0 + bn, gkb = k0 + bk;
+            Bt[bn * KP + bk] = (gn < g.N && gkb < g.K) ? g.B[(long)gkb * g.sbk + (long)gn * g.sbn] : (uint16_t)0;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        __syncthreads();
+        bf16x8_t a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8_t *)&As[(wm + 16 * i + r) * KP + kq];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8_t *)&Bt[(wn + 16 * j + r) * KP + kq];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    for (int t = 0; t < 4; ++t) {
-        const int m = m0 + kq + t, n = n0 + r;
-        if (m < g.M && n < g.N) {
-            float v = acc[t];
-            if (g.bias) v += g.bias[n];
-            if (g.relu) v = v > 0.f ? v : 0.f;
-            if (g.Cf) g.Cf[(long)m * g.ldc + n] = v;
-            if (g.Cb) g.Cb[(long)m * g.ldc + n] = f2bf(v);
-        }
-    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int m = m0 + wm + 16 * i + (lane >> 4) * 4 + t, n = n0 + wn + 16 * j + r;
+                if (m < g.M && n < g.N) {
+                    if (gridDim.z > 1) g.P[((long)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][t];
+                    else gemm_store(g, m, n, acc[i][j][t]);
+                }
+            }
+}
+
+// C = the sum of the split-K partials in slice order, then bias / relu / stores
+__global__ void k_gemm_reduce(GemmArgs g, int nz)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)g.M * g.N) return;
+    float v = 0.f;
+    for (int z = 0; z < nz; ++z) v += g.P[(long)z * g.M * g.N + q];
+    gemm_store(g, (int)(q / g.N), (int)(q % g.N), v);
 }
 
 // logit, probability and (training) the weighted-BCE gradient per row:
@@ -166,17 +221,46 @@ __global__ void k_mask(const float *dH, const uint16_t *H, long count, float *dZ
     dZb[q] = f2bf(v);
 }
 
-// column sums out[j] = sum_b w[b] * M[b][j] (w = NULL: plain sums), fp32, b ascending
-__global__ void k_colsum(const float *Mf, const uint16_t *Mb, const float *w, int n, int ncol, float *out)
+// column sums out[j] = sum_b w[b] * M[b][j] (w = NULL: plain sums), fp32, in
+// two levels: chunk c of the rows (gridDim.y chunks, rows ascending within a
+// chunk) into P[c][j], then the chunks in order (k_colsum_reduce)
+__global__ void k_colsum(const float *Mf, const uint16_t *Mb, const float *w, int n, int ncol, float *P)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ncol) return;
+    const int c = blockIdx.y, nc = gridDim.y;
+    const int b0 = (int)((long)n * c / nc), b1 = (int)((long)n * (c + 1) / nc);
+    float s = 0.f;
+    for (int b = b0; b < b1; ++b) {
+        const float m = Mf ? Mf[(long)b * ncol + j] : bf2f(Mb[(long)b * ncol + j]);
+        s += w ? w[b] * m : m;
+    }
+    P[(long)c * ncol + j] = s;
+}
+
+__global__ void k_colsum_reduce(const float *P, int nc, int ncol, float *out)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= ncol) return;
     float s = 0.f;
-    for (int b = 0; b < n; ++b) {
-        const float m = Mf ? Mf[(long)b * ncol + j] : bf2f(Mb[(long)b * ncol + j]);
-        s += w ? w[b] * m : m;
-    }
+    for (int c = 0; c < nc; ++c) s += P[(long)c * ncol + j];
     out[j] = s;
+}
+
+// sum of the n per-row losses in fp64 (fixed order: thread-strided, then a
+// pairwise tree) into out[slot]
+__global__ void __launch_bounds__(256) k_loss_sum(const float *loss, int n, double *out, long slot)
+{
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256) s += (double)loss[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[slot] = sh[0];
 }
 
 __global__ void k_adam(float *w, uint16_t *wb, const float *g, float *m1, float *m2, int n, float lr, float b1,
@@ -238,12 +322,33 @@ __global__ void k_prob_flags(const float *prob, const int *items, int n, float t
 // ---------------------------------------------------------------------------
 namespace {
 
+// Split K only when a workspace is given (the weight gradients): enough
+// slices for ~256 work-groups, each at least 4 k-steps; the workspace holds
+// GEMM_SPLIT_MAX x M x N floats.
+constexpr int GEMM_SPLIT_MAX = 32;
+
 void gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn, int M, int N,
-          int K, const float *bias, int relu, float *Cf, uint16_t *Cb, long ldc)
+          int K, const float *bias, int relu, float *Cf, uint16_t *Cb, long ldc, float *work = nullptr)
 {
-    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, bias, relu, Cf, Cb, ldc};
-    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, bias, relu, Cf, Cb, ldc, work};
+    const int tiles = ((N + 63) / 64) * ((M + 63) / 64), nstep = (K + 31) / 32;
+    int nz = 1;
+    if (work && tiles < 256) nz = std::max(1, std::min({GEMM_SPLIT_MAX, nstep / 4, (256 + tiles - 1) / tiles}));
+    dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
     hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+    if (nz > 1)
+        hipLaunchKernelGGL(k_gemm_reduce, dim3(((long)M * N + 255) / 256), dim3(256), 0, s, g, nz);
+}
+
+// column sums through the workspace (COLSUM_CHUNKS x ncol floats)
+constexpr int COLSUM_CHUNKS = 64;
+
+void colsum(hipStream_t s, const float *Mf, const uint16_t *Mb, const float *w, int n, int ncol, float *out,
+            float *work)
+{
+    const int nc = std::max(1, std::min(COLSUM_CHUNKS, n / 32));
+    hipLaunchKernelGGL(k_colsum, dim3((ncol + 127) / 128, nc), dim3(128), 0, s, Mf, Mb, w, n, ncol, work);
+    hipLaunchKernelGGL(k_colsum_reduce, dim3((ncol + 127) / 128), dim3(128), 0, s, (const float *)work, nc, ncol, out);
 }
 
 template <class T>
@@ -343,10 +448,14 @@ void mlp_prob_flags(hipStream_t s, const float *prob, const int *items, int n, f
 
 // One forward + backward pass on n rows: gradients (fp32, params layout) and mean loss.
 // X: normalised fp32 inputs (converted to bf16 here), params: fp32 master weights.
+// Workspace of fwd_bwd: split-K partials of the largest weight gradient, or
+// the chunked column sums
+constexpr size_t FWD_BWD_WORK = (size_t)GEMM_SPLIT_MAX * IC_MLP_IN * IC_MLP_HID;
+
 static void fwd_bwd(hipStream_t s, int n, const uint16_t *Xb, const uint8_t *y, float pw, const float *w,
                     const uint16_t *wb, float *grad, float *loss_rows, Buf<uint16_t> &H1, Buf<uint16_t> &H2,
                     Buf<float> &dz, Buf<float> &dZ2, Buf<uint16_t> &dZ2b, Buf<float> &dH1, Buf<float> &dZ1,
-                    Buf<uint16_t> &dZ1b)
+                    Buf<uint16_t> &dZ1b, float *work)
 {
     const uint16_t *W1 = wb + IC_MLP_OFF_W1, *W2 = wb + IC_MLP_OFF_W2, *w3 = wb + IC_MLP_OFF_W3;
     gemm(s, Xb, IC_MLP_IN, 1, W1, IC_MLP_HID, 1, n, IC_MLP_HID, IC_MLP_IN, w + IC_MLP_OFF_B1, 1, nullptr, H1.p,
@@ -356,26 +465,22 @@ static void fwd_bwd(hipStream_t s, int n, const uint16_t *Xb, const uint8_t *y, 
     hipLaunchKernelGGL(k_head, dim3((n + 255) / 256), dim3(256), 0, s, H2.p, w3, w + IC_MLP_OFF_B3, n, y, pw,
                        (float *)nullptr, (float *)nullptr, dz.p, loss_rows);
     // layer 3: dw3 = H2^T dz, db3 = sum dz
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, (const float *)nullptr, H2.p, dz.p, n,
-                       IC_MLP_HID, grad + IC_MLP_OFF_W3);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(1), 0, s, dz.p, (const uint16_t *)nullptr, (const float *)nullptr,
-                       n, 1, grad + IC_MLP_OFF_B3);
+    colsum(s, nullptr, H2.p, dz.p, n, IC_MLP_HID, grad + IC_MLP_OFF_W3, work);
+    colsum(s, dz.p, nullptr, nullptr, n, 1, grad + IC_MLP_OFF_B3, work);
     const long nh = (long)n * IC_MLP_HID;
     hipLaunchKernelGGL(k_back2, dim3((nh + 255) / 256), dim3(256), 0, s, dz.p, w3, H2.p, n, dZ2.p, dZ2b.p);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, dZ2.p, (const uint16_t *)nullptr,
-                       (const float *)nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B2);
+    colsum(s, dZ2.p, nullptr, nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B2, work);
     // dW2 = H1^T dZ2   (M = 128 (k of layer 2), N = 128, K = n)
     gemm(s, H1.p, 1, IC_MLP_HID, dZ2b.p, IC_MLP_HID, 1, IC_MLP_HID, IC_MLP_HID, n, nullptr, 0, grad + IC_MLP_OFF_W2,
-         nullptr, IC_MLP_HID);
+         nullptr, IC_MLP_HID, work);
     // dH1 = dZ2 W2^T   (B(k, j) = W2[j][k])
     gemm(s, dZ2b.p, IC_MLP_HID, 1, W2, 1, IC_MLP_HID, n, IC_MLP_HID, IC_MLP_HID, nullptr, 0, dH1.p, nullptr,
          IC_MLP_HID);
     hipLaunchKernelGGL(k_mask, dim3((nh + 255) / 256), dim3(256), 0, s, dH1.p, H1.p, nh, dZ1.p, dZ1b.p);
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(IC_MLP_HID), 0, s, dZ1.p, (const uint16_t *)nullptr,
-                       (const float *)nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B1);
+    colsum(s, dZ1.p, nullptr, nullptr, n, IC_MLP_HID, grad + IC_MLP_OFF_B1, work);
     // dW1 = X^T dZ1    (M = 512, N = 128, K = n)
     gemm(s, Xb, 1, IC_MLP_IN, dZ1b.p, IC_MLP_HID, 1, IC_MLP_IN, IC_MLP_HID, n, nullptr, 0, grad + IC_MLP_OFF_W1,
-         nullptr, IC_MLP_HID);
+         nullptr, IC_MLP_HID, work);
 }
 
 void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float *params, float *grad_out,
@@ -387,6 +492,7 @@ void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float
     Buf<uint16_t> xb((size_t)n * IC_MLP_IN), wb(IC_MLP_NPARAM), H1((size_t)n * IC_MLP_HID), H2((size_t)n * IC_MLP_HID),
         dZ2b((size_t)n * IC_MLP_HID), dZ1b((size_t)n * IC_MLP_HID);
     Buf<uint8_t> yd(n);
+    Buf<float> work(FWD_BWD_WORK);
     if (hipMemcpy(x.p, xnorm, (size_t)n * IC_MLP_IN * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(w.p, params, IC_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(yd.p, y, n, hipMemcpyHostToDevice) != hipSuccess)
@@ -394,7 +500,7 @@ void mlp_grad(const float *xnorm, const uint8_t *y, int n, float pw, const float
     hipLaunchKernelGGL(k_to_bf16, dim3(((long)n * IC_MLP_IN + 255) / 256), dim3(256), 0, s, x.p, xb.p,
                        (long)n * IC_MLP_IN);
     hipLaunchKernelGGL(k_to_bf16, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, w.p, wb.p, (long)IC_MLP_NPARAM);
-    fwd_bwd(s, n, xb.p, yd.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b);
+    fwd_bwd(s, n, xb.p, yd.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b, work.p);
     std::vector<float> lrow(n);
     if (hipMemcpy(grad_out, grad.p, IC_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess ||
         hipMemcpy(lrow.data(), loss.p, n * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
@@ -437,6 +543,9 @@ void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp,
         H2((size_t)B * IC_MLP_HID), dZ2b((size_t)B * IC_MLP_HID), dZ1b((size_t)B * IC_MLP_HID);
     Buf<uint8_t> yall(n), yb(B);
     Buf<long> orderd(n);
+    Buf<float> work(FWD_BWD_WORK);
+    const long nbatch = n / B;
+    Buf<double> lossacc(std::max(nbatch, 1L));           // per-minibatch loss sums, read once per epoch
     auto H2D = [](void *d, const void *h, size_t bytes) {
         if (hipMemcpy(d, h, bytes, hipMemcpyHostToDevice) != hipSuccess) throw std::runtime_error("hipMemcpy failed");
     };
@@ -461,26 +570,27 @@ void mlp_train(const float *raw, const uint8_t *y, long n, const MlpHparams &hp,
         return st;
     };
     long t = 0;
-    std::vector<float> lrow(B);
+    std::vector<double> lsums(std::max(nbatch, 1L));
     for (int ep = 0; ep < hp.epochs; ++ep) {
         for (long b = n - 1; b > 0; --b) std::swap(order[b], order[rnd() % (uint64_t)(b + 1)]);
         H2D(orderd.p, order.data(), n * sizeof(long));
-        double lsum = 0.0;
-        long lcount = 0;
-        for (long b0 = 0; b0 + B <= n; b0 += B) {
+        long q = 0;
+        for (long b0 = 0; b0 + B <= n; b0 += B, ++q) {
             hipLaunchKernelGGL(k_gather, dim3(((long)B * IC_MLP_IN + 255) / 256), dim3(256), 0, s, xall.p, yall.p,
                                orderd.p, b0, B, xb.p, yb.p);
-            fwd_bwd(s, B, xb.p, yb.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b);
+            fwd_bwd(s, B, xb.p, yb.p, pw, w.p, wb.p, grad.p, loss.p, H1, H2, dz, dZ2, dZ2b, dH1, dZ1, dZ1b, work.p);
+            hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, s, (const float *)loss.p, B, lossacc.p, q);
             ++t;
             const float c1 = 1.f - std::pow(hp.beta1, (float)t), c2 = 1.f - std::pow(hp.beta2, (float)t);
             hipLaunchKernelGGL(k_adam, dim3((IC_MLP_NPARAM + 255) / 256), dim3(256), 0, s, w.p, wb.p, grad.p, m1.p,
                                m2.p, IC_MLP_NPARAM, hp.lr, hp.beta1, hp.beta2, hp.eps, c1, c2);
-            if (hipMemcpy(lrow.data(), loss.p, B * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
-                throw std::runtime_error("hipMemcpy failed");
-            for (int q = 0; q < B; ++q) lsum += lrow[q];
-            lcount += B;
         }
-        if (loss_epochs) loss_epochs[ep] = lcount ? (float)(lsum / lcount) : 0.f;
+        // the epoch's minibatch losses, summed in batch order
+        if (q > 0 && hipMemcpy(lsums.data(), lossacc.p, q * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            throw std::runtime_error("hipMemcpy failed");
+        double lsum = 0.0;
+        for (long i = 0; i < q; ++i) lsum += lsums[i];
+        if (loss_epochs) loss_epochs[ep] = q ? (float)(lsum / (double)(q * B)) : 0.f;
     }
     if (hipMemcpy(params, w.p, IC_MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
         throw std::runtime_error("hipMemcpy failed");

@@ -3,6 +3,7 @@
 - Every member of a batched ensemble (one launch per kernel over all members'
   leaves, per-member dt, per-member regrid) equals the run of that member
   alone, bit for bit.
+- A batch of members against one oracle run per member: forests and states.
 - ic_advance with regrids every few steps (the captured step graph replayed
   across forest changes) matches the oracle doing the same, including the
   time series recorded at the sample point after every step.
@@ -84,6 +85,46 @@ def test_advance_with_regrids_matches_oracle():
     ref = np.array(series)
     assert np.allclose(ts[:, 0], ref[:, 0], rtol=1e-12)
     assert np.allclose(ts[:, 1:], ref[:, 1:], rtol=1e-9, atol=1e-12 * np.abs(ref[:, 1:]).max())
+    gpu.close()
+
+
+def _batch_cmes(n):
+    cmes = [as_dict(c) for c in cme_ensemble(n, 1000, t_start_s=0.0)]
+    for c in cmes:
+        c["lon_deg"] = (c["lon_deg"] + 30.0) % 360.0      # aim into the wedge
+        c["duration_s"] = 6 * 3600.0
+    return cmes
+
+
+def test_batch_members_match_the_oracle():
+    """A batch of three members (different cone CMEs, uneven forests, each
+    its own dt and regrids, one launch per kernel over all their leaves)
+    against one oracle run per member: forests equal and states within the
+    multi-step bar after three regrid cycles."""
+    import paper_2211_12867_amd as ic
+    wind = as_dict(Wind(seed=5))
+    cmes = _batch_cmes(3)
+    g, amr = _grid(3), _amr(4)
+    oras = [solver.Solver(g, wind, c, amr) for c in cmes]
+    for cycle in range(3):
+        for ora in oras:
+            for _ in range(4):
+                ora.step()
+            ties = []
+            f = ora.flags(ties)
+            assert not ties, ties[:3]
+            ora.regrid(f)
+    gpu = ic.Sim(g, wind, cmes, amr)
+    gpu.advance(1e9, max_steps=12)
+    sizes = set()
+    for m, ora in enumerate(oras):
+        assert gpu.blocks(m) == ora.blocks(), m
+        sizes.add(len(ora.blocks()))
+        e = rel_err(gpu.state(m)[1], ora.state()[1])
+        assert e <= 1e-10, (m, e)
+        t, _ = gpu.time(m)
+        assert abs(t / units.T0 - ora.t) <= 1e-12 * ora.t, m
+    assert len(sizes) > 1 and max(max(b[0] for b in o.blocks()) for o in oras) >= 2   # uneven, refined
     gpu.close()
 
 
