@@ -457,6 +457,23 @@ void ic_units(double out[6]);
 /* Block-pool capacity per member (the stride of the flags array of ic_regrid). */
 int ic_pool_capacity(const ic_sim *sim);
 
+/* Device memory from the caller (for callers whose framework owns device
+ * memory, e.g. PyTorch's caching allocator; the paper's method is unaffected).
+ * By default the library takes its device buffers from hipMalloc.  After this
+ * call, alloc(bytes, user) supplies every device buffer the library allocates
+ * -- sim pools, task lists, flux registers, network weights and work arrays
+ * -- and release(ptr, user) takes it back; both NULL restore hipMalloc /
+ * hipFree.  alloc must return memory of the current device aligned to at
+ * least 256 bytes, or NULL (the allocating call then fails with IC_E_NOMEM).
+ * Every buffer goes back through the allocator it came from, also after a
+ * later change.  Pinned host memory and the static scratch of
+ * ic_mlp_infer_noalloc are not affected.  Process-wide: do not call it while
+ * another thread is inside the library.  IC_E_INVALID if exactly one of alloc
+ * and release is NULL. */
+typedef void *(*ic_alloc_fn)(size_t bytes, void *user);
+typedef void (*ic_free_fn)(void *ptr, void *user);
+ic_status ic_set_device_allocator(ic_alloc_fn alloc, ic_free_fn release, void *user);
+
 /* 1 if the library has kernels for this block shape, else 0. */
 int ic_block_supported(int bi, int bj, int bk);
 

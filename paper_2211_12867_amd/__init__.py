@@ -117,7 +117,11 @@ EXPORTS = ("ic_create", "ic_destroy", "ic_step", "ic_advance", "ic_regrid", "ic_
            "ic_stage_timing", "ic_pool_capacity", "ic_features", "ic_mlp_set", "ic_eval_learned",
            "ic_regrid_stats", "ic_mlp_train", "ic_mlp_grad", "ic_mlp_infer", "ic_autotune", "ic_set_tuning",
            "ic_get_tuning", "ic_floor_counts", "ic_shock_diagnostics", "ic_mlp_infer_noalloc", "ic_get_clock",
-           "ic_set_clock", "ic_last_error")
+           "ic_set_clock", "ic_set_device_allocator", "ic_last_error")
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 def _load():
@@ -151,6 +155,7 @@ def _load():
     L.ic_get_time.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
     L.ic_floor_counts.argtypes = [vp, ctypes.c_int, P(ctypes.c_long), P(ctypes.c_long)]
     L.ic_get_clock.argtypes = [vp, ctypes.c_int, P(ctypes.c_double), P(ctypes.c_long)]
+    L.ic_set_device_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     L.ic_set_clock.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_long]
     dp = P(ctypes.c_double)
     L.ic_shock_diagnostics.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
@@ -272,6 +277,44 @@ def amr_cfg(amr):
     return a
 
 
+_alloc_keepalive = []      # installed callbacks stay alive: buffers go back through the one they came from
+_live_sims = None
+
+
+def use_torch_allocator(enable=True):
+    """Route the library's device buffers through PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / caching_allocator_delete on the
+    current device and stream) -- the library's ic_set_device_allocator;
+    enable=False restores hipMalloc.  Buffers keep the allocator they came
+    from.  Sims still open when the interpreter exits are closed first."""
+    import atexit
+    import weakref
+    global _live_sims
+    if not enable:
+        _check(lib.ic_set_device_allocator(_ALLOC_FN(), _FREE_FN(), None))
+        return
+    import torch
+
+    def _alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def _free(ptr, user):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _alloc_keepalive.append(cbs)
+    if _live_sims is None:
+        _live_sims = weakref.WeakSet()
+        atexit.register(lambda: [s.close() for s in list(_live_sims)])
+    _check(lib.ic_set_device_allocator(cbs[0], cbs[1], None))
+
+
 def _current_stream():
     try:
         import torch
@@ -312,6 +355,8 @@ class Sim:
         _check(lib.ic_create(ctypes.byref(g), ctypes.byref(p), ctypes.byref(w) if w is not None else None,
                              carr, self.n_members, ctypes.byref(a), st, ctypes.byref(h)))
         self.h = h
+        if _live_sims is not None:
+            _live_sims.add(self)
 
     def close(self):
         if getattr(self, "h", None):

@@ -21,6 +21,7 @@
 #include <string>
 #include <vector>
 
+#include "devmem.h"
 #include "kernels.h"
 #include "mlp.h"
 
@@ -358,15 +359,12 @@ struct Buf {
     explicit Buf(size_t count = 0) { alloc(count); }
     void alloc(size_t count)
     {
-        if (p) (void)hipFree(p);
+        dev_free(p);
         p = nullptr;
         n = count;
-        if (count && hipMalloc(&p, count * sizeof(T)) != hipSuccess) throw std::runtime_error("hipMalloc failed");
+        if (count && !(p = (T *)dev_malloc(count * sizeof(T)))) throw std::runtime_error("device allocation failed");
     }
-    ~Buf()
-    {
-        if (p) (void)hipFree(p);
-    }
+    ~Buf() { dev_free(p); }
     Buf(const Buf &) = delete;
     Buf &operator=(const Buf &) = delete;
 };
@@ -379,17 +377,17 @@ MlpDevice::~MlpDevice()
 {
     for (void *q : {(void *)w, (void *)wb, (void *)mean, (void *)istd, (void *)xb, (void *)h1, (void *)h2,
                     (void *)prob, (void *)flags_tmp})
-        if (q) (void)hipFree(q);
+        dev_free(q);
 }
 
 void MlpDevice::set(const float *params, const float *mean_h, const float *std_h)
 {
     if (!w) {
-        if (hipMalloc(&w, IC_MLP_NPARAM * sizeof(float)) != hipSuccess ||
-            hipMalloc(&wb, IC_MLP_NPARAM * sizeof(uint16_t)) != hipSuccess ||
-            hipMalloc(&mean, IC_MLP_IN * sizeof(float)) != hipSuccess ||
-            hipMalloc(&istd, IC_MLP_IN * sizeof(float)) != hipSuccess)
-            throw std::runtime_error("hipMalloc failed");
+        w = (float *)dev_malloc(IC_MLP_NPARAM * sizeof(float));
+        wb = (uint16_t *)dev_malloc(IC_MLP_NPARAM * sizeof(uint16_t));
+        mean = (float *)dev_malloc(IC_MLP_IN * sizeof(float));
+        istd = (float *)dev_malloc(IC_MLP_IN * sizeof(float));
+        if (!w || !wb || !mean || !istd) throw std::runtime_error("device allocation failed");
     }
     std::vector<float> is(IC_MLP_IN);
     for (int f = 0; f < IC_MLP_IN; ++f) is[f] = 1.0f / std_h[f];
@@ -405,14 +403,15 @@ void MlpDevice::set(const float *params, const float *mean_h, const float *std_h
 void MlpDevice::reserve(int n)
 {
     if (n <= cap) return;
-    for (void *q : {(void *)xb, (void *)h1, (void *)h2, (void *)prob})
-        if (q) (void)hipFree(q);
+    for (void *q : {(void *)xb, (void *)h1, (void *)h2, (void *)prob}) dev_free(q);
+    xb = h1 = h2 = nullptr;
+    prob = nullptr;
     cap = n + n / 2 + 64;
-    if (hipMalloc(&xb, (size_t)cap * IC_MLP_IN * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&h1, (size_t)cap * IC_MLP_HID * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&h2, (size_t)cap * IC_MLP_HID * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&prob, (size_t)cap * sizeof(float)) != hipSuccess)
-        throw std::runtime_error("hipMalloc failed");
+    xb = (uint16_t *)dev_malloc((size_t)cap * IC_MLP_IN * sizeof(uint16_t));
+    h1 = (uint16_t *)dev_malloc((size_t)cap * IC_MLP_HID * sizeof(uint16_t));
+    h2 = (uint16_t *)dev_malloc((size_t)cap * IC_MLP_HID * sizeof(uint16_t));
+    prob = (float *)dev_malloc((size_t)cap * sizeof(float));
+    if (!xb || !h1 || !h2 || !prob) throw std::runtime_error("device allocation failed");
 }
 
 // forward pass over n rows of xb (already filled) -> prob

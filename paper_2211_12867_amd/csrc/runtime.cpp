@@ -19,10 +19,12 @@
 #include <exception>
 #include <functional>
 #include <mutex>
+#include <unordered_map>
 #include <thread>
 #include <vector>
 
 #include "../../include/icarus.h"
+#include "devmem.h"
 #include "kernels.h"
 #include "mlp.h"
 
@@ -55,23 +57,87 @@ struct Error : std::runtime_error {
             throw Error(IC_E_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));              \
     } while (0)
 
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// device allocations: hipMalloc, or the caller's allocator
+// ---------------------------------------------------------------------------
+namespace {
+struct DevAllocator {
+    ic_alloc_fn alloc = nullptr;   // nullptr: hipMalloc / hipFree
+    ic_free_fn release = nullptr;
+    void *user = nullptr;
+};
+std::mutex g_dev_mutex;
+DevAllocator g_dev_alloc;
+std::unordered_map<void *, DevAllocator> g_dev_owner;   // pointers from a caller's allocator
+}  // namespace
+
+void *dev_malloc(size_t bytes)
+{
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    const DevAllocator a = g_dev_alloc;
+    if (!a.alloc) {
+        void *p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void *p = a.alloc(bytes, a.user);
+    if (p) g_dev_owner[p] = a;
+    return p;
+}
+
+void dev_free(void *p)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    auto it = g_dev_owner.find(p);
+    if (it == g_dev_owner.end()) {
+        (void)hipFree(p);
+        return;
+    }
+    const DevAllocator a = it->second;
+    g_dev_owner.erase(it);
+    a.release(p, a.user);
+}
+
+namespace {
 template <class T>
-struct DBuf {  // device buffer with a capacity in elements
+struct DBuf {  // device buffer with a capacity in elements; released with its owner
     T *p = nullptr;
     size_t cap = 0;
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), cap(o.cap)
+    {
+        o.p = nullptr;
+        o.cap = 0;
+    }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        if (this != &o) {
+            release();
+            p = o.p;
+            cap = o.cap;
+            o.p = nullptr;
+            o.cap = 0;
+        }
+        return *this;
+    }
+    ~DBuf() { release(); }
     void alloc(size_t n)
     {
         if (n <= cap) return;
-        if (p) HIPCHECK(hipFree(p));
+        dev_free(p);
         p = nullptr;
         cap = 0;
-        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess)
-            throw Error(IC_E_NOMEM, "device allocation failed");
+        p = (T *)dev_malloc(std::max<size_t>(n, 1) * sizeof(T));
+        if (!p) throw Error(IC_E_NOMEM, "device allocation failed");
         cap = std::max<size_t>(n, 1);
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        dev_free(p);
         p = nullptr;
         cap = 0;
     }
@@ -1901,6 +1967,17 @@ void ic_units(double out[6])
 }
 
 int ic_pool_capacity(const ic_sim *s) { return s ? s->max_blocks : 0; }
+
+ic_status ic_set_device_allocator(ic_alloc_fn alloc, ic_free_fn release, void *user)
+{
+    if (!alloc != !release) {
+        g_err = "ic_set_device_allocator: give both alloc and release, or neither";
+        return IC_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    g_dev_alloc = DevAllocator{alloc, release, user};
+    return IC_OK;
+}
 
 int ic_block_supported(int bi, int bj, int bk)
 {
