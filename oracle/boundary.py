@@ -112,6 +112,15 @@ def cme_distance(cme, theta, phi):
     return np.arccos(np.clip(arg, -1.0, 1.0))
 
 
+# Boundary points whose angular distance lies within MASK_TIE_RAD of the
+# opening angle: there the decision d <= theta(t) rests on the last bits of
+# two arccos evaluations (an implementation comparing the cosines, or
+# computing them in another order, may decide the other way), so parity tests
+# check that none occurred.  Entries (t, count) are appended by cme_mask.
+MASK_TIE_RAD = 1e-10
+MASK_NEAR_TIES = []
+
+
 def cme_mask(cme, theta, phi, r_in, t):
     """Boolean mask of boundary points inside the CME at code time t."""
     tau = t - units.time_code(cme["t_start_s"])
@@ -119,7 +128,12 @@ def cme_mask(cme, theta, phi, r_in, t):
     shape = np.shape(theta)
     if not (0.0 <= tau <= t_act):
         return np.zeros(shape, dtype=bool)
-    return cme_distance(cme, theta, phi) <= cme_opening_angle(cme, r_in, tau)
+    d = cme_distance(cme, theta, phi)
+    th = cme_opening_angle(cme, r_in, tau)
+    near = int(np.count_nonzero(np.abs(d - th) < MASK_TIE_RAD))
+    if near:
+        MASK_NEAR_TIES.append((t, near))
+    return d <= th
 
 
 def boundary_prims(wind, cme, theta, phi, r_in, omega, t):

@@ -20,3 +20,18 @@ def _oracle_built():
     if not os.path.exists(_clib.LIB):
         _clib.build()
     yield
+
+
+@pytest.fixture(autouse=True)
+def _no_cone_edge_ties(request):
+    """GPU parity tests: the oracle's cone-CME mask must have met no boundary
+    point within its near-tie margin of the cone edge (there the kernels'
+    comparison of cosines and the oracle's of arccos values may decide
+    differently, which would be no error of either); fails loudly if one did."""
+    if request.node.get_closest_marker("gpu") is None:
+        yield
+        return
+    from oracle import boundary
+    del boundary.MASK_NEAR_TIES[:]
+    yield
+    assert not boundary.MASK_NEAR_TIES, "cone-CME mask near-tie in the oracle: %r" % boundary.MASK_NEAR_TIES[:3]

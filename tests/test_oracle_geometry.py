@@ -146,6 +146,42 @@ def test_cme_mask_area_grows_then_shrinks():
     assert boundary.cme_mask(CME, th, ph, R, t_act * 1.01).sum() == 0
 
 
+def test_cme_mask_cosine_form_agrees_away_from_the_edge_and_edge_ties_are_flagged():
+    """Eqs. (2)-(4) compare two angles, d <= theta(t); comparing their cosines
+    instead, cos d >= cos theta(t), is the same test in exact arithmetic
+    (arccos decreases).  On 200,000 random boundary points over the active
+    span the two forms decide alike wherever |d - theta| exceeds the near-tie
+    margin; a point placed on the cone edge lands inside the margin and is
+    recorded, so a parity test can refuse such a case."""
+    rng = np.random.default_rng(9)
+    R = 0.1
+    cme = dict(CME, colat_deg=80.0, lon_deg=20.0)
+    _, _, t_act = boundary.cme_geometry(cme, R)
+    tc, pc = math.radians(80.0), math.radians(20.0)
+    for t in np.linspace(0.05, 0.95, 7) * t_act:
+        th = rng.uniform(0.2, 2.9, 200000 // 7)
+        ph = rng.uniform(-math.pi, math.pi, th.size)
+        del boundary.MASK_NEAR_TIES[:]
+        m = boundary.cme_mask(cme, th, ph, R, t)
+        theta = boundary.cme_opening_angle(cme, R, t)
+        cosd = np.clip(np.sin(th) * math.sin(tc) * np.cos(ph - pc) + np.cos(th) * math.cos(tc), -1.0, 1.0)
+        m_cos = cosd >= math.cos(theta)
+        far = np.abs(boundary.cme_distance(cme, th, ph) - theta) >= boundary.MASK_TIE_RAD
+        assert np.array_equal(m[far], m_cos[far])
+        assert 0 < m.sum() < m.size
+    # a point on the edge: same colatitude as the centre, longitude offset by theta(t)
+    t = 0.5 * t_act
+    theta = boundary.cme_opening_angle(cme, R, t)
+    del boundary.MASK_NEAR_TIES[:]
+    boundary.cme_mask(cme, np.array([math.pi / 2]), np.array([theta]), R, t)
+    assert not boundary.MASK_NEAR_TIES                     # (centre at colatitude 80: not on the edge)
+    c90 = dict(cme, colat_deg=90.0, lon_deg=0.0)
+    theta = boundary.cme_opening_angle(c90, R, t)
+    boundary.cme_mask(c90, np.array([math.pi / 2]), np.array([theta]), R, t)
+    assert boundary.MASK_NEAR_TIES and boundary.MASK_NEAR_TIES[-1][1] == 1
+    del boundary.MASK_NEAR_TIES[:]
+
+
 def test_wind_harmonics_orthonormal():
     n = 200
     th = (np.arange(n) + 0.5) * math.pi / n
