@@ -97,12 +97,13 @@ def test_unit_fraction_tracer_is_the_density_on_the_gpu():
     assert gpu.floor_counts() == (0, 0)
 
 
-@pytest.mark.parametrize("sch", ["two_stage", "hancock"])
-def test_cme_wedge_tracer_parity(sch):
+@pytest.mark.parametrize("sch,cd", [("two_stage", 0.0), ("hancock", 0.0), ("two_stage", 0.3)])
+def test_cme_wedge_tracer_parity(sch, cd):
+    """Both time schemes, and the parabolic cleaning beside the tracer."""
     ic = _ic()
     g, wind, cme, amr = tiny_wedge()
-    ora = solver.Solver(g, wind, cme, amr, tracer=True, scheme=sch)
-    gpu = ic.Sim(g, wind, [cme], amr, tracer=True, scheme=sch)
+    ora = solver.Solver(g, wind, cme, amr, tracer=True, scheme=sch, divb_cd=cd)
+    gpu = ic.Sim(g, wind, [cme], amr, tracer=True, scheme=sch, divb_cd=cd)
     bl, U = gpu.state()
     assert U.shape[1] == 9 and np.all(U[:, 8] == 0.0)     # no CME material initially
     gpu.set_state(*ora.state(), 0.0)
