@@ -176,7 +176,7 @@ def main():
                     help="skip the forecast comparison (equidistant vs learned AMR to the 1 AU arrival, ~40 s)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the single-run hot path has no multi-GPU path in this build "
+        print("bench.py measures one GPU: the single-run hot path has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -259,7 +259,8 @@ def main():
     if not args.no_forecast:
         # the forecast target: the learned-flag AMR runs against the equidistant
         # run to the shock arrival at 1 AU (wall times on this GPU, each run's
-        # relaxation included); after the timed region, outside it
+        # relaxation included, and of the CME phase alone); after the timed
+        # region, outside it
         from paper_2211_12867_amd import forecast
         print("bench: forecast comparison (equidistant vs learned AMR, 4 and 5 levels)", file=sys.stderr, flush=True)
         res = forecast.arrival_comparison(levels=(4, 5), log=lambda m: print("bench: " + m, file=sys.stderr,

@@ -3,7 +3,7 @@
 // TEST INFRASTRUCTURE ONLY (a measurement of the oracle, not part of the HIP
 // path).  oracle.c is compiled as C++ with `double` replaced by a type that
 // counts every floating-point add/subtract, multiply, divide, square root,
-// trigonometric call and comparison.  The driver counts
+// trigonometric call and comparison.  Its main program counts
 //   - the pointwise functions once each (prim, flux pieces, MC slope, fast
 //     speed, Rusanov flux, sources),
 //   - the spatial operator L(U) on a spherical 16 x 12 x 12 patch, per

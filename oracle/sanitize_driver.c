@@ -11,7 +11,7 @@
  * Patches: spherical and cartesian, 8 and 9 variables (the CME density
  * tracer), every limiter, odd interior sizes; states smooth with rho, p > 0.
  * Any out-of-bounds access, use of freed memory, signed overflow, misaligned
- * load or similar aborts the run with the sanitizer's report; the driver also
+ * load or similar aborts the run with the sanitizer's report; the program also
  * checks that every output is finite.  Prints "ok" and exits 0 otherwise.
  */
 #include <math.h>

@@ -4,7 +4,7 @@ oracle/sanitize_driver.c runs every entry point on patches whose arrays have
 exactly their documented sizes (spherical and cartesian, 8 and 9 variables,
 every limiter, odd and one-cell interiors); the build must run clean.  A
 planted heap overrun and a planted signed overflow must be caught, so the
-check cannot pass on an uninstrumented build.  (This build found ora_rhs
+check cannot pass on an uninstrumented build.  (It found ora_rhs
 reading face fluxes through a NULL buffer that its contract allowed.)"""
 import os
 import shutil

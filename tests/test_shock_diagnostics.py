@@ -32,7 +32,7 @@ def test_oracle_triangle_closed_forms():
 
 
 def test_oracle_width_ends_at_the_top_of_the_jump():
-    """A jump to 700 topping out at 46, a dip, then the driver's hump to 800
+    """A jump to 700 topping out at 46, a dip, then a second, higher hump to 800
     at 60: the level is 400 + (800 - 400)/2 = 600, crossed on the jump at
     t = 40 + 6 * 200/300 = 44; the width runs to the top of the jump (46), not
     to the later maximum, and the average gradient is (700 - 600)/2."""
