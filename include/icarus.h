@@ -411,9 +411,10 @@ ic_status ic_mlp_grad(const float *xnorm, const uint8_t *y, int n, float pos_wei
  * targets, grid the launch size (0 = one work-group per leaf block, else a
  * persistent grid striding over the work list), xcd_order = 1 lays the work
  * list out as 8 contiguous runs, one per XCD, so that neighbouring blocks
- * share an L2, ksplit (1, 2 or 4) gives each block that many work-groups, each
- * marching over BK / ksplit planes (for work lists too short to fill the GPU;
- * the face shared by two parts is computed by both from the same inputs).
+ * share an L2, ksplit (1 .. 12, at most BK) gives each block that many
+ * work-groups, each marching over about BK / ksplit planes (for work lists too
+ * short to fill the GPU; the face shared by two parts is computed by both from
+ * the same inputs).
  * stage_ms / default_ms: measured mean stage time of the choice and of
  * (2, 0, 0, 1); from_cache: taken from the cache file; candidates: the
  * schedules timed. */

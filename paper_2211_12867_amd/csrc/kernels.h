@@ -47,7 +47,9 @@ struct KArgs {
 };
 
 // CFL maxima are kept per block and k-part: rate[slot * KSPLIT_MAX + part]
-#define KSPLIT_MAX 4
+// (a block of up to KSPLIT_MAX planes along phi can give each plane its own
+// work-group)
+#define KSPLIT_MAX 12
 
 template <int BI, int BJ, int BK, int NV_ = 8>
 struct Shape {

@@ -717,14 +717,21 @@ __global__ void k_dt(KArgs a, const int *mbeg, const int *mend, int nmembers, do
                 const int q = q0 + u * (int)blockDim.x;
                 sl[u] = q < q1 ? a.items[q] : -1;
             }
+            // every part's entry (a part count changed since the last rate
+            // refresh leaves its entries valid: each stage clears the ones
+            // beyond its own parts), two per 16-byte load
+            static_assert(KSPLIT_MAX % 2 == 0, "rate entries in pairs");
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (sl[u] >= 0)
+                if (sl[u] >= 0) {
+                    const double2 *rp = (const double2 *)(a.rate + (size_t)sl[u] * KSPLIT_MAX);
 #pragma unroll
-                    for (int p = 0; p < KSPLIT_MAX; ++p) {
-                        const double x = a.rate[(size_t)sl[u] * KSPLIT_MAX + p];
-                        r = x > r ? x : r;
+                    for (int p = 0; p < KSPLIT_MAX / 2; ++p) {
+                        const double2 x = rp[p];
+                        r = x.x > r ? x.x : r;
+                        r = x.y > r ? x.y : r;
                     }
+                }
         }
         const double mx = block_max(r, sred);
         if (threadIdx.x == 0) {

@@ -1915,10 +1915,10 @@ std::string tune_prefix(const ic_sim *s)
 
 void apply_tuning(ic_sim *s, int waves, int grid, int xcd, int ksplit)
 {
-    if ((waves != 1 && waves != 2) || grid < 0 || (xcd != 0 && xcd != 1) ||
-        (ksplit != 1 && ksplit != 2 && ksplit != 4) || ksplit > s->B[2])
+    if ((waves != 1 && waves != 2) || grid < 0 || (xcd != 0 && xcd != 1) || ksplit < 1 || ksplit > KSPLIT_MAX ||
+        ksplit > s->B[2])
         throw Error(IC_E_INVALID, "tuning: waves_per_simd 1 or 2, grid >= 0, xcd_order 0 or 1, "
-                                  "ksplit 1, 2 or 4 (at most the block's phi size)");
+                                  "ksplit 1 .. " + std::to_string(KSPLIT_MAX) + " (at most the block's phi size)");
     s->tune_waves = waves;
     s->tune_grid = grid;
     s->tune_xcd = xcd;
@@ -2854,8 +2854,11 @@ ic_status ic_autotune(ic_sim *s, const char *cache_path, int reps, ic_tune_info 
             hipDeviceProp_t prop{};
             if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
                 cus = prop.multiProcessorCount;
-            for (int ks : {1, 2, 4}) {
+            for (int ks : {1, 2, 4, 6, 12}) {
                 if (ks > s->B[2]) continue;
+                // more than four parts (down to one plane per work-group) only
+                // for lists that four parts leave below two work-groups per CU
+                if (ks > 4 && s->n_items * 4 >= 2 * cus) continue;
                 const int n = std::max(1, s->n_items * ks);
                 std::vector<int> grids{0};
                 for (int g : {1024, 2048})

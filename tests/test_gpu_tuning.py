@@ -1,12 +1,13 @@
 """The stage-kernel schedule and its autotuner, through the C ABI.
 
 - every schedule (waves per SIMD 1 or 2, one work-group per leaf or a
-  persistent grid, plain or XCD-contiguous work order, 1, 2 or 4 work-groups
-  per block along phi) gives the same state bit for bit on the equidistant
-  512 x 60 x 180 domain (2,400 blocks);
-- with 4 work-groups per block, a refined wedge with regrids (reflux and flux
-  registers at coarse-fine faces, split boundaries inside blocks) matches
-  the oracle;
+  persistent grid, plain or XCD-contiguous work order, 1 to 12 work-groups
+  per block along phi, evenly or unevenly split, down to one plane each)
+  gives the same state bit for bit on the equidistant 512 x 60 x 180 domain
+  (2,400 blocks of 16 x 12 x 12);
+- with 4, 5 or 8 work-groups per 8^3 block (the last: one plane each), a
+  refined wedge with regrids (reflux and flux registers at coarse-fine
+  faces, split boundaries inside blocks) matches the oracle;
 - ic_autotune leaves the state and time untouched, picks a schedule at most
   1 % slower than the default on its own measurement (near-ties keep the
   earlier candidate), and returns the same choice from its cache on the
@@ -35,7 +36,7 @@ def _sim(ic):
 
 
 SCHEDULES = [(2, 0, 0, 1), (1, 0, 0, 1), (2, 1024, 0, 1), (2, 0, 1, 1), (1, 1024, 1, 1), (2, 0, 0, 2),
-             (2, 0, 1, 4), (2, 1024, 1, 2)]
+             (2, 0, 1, 4), (2, 1024, 1, 2), (2, 0, 0, 5), (1, 0, 1, 6), (2, 2048, 0, 12)]
 
 
 def test_schedules_are_bit_identical():
@@ -77,14 +78,15 @@ def test_autotune_keeps_state_and_caches(tmp_path):
 def test_invalid_schedule_rejected():
     ic = _ic()
     sim = _sim(ic)
-    for bad in ((3, 0, 0, 1), (2, 0, 0, 3), (2, -1, 0, 1)):
+    for bad in ((3, 0, 0, 1), (2, 0, 0, 0), (2, 0, 0, 13), (2, -1, 0, 1)):
         with pytest.raises(ic.ICError) as e:
             sim.set_tuning(*bad)
         assert e.value.status == ic.IC_E_INVALID
     sim.close()
 
 
-def test_ksplit_amr_wedge_matches_oracle():
+@pytest.mark.parametrize("ks", [4, 5, 8])
+def test_ksplit_amr_wedge_matches_oracle(ks):
     ic = _ic()
     from gpu_helpers import rel_err
     from oracle import solver, units
@@ -93,7 +95,7 @@ def test_ksplit_amr_wedge_matches_oracle():
     ora = solver.Solver(grid, wind, cme, amr)
     gpu = ic.Sim(grid, wind, [cme], amr)
     gpu.set_state(*ora.state(), 0.0)
-    gpu.set_tuning(2, 0, 1, 4)
+    gpu.set_tuning(2, 0, 1, ks)
     for cycle in range(3):
         for _ in range(5):
             ora.step()
