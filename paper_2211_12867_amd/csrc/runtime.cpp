@@ -386,10 +386,13 @@ struct ic_sim {
     double sample_point[3] = {1.0, 90.0, 0.0};
 
     // graph
-    hipGraphExec_t gexec = nullptr;
-    bool graph_dirty = true;
-    std::vector<int> graph_sig;     // launch sizes the captured graph was made with
-    double graph_dt_fixed = -1.0;
+    // graph: [0] one step, [1] GRAPH_STEPS steps in one replay
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<int> sig;       // launch sizes the graph was captured with
+        double dt_fixed = -1.0;
+    } graphs[2];
+    bool graph_dirty = true;        // a buffer or the schedule changed: both graphs are stale
     bool use_graph = true;
 
     // learned flags
@@ -1200,28 +1203,48 @@ void enqueue_step(ic_sim *s, double dt_fixed_code, bool record)
     else launch_time(s->stream, s->t.p, s->dt.p, s->nsteps.p, s->nm);
 }
 
-void run_step(ic_sim *s, double dt_fixed_code, bool record)
+// Steps per replay of the multi-step graph: one graph launch per step leaves
+// a gap of ~8 us before each step's first kernel, as long as a short step on
+// a small grid.  Within a replay the steps follow each other on the device
+// (dt, clipped to the end time, is reduced on the device; a member past its
+// end time takes dt = 0 and its kernels do nothing).
+constexpr int GRAPH_STEPS = 5;
+
+void release_graphs(ic_sim *s)
+{
+    for (auto &g : s->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
+    }
+}
+
+// nsteps (1 or GRAPH_STEPS) steps, each recording the sample, in one replay of
+// a captured graph (re-captured when a buffer, the schedule or a launch size
+// changed), or enqueued directly while kernel timing is on
+void run_steps(ic_sim *s, double dt_fixed_code, int nsteps)
 {
     if (s->timing || !s->use_graph) {
-        enqueue_step(s, dt_fixed_code, record);
+        for (int q = 0; q < nsteps; ++q) enqueue_step(s, dt_fixed_code, true);
         return;
     }
-    if (s->graph_dirty || s->gexec == nullptr || s->graph_dt_fixed != dt_fixed_code ||
-        s->graph_sig != launch_sig(s)) {
-        if (s->gexec) HIPCHECK(hipGraphExecDestroy(s->gexec));
-        s->gexec = nullptr;
+    if (s->graph_dirty) {
+        release_graphs(s);
+        s->graph_dirty = false;
+    }
+    auto &G = s->graphs[nsteps > 1 ? 1 : 0];
+    if (G.exec == nullptr || G.dt_fixed != dt_fixed_code || G.sig != launch_sig(s)) {
+        if (G.exec) HIPCHECK(hipGraphExecDestroy(G.exec));
+        G.exec = nullptr;
         hipGraph_t g;
         HIPCHECK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_step(s, dt_fixed_code, true);
+        for (int q = 0; q < nsteps; ++q) enqueue_step(s, dt_fixed_code, true);
         HIPCHECK(hipStreamEndCapture(s->stream, &g));
-        HIPCHECK(hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0));
+        HIPCHECK(hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0));
         HIPCHECK(hipGraphDestroy(g));
-        s->graph_dirty = false;
-        s->graph_dt_fixed = dt_fixed_code;
-        s->graph_sig = launch_sig(s);
+        G.dt_fixed = dt_fixed_code;
+        G.sig = launch_sig(s);
     }
-    (void)record;
-    HIPCHECK(hipGraphLaunch(s->gexec, s->stream));
+    HIPCHECK(hipGraphLaunch(G.exec, s->stream));
 }
 
 std::string describe_bad(ic_sim *s, int m, int slot, int cell);
@@ -2169,7 +2192,7 @@ void ic_destroy(ic_sim *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    release_graphs(s);
     for (auto e : s->ev) (void)hipEventDestroy(e);
     for (auto &L : s->lv) {
         L.dr.release(); L.dt.release(); L.dp.release(); L.dwind.release(); L.dcosd.release();
@@ -2264,7 +2287,7 @@ ic_status ic_step(ic_sim *s, double dt_fixed_s, ic_info *out)
         check_sim(s);
         if (dt_fixed_s < 0.0) throw Error(IC_E_INVALID, "negative dt");
         if (s->tend_finite) clear_tend(s);
-        run_step(s, dt_fixed_s / kT0, true);
+        run_steps(s, dt_fixed_s / kT0, 1);
         s->zone_updates += (double)total_cells(s);
         s->host_steps++;
         s->since_regrid++;
@@ -2298,7 +2321,9 @@ ic_status ic_advance(ic_sim *s, double dt_s, long max_steps, ic_info *out)
         while (done < max_steps) {
             const long due = every > 0 ? every - s->since_regrid : 20;
             const long batch = std::min<long>(max_steps - done, due);
-            for (long q = 0; q < batch; ++q) run_step(s, 0.0, true);
+            long q = 0;
+            for (; q + GRAPH_STEPS <= batch; q += GRAPH_STEPS) run_steps(s, 0.0, GRAPH_STEPS);
+            for (; q < batch; ++q) run_steps(s, 0.0, 1);
             done += batch;
             st = read_status(s);
             long taken = 0;
