@@ -79,13 +79,16 @@ __global__ void __launch_bounds__(256) k_features(KArgs a, const int *items, con
 // GEMM: C = A B (+ bias, relu), bf16 operands, fp32 accumulate on gfx950's
 // v_mfma_f32_16x16x32_bf16.  A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn].
 // A work-group of 4 waves computes a 64x64 tile of C, each wave a 32x32
-// quarter as 2x2 MFMA blocks of 16x16.  K advances in steps of 32 staged
-// through LDS: As[m][k] and Bt[n][k] with k contiguous, so that a lane's
-// MFMA operand -- row (A) or column (B) l % 16 and eight consecutive k,
+// quarter as 2x2 MFMA blocks of 16x16.  K advances in MFMA steps of 32 (the
+// order in which they accumulate), staged through LDS four steps (128 k) at
+// a time: As[m][k] and Bt[n][k] with k contiguous, so that a lane's MFMA
+// operand -- row (A) or column (B) l % 16 and eight consecutive k,
 // 8 (l / 16) + 0..7 -- is one 16-byte LDS read (rows padded by 8 bf16 to
-// spread them over the banks); the global loads of a stage run along
-// whichever of m/k (A) or k/n (B) is contiguous in memory.  The accumulator
-// holds column l % 16 and rows 4 (l / 16) + 0..3 of a block.
+// spread them over the banks).  Each thread moves 16-byte pieces (eight
+// elements along whichever index is contiguous in memory) with one global
+// load each; the next stage's loads are in flight while the MFMAs of the
+// current one run, from the other of two LDS buffers.  The accumulator holds
+// column l % 16 and rows 4 (l / 16) + 0..3 of a block.
 // Split K (gridDim.z > 1, weight gradients with K = the batch rows): each
 // z-slice accumulates its share of the k-steps and writes fp32 partials
 // P[z][m][n]; k_gemm_reduce sums them in slice order (deterministic) and
@@ -113,46 +116,91 @@ DEV_EPI void gemm_store(const GemmArgs &g, int m, int n, float v)
     if (g.Cb) g.Cb[(long)m * g.ldc + n] = f2bf(v);
 }
 
+constexpr int GEMM_KS = 128;               // k per LDS stage (four MFMA steps)
+constexpr int GEMM_KP = GEMM_KS + 8;       // padded LDS row, bf16
+
+// The 16-byte pieces of one stage of a 64-row operand tile X(r, k) (r = m of
+// A or n of B): piece e of thread tid.  kc: X is contiguous along k (pieces
+// run along k, 16 per row of the stage); else along r (8 per k-row).
+// Pieces outside 0 <= r < R or k < K are zero.
+DEV_EPI void tile_load(const uint16_t *X, long sr, long sk, bool kc, int r0, int R, int kb, int K, int tid,
+                       uint4 *out)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = e * 256 + tid;
+        const int r = kc ? c >> 4 : (c & 7) * 8, k = kc ? (c & 15) * 8 : c >> 3;
+        const int gr = r0 + r, gk = kb + k;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gr < R && gk < K) v = *(const uint4 *)(X + (long)gr * sr + (long)gk * sk);
+        out[e] = v;
+    }
+}
+
+DEV_EPI void tile_store(uint16_t *L, bool kc, int tid, const uint4 *in)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = e * 256 + tid;
+        if (kc) {
+            *(uint4 *)&L[(c >> 4) * GEMM_KP + (c & 15) * 8] = in[e];
+        } else {                                  // eight rows, one k: transposed into LDS
+            const int r = (c & 7) * 8, k = c >> 3;
+            const uint32_t w[4] = {in[e].x, in[e].y, in[e].z, in[e].w};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) L[(r + i) * GEMM_KP + k] = (uint16_t)(w[i >> 1] >> (16 * (i & 1)));
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g)
 {
-    constexpr int KP = 40;                         // padded row of 32 bf16
-    __shared__ __attribute__((aligned(16))) uint16_t As[64 * KP];
-    __shared__ __attribute__((aligned(16))) uint16_t Bt[64 * KP];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * GEMM_KP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bt[2][64 * GEMM_KP];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
     const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
     const int r = lane & 15, kq = (lane >> 4) * 8;
     const int nstep = (g.K + 31) / 32;
     const int s0 = (int)((long)nstep * blockIdx.z / gridDim.z), s1 = (int)((long)nstep * (blockIdx.z + 1) / gridDim.z);
-    const bool a_k = g.sak == 1, b_n = g.sbn == 1;
+    // A as X(m, k): contiguous along k when sak == 1; B as X(n, k): along k when sbk == 1
+    const bool a_k = g.sak == 1, b_k = g.sbk == 1;
+    const long ar = g.sam, ak = g.sak, br = g.sbn, bk = g.sbk;
     float4_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int st = s0; st < s1; ++st) {
-        const int k0 = st * 32;
-        __syncthreads();                           // the previous stage's operands are consumed
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = e * 256 + tid;
-            const int am = a_k ? idx >> 5 : idx & 63, ak = a_k ? idx & 31 : idx >> 6;
-            const int gm = m0 + am, gka = k0 + ak;
-            As[am * KP + ak] = (gm < g.M && gka < g.K) ? g.A[(long)gm * g.sam + (long)gka * g.sak] : (uint16_t)0;
-            const int bn = b_n ? idx & 63 : idx >> 5, bk = b_n ? idx >> 6 : idx & 31;
-            const int gn = n0 + bn, gkb = k0 + bk;
-            Bt[bn * KP + bk] = (gn < g.N && gkb < g.K) ? g.B[(long)gkb * g.sbk + (long)gn * g.sbn] : (uint16_t)0;
-        }
+    const int kend = s1 * 32;
+    uint4 ra[4], rb[4];
+    int kb = s0 * 32;
+    if (kb < kend) {
+        tile_load(g.A, ar, ak, a_k, m0, g.M, kb, g.K, tid, ra);
+        tile_load(g.B, br, bk, b_k, n0, g.N, kb, g.K, tid, rb);
+    }
+    for (int buf = 0; kb < kend; kb += GEMM_KS, buf ^= 1) {
+        // the buffer written here was last read two stages ago, before the
+        // barrier of the previous stage
+        tile_store(As[buf], a_k, tid, ra);
+        tile_store(Bt[buf], b_k, tid, rb);
         __syncthreads();
-        bf16x8_t a[2], b[2];
+        if (kb + GEMM_KS < kend) {
+            tile_load(g.A, ar, ak, a_k, m0, g.M, kb + GEMM_KS, g.K, tid, ra);
+            tile_load(g.B, br, bk, b_k, n0, g.N, kb + GEMM_KS, g.K, tid, rb);
+        }
+        const int nk = (kend - kb < GEMM_KS ? kend - kb : GEMM_KS) / 32;
+        for (int kk = 0; kk < nk; ++kk) {
+            bf16x8_t a[2], b[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8_t *)&As[(wm + 16 * i + r) * KP + kq];
+            for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8_t *)&As[buf][(wm + 16 * i + r) * GEMM_KP + kk * 32 + kq];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8_t *)&Bt[(wn + 16 * j + r) * KP + kq];
+            for (int j = 0; j < 2; ++j) b[j] = *(const bf16x8_t *)&Bt[buf][(wn + 16 * j + r) * GEMM_KP + kk * 32 + kq];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -331,6 +379,13 @@ constexpr int GEMM_SPLIT_MAX = 32;
 void gemm(hipStream_t s, const uint16_t *A, long sam, long sak, const uint16_t *B, long sbk, long sbn, int M, int N,
           int K, const float *bias, int relu, float *Cf, uint16_t *Cb, long ldc, float *work = nullptr)
 {
+    // the stage loads move 16-byte pieces along the contiguous index of each
+    // operand: a unit stride, the other stride and that index's extent
+    // multiples of 8, 16-byte aligned bases (every call of this file)
+    const bool a_ok = (sak == 1 && sam % 8 == 0 && K % 8 == 0) || (sam == 1 && sak % 8 == 0 && M % 8 == 0);
+    const bool b_ok = (sbk == 1 && sbn % 8 == 0 && K % 8 == 0) || (sbn == 1 && sbk % 8 == 0 && N % 8 == 0);
+    if (!a_ok || !b_ok || ((uintptr_t)A & 15) || ((uintptr_t)B & 15))
+        throw std::runtime_error("gemm: operand layout not supported by the staged loads");
     GemmArgs g{A, sam, sak, B, sbk, sbn, M, N, K, bias, relu, Cf, Cb, ldc, work};
     const int tiles = ((N + 63) / 64) * ((M + 63) / 64), nstep = (K + 31) / 32;
     int nz = 1;

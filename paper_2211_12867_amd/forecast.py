@@ -505,8 +505,8 @@ def main(argv=None):
         c1 = dict(c1, t_start_s=args.relax_days * DAY)
         log("== equidistant")
         res["equidistant"] = cme_run(g1, w1, c1, dict(regrid_every=0), None, t_end, log=log, chunk_s=DAY)
-    summary = {k: {q: v[q] for q in ("arrival_h", "width_h", "wall_s", "steps", "leaf_block_steps", "max_leaves",
-                                     "regrid_stats")} for k, v in res.items()}
+    summary = {k: {q: v[q] for q in ("arrival_h", "width_h", "wall_s", "cme_wall_s", "steps", "leaf_block_steps",
+                                     "max_leaves", "regrid_stats")} for k, v in res.items()}
     log(json.dumps(summary))
     if args.out:
         np.savez(args.out, **{"%s_%s" % (k, q): res[k][q] for k in res for q in ("t_h", "v_kms")},
