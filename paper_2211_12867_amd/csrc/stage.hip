@@ -209,46 +209,56 @@ k_stage(KArgs a)
         }
         // halos of plane k0 and the halo address table (a halo cell's address
         // is affine in v and in k within the block's k-range), by the threads
-        // that own no column, beside the column prologue; all loads first
-        if (!col) {
-            constexpr int NSP = NT - NCOL, HIT = (NHALO + NSP - 1) / NSP;
-            const FaceMap fm[4] = {face_map<S>(a, slot, nb, 0, 0), face_map<S>(a, slot, nb, 0, 1),
-                                   face_map<S>(a, slot, nb, 1, 0), face_map<S>(a, slot, nb, 1, 1)};
-            double u[HIT][NV];
+        // that own no column beside the column prologue, one cell each; where
+        // the halo has more cells than they are threads, the last column
+        // threads take one cell each as well (their loads go out with the
+        // column loads; all loads first)
+        {
+            constexpr int NSP = NT - NCOL;
+            constexpr int NXH = NHALO > NSP ? NHALO - NSP : 0;
+            static_assert(NXH <= 64 && NHALO <= NSP + NXH, "halo cells per thread");
+            constexpr int HIT = NXH > 0 ? 1 : (NHALO + NSP - 1) / NSP;
+            const bool helper = NXH > 0 && col && tid >= NCOL - NXH;
+            const int tb = col ? (helper ? NSP + tid - (NCOL - NXH) : NHALO) : tid - NCOL;
+            if (tb < NHALO) {
+                const FaceMap fm[4] = {face_map<S>(a, slot, nb, 0, 0), face_map<S>(a, slot, nb, 0, 1),
+                                       face_map<S>(a, slot, nb, 1, 0), face_map<S>(a, slot, nb, 1, 1)};
+                double u[HIT][NV];
 #pragma unroll
-            for (int h = 0; h < HIT; ++h) {
-                const int t = tid - NCOL + h * NSP;
-                if (t < NHALO) {
-                    int i, j;
-                    halo_cell<BI, BJ>(t, i, j);
-                    const bool rh = t < NHR;                  // r-halo, else theta-halo
-                    const int idx = rh ? i : j, bd_ = rh ? BI : BJ;
-                    const int side = idx >= bd_ ? 1 : 0, l = side ? idx - bd_ : idx + 2, q = rh ? j : i;
-                    const int f = (rh ? 0 : 2) + side;
-                    const FaceMap &m0 = fm[0], &m1 = fm[1], &m2 = fm[2], &m3 = fm[3];
-                    const double *fb = f == 0 ? m0.base : f == 1 ? m1.base : f == 2 ? m2.base : m3.base;
-                    const int fl = f == 0 ? m0.sl : f == 1 ? m1.sl : f == 2 ? m2.sl : m3.sl;
-                    const int fa = f == 0 ? m0.sa : f == 1 ? m1.sa : f == 2 ? m2.sa : m3.sa;
-                    const int hk = f == 0 ? m0.sk : f == 1 ? m1.sk : f == 2 ? m2.sk : m3.sk;
-                    const int hv = f == 0 ? m0.sv : f == 1 ? m1.sv : f == 2 ? m2.sv : m3.sv;
-                    const double *p0 = fb + l * fl + q * fa;
-                    sHB[t] = p0;
-                    sHV[t] = hv;
-                    sHK[t] = hk;
+                for (int h = 0; h < HIT; ++h) {
+                    const int t = tb + h * NSP;
+                    if (t < NHALO) {
+                        int i, j;
+                        halo_cell<BI, BJ>(t, i, j);
+                        const bool rh = t < NHR;                  // r-halo, else theta-halo
+                        const int idx = rh ? i : j, bd_ = rh ? BI : BJ;
+                        const int side = idx >= bd_ ? 1 : 0, l = side ? idx - bd_ : idx + 2, q = rh ? j : i;
+                        const int f = (rh ? 0 : 2) + side;
+                        const FaceMap &m0 = fm[0], &m1 = fm[1], &m2 = fm[2], &m3 = fm[3];
+                        const double *fb = f == 0 ? m0.base : f == 1 ? m1.base : f == 2 ? m2.base : m3.base;
+                        const int fl = f == 0 ? m0.sl : f == 1 ? m1.sl : f == 2 ? m2.sl : m3.sl;
+                        const int fa = f == 0 ? m0.sa : f == 1 ? m1.sa : f == 2 ? m2.sa : m3.sa;
+                        const int hk = f == 0 ? m0.sk : f == 1 ? m1.sk : f == 2 ? m2.sk : m3.sk;
+                        const int hv = f == 0 ? m0.sv : f == 1 ? m1.sv : f == 2 ? m2.sv : m3.sv;
+                        const double *p0 = fb + l * fl + q * fa;
+                        sHB[t] = p0;
+                        sHV[t] = hv;
+                        sHK[t] = hk;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) u[h][v] = p0[v * hv + k0 * hk];
+                        for (int v = 0; v < NV; ++v) u[h][v] = p0[v * hv + k0 * hk];
+                    }
                 }
-            }
 #pragma unroll
-            for (int h = 0; h < HIT; ++h) {
-                const int t = tid - NCOL + h * NSP;
-                if (t < NHALO) {
-                    int i, j;
-                    halo_cell<BI, BJ>(t, i, j);
-                    double w[NV];
-                    cons_to_prim<false, NV>(u[h], w, gs);
+                for (int h = 0; h < HIT; ++h) {
+                    const int t = tb + h * NSP;
+                    if (t < NHALO) {
+                        int i, j;
+                        halo_cell<BI, BJ>(t, i, j);
+                        double w[NV];
+                        cons_to_prim<false, NV>(u[h], w, gs);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) sW[v][j + 2][i + 2] = w[v];
+                        for (int v = 0; v < NV; ++v) sW[v][j + 2][i + 2] = w[v];
+                    }
                 }
             }
         }
