@@ -151,15 +151,19 @@ k_stage(KArgs a)
     __shared__ RecP sP[BK + 4];
     __shared__ double sred[NT / 64];
 
-    const int tid = threadIdx.x;
-    const bool col = tid < NCOL;
-    const int ci = tid % BI, cj = tid / BI;      // column owned by this thread
     const Gas gs = a.gas;
     const int nitems = *a.nitems;
 
     const int ks = a.ksplit;                     // parts of the march along k per block
     const int nwork = nitems * ks;
     for (int wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        // the thread index, opaque to the compiler once per work item: the
+        // addresses and masks derived from it are formed per item instead of
+        // being kept live (or spilled) across the whole kernel
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const bool col = tid < NCOL;
+        const int ci = tid % BI, cj = tid / BI;      // column owned by this thread
         const int ww = a.xcd_order ? xcd_item(wi, nwork) : wi;
         const int it = ww / ks, part = ww % ks;
         const int k0 = part * BK / ks, k1 = (part + 1) * BK / ks;
