@@ -6,7 +6,8 @@ time and the steps since the last regrid); a fresh sim restored from it
 continues bit for bit like the run that was never interrupted, through
 regrids at the original cadence.  Two sims of the same configuration give
 bit-identical blocks and states (no order-dependent reductions on the
-path)."""
+path), and an advance over captured multi-step graphs gives what single
+steps with the same regrids give."""
 import numpy as np
 import pytest
 
@@ -67,6 +68,26 @@ def test_two_runs_are_bit_identical():
     assert np.array_equal(out[0][1], out[1][1])
     assert out[0][2] == out[1][2]
     assert np.array_equal(out[0][3], out[1][3])
+
+
+def test_advance_equals_single_steps_and_regrids():
+    """ic_advance replays captured graphs of five steps (and of one step for
+    the rest of a batch); 13 steps with regrids after steps 5 and 10 equal 13
+    single ic_step calls with ic_regrid after the 5th and 10th, bit for bit."""
+    ic = _ic()
+    grid, wind, cme, amr = _wedge()
+    a = ic.Sim(grid, wind, [cme], amr)
+    a.advance(BIG, 13)
+    b = ic.Sim(grid, wind, [cme], amr)
+    for n in range(1, 14):
+        b.step()
+        if n in (5, 10):
+            b.regrid()
+    assert a.blocks() == b.blocks()
+    assert max(blk[0] for blk in a.blocks()) >= 2
+    assert np.array_equal(a.state()[1], b.state()[1])
+    assert a.clock() == b.clock() and a.clock()[1] == 3
+    assert np.array_equal(a.timeseries(), b.timeseries())
 
 
 def test_clock_rejects_bad_values():

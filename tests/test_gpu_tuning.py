@@ -57,6 +57,35 @@ def test_schedules_are_bit_identical():
             assert np.array_equal(U, ref[0]), (waves, grid, xcd, ks)
 
 
+@pytest.mark.parametrize("tracer", [False, True])
+def test_schedules_are_bit_identical_on_a_refined_12cubed_wedge(tracer):
+    """AMR blocks of 12^3 (ghost slabs, flux registers, reflux), with and
+    without the CME density tracer, over a regrid."""
+    ic = _ic()
+    grid = dict(geometry="spherical", x0=(0.1, 60.0, 0.0), x1=(1.1, 120.0, 90.0), n=(48, 12, 24),
+                block=(12, 12, 12), stretched_r=True, max_level=3, periodic=(False, False, False), gamma=1.5,
+                cfl=0.4)
+    from synthetic import Cme, Wind
+    wind = as_dict(Wind(seed=11))
+    cme = as_dict(Cme(t_start_s=0.0, duration_s=6 * 3600.0, v_kms=1400.0, half_width_deg=35.0,
+                      colat_deg=90.0, lon_deg=40.0, n_cm3=1500.0, T_K=0.8e6))
+    amr = dict(dlon_earth_deg=60.0, dclt_earth_deg=30.0, regrid_every=4, buffer_blocks=1)
+    ref = None
+    for sched in ((2, 0, 0, 1), (2, 0, 1, 4), (1, 1024, 0, 12), (2, 0, 0, 5), (2, 256, 1, 6)):
+        sim = ic.Sim(grid, wind, [cme], amr, tracer=tracer)
+        sim.set_tuning(*sched)
+        sim.advance(1e12, 9)                       # regrids after steps 4 and 8
+        out = (sim.blocks(), sim.state()[1], sim.clock())
+        sim.close()
+        if ref is None:
+            ref = out
+            assert max(b[0] for b in out[0]) >= 2
+        else:
+            assert out[0] == ref[0], sched
+            assert np.array_equal(out[1], ref[1]), sched
+            assert out[2] == ref[2], sched
+
+
 def test_autotune_keeps_state_and_caches(tmp_path):
     ic = _ic()
     sim = _sim(ic)
