@@ -257,7 +257,8 @@ ic_status ic_sample(ic_sim *sim, int member, double r_au, double colat_deg, doub
  * 90, 0): Earth in the co-rotating frame, Sect. 3.1). */
 ic_status ic_set_sample_point(ic_sim *sim, double r_au, double colat_deg, double lon_deg);
 
-/* Recorded time series at the sample point (Sect. 3.1), one entry per step:
+/* Recorded time series at the sample point (Sect. 3.1), one entry per step
+ * a member took (a step past its end time, dt = 0, records nothing):
  * out[s * 9 + 0] = t [s], out[s * 9 + 1..8] =
  * primitives (code units); *n_inout is the capacity in samples on entry and
  * the count written on return (the most recent ones if the record is longer).

@@ -976,7 +976,9 @@ __global__ void k_sample(KArgs a, const SampleDesc *sd, int nmembers, double *ou
     for (int e = 0; e < 8; ++e)                 // summed in entry order
         for (int v = 0; v < 8; ++v) acc[v] += sw[e][8] * sw[e][v];
     for (int v = 0; v < 8; ++v) out[m * 8 + v] = acc[v];
-    if (record) {
+    // a launch that ends a step records the sample only for a member that took
+    // the step (one past its end time takes dt = 0 and records nothing)
+    if (record && !(t_step && !(a.dt[m] > 0.0))) {
         const int c = ring_count[m];
         double *r = ring + ((size_t)m * ring_cap + (c % ring_cap)) * 9;
         r[0] = t_step ? t_step[m] : a.t[m];
