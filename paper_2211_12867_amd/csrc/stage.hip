@@ -2,7 +2,8 @@
 //
 // k_stage is the fused finite-volume stage (paper Sect. 2.1: TVDLF with a
 // Woodward-type limiter, second order): a work-group marches along k (phi)
-// through a leaf block (or through 1/2 or 1/4 of it, for short work lists).
+// through a leaf block (or through a part of it, down to one plane, for short
+// work lists).
 // For each k-plane the primitives of the plane and of its two-cell i/j halos
 // sit in LDS; every cell is reconstructed once per direction, and every r- and
 // theta-face flux of the plane is computed once by one thread (which takes the
