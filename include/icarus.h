@@ -107,7 +107,7 @@ typedef struct {
  * ninth conserved variable rho s (s the CME mass fraction: 1 in the cone CME
  * at the inner boundary, 0 in the wind and in the initial state), advected
  * by the same TVDLF flux with the same maximum speed, no source, left alone
- * by the floors; IC_LIM_MC only. */
+ * by the floors; with any limiter and either time scheme. */
 enum { IC_LIM_MC = 0, IC_LIM_MINMOD = 1, IC_LIM_VANLEER = 2 };
 enum { IC_SCHEME_TWO_STAGE = 0, IC_SCHEME_HANCOCK = 1 };
 typedef struct {

@@ -537,14 +537,9 @@ __global__ void __launch_bounds__(NT) k_hancock(KArgs a)
 template <int BI, int BJ, int BK, int NV>
 void launch_hancock(dim3 g, hipStream_t s, const KArgs &a, int limiter)
 {
-    if constexpr (NV > 8) {
-        hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MC>), g, dim3(NT), 0, s, a);
-    } else {
-        if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MINMOD>), g, dim3(NT), 0, s, a);
-        else if (limiter == LIM_VANLEER)
-            hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_VANLEER>), g, dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MC>), g, dim3(NT), 0, s, a);
-    }
+    if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+    else if (limiter == LIM_VANLEER) hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_hancock<BI, BJ, BK, NV, LIM_MC>), g, dim3(NT), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------

@@ -2026,8 +2026,6 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         if (!(phys->divb_cd >= 0.0 && phys->divb_cd <= 1.0))
             throw Error(IC_E_INVALID, "the cleaning coefficient divb_cd must lie in [0, 1]");
         if (phys->tracer != 0 && phys->tracer != 1) throw Error(IC_E_INVALID, "tracer must be 0 or 1");
-        if (phys->tracer && phys->limiter != IC_LIM_MC)
-            throw Error(IC_E_INVALID, "the tracer is built with the IC_LIM_MC limiter only");
         if (amr) {
             if (amr->criterion < IC_CRIT_SHOCK || amr->criterion > IC_CRIT_COMBINED)
                 throw Error(IC_E_INVALID, "unknown refinement criterion");

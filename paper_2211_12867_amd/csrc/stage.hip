@@ -530,14 +530,17 @@ k_stage(KArgs a)
 // instantiations and launch
 // ---------------------------------------------------------------------------
 // the other limiters are built for two waves per SIMD only; the tracer (NV =
-// 9) with the paper's limiter and two waves per SIMD where two work-groups'
-// LDS fits a CU (one on planes of more than 160 cells)
+// 9) with two waves per SIMD where two work-groups' LDS fits a CU (one on
+// planes of more than 160 cells), every limiter
 template <int BI, int BJ, int BK, int NV>
 void launch_stage(dim3 g, hipStream_t s, const KArgs &a, int waves, int limiter)
 {
     if constexpr (NV > 8) {
         constexpr int W9 = BI * BJ > 160 ? 1 : 2;
-        hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, W9, LIM_MC>), g, dim3(NT), 0, s, a);
+        if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, W9, LIM_MINMOD>), g, dim3(NT), 0, s, a);
+        else if (limiter == LIM_VANLEER)
+            hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, W9, LIM_VANLEER>), g, dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, W9, LIM_MC>), g, dim3(NT), 0, s, a);
     } else {
         if (limiter == LIM_MINMOD) hipLaunchKernelGGL((k_stage<BI, BJ, BK, NV, 2, LIM_MINMOD>), g, dim3(NT), 0, s, a);
         else if (limiter == LIM_VANLEER)

@@ -51,7 +51,6 @@ def test_tracer_configs_are_checked_before_any_device_work():
     g = dict(geometry="cartesian", x0=(0.0, 0.0, 0.0), x1=(1.0, 1.0, 1.0), n=(8, 8, 8), block=(8, 8, 8),
              periodic=(True, True, True), max_level=2, gamma=1.5, cfl=0.4)
     for kw, amr in ((dict(), dict(criterion="tracer")),                       # criterion without the tracer
-                    (dict(tracer=True, limiter="minmod"), dict()),            # the tracer is built for MC only
                     (dict(tracer=True), dict(criterion="combined", source=1)),  # learned flags: shock only
                     (dict(tracer=True), dict(criterion="tracer", tracer_refine=0.001, tracer_coarsen=0.01)),
                     (dict(tracer=True), dict(criterion=3))):

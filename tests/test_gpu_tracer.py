@@ -9,8 +9,8 @@ tracer condition combined with the shock criterion inside the windows).
 - With s = 1 everywhere rho s stays equal to rho bit for bit on the GPU too
   (the same flux form, maximum speed, reflux and ghost operators).
 - Parity of all nine variables with the oracle on the refined box and on the
-  cone-CME wedge (both time schemes), where the inner boundary brings s = 1
-  inside the cone and s = 0 in the wind.
+  cone-CME wedge (both time schemes, each limiter), where the inner boundary
+  brings s = 1 inside the cone and s = 0 in the wind.
 - Criterion parity: block flags bit-exact with the oracle's on identical
   states, then the regridded forest and the moved state, over several cycles
   of a refined wedge with the tracer and the combined criteria.
@@ -97,13 +97,15 @@ def test_unit_fraction_tracer_is_the_density_on_the_gpu():
     assert gpu.floor_counts() == (0, 0)
 
 
-@pytest.mark.parametrize("sch,cd", [("two_stage", 0.0), ("hancock", 0.0), ("two_stage", 0.3)])
-def test_cme_wedge_tracer_parity(sch, cd):
-    """Both time schemes, and the parabolic cleaning beside the tracer."""
+@pytest.mark.parametrize("sch,cd,lim", [("two_stage", 0.0, "mc"), ("hancock", 0.0, "mc"), ("two_stage", 0.3, "mc"),
+                                        ("two_stage", 0.0, "minmod"), ("hancock", 0.0, "vanleer")])
+def test_cme_wedge_tracer_parity(sch, cd, lim):
+    """Both time schemes, the parabolic cleaning and the other limiters beside
+    the tracer."""
     ic = _ic()
     g, wind, cme, amr = tiny_wedge()
-    ora = solver.Solver(g, wind, cme, amr, tracer=True, scheme=sch, divb_cd=cd)
-    gpu = ic.Sim(g, wind, [cme], amr, tracer=True, scheme=sch, divb_cd=cd)
+    ora = solver.Solver(g, wind, cme, amr, tracer=True, scheme=sch, divb_cd=cd, limiter=lim)
+    gpu = ic.Sim(g, wind, [cme], amr, tracer=True, scheme=sch, divb_cd=cd, limiter=lim)
     bl, U = gpu.state()
     assert U.shape[1] == 9 and np.all(U[:, 8] == 0.0)     # no CME material initially
     gpu.set_state(*ora.state(), 0.0)
