@@ -180,11 +180,13 @@ def _amr_wedge(max_level=3, n=(32, 16, 16), block=(8, 8, 8)):
     return grid, wind, cme, amr
 
 
-@pytest.mark.parametrize("n,block", [((32, 16, 16), (8, 8, 8)), ((32, 24, 24), (16, 12, 12))])
+@pytest.mark.parametrize("n,block", [((32, 16, 16), (8, 8, 8)), ((32, 24, 24), (16, 12, 12)),
+                                     ((36, 16, 24), (12, 8, 12))])
 def test_stretched_amr_wedge_flags_forest_and_state(n, block):
     """Three cycles of steps, flags on identical states and regrids; the second
     case has the non-cubic blocks of the equidistant benchmark (k-split 4 by
-    the schedule rule for 8 base blocks)."""
+    the schedule rule for 8 base blocks), the third the 12 x 8 x 12 blocks
+    that tile the literal 16-cell theta base grid of the AMR runs."""
     ic = _ic()
     grid, wind, cme, amr = _amr_wedge(n=n, block=block)
     ora = solver.Solver(grid, wind, cme, amr)
