@@ -74,8 +74,11 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // that every per-direction index below is a register, not private memory).
 // Slab layout: element ((v * 2 + l) * FB + b) * FA + a, layer l = 0 nearest
 // the low side.  sP, sOk: LDS for the prolongation's per-parent values.
+// part, nparts: the inner-boundary and restriction slabs split their elements
+// over nparts work-groups (part is this one's share); the prolongation keeps a
+// task in one work-group (nparts = 1).
 template <int BI, int BJ, int BK, int NV, int D, int PASS>
-DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
+DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk, double *sOff, int part, int nparts)
 {
     using S = Shape<BI, BJ, BK, NV>;
     constexpr int E1 = tan1(D), E2 = tan2(D);
@@ -94,6 +97,13 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         const Faces cnb = load_faces(a.desc, cs);   // the coarse parent block's face codes
         const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
         const int cwrap[3] = {tkp->cwrap[0], tkp->cwrap[1], tkp->cwrap[2]};
+        // the children's offsets from their parents' centres, in LDS for (2) and
+        // (3): the two layers along D, then the in-face indices along E1 and E2
+        for (int t = threadIdx.x; t < 2 + FA + FB; t += blockDim.x) {
+            const int e = t < 2 ? D : (t < 2 + FA ? E1 : E2);
+            const int g = t < 2 ? g0d + t : (t < 2 + FA ? bd.org[E1] + t - 2 : bd.org[E2] + t - 2 - FA);
+            sOff[t] = e == 0 ? lg.r[g + 2].poff : (e == 1 ? lg.t[g + 2].poff : lg.p[g + 2].poff);
+        }
         // (1) per parent and variable: coarse value and minmod slopes along r, theta, phi
         for (int t = threadIdx.x; t < NP * NV; t += blockDim.x) {
             const int c = t % NP, v = t / NP;
@@ -127,13 +137,14 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         __syncthreads();
         // (2) per parent: do the linear values give all 8 children rho > 0 and p > 0?
         for (int c = threadIdx.x; c < NP; c += blockDim.x) {
-            int g0[3];
-            g0[D] = g0d;
-            g0[E1] = bd.org[E1] + 2 * (c % HA);
-            g0[E2] = bd.org[E2] + 2 * (c / HA);
-            const double off[3][2] = {{lg.r[g0[0] + 2].poff, lg.r[g0[0] + 3].poff},
-                                      {lg.t[g0[1] + 2].poff, lg.t[g0[1] + 3].poff},
-                                      {lg.p[g0[2] + 2].poff, lg.p[g0[2] + 3].poff}};
+            // the offsets of the parent's two children along each direction
+            int x0[3];
+            x0[D] = 0;
+            x0[E1] = 2 + 2 * (c % HA);
+            x0[E2] = 2 + FA + 2 * (c / HA);
+            const double off[3][2] = {{sOff[x0[0]], sOff[x0[0] + 1]},
+                                      {sOff[x0[1]], sOff[x0[1] + 1]},
+                                      {sOff[x0[2]], sOff[x0[2] + 1]}};
             const double *P = sP + c * 4 * NV;
             bool ok = true;
 #pragma unroll
@@ -162,22 +173,22 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
             const double *P = sP + (c * NV + v) * 4;
             double x = P[0];
             if (sOk[c]) {
-                int g[3];
-                g[D] = g0d + l;
-                g[E1] = bd.org[E1] + ia;
-                g[E2] = bd.org[E2] + ib;
-                x += P[1] * lg.r[g[0] + 2].poff;
-                x += P[2] * lg.t[g[1] + 2].poff;
-                x += P[3] * lg.p[g[2] + 2].poff;
+                int xo[3];
+                xo[D] = l;
+                xo[E1] = 2 + ia;
+                xo[E2] = 2 + FA + ib;
+                x += P[1] * sOff[xo[0]];
+                x += P[2] * sOff[xo[1]];
+                x += P[3] * sOff[xo[2]];
             }
             out[e] = x;
         }
-        __syncthreads();                            // sP and sOk are reused by the next task
+        __syncthreads();                            // sP, sOk and sOff are reused by the next task
         return;
     }
     if (type == SLAB_INNER) {
         const Gas gs = a.gas;
-        for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        for (int c = part * blockDim.x + threadIdx.x; c < NCELL; c += nparts * blockDim.x) {
             const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
             int g[3];                               // owner-level global index (unwrapped)
             g[D] = g0d + l;
@@ -224,14 +235,17 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
         return;
     }
     // SLAB_RESTRICT: one thread per ghost cell and group of VG variables (the
-    // variables in NG groups; 8 VG independent loads each, issued together)
+    // variables in NG groups; the two children along r of each (theta, phi)
+    // child pair are adjacent in memory and 16-byte aligned -- even r index,
+    // even block dimensions -- so 4 VG independent 16-byte loads, issued
+    // together; the sums run over the children in the same order as one by one)
     constexpr int NG = NV % 4 == 0 ? 2 : 3, VG = NV / NG;
     static_assert(NG * VG == NV, "variable groups of the restriction");
     const LevelGeo fg = a.geo[bd.level + 1];
     const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
     const int fbase[3] = {tkp->fbase[0], tkp->fbase[1], tkp->fbase[2]};
     const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
-    for (int e = threadIdx.x; e < NG * NCELL; e += blockDim.x) {
+    for (int e = part * blockDim.x + threadIdx.x; e < NG * NCELL; e += nparts * blockDim.x) {
         const int c = e % NCELL, h = e / NCELL;
         const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
         int gw[3];                                  // owner-level global index, wrapped
@@ -246,43 +260,60 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk)
 #pragma unroll
         for (int v = 0; v < VG; ++v) num[v] = 0.0;
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
+        for (int o2 = 0; o2 < 4; ++o2) {            // children o = 2 o2 and 2 o2 + 1 (r offset 0, 1)
             int fl[3], q[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int fgi = 2 * gw[d] + ((o >> d) & 1);
+                const int fgi = 2 * gw[d] + (d == 0 ? 0 : (o2 >> (d - 1)) & 1);
                 const int fb = fgi / S::dim(d);
                 q[d] = fb - fbase[d];
                 fl[d] = fgi - fb * S::dim(d);
             }
             const int qq = q[E1] + 2 * q[E2];
             const int fslot = qq == 0 ? src0 : (qq == 1 ? src1 : (qq == 2 ? src2 : src3));
-            const double wgt = wr[o & 1] * wt[(o >> 1) & 1] * wp[(o >> 2) & 1];
+            const double wgt0 = wr[0] * wt[o2 & 1] * wp[(o2 >> 1) & 1];
+            const double wgt1 = wr[1] * wt[o2 & 1] * wp[(o2 >> 1) & 1];
+            double2 x[VG];
 #pragma unroll
-            for (int v = 0; v < VG; ++v) num[v] += wgt * a.U[cidx<S>(fslot, VG * h + v, fl[0], fl[1], fl[2])];
-            den += wgt;
+            for (int v = 0; v < VG; ++v)
+                x[v] = *reinterpret_cast<const double2 *>(a.U + cidx<S>(fslot, VG * h + v, fl[0], fl[1], fl[2]));
+#pragma unroll
+            for (int v = 0; v < VG; ++v) num[v] += wgt0 * x[v].x;
+            den += wgt0;
+#pragma unroll
+            for (int v = 0; v < VG; ++v) num[v] += wgt1 * x[v].y;
+            den += wgt1;
         }
 #pragma unroll
         for (int v = 0; v < VG; ++v) out[((size_t)((VG * h + v) * 2 + l) * FB + ib) * FA + ia] = num[v] / den;
     }
 }
 
-// PASS 0: inner-boundary and restriction slabs; PASS 1: prolongation slabs
-// (separate kernels, so that each is compiled for its own register needs)
+// PASS 0: inner-boundary and restriction slabs, each task's elements split
+// over SLAB_PARTS work-groups (a pass of few tasks then spreads over more
+// compute units, and each work-group's chain of dependent loads is shorter);
+// PASS 1: prolongation slabs, one work-group per task (separate kernels, so
+// that each is compiled for its own register needs)
+constexpr int SLAB_PARTS = 3;
+
 template <int BI, int BJ, int BK, int NV, int PASS>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 4 : 1)))
 k_slabs(KArgs a, const SlabTask *tasks, const int *range)
 {
     using S = Shape<BI, BJ, BK, NV>;
     constexpr int NPL = PASS == 1 ? S::MAXFACE / 4 : 1;
+    constexpr int NPART = PASS == 1 ? 1 : SLAB_PARTS;
     __shared__ double sP[NPL * 4 * NV];
     __shared__ int sOk[NPL];
+    __shared__ double sOff[PASS == 1 ? 2 + BI + BJ + BK : 1];
     const int t0 = range[0], t1 = range[1];
-    for (int it = t0 + blockIdx.x; it < t1; it += gridDim.x) {
+    const int nu = (t1 - t0) * NPART;
+    for (int u = blockIdx.x; u < nu; u += gridDim.x) {
+        const int it = t0 + u / NPART, part = u % NPART;
         const int d = tasks[it].face >> 1;          // uniform over the work-group
-        if (d == 0) slab_task<BI, BJ, BK, NV, 0, PASS>(a, tasks + it, sP, sOk);
-        else if (d == 1) slab_task<BI, BJ, BK, NV, 1, PASS>(a, tasks + it, sP, sOk);
-        else slab_task<BI, BJ, BK, NV, 2, PASS>(a, tasks + it, sP, sOk);
+        if (d == 0) slab_task<BI, BJ, BK, NV, 0, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
+        else if (d == 1) slab_task<BI, BJ, BK, NV, 1, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
+        else slab_task<BI, BJ, BK, NV, 2, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
     }
 }
 
@@ -1010,7 +1041,8 @@ template <int BI, int BJ, int BK, int NV>
 struct L {
     static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r, int pass)
     {
-        if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 0>), g, dim3(NT), 0, s, a, t, r);
+        // g: one work-group per task; pass 0 splits a task over SLAB_PARTS
+        if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 0>), dim3(g.x * SLAB_PARTS), dim3(NT), 0, s, a, t, r);
         else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 1>), g, dim3(NT), 0, s, a, t, r);
     }
     static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *b, const int *n)
