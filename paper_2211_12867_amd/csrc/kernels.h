@@ -197,7 +197,7 @@ template <int BI, int BJ, int BK, int NV> void launch_hancock(dim3 g, hipStream_
 template <int BI, int BJ, int BK, int NV, int PASS>
 __global__ void k_slabs(KArgs a, const SlabTask *tasks, const int *range);
 template <int BI, int BJ, int BK, int NV>
-__global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks);
+__global__ void k_reflux(KArgs a, const RefluxTask *tasks, const int *ranges, const int *ntasks);
 template <int BI, int BJ, int BK, int NV> __global__ void k_rate(KArgs a);
 template <int BI, int BJ, int BK, int NV>
 __global__ void k_indicator(KArgs a, int8_t *flags, IndicatorParams p);

@@ -70,15 +70,113 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // ---------------------------------------------------------------------------
 // ghost slabs: inner boundary (wind + cone CME), restriction, prolongation
 // ---------------------------------------------------------------------------
-// One slab task whose face is normal to direction D (a template parameter, so
+// Slab tasks whose face is normal to direction D (a template parameter, so
 // that every per-direction index below is a register, not private memory).
 // Slab layout: element ((v * 2 + l) * FB + b) * FA + a, layer l = 0 nearest
-// the low side.  sP, sOk: LDS for the prolongation's per-parent values.
-// part, nparts: the inner-boundary and restriction slabs split their elements
-// over nparts work-groups (part is this one's share); the prolongation keeps a
-// task in one work-group (nparts = 1).
-template <int BI, int BJ, int BK, int NV, int D, int PASS>
-DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk, double *sOff, int part, int nparts)
+// the low side.
+//
+// Prolongation slab, one coarse parent cell c (HA x HB parents behind the
+// face): the parent's value and minmod slopes along r, theta, phi per
+// variable; if the linear values give all 8 children (2 layers x 2 x 2 fine
+// cells) rho > 0 and p > 0 they take them, else the parent's own value (R24b).
+template <int BI, int BJ, int BK, int NV, int D>
+DEV void prolong_parent(const KArgs &a, const SlabTask *tkp, int c)
+{
+    using S = Shape<BI, BJ, BK, NV>;
+    constexpr int E1 = tan1(D), E2 = tan2(D);
+    constexpr int FA = S::dim(E1), FB = S::dim(E2), Bd = S::dim(D);
+    constexpr int HA = FA / 2;
+    const int side = tkp->face & 1;
+    const BlockDesc bd = a.desc[tkp->slot];
+    const LevelGeo lg = a.geo[bd.level];
+    const LevelGeo cg = a.geo[bd.level - 1];
+    double *out = a.slabs + (size_t)tkp->slab * a.slab_stride;
+    const int g0d = side ? bd.org[D] + Bd : bd.org[D] - 2;     // owner-level index of layer 0 along D
+    const int cs = tkp->src[0];
+    const Faces cnb = load_faces(a.desc, cs);       // the coarse parent block's face codes
+    const int pa = c % HA, pb = c / HA;
+    int g0[3];                                      // the first child, owner-level global index
+    g0[D] = g0d;
+    g0[E1] = bd.org[E1] + 2 * pa;
+    g0[E2] = bd.org[E2] + 2 * pb;
+    int cl[3], cw[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int c2 = g0[e] >= 0 ? g0[e] / 2 : -((-g0[e] + 1) / 2);   // floor(g/2)
+        cl[e] = c2 + tkp->shift[e];
+        cw[e] = c2 + tkp->cwrap[e];
+    }
+    const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
+    const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
+    // the children's offsets from the parent's centre, two per direction
+    const double off[3][2] = {{lg.r[g0[0] + 2].poff, lg.r[g0[0] + 3].poff},
+                              {lg.t[g0[1] + 2].poff, lg.t[g0[1] + 3].poff},
+                              {lg.p[g0[2] + 2].poff, lg.p[g0[2] + 3].poff}};
+    double P[NV][4];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const double uc = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, cl[0], cl[1], cl[2]);
+        P[v][0] = uc;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
+            lm[e] -= 1;
+            lp[e] += 1;
+            const double um = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lm[0], lm[1], lm[2]);
+            const double up = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lp[0], lp[1], lp[2]);
+            const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
+            P[v][1 + e] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
+        }
+    }
+    bool ok = true;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        double q[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            double x = P[v][0];
+            x += P[v][1] * off[0][o & 1];
+            x += P[v][2] * off[1][(o >> 1) & 1];
+            x += P[v][3] * off[2][(o >> 2) & 1];
+            q[v] = x;
+        }
+        const double kin = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
+        const double mag = 0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
+        ok = ok && q[0] > 0.0 && q[4] - kin - mag > 0.0;
+    }
+    // the children, a pair along E1 (adjacent, 16-byte aligned: even index,
+    // even face width) per store
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int hb = 0; hb < 2; ++hb) {
+                double x[2];
+#pragma unroll
+                for (int ha = 0; ha < 2; ++ha) {
+                    int h[3];                       // the child's half along each direction
+                    h[D] = l;
+                    h[E1] = ha;
+                    h[E2] = hb;
+                    x[ha] = P[v][0];
+                    if (ok) {
+                        x[ha] += P[v][1] * off[0][h[0]];
+                        x[ha] += P[v][2] * off[1][h[1]];
+                        x[ha] += P[v][3] * off[2][h[2]];
+                    }
+                }
+                const int ib = 2 * pb + hb;
+                *reinterpret_cast<double2 *>(out + ((size_t)(v * 2 + l) * FB + ib) * FA + 2 * pa) =
+                    make_double2(x[0], x[1]);
+            }
+}
+
+// Inner-boundary or restriction slab task, elements part, part + nparts, ...
+// (in units of the work-group size): a task's elements split over nparts
+// work-groups.
+template <int BI, int BJ, int BK, int NV, int D>
+DEV void slab_task(const KArgs &a, const SlabTask *tkp, int part, int nparts)
 {
     using S = Shape<BI, BJ, BK, NV>;
     constexpr int E1 = tan1(D), E2 = tan2(D);
@@ -89,103 +187,6 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk, do
     const LevelGeo lg = a.geo[bd.level];
     double *out = a.slabs + (size_t)tkp->slab * a.slab_stride;
     const int g0d = side ? bd.org[D] + Bd : bd.org[D] - 2;     // owner-level index of layer 0 along D
-    if (PASS == 1) {                                    // SLAB_PROLONG
-        // children = 2 layers x 2 x 2 fine cells per coarse parent
-        constexpr int HA = FA / 2, HB = FB / 2, NP = HA * HB;
-        const LevelGeo cg = a.geo[bd.level - 1];
-        const int cs = tkp->src[0];
-        const Faces cnb = load_faces(a.desc, cs);   // the coarse parent block's face codes
-        const int shift[3] = {tkp->shift[0], tkp->shift[1], tkp->shift[2]};
-        const int cwrap[3] = {tkp->cwrap[0], tkp->cwrap[1], tkp->cwrap[2]};
-        // the children's offsets from their parents' centres, in LDS for (2) and
-        // (3): the two layers along D, then the in-face indices along E1 and E2
-        for (int t = threadIdx.x; t < 2 + FA + FB; t += blockDim.x) {
-            const int e = t < 2 ? D : (t < 2 + FA ? E1 : E2);
-            const int g = t < 2 ? g0d + t : (t < 2 + FA ? bd.org[E1] + t - 2 : bd.org[E2] + t - 2 - FA);
-            sOff[t] = e == 0 ? lg.r[g + 2].poff : (e == 1 ? lg.t[g + 2].poff : lg.p[g + 2].poff);
-        }
-        // (1) per parent and variable: coarse value and minmod slopes along r, theta, phi
-        for (int t = threadIdx.x; t < NP * NV; t += blockDim.x) {
-            const int c = t % NP, v = t / NP;
-            int g0[3];
-            g0[D] = g0d;
-            g0[E1] = bd.org[E1] + 2 * (c % HA);
-            g0[E2] = bd.org[E2] + 2 * (c / HA);
-            int cl[3], cw[3];
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                const int c2 = g0[e] >= 0 ? g0[e] / 2 : -((-g0[e] + 1) / 2);   // floor(g/2)
-                cl[e] = c2 + shift[e];
-                cw[e] = c2 + cwrap[e];
-            }
-            const double idm[3] = {cg.r[cw[0] + 2].idm, cg.t[cw[1] + 2].idm, cg.p[cw[2] + 2].idm};
-            const double idp[3] = {cg.r[cw[0] + 2].idp, cg.t[cw[1] + 2].idp, cg.p[cw[2] + 2].idp};
-            const double uc = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, cl[0], cl[1], cl[2]);
-            double *P = sP + (c * NV + v) * 4;
-            P[0] = uc;
-#pragma unroll
-            for (int e = 0; e < 3; ++e) {
-                int lm[3] = {cl[0], cl[1], cl[2]}, lp[3] = {cl[0], cl[1], cl[2]};
-                lm[e] -= 1;
-                lp[e] += 1;
-                const double um = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lm[0], lm[1], lm[2]);
-                const double up = *cell_addr<S>(a.U, a.slabs, a.slab_stride, cs, cnb, v, lp[0], lp[1], lp[2]);
-                const double sa = (uc - um) * idm[e], sb = (up - uc) * idp[e];
-                P[1 + e] = sa * sb > 0.0 ? copysign(fmin(fabs(sa), fabs(sb)), sa) : 0.0;
-            }
-        }
-        __syncthreads();
-        // (2) per parent: do the linear values give all 8 children rho > 0 and p > 0?
-        for (int c = threadIdx.x; c < NP; c += blockDim.x) {
-            // the offsets of the parent's two children along each direction
-            int x0[3];
-            x0[D] = 0;
-            x0[E1] = 2 + 2 * (c % HA);
-            x0[E2] = 2 + FA + 2 * (c / HA);
-            const double off[3][2] = {{sOff[x0[0]], sOff[x0[0] + 1]},
-                                      {sOff[x0[1]], sOff[x0[1] + 1]},
-                                      {sOff[x0[2]], sOff[x0[2] + 1]}};
-            const double *P = sP + c * 4 * NV;
-            bool ok = true;
-#pragma unroll
-            for (int o = 0; o < 8; ++o) {
-                double q[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) {
-                    double x = P[v * 4];
-                    x += P[v * 4 + 1] * off[0][o & 1];
-                    x += P[v * 4 + 2] * off[1][(o >> 1) & 1];
-                    x += P[v * 4 + 3] * off[2][(o >> 2) & 1];
-                    q[v] = x;
-                }
-                const double kin = 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
-                const double mag = 0.5 * (q[5] * q[5] + q[6] * q[6] + q[7] * q[7]);
-                ok = ok && q[0] > 0.0 && q[4] - kin - mag > 0.0;
-            }
-            sOk[c] = ok;
-        }
-        __syncthreads();
-        // (3) the slab element by element (coalesced); a failing parent hands
-        // its own value to its children
-        for (int e = threadIdx.x; e < NV * NCELL; e += blockDim.x) {
-            const int ia = e % FA, ib = (e / FA) % FB, l = (e / (FA * FB)) & 1, v = e / NCELL;
-            const int c = (ia >> 1) + HA * (ib >> 1);
-            const double *P = sP + (c * NV + v) * 4;
-            double x = P[0];
-            if (sOk[c]) {
-                int xo[3];
-                xo[D] = l;
-                xo[E1] = 2 + ia;
-                xo[E2] = 2 + FA + ib;
-                x += P[1] * sOff[xo[0]];
-                x += P[2] * sOff[xo[1]];
-                x += P[3] * sOff[xo[2]];
-            }
-            out[e] = x;
-        }
-        __syncthreads();                            // sP, sOk and sOff are reused by the next task
-        return;
-    }
     if (type == SLAB_INNER) {
         const Gas gs = a.gas;
         for (int c = part * blockDim.x + threadIdx.x; c < NCELL; c += nparts * blockDim.x) {
@@ -247,7 +248,12 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk, do
     const int src0 = tkp->src[0], src1 = tkp->src[1], src2 = tkp->src[2], src3 = tkp->src[3];
     for (int e = part * blockDim.x + threadIdx.x; e < NG * NCELL; e += nparts * blockDim.x) {
         const int c = e % NCELL, h = e / NCELL;
-        const int ia = c % FA, ib = (c / FA) % FB, l = c / (FA * FB);
+        // along r the two layers of a ghost cell go to adjacent lanes: their
+        // children are the four fine r-cells of one row, contiguous in memory;
+        // across r, lanes follow the slab (the children rows run along r)
+        const int ia = D == 0 ? (c >> 1) % FA : c % FA;
+        const int ib = D == 0 ? (c >> 1) / FA : (c / FA) % FB;
+        const int l = D == 0 ? c & 1 : c / (FA * FB);
         int gw[3];                                  // owner-level global index, wrapped
         gw[D] = g0d + l + shift[D];
         gw[E1] = bd.org[E1] + ia + shift[E1];
@@ -292,28 +298,40 @@ DEV void slab_task(const KArgs &a, const SlabTask *tkp, double *sP, int *sOk, do
 // PASS 0: inner-boundary and restriction slabs, each task's elements split
 // over SLAB_PARTS work-groups (a pass of few tasks then spreads over more
 // compute units, and each work-group's chain of dependent loads is shorter);
-// PASS 1: prolongation slabs, one work-group per task (separate kernels, so
-// that each is compiled for its own register needs)
+// PASS 1: prolongation slabs, one wave per task and one lane per coarse
+// parent (at most 64 per face), so no task waits on a barrier (separate
+// kernels, so that each is compiled for its own register needs)
 constexpr int SLAB_PARTS = 3;
+constexpr int PROLONG_TASKS = NT / 64;          // prolongation tasks per work-group
 
 template <int BI, int BJ, int BK, int NV, int PASS>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 4 : 1)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 2 : 1)))
 k_slabs(KArgs a, const SlabTask *tasks, const int *range)
 {
     using S = Shape<BI, BJ, BK, NV>;
-    constexpr int NPL = PASS == 1 ? S::MAXFACE / 4 : 1;
-    constexpr int NPART = PASS == 1 ? 1 : SLAB_PARTS;
-    __shared__ double sP[NPL * 4 * NV];
-    __shared__ int sOk[NPL];
-    __shared__ double sOff[PASS == 1 ? 2 + BI + BJ + BK : 1];
     const int t0 = range[0], t1 = range[1];
-    const int nu = (t1 - t0) * NPART;
+    if (PASS == 1) {
+        static_assert(S::MAXFACE / 4 <= 64, "coarse parents of a face per wave");
+        const int lane = threadIdx.x % 64;
+        for (int it = t0 + blockIdx.x * PROLONG_TASKS + threadIdx.x / 64; it < t1; it += gridDim.x * PROLONG_TASKS) {
+            const int d = tasks[it].face >> 1;      // uniform over the wave
+            if (d == 0) {
+                if (lane < S::face_cells(0) / 4) prolong_parent<BI, BJ, BK, NV, 0>(a, tasks + it, lane);
+            } else if (d == 1) {
+                if (lane < S::face_cells(1) / 4) prolong_parent<BI, BJ, BK, NV, 1>(a, tasks + it, lane);
+            } else if (lane < S::face_cells(2) / 4) {
+                prolong_parent<BI, BJ, BK, NV, 2>(a, tasks + it, lane);
+            }
+        }
+        return;
+    }
+    const int nu = (t1 - t0) * SLAB_PARTS;
     for (int u = blockIdx.x; u < nu; u += gridDim.x) {
-        const int it = t0 + u / NPART, part = u % NPART;
+        const int it = t0 + u / SLAB_PARTS, part = u % SLAB_PARTS;
         const int d = tasks[it].face >> 1;          // uniform over the work-group
-        if (d == 0) slab_task<BI, BJ, BK, NV, 0, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
-        else if (d == 1) slab_task<BI, BJ, BK, NV, 1, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
-        else slab_task<BI, BJ, BK, NV, 2, PASS>(a, tasks + it, sP, sOk, sOff, part, NPART);
+        if (d == 0) slab_task<BI, BJ, BK, NV, 0>(a, tasks + it, part, SLAB_PARTS);
+        else if (d == 1) slab_task<BI, BJ, BK, NV, 1>(a, tasks + it, part, SLAB_PARTS);
+        else slab_task<BI, BJ, BK, NV, 2>(a, tasks + it, part, SLAB_PARTS);
     }
 }
 
@@ -330,121 +348,131 @@ __device__ inline double cell_rate(const double *u, const RecR &rr, const RecT &
          + (fabs(w[3]) + fast_speed<2>(w, gs)) * rr.irc * tt.isinc * pp.iw;
 }
 
-// Reflux at one coarse-fine face of a coarse block, face direction D (a
-// template parameter: every per-direction index stays in registers): for each
-// cell behind the face, U += +-adt (A_c F_c - sum of the 4 fine A F) / V_c,
-// the fine faces summed in fixed order.
+// Reflux correction of one coarse cell (loc, block coordinates) behind the
+// coarse-fine face of task tk, face direction D (a template parameter: every
+// per-direction index stays in registers): (A_c F_c - sum of the 4 fine A F)
+// / V_c per variable, the fine faces summed in fixed order.
 template <int BI, int BJ, int BK, int NV, int D>
-DEV void reflux_face(const KArgs &a, const RefluxTask *tkp, const BlockDesc &bd, const LevelGeo &lg,
-                     const LevelGeo &fg, int slot, double adt)
+DEV void reflux_corr(const KArgs &a, const RefluxTask &tk, const BlockDesc &bd, const LevelGeo &lg,
+                     const LevelGeo &fg, const int loc[3], double corr[NV])
 {
     using S = Shape<BI, BJ, BK, NV>;
     constexpr int E1 = tan1(D), E2 = tan2(D);
     constexpr int FA = S::dim(E1), FB = S::dim(E2);
-    const int side = tkp->face & 1;
-    const int reg4[4] = {tkp->freg[0], tkp->freg[1], tkp->freg[2], tkp->freg[3]};
-    const double *Fc = a.freg + (size_t)tkp->creg * a.reg_stride;
-    for (int c = threadIdx.x; c < FA * FB; c += blockDim.x) {
-        const int ia = c % FA, ib = c / FA;
-        int loc[3];
-        loc[D] = side ? S::dim(D) - 1 : 0;
-        loc[E1] = ia;
-        loc[E2] = ib;
-        int g[3];
+    const int side = tk.face & 1;
+    const int ia = loc[E1], ib = loc[E2];
+    int g[3];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) g[e] = bd.org[e] + loc[e];
-        const RecR rr = lg.r[g[0] + 2];
-        const RecT tt = lg.t[g[1] + 2];
-        const RecP pp = lg.p[g[2] + 2];
-        const double Vc = rr.vw * tt.vw * pp.vw;
-        double ac;
-        if (D == 0) ac = side ? rr.ap : rr.am;
-        else if (D == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
-        else ac = rr.rt * tt.phf * pp.iw;
-        const int gf = 2 * (bd.org[D] + (side ? S::dim(D) : 0));   // fine face index along D
-        double sum[NV];
+    for (int e = 0; e < 3; ++e) g[e] = bd.org[e] + loc[e];
+    const RecR rr = lg.r[g[0] + 2];
+    const RecT tt = lg.t[g[1] + 2];
+    const RecP pp = lg.p[g[2] + 2];
+    const double Vc = rr.vw * tt.vw * pp.vw;
+    double ac;
+    if (D == 0) ac = side ? rr.ap : rr.am;
+    else if (D == 1) ac = rr.rt * (side ? tt.thp : tt.thm);
+    else ac = rr.rt * tt.phf * pp.iw;
+    const int gf = 2 * (bd.org[D] + (side ? S::dim(D) : 0));   // fine face index along D
+    const double *Fc = a.freg + (size_t)tk.creg * a.reg_stride;
+    double sum[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sum[v] = 0.0;
+    for (int v = 0; v < NV; ++v) sum[v] = 0.0;
 #pragma unroll
-        for (int ob = 0; ob < 2; ++ob) {
+    for (int ob = 0; ob < 2; ++ob) {
 #pragma unroll
-            for (int oa = 0; oa < 2; ++oa) {
-                const int fa = 2 * ia + oa, fb = 2 * ib + ob;
-                const int qa = fa / FA, qb = fb / FB;
-                const int qq = qa + 2 * qb;
-                const int reg = qq == 0 ? reg4[0] : (qq == 1 ? reg4[1] : (qq == 2 ? reg4[2] : reg4[3]));
-                int fgl[3];
-                fgl[D] = gf;
-                fgl[E1] = 2 * g[E1] + oa;
-                fgl[E2] = 2 * g[E2] + ob;
-                double A;
-                if (D == 0) A = fg.r[fgl[0] + 2].r2f * fg.t[fgl[1] + 2].vw * fg.p[fgl[2] + 2].vw;
-                else if (D == 1) A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].sf * fg.p[fgl[2] + 2].vw;
-                else A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].dth;
-                const double *F = a.freg + (size_t)reg * a.reg_stride;
-                const int la = fa - qa * FA, lb = fb - qb * FB;
+        for (int oa = 0; oa < 2; ++oa) {
+            const int fa = 2 * ia + oa, fb = 2 * ib + ob;
+            const int qa = fa / FA, qb = fb / FB;
+            const int qq = qa + 2 * qb;
+            const int reg = qq == 0 ? tk.freg[0] : (qq == 1 ? tk.freg[1] : (qq == 2 ? tk.freg[2] : tk.freg[3]));
+            int fgl[3];
+            fgl[D] = gf;
+            fgl[E1] = 2 * g[E1] + oa;
+            fgl[E2] = 2 * g[E2] + ob;
+            double A;
+            if (D == 0) A = fg.r[fgl[0] + 2].r2f * fg.t[fgl[1] + 2].vw * fg.p[fgl[2] + 2].vw;
+            else if (D == 1) A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].sf * fg.p[fgl[2] + 2].vw;
+            else A = fg.r[fgl[0] + 2].r2h * fg.t[fgl[1] + 2].dth;
+            const double *F = a.freg + (size_t)reg * a.reg_stride;
+            const int la = fa - qa * FA, lb = fb - qb * FB;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double corr = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
-            const size_t o = cidx<S>(slot, v, loc[0], loc[1], loc[2]);
-            a.Uout[o] += side ? adt * corr : -adt * corr;
+            for (int v = 0; v < NV; ++v) sum[v] += A * F[((size_t)v * FB + lb) * FA + la];
         }
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) corr[v] = ac * Fc[((size_t)v * FB + ib) * FA + ia] - sum[v] / Vc;
 }
 
+// Is cell (i, j, k) on face f (2 d + side) of its block?
+template <int BI, int BJ, int BK>
+DEV bool on_face(int f, int i, int j, int k)
+{
+    const int d = f >> 1;
+    const int x = d == 0 ? i : (d == 1 ? j : k);
+    const int n = d == 0 ? BI : (d == 1 ? BJ : BK);
+    return x == ((f & 1) ? n - 1 : 0);
+}
+
+// One work-group per reflux task (a coarse-fine face of a coarse block; the
+// block's tasks are ranges[2q] .. ranges[2q+1], in face order).  Each cell
+// behind the face takes U += +-adt (A_c F_c - sum A F) / V_c; a cell on
+// several of the block's reflux faces (an edge or corner) is corrected by the
+// work-group of the last of them, face by face in task order, so every cell
+// has one writer and the corrections add in the same order as face after
+// face.  Then the floors and the CFL rate of each corrected cell (the stage
+// kernel left these cells out of its maxima), folded into the block's entry.
 template <int BI, int BJ, int BK, int NV>
-__global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks, const int *blocks, const int *nblocks)
+__global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks, const int *ranges, const int *ntasks)
 {
     using S = Shape<BI, BJ, BK, NV>;
     __shared__ double sred[NT / 64];
-    const int nb = *nblocks;
-    for (int it = blockIdx.x; it < nb; it += gridDim.x) {
-        const int t0 = blocks[2 * it], t1 = blocks[2 * it + 1];
-        const int slot = tasks[t0].slot;
+    const int nt = *ntasks;
+    for (int q = blockIdx.x; q < nt; q += gridDim.x) {
+        const int t0 = ranges[2 * q], t1 = ranges[2 * q + 1];
+        const int slot = tasks[q].slot;
         const BlockDesc bd = a.desc[slot];
         const double dt = a.dt[bd.member];
-        if (dt <= 0.0) continue;
+        if (dt <= 0.0) continue;                    // uniform over the work-group
         const double adt = a.alpha * dt;
         const LevelGeo lg = a.geo[bd.level], fg = a.geo[bd.level + 1];
-        for (int q = t0; q < t1; ++q) {
-            const int d = tasks[q].face >> 1;          // uniform over the work-group
-            if (d == 0) reflux_face<BI, BJ, BK, NV, 0>(a, tasks + q, bd, lg, fg, slot, adt);
-            else if (d == 1) reflux_face<BI, BJ, BK, NV, 1>(a, tasks + q, bd, lg, fg, slot, adt);
-            else reflux_face<BI, BJ, BK, NV, 2>(a, tasks + q, bd, lg, fg, slot, adt);
-            __syncthreads();
-        }
-        // floors on the corrected cells and their CFL rates (the stage kernel took
-        // the maximum over the other cells): each corrected cell once, listed
-        // face by face, an edge cell with the first of its faces
-        int total = 0;
-        for (int q = t0; q < t1; ++q) total += S::face_cells(tasks[q].face >> 1);
+        // the block's reflux faces in task order, 3 bits each (at most 6)
+        const int nf = t1 - t0, me = q - t0;
+        unsigned fc = 0;
+        for (int p = 0; p < nf; ++p) fc |= (unsigned)tasks[t0 + p].face << (3 * p);
+        const int d = tasks[q].face >> 1, side = tasks[q].face & 1;
         double rmax = 0.0;
         int badc = -1, nfr = 0, nfp = 0;
-        for (int w = threadIdx.x; w < total; w += blockDim.x) {
-            int q = t0, c = w;
-            while (c >= S::face_cells(tasks[q].face >> 1)) c -= S::face_cells(tasks[q].face >> 1), ++q;
-            const int d = tasks[q].face >> 1, side = tasks[q].face & 1;
-            int i, j, k;                               // the cell: index c on face (d, side)
+        for (int c = threadIdx.x; c < S::face_cells(d); c += blockDim.x) {
+            int i, j, k;                            // the cell: index c on face (d, side)
             if (d == 0) i = side ? BI - 1 : 0, j = c % BJ, k = c / BJ;
             else if (d == 1) i = c % BI, j = side ? BJ - 1 : 0, k = c / BI;
             else i = c % BI, j = c / BI, k = side ? BK - 1 : 0;
-            bool first = true;
-            for (int p = t0; p < q; ++p) {
-                const int f = tasks[p].face, dd = f >> 1;
-                const int x = dd == 0 ? i : (dd == 1 ? j : k);
-                if (x == ((f & 1) ? S::dim(dd) - 1 : 0)) first = false;
-            }
-            if (!first) continue;
+            bool last = true;
+            for (int p = me + 1; p < nf; ++p)
+                if (on_face<BI, BJ, BK>((fc >> (3 * p)) & 7, i, j, k)) last = false;
+            if (!last) continue;
             double u[NV];
+#pragma unroll
             for (int v = 0; v < NV; ++v) u[v] = a.Uout[cidx<S>(slot, v, i, j, k)];
+            const int loc[3] = {i, j, k};
+            for (int p = 0; p <= me; ++p) {
+                const int fp = (fc >> (3 * p)) & 7;
+                if (!on_face<BI, BJ, BK>(fp, i, j, k)) continue;
+                const RefluxTask tk = tasks[t0 + p];
+                double corr[NV];
+                const int dp = fp >> 1;
+                if (dp == 0) reflux_corr<BI, BJ, BK, NV, 0>(a, tk, bd, lg, fg, loc, corr);
+                else if (dp == 1) reflux_corr<BI, BJ, BK, NV, 1>(a, tk, bd, lg, fg, loc, corr);
+                else reflux_corr<BI, BJ, BK, NV, 2>(a, tk, bd, lg, fg, loc, corr);
+                const int sp = fp & 1;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) u[v] += sp ? adt * corr[v] : -adt * corr[v];
+            }
             const int f = apply_floors(u, a.gas, a.rho_floor, a.p_floor);
             nfr += f & 1;
             nfp += f >> 1;
-            for (int v = 0; v < 8; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];   // the floors leave rho s
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a.Uout[cidx<S>(slot, v, i, j, k)] = u[v];
             if (a.want_rate) {
                 double w[NV];
                 cons_to_prim<false, NV>(u, w, a.gas);
@@ -460,11 +488,13 @@ __global__ void __launch_bounds__(NT) k_reflux(KArgs a, const RefluxTask *tasks,
             atomicAdd(&a.floors[2 * bd.member + 1], (unsigned long long)nfp);
         }
         if (a.want_rate) {
+            // the block's other faces may fold theirs in concurrently: rates are
+            // >= 0 and not NaN (a NaN rate fails the comparisons above), so the
+            // unsigned order of their bits is their numeric order
             const double m = block_max(rmax, sred);
-            if (threadIdx.x == 0) {
-                double &r0 = a.rate[(size_t)slot * KSPLIT_MAX];
-                r0 = m > r0 ? m : r0;
-            }
+            if (threadIdx.x == 0)
+                atomicMax((unsigned long long *)&a.rate[(size_t)slot * KSPLIT_MAX],
+                          (unsigned long long)__double_as_longlong(m));
         }
         __syncthreads();
     }
@@ -1041,13 +1071,15 @@ template <int BI, int BJ, int BK, int NV>
 struct L {
     static void slabs(dim3 g, hipStream_t s, const KArgs &a, const SlabTask *t, const int *r, int pass)
     {
-        // g: one work-group per task; pass 0 splits a task over SLAB_PARTS
+        // g: one work-group per task; pass 0 splits a task over SLAB_PARTS,
+        // pass 1 gives each task one wave
         if (pass == 0) hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 0>), dim3(g.x * SLAB_PARTS), dim3(NT), 0, s, a, t, r);
-        else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 1>), g, dim3(NT), 0, s, a, t, r);
+        else hipLaunchKernelGGL((k_slabs<BI, BJ, BK, NV, 1>), dim3((g.x + PROLONG_TASKS - 1) / PROLONG_TASKS),
+                                dim3(NT), 0, s, a, t, r);
     }
-    static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *b, const int *n)
+    static void reflux(dim3 g, hipStream_t s, const KArgs &a, const RefluxTask *t, const int *r, const int *n)
     {
-        hipLaunchKernelGGL((k_reflux<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a, t, b, n);
+        hipLaunchKernelGGL((k_reflux<BI, BJ, BK, NV>), g, dim3(NT), 0, s, a, t, r, n);
     }
     static void rate(dim3 g, hipStream_t s, const KArgs &a)
     {

@@ -365,7 +365,7 @@ struct ic_sim {
     DBuf<SlabTask> slab_tasks;
     DBuf<int> slab_ranges;        // [2 * (IC_MAX_LEVEL + 2)]
     DBuf<RefluxTask> rf_tasks;
-    DBuf<int> rf_blocks, rf_nblocks;
+    DBuf<int> rf_ranges, rf_ntasks;
     DBuf<int8_t> flags;
     DBuf<MoveTask> moves;
     DBuf<SampleDesc> sdesc;
@@ -376,7 +376,7 @@ struct ic_sim {
 
     // host mirrors of the task lists
     int n_items = 0;
-    int n_slabs = 0, n_regs = 0, n_rf_blocks = 0;
+    int n_slabs = 0, n_regs = 0, n_rf_tasks = 0;
     int pass_lo[IC_MAX_LEVEL + 2] = {0}, pass_hi[IC_MAX_LEVEL + 2] = {0};
     bool any_prolong = false, any_reflux = false;
     std::vector<BlockDesc> hdesc;
@@ -963,18 +963,22 @@ void rebuild(ic_sim *s)
     std::sort(rf.begin(), rf.end(), [](const RefluxTask &a, const RefluxTask &b) {
         return a.slot != b.slot ? a.slot < b.slot : a.face < b.face;
     });
-    std::vector<int> rfb;
+    // per reflux task, the range of its coarse block's tasks (a work-group per
+    // task; a cell on several of the block's faces is corrected by the last)
+    std::vector<int> rfr(2 * rf.size());
     for (size_t q = 0; q < rf.size();) {
         size_t e = q;
         while (e < rf.size() && rf[e].slot == rf[q].slot) ++e;
-        rfb.push_back((int)q);
-        rfb.push_back((int)e);
+        for (size_t p = q; p < e; ++p) {
+            rfr[2 * p] = (int)q;
+            rfr[2 * p + 1] = (int)e;
+        }
         q = e;
     }
     s->n_items = (int)items.size();
     s->n_slabs = nslab;
     s->n_regs = reg_off[s->nm];
-    s->n_rf_blocks = (int)rfb.size() / 2;
+    s->n_rf_tasks = (int)rf.size();
     s->any_reflux = !rf.empty();
 
     // capacities (growing a buffer invalidates a captured graph)
@@ -988,7 +992,7 @@ void rebuild(ic_sim *s)
     grow(s->freg, (size_t)std::max(s->n_regs, 1) * s->reg_stride);
     grow(s->slab_tasks, all.size() + 1);
     grow(s->rf_tasks, rf.size() + 1);
-    grow(s->rf_blocks, rfb.size() + 2);
+    grow(s->rf_ranges, rfr.size() + 2);
 
     Upload up(s);
     for (int m = 0; m < s->nm; ++m)
@@ -1016,8 +1020,8 @@ void rebuild(ic_sim *s)
     ranges[3] = s->pass_hi[s->max_level];
     up.add(s->slab_ranges.p, ranges.data(), ranges.size() * sizeof(int));
     up.add(s->rf_tasks.p, rf.data(), rf.size() * sizeof(RefluxTask));
-    up.add(s->rf_blocks.p, rfb.data(), rfb.size() * sizeof(int));
-    up.add(s->rf_nblocks.p, &s->n_rf_blocks, sizeof(int));
+    up.add(s->rf_ranges.p, rfr.data(), rfr.size() * sizeof(int));
+    up.add(s->rf_ntasks.p, &s->n_rf_tasks, sizeof(int));
     up.flush();
     for (int l = 0; l < 8; ++l) s->leaves_per_level0[l] = 0;
     for (auto &kv : s->mem[0].leaves)
@@ -1093,7 +1097,7 @@ int slab_grid(const ic_sim *s, int pass)
     return quant_grid(n, 8192);
 }
 
-int reflux_grid(const ic_sim *s) { return s->any_reflux ? quant_grid(s->n_rf_blocks, 8192) : 0; }
+int reflux_grid(const ic_sim *s) { return s->any_reflux ? quant_grid(s->n_rf_tasks, 8192) : 0; }
 
 // launch sizes of a step; a captured step graph is re-made when they change
 std::vector<int> launch_sig(const ic_sim *s)
@@ -1133,7 +1137,7 @@ void stage(ic_sim *s, double *Uin, double *Ubase, double *Uout, double alpha, in
     } else {
         s->L.stage(dim3(g), s->stream, a, s->tune_waves, s->phys.limiter);
     }
-    if (s->any_reflux) s->L.reflux(dim3(reflux_grid(s)), s->stream, a, s->rf_tasks.p, s->rf_blocks.p, s->rf_nblocks.p);
+    if (s->any_reflux) s->L.reflux(dim3(reflux_grid(s)), s->stream, a, s->rf_tasks.p, s->rf_ranges.p, s->rf_ntasks.p);
 }
 
 // div B of the stage input Uin (ghosts filled) into s->divb
@@ -2142,7 +2146,7 @@ ic_status ic_create(const ic_grid_cfg *grid, const ic_phys_cfg *phys, const ic_w
         s->floors.alloc(2 * s->nm);
         s->nsteps.alloc(s->nm);
         s->slab_ranges.alloc(2 * (IC_MAX_LEVEL + 2));
-        s->rf_nblocks.alloc(1);
+        s->rf_ntasks.alloc(1);
         s->flags.alloc(NS);
         s->sdesc.alloc(s->nm);
         s->sout.alloc((size_t)s->nm * 8);
@@ -2199,7 +2203,7 @@ void ic_destroy(ic_sim *s)
     s->geo.release(); s->mc.release(); s->items.release(); s->nitems.release(); s->mbeg.release();
     s->mend.release(); s->dt.release(); s->t.release(); s->tend.release(); s->dt_last.release();
     s->rate.release(); s->bad.release(); s->floors.release(); s->nsteps.release(); s->slab_tasks.release();
-    s->slab_ranges.release(); s->rf_tasks.release(); s->rf_blocks.release(); s->rf_nblocks.release();
+    s->slab_ranges.release(); s->rf_tasks.release(); s->rf_ranges.release(); s->rf_ntasks.release();
     s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
     s->ring_count.release();
     if (s->hstage) (void)hipHostFree(s->hstage);
