@@ -413,9 +413,10 @@ struct ic_sim {
     bool tune_pinned = false;
     std::vector<hipEvent_t> ev;   // pairs
     long timed = 0;
-    // pinned staging area of the table uploads (Upload)
+    // pinned staging area of the table uploads (Upload) and its device copy
     char *hstage = nullptr;
     size_t hstage_cap = 0;
+    DBuf<char> dstage;
     // pinned landing area of the per-step status (non-physical flags, step
     // count, t, dt), read back with one synchronisation per ic_step
     char *hstat = nullptr;
@@ -744,6 +745,31 @@ void for_members(int nm, F &&f)
 // buffer and enqueued as asynchronous copies on the sim's stream, with one
 // synchronisation at the end (a synchronous copy from pageable memory costs
 // tens of microseconds each).  Sources must stay alive until flush().
+// Table uploads.  The items are packed into the pinned staging area behind a
+// table of where each goes, moved to the device in one copy, and placed there
+// by one kernel (a copy per item cost ~10 us of launch latency each, about
+// ten per regrid).
+struct UpItem {
+    unsigned long long dst, off, n;     // device address, offset in the staging area, bytes
+};
+
+__global__ void __launch_bounds__(256) k_scatter(const char *__restrict__ stage, int nitems)
+{
+    const UpItem *items = reinterpret_cast<const UpItem *>(stage);
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const UpItem e = items[i];
+        if (((e.dst | e.n) & 15) == 0) {           // 16-byte pieces (staging offsets are 256-byte aligned)
+            const uint4 *src = reinterpret_cast<const uint4 *>(stage + e.off);
+            uint4 *dst = reinterpret_cast<uint4 *>(e.dst);
+            for (unsigned long long w = threadIdx.x; w < e.n / 16; w += blockDim.x) dst[w] = src[w];
+        } else {                                   // 4-byte pieces (every table holds 4-byte fields)
+            const unsigned *src = reinterpret_cast<const unsigned *>(stage + e.off);
+            unsigned *dst = reinterpret_cast<unsigned *>(e.dst);
+            for (unsigned long long w = threadIdx.x; w < e.n / 4; w += blockDim.x) dst[w] = src[w];
+        }
+    }
+}
+
 struct Upload {
     ic_sim *s;
     struct Item { void *dst; const void *src; size_t n; };
@@ -755,7 +781,9 @@ struct Upload {
     }
     void flush()
     {
-        size_t tot = 0;
+        if (q.empty()) return;
+        const size_t head = (q.size() * sizeof(UpItem) + 255) & ~(size_t)255;
+        size_t tot = head;
         for (const Item &e : q) tot += (e.n + 255) & ~(size_t)255;
         if (tot > s->hstage_cap) {
             HIPCHECK(hipStreamSynchronize(s->stream));
@@ -766,14 +794,25 @@ struct Upload {
             if (hipHostMalloc((void **)&s->hstage, cap) != hipSuccess)
                 throw Error(IC_E_NOMEM, "pinned host allocation failed");
             s->hstage_cap = cap;
+            s->dstage.alloc(cap);
         }
-        size_t off = 0;
+        UpItem *tab = reinterpret_cast<UpItem *>(s->hstage);
+        size_t off = head;
+        int n = 0;
         for (const Item &e : q) {
             std::memcpy(s->hstage + off, e.src, e.n);
-            HIPCHECK(hipMemcpyAsync(e.dst, s->hstage + off, e.n, hipMemcpyHostToDevice, s->stream));
+            if (e.n % 4 == 0)
+                tab[n++] = UpItem{(unsigned long long)(uintptr_t)e.dst, off, e.n};
+            else
+                HIPCHECK(hipMemcpyAsync(e.dst, s->hstage + off, e.n, hipMemcpyHostToDevice, s->stream));
             off += (e.n + 255) & ~(size_t)255;
         }
-        HIPCHECK(hipStreamSynchronize(s->stream));   // the staging area may be reused now
+        if (n > 0) {
+            HIPCHECK(hipMemcpyAsync(s->dstage.p, s->hstage, off, hipMemcpyHostToDevice, s->stream));
+            hipLaunchKernelGGL(k_scatter, dim3(std::min(n, 1024)), dim3(256), 0, s->stream, s->dstage.p, n);
+            HIPCHECK(hipGetLastError());
+        }
+        HIPCHECK(hipStreamSynchronize(s->stream));   // the staging areas may be reused now
         q.clear();
     }
 };
@@ -2205,7 +2244,7 @@ void ic_destroy(ic_sim *s)
     s->rate.release(); s->bad.release(); s->floors.release(); s->nsteps.release(); s->slab_tasks.release();
     s->slab_ranges.release(); s->rf_tasks.release(); s->rf_ranges.release(); s->rf_ntasks.release();
     s->flags.release(); s->moves.release(); s->sdesc.release(); s->sout.release(); s->ring.release();
-    s->ring_count.release();
+    s->ring_count.release(); s->dstage.release();
     if (s->hstage) (void)hipHostFree(s->hstage);
     if (s->hstat) (void)hipHostFree(s->hstat);
     if (s->own_stream) (void)hipStreamDestroy(s->stream);
