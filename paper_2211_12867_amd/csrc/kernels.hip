@@ -78,7 +78,8 @@ DEV void prolong_setup(const KArgs &a, int src, const int cl[3], const int cw[3]
 // Prolongation slab, one coarse parent cell c (HA x HB parents behind the
 // face): the parent's value and minmod slopes along r, theta, phi per
 // variable; if the linear values give all 8 children (2 layers x 2 x 2 fine
-// cells) rho > 0 and p > 0 they take them, else the parent's own value (R24b).
+// cells) rho > 0 and p > 0 they take them, else the parent's own value (the
+// prolongation stays conservative either way).
 template <int BI, int BJ, int BK, int NV, int D>
 DEV void prolong_parent(const KArgs &a, const SlabTask *tkp, int c)
 {
