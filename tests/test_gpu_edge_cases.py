@@ -8,6 +8,9 @@
   step, with the CME entering through the inner boundary.
 - A block of the smallest shape (4 cells along each direction: two ghost
   layers span a whole block) on a periodic refined box matches the oracle.
+- A coarse block whose neighbours along all three axes are refined (reflux
+  faces that share edges and a corner, each such cell corrected once per face
+  in face order by one thread) matches the oracle step by step.
 - A regrid that asks every leaf of the top level to refine leaves the forest
   at the top level."""
 import numpy as np
@@ -79,6 +82,41 @@ def test_smallest_block_shape_on_a_refined_box():
     gpu = ic.Sim(box, amr=dict(buffer_blocks=0))
     gpu.set_state(*ora.state(), 0.0)
     assert max(b[0] for b in gpu.blocks()) == 2
+    for n in range(6):
+        gpu.step()
+        ora.step()
+        e = rel_err(gpu.state()[1], ora.state()[1])
+        assert e <= 1e-12 * (n + 1), (n, e)
+    gpu.close()
+
+
+def _smooth_box_state(ora, seed):
+    from oracle import boundary
+    g = np.random.default_rng(seed)
+    for leaf in ora.forest.leaves:
+        x = [ora.centres(leaf, d) for d in range(3)]
+        Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+        W = np.zeros((8,) + X.shape)
+        base = [1.0, 0.2, -0.1, 0.15, 1.0, 0.3, 0.2, -0.1]
+        for v in range(8):
+            k = g.integers(1, 3, size=3)
+            W[v] = base[v] + (0.1 if v in (0, 4) else 0.2) * np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z)
+                                                                  + g.uniform(0, 2 * np.pi))
+        ora.U[leaf] = boundary.prims_to_cons(W, 1.5)
+
+
+def test_reflux_faces_meeting_at_edges_and_a_corner():
+    ic = _ic()
+    box = dict(geometry="cartesian", x0=(0.0, 0.0, 0.0), x1=(1.0, 1.0, 1.0), n=(16, 16, 16), block=(4, 4, 4),
+               periodic=(True, True, True), max_level=2, gamma=1.5, cfl=0.4)
+    ora = solver.Solver(box, initial="zero", amr=dict(buffer_blocks=0))
+    _smooth_box_state(ora, 33)
+    # the coarse block (1, 1, 1) keeps level 1; its -x, -y and -z neighbours refine
+    fine = {(1, 0, 1, 1), (1, 1, 0, 1), (1, 1, 1, 0)}
+    ora.regrid({b: (fo.REFINE if b in fine else fo.KEEP) for b in ora.forest.leaves}, buffer_blocks=0)
+    gpu = ic.Sim(box, amr=dict(buffer_blocks=0), max_blocks=256)
+    gpu.set_state(*ora.state(), 0.0)
+    assert sum(1 for b in gpu.blocks() if b[0] == 2) == 24
     for n in range(6):
         gpu.step()
         ora.step()
